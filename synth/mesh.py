@@ -1,0 +1,133 @@
+"""Structured simplex meshes of the unit square / unit cube.
+
+The paper's 2D convergence meshes (Table 1) are N x N squares with every
+cell cut into two triangles: (N+1)^2 vertices, 2 N^2 triangles and
+3 N^2 + 2 N edges (its "dual elements").  The 3D workloads use the Kuhn
+split of each cube cell into six tetrahedra, which is conforming and has
+(n+1)^3 vertices and 6 n^3 tetrahedra.
+
+Numbering (all integer, fixed):
+  * lattice node (i, j[, k]) has id  i + (n+1) * (j + (n+1) * k);
+  * 2D cell (i, j) has id i + n*j and yields triangles 2*cell + t,
+      t = 0: [v(i,j), v(i+1,j), v(i+1,j+1)],
+      t = 1: [v(i,j), v(i+1,j+1), v(i,j+1)]      (both counter-clockwise);
+  * 3D cell (i, j, k) has id i + n*(j + n*k) and yields tetrahedra
+    6*cell + s for the axis permutations s in lexicographic order
+    (012, 021, 102, 120, 201, 210); the tetrahedron of permutation
+    (a, b, c) is [v0, v0 + e_a, v0 + e_a + e_b, v0 + (1,1,1)], and for the
+    odd permutations (021, 102, 210) vertices 1 and 2 are swapped so that
+    every tetrahedron has positive orientation (decided from the parity of
+    the permutation, not from floating point).
+
+Coordinates: interior nodes (no lattice index equal to 0 or n) are moved by
+a seeded jitter of up to ``jitter`` * h per axis,
+    x = (i + jitter * (2u - 1)) / n,  u = uniform(seed, 1, 3*id + axis),
+evaluated in that order; boundary nodes stay on the lattice so the domain
+is exactly the unit square/cube.  Every boundary node is a Dirichlet
+pressure node.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .rng import STREAM_JITTER, uniform
+
+
+@dataclass
+class Mesh:
+    dim: int
+    n: int                    # cells per axis
+    coords: np.ndarray        # float64 [n_nodes, dim]
+    elems: np.ndarray         # int32  [n_elems, dim+1]
+    dirichlet: np.ndarray     # uint8  [n_nodes]
+    lattice: np.ndarray       # int32  [n_nodes, dim]
+
+    @property
+    def n_nodes(self):
+        return self.coords.shape[0]
+
+    @property
+    def n_elems(self):
+        return self.elems.shape[0]
+
+    @property
+    def h(self):
+        return 1.0 / self.n
+
+
+# Kuhn permutations in lexicographic order and their parity (1 = odd).
+KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+KUHN_ODD = (0, 1, 1, 0, 0, 1)
+
+
+def table1_counts(N):
+    """Vertices, triangles and edges of the N x N two-triangle split."""
+    return (N + 1) ** 2, 2 * N * N, 3 * N * N + 2 * N
+
+
+def _lattice(dim, n):
+    m = n + 1
+    ids = np.arange(m ** dim, dtype=np.int64)
+    lat = np.empty((m ** dim, dim), dtype=np.int32)
+    rem = ids
+    for ax in range(dim):
+        lat[:, ax] = rem % m
+        rem = rem // m
+    return lat
+
+
+def _elements_2d(n):
+    m = n + 1
+    j, i = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    i = i.ravel().astype(np.int64)
+    j = j.ravel().astype(np.int64)
+    v00 = i + m * j
+    v10 = v00 + 1
+    v11 = v00 + 1 + m
+    v01 = v00 + m
+    el = np.empty((n * n, 2, 3), dtype=np.int64)
+    el[:, 0] = np.stack([v00, v10, v11], axis=1)
+    el[:, 1] = np.stack([v00, v11, v01], axis=1)
+    return el.reshape(-1, 3).astype(np.int32)
+
+
+def _elements_3d(n):
+    m = n + 1
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    i = i.ravel().astype(np.int64)
+    j = j.ravel().astype(np.int64)
+    k = k.ravel().astype(np.int64)
+    v0 = i + m * (j + m * k)
+    step = (1, m, m * m)
+    el = np.empty((n ** 3, 6, 4), dtype=np.int64)
+    for s, (a, b, _c) in enumerate(KUHN_PERMS):
+        w1 = v0 + step[a]
+        w2 = w1 + step[b]
+        w3 = v0 + step[0] + step[1] + step[2]
+        if KUHN_ODD[s]:
+            el[:, s] = np.stack([v0, w2, w1, w3], axis=1)
+        else:
+            el[:, s] = np.stack([v0, w1, w2, w3], axis=1)
+    return el.reshape(-1, 4).astype(np.int32)
+
+
+def structured_mesh(dim, n, jitter=0.0, seed=0):
+    """Unit square (dim 2) or cube (dim 3) with n cells per axis."""
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    lat = _lattice(dim, n)
+    interior = np.all((lat > 0) & (lat < n), axis=1)
+    coords = lat.astype(np.float64)
+    if jitter != 0.0:
+        ids = np.nonzero(interior)[0].astype(np.uint64)
+        for ax in range(dim):
+            u = uniform(seed, STREAM_JITTER, np.uint64(3) * ids + np.uint64(ax))
+            coords[ids.astype(np.int64), ax] = lat[ids.astype(np.int64), ax] + jitter * (2.0 * u - 1.0)
+    coords = coords / float(n)
+    elems = _elements_2d(n) if dim == 2 else _elements_3d(n)
+    dirichlet = (~interior).astype(np.uint8)
+    return Mesh(dim=dim, n=n, coords=np.ascontiguousarray(coords), elems=elems,
+                dirichlet=dirichlet, lattice=lat)

@@ -1,0 +1,100 @@
+"""The synthetic workloads, with their sizes, seeds and value distributions.
+
+  tgv2d_32   2D unit square, 32 x 32 cells x 2 triangles (mesh M2 of the
+             paper's Table 1: 2048 triangles, 1089 vertices), jitter 0.2 h,
+             c = 1, w = 1e-2, source of p = sin(pi x) sin(pi y), rtol 1e-12.
+  cube64     3D unit cube, 64^3 cells x 6 tetrahedra (1,572,864 tets,
+             274,625 nodes), no jitter, rho ~ U[0.5, 2], c = 1/rho,
+             w in {1e-6, 1e-3, 1}, rtol 1e-10.
+  cube160    3D unit cube, 160^3 x 6 (24,576,000 tets, 4,173,281 nodes),
+             jitter 0.2 h, rho = exp(0.5 z), z ~ N(0, 1), c = 1/rho,
+             w = 1e-4, rtol 1e-10.
+  batch256   256 independent meshes: dim 2 or 3 with probability 1/2, node
+             count log-uniform in [2e3, 2e5], w log-uniform in [1e-6, 1],
+             jitter 0.2 h, rho ~ U[0.5, 2].
+  serve10k   10,000 requests over the batch256 meshes, exponential
+             inter-arrival times, uniform mesh choice, 1 % right-hand-side
+             perturbation per request.
+All meshes carry Dirichlet pressure nodes on the whole boundary.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fields
+from .mesh import structured_mesh
+from .rng import MASTER_SEED, STREAM_ARRIVAL, STREAM_BATCH, STREAM_CHOICE, uniform
+
+
+@dataclass
+class Problem:
+    name: str
+    mesh: object
+    coef: np.ndarray          # c_e > 0 per element
+    alpha: float              # mass weight
+    beta: float               # stiffness scale
+    rtol: float
+    seed: int
+    extra: dict = field(default_factory=dict)
+
+
+def tgv2d(n=32, seed=MASTER_SEED, w=1e-2):
+    m = structured_mesh(2, n, jitter=0.2, seed=seed)
+    coef = np.ones(m.n_elems)
+    return Problem("tgv2d_%d" % n, m, coef, w, 1.0, 1e-12, seed,
+                   extra={"source": fields.helmholtz_source(m.coords, w)})
+
+
+def cube(n=64, seed=MASTER_SEED, w=1e-3, jitter=0.0, rho="uniform", rtol=1e-10):
+    m = structured_mesh(3, n, jitter=jitter, seed=seed)
+    if rho == "uniform":
+        r = fields.rho_uniform(seed, m.n_elems)
+    elif rho == "lognormal":
+        r = fields.rho_lognormal(seed, m.n_elems, 0.5)
+    else:
+        raise ValueError(rho)
+    return Problem("cube%d" % n, m, 1.0 / r, w, 1.0, rtol, seed,
+                   extra={"xstar": fields.sine_product(m.coords)})
+
+
+def cube64(w=1e-3, seed=MASTER_SEED):
+    return cube(64, seed, w, 0.0, "uniform")
+
+
+CUBE64_W = (1e-6, 1e-3, 1.0)
+
+
+def cube160(seed=MASTER_SEED):
+    return cube(160, seed, 1e-4, 0.2, "lognormal")
+
+
+def batch_params(n_meshes=256, seed=MASTER_SEED):
+    """(dim, n, w) of each mesh of the batched mix (stream 3)."""
+    out = []
+    for mi in range(n_meshes):
+        u = uniform(seed, STREAM_BATCH, np.arange(4 * mi, 4 * mi + 3, dtype=np.uint64))
+        dim = 2 if u[0] < 0.5 else 3
+        target = np.exp(np.log(2e3) + u[1] * np.log(100.0))
+        n = max(2, int(round(target ** (1.0 / dim))) - 1)
+        w = float(np.exp(np.log(1e-6) + u[2] * np.log(1e6)))
+        out.append((dim, n, w))
+    return out
+
+
+def batch_problem(mi, params, seed=MASTER_SEED):
+    dim, n, w = params[mi]
+    s = seed + 1 + mi
+    m = structured_mesh(dim, n, jitter=0.2, seed=s)
+    r = fields.rho_uniform(s, m.n_elems)
+    return Problem("batch%d" % mi, m, 1.0 / r, w, 1.0, 1e-10, s,
+                   extra={"xstar": fields.sine_product(m.coords)})
+
+
+def arrivals(n_requests, rate, n_meshes, seed=MASTER_SEED):
+    """Arrival times (s) of a Poisson stream of the given rate and the mesh
+    each request targets."""
+    k = np.arange(n_requests, dtype=np.uint64)
+    gaps = -np.log1p(-uniform(seed, STREAM_ARRIVAL, k)) / rate
+    choice = np.minimum((uniform(seed, STREAM_CHOICE, k) * n_meshes).astype(np.int64), n_meshes - 1)
+    return np.cumsum(gaps), choice
