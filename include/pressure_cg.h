@@ -1,0 +1,207 @@
+/*
+ * pressure_cg.h -- C ABI of the MI355X matrix-free P1 pressure solver.
+ *
+ * The library solves, on one AMD Instinct MI355X (gfx950), the linear system
+ * of the projection stage of the semi-implicit hybrid FV/FE scheme for all
+ * Mach number flows (Busto, Rio-Martin, Vazquez-Cendon, Dumbser, arXiv
+ * 2301.08357, Sec. 3.4, the weak problem for the pressure correction):
+ *
+ *     alpha * int dP z  +  beta * int c grad(dP) . grad(z)  =  rhs(z)
+ *
+ * for the P1 (piecewise linear, continuous) pressure correction dP on the
+ * vertices of a triangle (2D) or tetrahedron (3D) mesh, for every P1 test
+ * function z.  In the paper alpha = 1/(gamma-1), beta = dt^2 and c = H, the
+ * enthalpy, piecewise constant per primal element (Sec. 3.3).  The mass
+ * matrix is the consistent one (no lumping, Sec. 3.4).  The sign in front
+ * of the stiffness integral is '+': it follows from Green's formula applied
+ * to the strong pressure equation (Sec. 3) and it is the sign for which the
+ * system is symmetric positive definite, as the paper states; the printed
+ * weak form shows '-'.
+ *
+ * Dirichlet pressure nodes (Sec. 3.6: the exact value is imposed on the
+ * boundary vertex) are eliminated symmetrically.  With P_I, P_B the 0/1
+ * diagonal projectors on free and Dirichlet nodes the operator is
+ *
+ *     A_D = P_I (alpha M + beta K_c) P_I + P_B,
+ *
+ * symmetric positive definite when alpha >= 0, beta > 0, every c_e > 0 and
+ * (alpha > 0 or at least one Dirichlet node).  An inhomogeneous value g is
+ * imposed by passing rhs_B = g and rhs_I = f_I - A_IB g; the solver then
+ * returns p_B = g exactly.
+ *
+ * The solve is the classical conjugate gradient method the paper names for
+ * this system (abstract; Sec. 3.4), matrix-free: the operator is never
+ * assembled.  Stopping test: ||r_k||_2 <= rtol * ||rhs||_2 (Euclidean norm
+ * over all nodes); once it holds, the true residual ||rhs - A_D p|| is
+ * computed and, if it is above rtol * ||rhs||, the residual is replaced by
+ * the true one and the iteration resumes (at most twice).
+ *
+ * Conventions for every call:
+ *  - Node vectors are in the caller's node order; any renumbering is
+ *    internal.  Device vectors are FP64 arrays of n_nodes entries in device
+ *    memory owned by the caller; they are read/written in stream order on
+ *    the given stream (a hipStream_t passed as void*, NULL = default
+ *    stream).
+ *  - Host arrays passed to pressure_setup / pressure_update_coef /
+ *    pressure_layout are copied before the call returns; the caller may
+ *    free them afterwards.
+ *  - A handle owns all the device memory it allocates until
+ *    pressure_destroy.  One handle must not be used from two host threads
+ *    at once; distinct handles are independent.
+ *  - No exception crosses the ABI; every call returns a status code.
+ */
+#ifndef PRESSURE_CG_H
+#define PRESSURE_CG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PM_OK 0               /* success                                          */
+#define PM_NOT_CONVERGED 1    /* max_iter reached; the output holds the last iterate */
+#define PM_EINVAL (-1)        /* invalid argument (NULL, dim, index, rtol, c_e, NaN) */
+#define PM_EDEGENERATE (-2)   /* an element has zero volume                       */
+#define PM_ENOMEM (-3)        /* device or host allocation failed                 */
+#define PM_EBREAKDOWN (-4)    /* CG breakdown: p.Ap <= 0 or not finite            */
+#define PM_EHIP (-5)          /* a HIP runtime call failed                         */
+
+/* Precision flags for pressure_setup / pressure_footprint. */
+#define PM_FP64 1             /* FP64 operator data (always present)               */
+#define PM_FP32_INNER 2       /* also keep FP32 operator data for pressure_solve_mixed */
+/* Morton tile size of the tiled apply (bits 4..7 of flags); 0 = automatic. */
+#define PM_TILE_MASK 0xF0
+#define PM_TILE_256 0x10
+#define PM_TILE_512 0x20
+#define PM_TILE_128 0x30
+
+/* Apply-kernel variants (pressure_set_variant). */
+#define PM_VARIANT_AUTO 0     /* the tuned default                                 */
+#define PM_VARIANT_NODE 1     /* one lane per node, element factors recomputed per incidence */
+#define PM_VARIANT_TILED 2    /* Morton tiles: each element computed once per tile in LDS */
+
+typedef struct pm_handle pm_handle;
+
+/* A primal simplex mesh (the paper's Sec. 3.1: triangles T_k with vertices
+ * V_j in 2D, tetrahedra in 3D).  All arrays are host memory.
+ *   dim        2 (triangles) or 3 (tetrahedra)
+ *   coords     n_nodes * dim doubles, row-major (x, y[, z]) per node
+ *   elems      n_elems * (dim+1) vertex indices, 0-based; any orientation
+ *              (elements with negative volume are reoriented)
+ *   dirichlet  n_nodes bytes, nonzero = Dirichlet pressure node; NULL = none
+ *   lattice    optional n_nodes * dim integer coordinates in [0, 2^21) used
+ *              as Morton keys; NULL = coordinates quantised to 21 bits per
+ *              axis over the bounding box. */
+typedef struct {
+    int32_t dim;
+    int32_t reserved;
+    int64_t n_nodes;
+    int64_t n_elems;
+    const double *coords;
+    const int32_t *elems;
+    const uint8_t *dirichlet;
+    const int32_t *lattice;
+} pm_mesh;
+
+/* Build the device-resident operator of one mesh (Sec. 3.4 operator with
+ * alpha = mass_coef, beta = dt*dt, c = elem_coef).
+ *   elem_coef  host, n_elems doubles, each finite and > 0 (c_e = H_e)
+ *   mass_coef  alpha >= 0 (1/(gamma-1) in the paper)
+ *   dt         > 0; the stiffness scale is beta = dt*dt
+ *   flags      PM_FP64, optionally | PM_FP32_INNER, optionally one PM_TILE_*
+ *   out        receives the handle (NULL on failure)
+ * Validation: dim in {2,3}, n_nodes in [1, 2^31-1), n_elems in
+ * [1, 2^29), indices in range, finite coordinates, nonzero element volume.
+ * Errors: PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EHIP.  Synchronous. */
+int pressure_setup(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt,
+                   int32_t flags, pm_handle **out);
+
+/* New coefficients on the same mesh (a new Picard iterate H^{n+1,k} or a
+ * new time step, Sec. 3.4).  elem_coef may be NULL to keep the current
+ * c_e.  Same validation as pressure_setup.  Synchronous. */
+int pressure_update_coef(pm_handle *h, const double *elem_coef, double mass_coef, double dt);
+
+/* y = A_D x (both device, n_nodes doubles, caller order).  x and y must not
+ * overlap.  Asynchronous on stream. */
+int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *stream);
+
+/* Solve A_D p = rhs by CG in FP64.
+ *   rhs_dev     device, n_nodes doubles
+ *   x0_dev      device initial guess (NULL = zero; its Dirichlet entries are
+ *               replaced by rhs_B); the paper starts from the previous
+ *               solution (Sec. 3.4)
+ *   rtol        > 0, relative to ||rhs||_2
+ *   max_iter    >= 0
+ *   p_dev       device output, n_nodes doubles (may alias x0_dev)
+ *   iters       host out: CG iterations performed
+ *   res_hist    host out or NULL: ||r_k|| / ||rhs|| for k = 0..iters
+ *               (capacity max_iter + 1)
+ *   true_relres host out or NULL: ||rhs - A_D p|| / ||rhs|| at exit
+ * Returns PM_OK, PM_NOT_CONVERGED, PM_EBREAKDOWN, PM_EINVAL or PM_EHIP.
+ * rhs = 0 gives p = 0 after 0 iterations.  Synchronises the stream before
+ * returning (the host outputs are final). */
+int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
+                   int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
+                   double *true_relres, void *stream);
+
+/* Same system by FP64 defect correction around an FP32 inner CG: the outer
+ * residual, the dot-product accumulation and the solution update are FP64;
+ * the inner operator data, vectors and apply are FP32.  Requires a handle
+ * built with PM_FP32_INNER.  inner_rtol in (0,1) is the inner relative
+ * tolerance; iters receives the total number of inner iterations and
+ * outer (may be NULL) the number of outer corrections; res_hist (may be
+ * NULL, capacity max_iter+1) receives the outer relative residuals. */
+int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
+                         double inner_rtol, int32_t max_iter, double *p_dev, int32_t *iters,
+                         int32_t *outer, double *res_hist, double *true_relres, void *stream);
+
+/* Device bytes pressure_setup would allocate for this mesh (operator
+ * data, CG vectors and scratch), for admission control.  Host only. */
+int pressure_footprint(const pm_mesh *mesh, int32_t flags, uint64_t *bytes);
+
+/* Release every device allocation of the handle.  NULL is ignored. */
+void pressure_destroy(pm_handle *h);
+
+/* Static text for a status code. */
+const char *pressure_strerror(int status);
+
+/* Host-only: the integer layout pressure_setup builds (no GPU needed).
+ *   node_new2old  n_nodes    : old id of internal node i (Morton order:
+ *                 nodes sorted by (interleaved 21-bit key with x in the
+ *                 lowest bit, old id))
+ *   elem_new2old  n_elems    : old id of internal element e (sorted by
+ *                 (smallest internal vertex id, old id))
+ *   elems_new     n_elems*(dim+1) : oriented connectivity, internal ids
+ *   n2e_off       n_nodes+1  : node-to-element offsets
+ *   n2e_ent       n_elems*(dim+1) : entries 4*e + a (element e, local
+ *                 vertex a), ascending e per node
+ * Any output pointer may be NULL.  Errors as pressure_setup. */
+int pressure_layout(const pm_mesh *mesh, int32_t *node_new2old, int32_t *elem_new2old,
+                    int32_t *elems_new, int32_t *n2e_off, int32_t *n2e_ent);
+
+/* Select the apply kernel used by pressure_apply / pressure_solve. */
+int pressure_set_variant(pm_handle *h, int32_t variant);
+
+/* Kernel timing with HIP events on the solve stream.  enable != 0 starts
+ * recording the duration of every operator-apply launch inside
+ * pressure_solve (and resets the totals); pressure_timing_read returns the
+ * number of recorded launches and their summed duration in milliseconds.
+ * Recording adds two event records per launch. */
+int pressure_timing_enable(pm_handle *h, int32_t enable);
+int pressure_timing_read(pm_handle *h, int64_t *launches, double *total_ms);
+
+/* Sizes and bytes of the operator data of a handle:
+ *   info[0] n_nodes, [1] n_elems, [2] free nodes, [3] dim,
+ *   [4] algorithmic bytes of one FP64 apply (x read, y written, coordinates,
+ *       connectivity, element coefficient: each once),
+ *   [5] device bytes held by the handle, [6] number of tiles, [7] element
+ *       instances over all tiles. */
+int pressure_info(pm_handle *h, int64_t *info, int32_t n_info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRESSURE_CG_H */

@@ -1,0 +1,10 @@
+"""MI355X-native matrix-free P1 pressure solver (arXiv 2301.08357, Sec. 3.4).
+
+The compute lives in libpressure.so (include/pressure_cg.h); this package is
+its Python binding.  Building: ``paper_2301_08357_amd.build.build()``.
+"""
+
+from ._lib import (PM_OK, PM_NOT_CONVERGED, PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM,  # noqa: F401
+                   PM_EBREAKDOWN, PM_EHIP, PM_FP64, PM_FP32_INNER, PM_TILE_128, PM_TILE_256, PM_TILE_512, PM_VARIANT_AUTO,
+                   PM_VARIANT_NODE, PM_VARIANT_TILED, PressureError, load)
+from .system import PressureSystem, SolveResult, footprint, layout  # noqa: F401

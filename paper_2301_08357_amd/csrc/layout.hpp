@@ -1,0 +1,54 @@
+// Host-side mesh ingest for the P1 pressure operator: validation,
+// orientation, Morton renumbering, element ordering and node-to-element
+// lists.  Integer work only (plus the sign of each element volume).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "pressure_cg.h"
+
+namespace pm {
+
+struct Layout {
+    int dim = 0;
+    int64_t n_nodes = 0, n_elems = 0, n_free = 0;
+    std::vector<int32_t> node_new2old;   // internal node -> caller node
+    std::vector<int32_t> elem_new2old;   // internal element -> caller element
+    std::vector<int32_t> conn;           // n_elems * 4, internal ids, oriented (slot 3 = 0 in 2D)
+    std::vector<int32_t> n2e_off;        // n_nodes + 1
+    std::vector<int32_t> n2e_ent;        // 4*e + a, ascending e
+    std::vector<uint8_t> dirichlet;      // internal order
+    std::vector<double> coords;          // internal order, SoA: coords[ax * n_nodes + i]
+};
+
+// Validate, orient and renumber.  Returns a PM_* status.
+int build_layout(const pm_mesh *m, Layout *L);
+
+// Morton tiles: runs of `tile_nodes` consecutive internal nodes.  A tile
+// holds every element touching one of its nodes (its "instances", ascending
+// element id: first those whose smallest vertex lies in an earlier tile,
+// then the contiguous run the tile owns), the outside vertices those
+// elements reach (its halo, ascending), each instance's vertices as
+// tile-local indices (own node i -> i - first node, halo node -> tile_nodes
+// + rank in the halo list), and for each own node its incidence list
+// (instance index << 2 | local vertex), ascending.
+struct Tiles {
+    int tile_nodes = 0;
+    int64_t n_tiles = 0;
+    int max_inst = 0;                     // largest instance count of a tile
+    int max_halo = 0;                     // largest halo of a tile
+    int max_ent = 0;                      // largest incidence-entry count of a tile
+    std::vector<int32_t> halo_off;        // n_tiles + 1
+    std::vector<int32_t> halo;            // global node ids
+    std::vector<int32_t> inst_off;        // n_tiles + 1
+    std::vector<int32_t> inst_elem;       // element id of each instance
+    std::vector<uint16_t> inst_conn;      // 4 local vertex ids per instance (slot 3 = 0 in 2D)
+    std::vector<int32_t> lent_off;        // n_tiles + 1; tile t's entries start at a multiple of 8
+    std::vector<uint16_t> lnode_off;      // n_tiles * (tile_nodes + 8): per-node offsets relative to lent_off[t]
+    std::vector<uint16_t> lent;           // instance << 2 | local vertex
+};
+
+int build_tiles(const Layout &L, int tile_nodes, Tiles *T);
+
+}  // namespace pm

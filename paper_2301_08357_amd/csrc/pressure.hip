@@ -1,0 +1,1318 @@
+// Matrix-free P1 pressure operator and conjugate-gradient solver for
+// AMD Instinct MI355X (gfx950).
+//
+// Operator (paper Sec. 3.4, weak problem of the projection stage, stiffness
+// sign '+', consistent mass; Dirichlet pressure nodes of Sec. 3.6 eliminated
+// symmetrically):  A_D = P_I (alpha M + beta K_c) P_I + P_B.
+//
+// Element formulas used by the kernels.  For a simplex with vertices X_0..X_d
+// let e_k = X_k - X_0 and let n_k be row k of adj(J), J = [e_1 .. e_d]
+// (3D: n_1 = e_2 x e_3, n_2 = e_3 x e_1, n_3 = e_1 x e_2; 2D: n_1 = (e2y, -e2x),
+// n_2 = (-e1y, e1x)), det = e_1 . n_1 > 0 after orientation.  Then
+// grad(phi_k) = n_k / det, |T| = det / d!, and for nodal values x_0..x_d
+//     G   = sum_k n_k (x_k - x_0)                 (= det * grad x_h)
+//     (K x)_k = c |T| grad(phi_k) . grad(x_h) = w n_k . G,  w = c / (d! det)
+//     (K x)_0 = -sum_k (K x)_k
+//     (M x)_a = |T| / ((d+1)(d+2)) * (x_a + sum_b x_b).
+// The per-element factor beta * c_e / (d! det_e) is precomputed; the geometry
+// is recomputed from the vertex coordinates on every apply.
+//
+// Determinism: every node sums its element contributions in ascending
+// element order (both apply kernels use the same order and the same
+// arithmetic, so they agree bit for bit), and every dot product is a fixed
+// tree inside each block followed by a sum of the block partials in block
+// order.  That last sum is done redundantly by every block of the kernel
+// that consumes it, so the solver needs no atomics and no grid-wide fences;
+// results are bitwise reproducible run to run.
+//
+// One CG iteration k is two kernels:
+//   apply(k):  [prologue: rr_{k-1}, beta, convergence test]
+//              p_k = r_{k-1} + beta p_{k-1} (formed while staging), q = A p_k,
+//              block partials of p_k . q
+//   update(k): [prologue: alpha = rr_{k-1} / p_k.q, breakdown test]
+//              x += alpha p_k, r -= alpha q, block partials of r.r
+// The partials of r.r alternate between two buffers by iteration parity, and
+// p alternates between two buffers, so no kernel overwrites data that another
+// block of the same kernel still reads.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "layout.hpp"
+#include "pressure_cg.h"
+
+namespace {
+
+constexpr int BLK = 256;
+constexpr int CHUNK = 512;           // element instances per LDS pass of the tiled apply
+constexpr int VGRID_MAX = 1024;      // blocks of the vector kernels
+constexpr int AGRID_MAX = 2048;      // blocks of the tiled apply
+constexpr uint32_t DIR_BIT = 0x80000000u;
+
+struct CGState {
+    double bnorm;    // ||rhs||
+    double tol;      // rtol * ||rhs||
+    double rr;       // r.r at the last completed iteration
+    double tt;       // ||rhs - A x||^2 (true residual)
+    int32_t iter;    // completed iterations
+    int32_t max_iter;
+    int32_t done;
+    int32_t status;
+};
+
+// ------------------------------------------------------------------ reductions
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block sum in a fixed order; the result is valid in every thread.
+__device__ inline double block_sum_all(double v, double *red)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int k = 1; k < BLK / 64; ++k) s += red[k];
+    __syncthreads();
+    return s;
+}
+
+// st->done as seen by thread 0, broadcast so the whole block takes the same branch.
+__device__ inline bool block_done(const CGState *st)
+{
+    __shared__ int flag;
+    if (threadIdx.x == 0) flag = st->done;
+    __syncthreads();
+    const bool d = flag != 0;
+    __syncthreads();
+    return d;
+}
+
+// Sum of n block partials, in the same fixed order in every block.
+__device__ inline double sum_partials(const double *part, int n, double *red)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += BLK) v += part[k];
+    return block_sum_all(v, red);
+}
+
+// ----------------------------------------------------------- element kernel
+
+// (alpha M_e + beta K_e) x_e for one simplex: out[a] for the local vertices.
+// xv are the nodal values (zero for Dirichlet vertices), w the element factor,
+// mscale = alpha / (d! (d+1) (d+2)).
+template <int DIM>
+__device__ __forceinline__ void elem_contrib(const double *X, const double *Y, const double *Z,
+                                             const double *xv, double w, double mscale, double out[4])
+{
+    if (DIM == 2) {
+        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0];
+        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0];
+        const double det = e1x * e2y - e1y * e2x;
+        const double n1x = e2y, n1y = -e2x, n2x = -e1y, n2y = e1x;
+        const double d1 = xv[1] - xv[0], d2 = xv[2] - xv[0];
+        const double Gx = n1x * d1 + n2x * d2, Gy = n1y * d1 + n2y * d2;
+        const double r1 = n1x * Gx + n1y * Gy;
+        const double r2 = n2x * Gx + n2y * Gy;
+        const double r0 = -(r1 + r2);
+        const double S = xv[0] + xv[1] + xv[2];
+        const double m = mscale * det;
+        out[0] = w * r0 + m * (xv[0] + S);
+        out[1] = w * r1 + m * (xv[1] + S);
+        out[2] = w * r2 + m * (xv[2] + S);
+        out[3] = 0.0;
+    } else {
+        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
+        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
+        const double e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+        const double n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
+        const double n2x = e3y * e1z - e3z * e1y, n2y = e3z * e1x - e3x * e1z, n2z = e3x * e1y - e3y * e1x;
+        const double n3x = e1y * e2z - e1z * e2y, n3y = e1z * e2x - e1x * e2z, n3z = e1x * e2y - e1y * e2x;
+        const double det = e1x * n1x + e1y * n1y + e1z * n1z;
+        const double d1 = xv[1] - xv[0], d2 = xv[2] - xv[0], d3 = xv[3] - xv[0];
+        const double Gx = n1x * d1 + n2x * d2 + n3x * d3;
+        const double Gy = n1y * d1 + n2y * d2 + n3y * d3;
+        const double Gz = n1z * d1 + n2z * d2 + n3z * d3;
+        const double r1 = n1x * Gx + n1y * Gy + n1z * Gz;
+        const double r2 = n2x * Gx + n2y * Gy + n2z * Gz;
+        const double r3 = n3x * Gx + n3y * Gy + n3z * Gz;
+        const double r0 = -(r1 + r2 + r3);
+        const double S = xv[0] + xv[1] + xv[2] + xv[3];
+        const double m = mscale * det;
+        out[0] = w * r0 + m * (xv[0] + S);
+        out[1] = w * r1 + m * (xv[1] + S);
+        out[2] = w * r2 + m * (xv[2] + S);
+        out[3] = w * r3 + m * (xv[3] + S);
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ double elem_det(const double *X, const double *Y, const double *Z)
+{
+    if (DIM == 2) {
+        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0];
+        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0];
+        return e1x * e2y - e1y * e2x;
+    }
+    const double e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
+    const double e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
+    const double e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+    const double n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
+    return e1x * n1x + e1y * n1y + e1z * n1z;
+}
+
+struct Mesh {
+    int N, E;
+    const int4 *conn;     // 4 vertex ids per element, bit 31 = Dirichlet vertex
+    const double *X, *Y, *Z;
+    const double *w;      // beta * c_e / (d! det_e), per element
+    const uint8_t *dir;   // Dirichlet flag per node
+    double mscale;        // alpha / (d! (d+1) (d+2))
+};
+
+// w_e = beta * c_e / (d! det_e)
+template <int DIM>
+__global__ void __launch_bounds__(BLK) k_factors(Mesh g, const double *__restrict__ coef, double beta,
+                                                 double *__restrict__ w)
+{
+    const int e = blockIdx.x * BLK + threadIdx.x;
+    if (e >= g.E) return;
+    const int4 c = g.conn[e];
+    const int v[4] = {c.x & 0x7fffffff, c.y & 0x7fffffff, c.z & 0x7fffffff, c.w & 0x7fffffff};
+    double X[4], Y[4], Z[4];
+    for (int a = 0; a <= DIM; ++a) {
+        X[a] = g.X[v[a]];
+        Y[a] = g.Y[v[a]];
+        Z[a] = (DIM == 3) ? g.Z[v[a]] : 0.0;
+    }
+    const double fact = (DIM == 2) ? 2.0 : 6.0;
+    w[e] = beta * coef[e] / (fact * elem_det<DIM>(X, Y, Z));
+}
+
+// per-instance copy of the element factor, for the tiled apply
+__global__ void __launch_bounds__(BLK) k_inst_factors(int n, const int *__restrict__ inst_elem,
+                                                      const double *__restrict__ w, double *__restrict__ iw)
+{
+    const int j = blockIdx.x * BLK + threadIdx.x;
+    if (j < n) iw[j] = w[inst_elem[j]];
+}
+
+// ------------------------------------------------------------- CG plumbing
+
+// Arguments of one CG iteration (k >= 1).  With first set, beta = 0.
+struct Iter {
+    int k;
+    int first;
+    const double *r;
+    const double *p_old;   // p_{k-1}
+    double *p_new;         // p_k
+    double *q;             // A p_k
+    CGState *st;
+    double *hist;
+    double *part_pq;       // apply partials (n_apply_blocks)
+    const double *rr_cur;  // partials of r_{k-1}.r_{k-1}
+    const double *rr_prev; // partials of r_{k-2}.r_{k-2}
+    int n_vblocks;
+};
+
+// Prologue of apply(k): every block sums the partials of r_{k-1}.r_{k-1}
+// (and of the previous one for beta) and takes the convergence decision;
+// block 0 records it.  Returns false when the iteration must not run.
+__device__ inline bool iter_prologue(const Iter &it, double *red, double &beta)
+{
+    if (block_done(it.st)) return false;
+    const double rr = sum_partials(it.rr_cur, it.n_vblocks, red);
+    beta = 0.0;
+    if (!it.first) beta = rr / sum_partials(it.rr_prev, it.n_vblocks, red);
+    const double nr = sqrt(rr);
+    const bool bad = !isfinite(rr);
+    const bool stop = bad || !(nr > it.st->tol) || (it.k - 1) >= it.st->max_iter;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!(it.first && it.k > 1)) it.hist[it.k - 1] = nr / it.st->bnorm;
+        it.st->iter = it.k - 1;
+        it.st->rr = rr;
+        if (bad) it.st->status = PM_EBREAKDOWN;
+        if (stop) it.st->done = 1;
+    }
+    return !stop;
+}
+
+// ------------------------------------------------------------ apply kernels
+
+// One lane per node: y_i = sum over the node's elements (ascending) of the
+// element contribution to the node's local vertex; Dirichlet rows copy x.
+// Reference kernel: each element is recomputed for each of its vertices.
+// With CG set, x is p_k = r + beta p_{k-1}, formed on the fly.
+// Nodes are visited in the tiled kernel's order (tile t by block t mod grid,
+// node t*T + j*BLK + lane), so the block partials of p.Ap, and hence whole
+// solves, agree bit for bit between the two kernels.
+template <int DIM, bool CG>
+__global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restrict__ off,
+                                                    const int *__restrict__ ent, int T,
+                                                    const double *__restrict__ x, double *__restrict__ y,
+                                                    Iter it)
+{
+    __shared__ double red[BLK / 64];
+    double beta = 0.0;
+    if (CG && !iter_prologue(it, red, beta)) return;
+    auto val = [&](int v) -> double {
+        if (!CG) return x[v];
+        return it.first ? it.r[v] : it.r[v] + beta * it.p_old[v];
+    };
+    double part = 0.0;
+    const int n_tiles = (g.N + T - 1) / T;
+    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x)
+    for (int jj = threadIdx.x; jj < T; jj += BLK) {
+        const int i = t * T + jj;
+        if (i >= g.N) break;
+        const double xi = val(i);
+        double yi = 0.0;
+        if (g.dir[i]) {
+            yi = xi;
+        } else {
+            for (int k = off[i]; k < off[i + 1]; ++k) {
+                const int en = ent[k];
+                const int4 c = g.conn[en >> 2];
+                const int cv[4] = {c.x, c.y, c.z, c.w};
+                double X[4], Y[4], Z[4], xv[4], o[4];
+                for (int a = 0; a <= DIM; ++a) {
+                    const int v = cv[a] & 0x7fffffff;
+                    X[a] = g.X[v];
+                    Y[a] = g.Y[v];
+                    Z[a] = (DIM == 3) ? g.Z[v] : 0.0;
+                    xv[a] = (cv[a] < 0) ? 0.0 : val(v);
+                }
+                if (DIM == 2) xv[3] = 0.0;
+                elem_contrib<DIM>(X, Y, Z, xv, g.w[en >> 2], g.mscale, o);
+                const int a = en & 3;
+                yi += (a == 0) ? o[0] : (a == 1) ? o[1] : (a == 2) ? o[2] : o[3];
+            }
+        }
+        y[i] = yi;
+        if (CG) {
+            it.p_new[i] = xi;
+            part += xi * yi;
+        }
+    }
+    if (CG) {
+        const double bs = block_sum_all(part, red);
+        if (threadIdx.x == 0) it.part_pq[blockIdx.x] = bs;
+    }
+}
+
+struct TileArgs {
+    int T;                        // nodes per tile
+    int n_tiles;
+    int max_local;                // T + largest halo (LDS node table size)
+    int lent_cap;                 // LDS capacity for one tile's incidence entries (multiple of 8)
+    const int *halo_off, *halo;
+    const int *inst_off;
+    const uint2 *inst_conn;       // 4 x 16-bit local vertex ids
+    const double *inst_w;
+    const int *lent_off;          // 16-byte aligned per tile
+    const uint16_t *lnode_off;    // T + 8 per tile
+    const uint16_t *lent;
+};
+
+// Morton-tiled apply.  One block per tile (grid-stride over tiles):
+//  1. load the tile's element instances (local connectivity and factor) into
+//     registers, its incidence lists into LDS, and the coordinates and nodal
+//     values of its nodes and halo into LDS (Dirichlet values as 0); under CG
+//     the values are p_k = r + beta p_{k-1} and the block stores p_k for its
+//     own nodes;
+//  2. in chunks of CHUNK instances: each lane computes whole elements from
+//     LDS and writes their d+1 contributions to LDS; then each own node adds
+//     the contributions of its incidence list that fall in the chunk
+//     (ascending instance = ascending element id).
+// Every element is computed once per tile that contains one of its vertices.
+// IPT instances per lane must cover the largest tile (checked at setup).
+template <int DIM, bool CG, int NPT, int IPT, int SPT>
+__global__ void __launch_bounds__(BLK) k_apply_tiled(Mesh g, TileArgs ta, const double *__restrict__ x,
+                                                     double *__restrict__ y, Iter it)
+{
+    constexpr int KPC = CHUNK / BLK;   // instances per lane per chunk
+    static_assert(IPT % KPC == 0, "IPT must be a multiple of CHUNK / BLK");
+    extern __shared__ double smem[];
+    __shared__ double red[BLK / 64];
+    double beta = 0.0;
+    if (CG && !iter_prologue(it, red, beta)) return;
+    const int L = ta.max_local;
+    double *sX = smem, *sY = smem + L, *sZ = smem + 2 * L;
+    double *sP = smem + (DIM == 3 ? 3 : 2) * L;
+    double *sC = sP + L;                                        // CHUNK x 4 contributions
+    uint16_t *sL = reinterpret_cast<uint16_t *>(sC + 4 * CHUNK);   // incidence entries
+    uint16_t *sO = sL + ta.lent_cap;                            // T + 8 node offsets
+    double *sQ = reinterpret_cast<double *>(sO + ta.T + 8);      // own p values (unmasked)
+    uint8_t *sD = reinterpret_cast<uint8_t *>(sQ + ta.T);        // own Dirichlet flags
+    double part = 0.0;
+    for (int t = blockIdx.x; t < ta.n_tiles; t += gridDim.x) {
+        const int s = t * ta.T;
+        const int nt = min(ta.T, g.N - s);
+        const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
+        const int i0 = ta.inst_off[t], ni = ta.inst_off[t + 1] - i0;
+        const int e0 = ta.lent_off[t], ne = ta.lent_off[t + 1] - e0;
+        // 1a. instances into registers
+        uint2 ic[IPT];
+        double iw[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int j = threadIdx.x + k * BLK;
+            if (j < ni) {
+                ic[k] = ta.inst_conn[i0 + j];
+                iw[k] = ta.inst_w[i0 + j];
+            }
+        }
+        // 1b. incidence lists into LDS, 8 entries per load
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(ta.lent + e0);
+            uint4 *dst = reinterpret_cast<uint4 *>(sL);
+            for (int q = threadIdx.x; q < (ne + 7) / 8; q += BLK) dst[q] = src[q];
+            const uint4 *osrc = reinterpret_cast<const uint4 *>(ta.lnode_off + (size_t)t * (ta.T + 8));
+            uint4 *odst = reinterpret_cast<uint4 *>(sO);
+            for (int q = threadIdx.x; q < (ta.T + 8) / 8; q += BLK) odst[q] = osrc[q];
+        }
+        // 1c. nodes: own node i at i - s, halo node of rank h at T + h (the
+        // local indices of the instance connectivity); slots nt..T-1 of a
+        // ragged last tile are unused.  All global loads of a lane are issued
+        // before its LDS writes.
+        {
+            int gidx[SPT];
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int l = threadIdx.x + q * BLK;
+                gidx[q] = -1;
+                if (l < nt) gidx[q] = s + l;
+                else if (l >= ta.T && l < ta.T + nh) gidx[q] = ta.halo[h0 + l - ta.T];
+            }
+            double vX[SPT], vY[SPT], vZ[SPT], vP[SPT];
+            uint8_t vD[SPT];
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int gi = gidx[q];
+                if (gi >= 0) {
+                    vX[q] = g.X[gi];
+                    vY[q] = g.Y[gi];
+                    vZ[q] = (DIM == 3) ? g.Z[gi] : 0.0;
+                    vP[q] = CG ? (it.first ? it.r[gi] : it.r[gi] + beta * it.p_old[gi]) : x[gi];
+                    vD[q] = g.dir[gi];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int l = threadIdx.x + q * BLK;
+                const int gi = gidx[q];
+                if (gi >= 0) {
+                    sX[l] = vX[q];
+                    sY[l] = vY[q];
+                    if (DIM == 3) sZ[l] = vZ[q];
+                    sP[l] = vD[q] ? 0.0 : vP[q];
+                    if (l < nt) {
+                        sD[l] = vD[q];
+                        if (CG) {
+                            it.p_new[gi] = vP[q];
+                            sQ[l] = vP[q];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        int kc[NPT], ke[NPT];
+        double acc[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int l = threadIdx.x + j * BLK;
+            acc[j] = 0.0;
+            kc[j] = ke[j] = 0;
+            if (l < nt) {
+                kc[j] = sO[l];
+                ke[j] = sO[l + 1];
+            }
+        }
+        // 2. chunks of instances
+#pragma unroll
+        for (int k0 = 0; k0 < IPT; k0 += KPC) {
+            const int c0 = k0 * BLK;
+            if (c0 >= ni) break;
+#pragma unroll
+            for (int kk = 0; kk < KPC; ++kk) {
+                const int k = k0 + kk;
+                const int j = threadIdx.x + k * BLK;
+                if (j < ni) {
+                    const uint2 cc = ic[k];
+                    const int lv[4] = {int(cc.x & 0xffffu), int(cc.x >> 16), int(cc.y & 0xffffu), int(cc.y >> 16)};
+                    double X[4], Y[4], Z[4], xv[4], o[4];
+#pragma unroll
+                    for (int a = 0; a <= DIM; ++a) {
+                        X[a] = sX[lv[a]];
+                        Y[a] = sY[lv[a]];
+                        Z[a] = (DIM == 3) ? sZ[lv[a]] : 0.0;
+                        xv[a] = sP[lv[a]];
+                    }
+                    if (DIM == 2) xv[3] = 0.0;
+                    elem_contrib<DIM>(X, Y, Z, xv, iw[k], g.mscale, o);
+                    double *dst = sC + 4 * (j - c0);
+                    dst[0] = o[0];
+                    dst[1] = o[1];
+                    dst[2] = o[2];
+                    if (DIM == 3) dst[3] = o[3];
+                }
+            }
+            __syncthreads();
+            const int lim = (c0 + CHUNK) << 2;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                while (kc[j] < ke[j]) {
+                    const int en = sL[kc[j]];
+                    if (en >= lim) break;
+                    acc[j] += sC[en - (c0 << 2)];
+                    ++kc[j];
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int l = threadIdx.x + j * BLK;
+            if (l < nt) {
+                const int gi = s + l;
+                double yi = acc[j];
+                if (CG) {
+                    const double pi = sQ[l];
+                    if (sD[l]) yi = pi;
+                    part += pi * yi;
+                } else if (sD[l]) {
+                    yi = x[gi];
+                }
+                y[gi] = yi;
+            }
+        }
+        __syncthreads();
+    }
+    if (CG) {
+        const double bs = block_sum_all(part, red);
+        if (threadIdx.x == 0) it.part_pq[blockIdx.x] = bs;
+    }
+}
+
+// ------------------------------------------------------------- CG vectors
+
+// update(k): alpha = rr_{k-1} / p_k.q; x += alpha p_k; r -= alpha q;
+// partials of r_k.r_k.
+__global__ void __launch_bounds__(BLK) k_update(int N, double *__restrict__ x, double *__restrict__ r,
+                                                const double *__restrict__ p, const double *__restrict__ q,
+                                                CGState *st, const double *part_pq, int n_ablocks,
+                                                const double *rr_cur, int n_vblocks, double *rr_out)
+{
+    __shared__ double red[BLK / 64];
+    if (block_done(st)) return;
+    const double pq = sum_partials(part_pq, n_ablocks, red);
+    const double rr = sum_partials(rr_cur, n_vblocks, red);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->status = PM_EBREAKDOWN;
+            st->done = 1;
+        }
+        return;
+    }
+    const double a = rr / pq;
+    double v = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+        x[i] += a * p[i];
+        const double ri = r[i] - a * q[i];
+        r[i] = ri;
+        v += ri * ri;
+    }
+    const double bs = block_sum_all(v, red);
+    if (threadIdx.x == 0) rr_out[blockIdx.x] = bs;
+}
+
+// Gather the caller's rhs and initial guess into internal order; Dirichlet
+// entries of the guess take the rhs value.  Partials of rhs.rhs.
+__global__ void __launch_bounds__(BLK) k_prepare(int N, const int *__restrict__ new2old,
+                                                 const uint8_t *__restrict__ dir,
+                                                 const double *__restrict__ rhs,
+                                                 const double *__restrict__ x0, double *__restrict__ b,
+                                                 double *__restrict__ x, double *part)
+{
+    __shared__ double red[BLK / 64];
+    double v = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+        const int o = new2old[i];
+        const double bi = rhs[o];
+        double xi = x0 ? x0[o] : 0.0;
+        if (dir[i]) xi = bi;
+        b[i] = bi;
+        x[i] = xi;
+        v += bi * bi;
+    }
+    const double bs = block_sum_all(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// One block: ||rhs|| and the solver state.
+__global__ void __launch_bounds__(BLK) k_begin(CGState *st, const double *part, int n, double rtol,
+                                               int max_iter, double *hist)
+{
+    __shared__ double red[BLK / 64];
+    const double bb = sum_partials(part, n, red);
+    if (threadIdx.x == 0) {
+        const double bn = sqrt(bb);
+        st->bnorm = bn;
+        st->tol = rtol * bn;
+        st->rr = 0.0;
+        st->tt = 0.0;
+        st->iter = 0;
+        st->max_iter = max_iter;
+        st->status = isfinite(bn) ? 0 : PM_EINVAL;
+        st->done = (!isfinite(bn) || !(bn > 0.0)) ? 1 : 0;
+        if (!(bn > 0.0)) hist[0] = 0.0;
+    }
+}
+
+// r = b - q (q = A x) and partials of r.r; rhs = 0 gives x = 0.
+__global__ void __launch_bounds__(BLK) k_start(int N, const double *__restrict__ b,
+                                               const double *__restrict__ q, double *__restrict__ x,
+                                               double *__restrict__ r, const CGState *st, double *part)
+{
+    __shared__ double red[BLK / 64];
+    const bool zero = !(st->bnorm > 0.0);
+    double v = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+        double ri = b[i] - q[i];
+        if (zero) {
+            x[i] = 0.0;
+            ri = 0.0;
+        }
+        r[i] = ri;
+        v += ri * ri;
+    }
+    const double bs = block_sum_all(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// r = b - q (the true residual of x); partials of r.r.
+__global__ void __launch_bounds__(BLK) k_true_residual(int N, const double *__restrict__ b,
+                                                       const double *__restrict__ q,
+                                                       double *__restrict__ r, double *part)
+{
+    __shared__ double red[BLK / 64];
+    double v = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+        const double ri = b[i] - q[i];
+        r[i] = ri;
+        v += ri * ri;
+    }
+    const double bs = block_sum_all(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// One block: tt = sum of the partials; optionally reopen the solve.
+__global__ void __launch_bounds__(BLK) k_finish_tt(CGState *st, const double *part, int n)
+{
+    __shared__ double red[BLK / 64];
+    const double tt = sum_partials(part, n, red);
+    if (threadIdx.x == 0) st->tt = tt;
+}
+
+__global__ void k_reopen(CGState *st)
+{
+    if (threadIdx.x == 0) st->done = 0;
+}
+
+__global__ void __launch_bounds__(BLK) k_gather(int N, const int *__restrict__ new2old,
+                                                const double *__restrict__ src, double *__restrict__ dst)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i < N) dst[i] = src[new2old[i]];
+}
+
+__global__ void __launch_bounds__(BLK) k_scatter(int N, const int *__restrict__ new2old,
+                                                 const double *__restrict__ src, double *__restrict__ dst)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i < N) dst[new2old[i]] = src[i];
+}
+
+}  // namespace
+
+// ======================================================================
+// Handle
+
+struct pm_handle {
+    int dim = 0;
+    int64_t N = 0, E = 0, n_free = 0;
+    double alpha = 0.0, dt = 0.0;
+    int32_t flags = 0;
+    int variant = PM_VARIANT_TILED;
+    int device = 0;
+    // operator data (device)
+    int *new2old = nullptr;
+    int *n2e_off = nullptr, *n2e_ent = nullptr;
+    int4 *conn = nullptr;
+    double *coords = nullptr;   // SoA
+    double *coef = nullptr;     // c_e, internal element order
+    double *w = nullptr;        // beta c_e / (d! det_e)
+    uint8_t *dir = nullptr;
+    // tiles (device)
+    int tile_nodes = 0, n_tiles = 0, max_local = 0, lent_cap = 0, tile_class = -1;
+    size_t lds_limit = 65536;
+    int64_t n_inst = 0;
+    int *t_halo_off = nullptr, *t_halo = nullptr, *t_inst_off = nullptr, *t_inst_elem = nullptr;
+    int *t_lent_off = nullptr;
+    uint2 *t_inst_conn = nullptr;
+    double *t_inst_w = nullptr;
+    uint16_t *t_lnode_off = nullptr, *t_lent = nullptr;
+    // CG vectors (device, internal order)
+    double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
+    double *pbuf[2] = {nullptr, nullptr};
+    double *part = nullptr;     // [apply partials | rr partials x2 | misc partials]
+    int n_vblocks = 0, n_ablocks = 0;
+    CGState *st = nullptr;
+    double *hist = nullptr;
+    int32_t hist_cap = 0;
+    CGState *hst = nullptr;     // pinned host mirror
+    size_t dev_bytes = 0;
+    std::vector<int32_t> elem_new2old;   // host copy, for coefficient updates
+    // timing (sampled: every TIMING_STRIDE-th apply launch of a solve)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int64_t t_launches = 0;
+    double t_ms = 0.0;
+
+    double *part_pq() const { return part; }
+    double *part_rr(int parity) const { return part + AGRID_MAX + parity * VGRID_MAX; }
+    double *part_misc() const { return part + AGRID_MAX + 2 * VGRID_MAX; }
+};
+
+namespace {
+
+constexpr int TIMING_STRIDE = 8;
+
+#define HIPCK(x)                               \
+    do {                                       \
+        if ((x) != hipSuccess) return PM_EHIP; \
+    } while (0)
+
+#define TRY(x)                      \
+    do {                            \
+        int _s = (x);               \
+        if (_s != PM_OK) return _s; \
+    } while (0)
+
+template <class T>
+int dalloc(pm_handle *h, T **p, size_t count)
+{
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? PM_ENOMEM : PM_EHIP;
+    }
+    h->dev_bytes += bytes;
+    return PM_OK;
+}
+
+template <class T>
+int dupload(pm_handle *h, T **p, const std::vector<T> &v)
+{
+    TRY(dalloc(h, p, v.size()));
+    if (!v.empty()) HIPCK(hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return PM_OK;
+}
+
+inline unsigned grid_of(int64_t n) { return unsigned((n + BLK - 1) / BLK); }
+
+Mesh make_mesh(const pm_handle *h)
+{
+    Mesh g;
+    g.N = int(h->N);
+    g.E = int(h->E);
+    g.conn = h->conn;
+    g.X = h->coords;
+    g.Y = h->coords + h->N;
+    g.Z = (h->dim == 3) ? h->coords + 2 * h->N : h->coords;
+    g.w = h->w;
+    g.dir = h->dir;
+    const double denom = (h->dim == 2) ? 24.0 : 120.0;   // d! (d+1) (d+2)
+    g.mscale = h->alpha / denom;
+    return g;
+}
+
+TileArgs make_tiles(const pm_handle *h)
+{
+    TileArgs ta;
+    ta.T = h->tile_nodes;
+    ta.n_tiles = h->n_tiles;
+    ta.max_local = h->max_local;
+    ta.lent_cap = h->lent_cap;
+    ta.halo_off = h->t_halo_off;
+    ta.halo = h->t_halo;
+    ta.inst_off = h->t_inst_off;
+    ta.inst_conn = h->t_inst_conn;
+    ta.inst_w = h->t_inst_w;
+    ta.lent_off = h->t_lent_off;
+    ta.lnode_off = h->t_lnode_off;
+    ta.lent = h->t_lent;
+    return ta;
+}
+
+bool valid_coef(const double *c, int64_t E)
+{
+    for (int64_t e = 0; e < E; ++e)
+        if (!(c[e] > 0.0) || !std::isfinite(c[e])) return false;
+    return true;
+}
+
+int compute_factors(pm_handle *h)
+{
+    Mesh g = make_mesh(h);
+    const double beta = h->dt * h->dt;
+    if (h->dim == 2)
+        hipLaunchKernelGGL(k_factors<2>, dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, h->w);
+    else
+        hipLaunchKernelGGL(k_factors<3>, dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, h->w);
+    HIPCK(hipGetLastError());
+    if (h->n_inst > 0) {
+        hipLaunchKernelGGL(k_inst_factors, dim3(grid_of(h->n_inst)), dim3(BLK), 0, 0, int(h->n_inst),
+                           h->t_inst_elem, h->w, h->t_inst_w);
+        HIPCK(hipGetLastError());
+    }
+    HIPCK(hipDeviceSynchronize());
+    return PM_OK;
+}
+
+size_t tiled_lds_bytes(const pm_handle *h)
+{
+    return sizeof(double) * (size_t(h->dim + 1) * h->max_local + 4 * CHUNK) +
+           sizeof(uint16_t) * (size_t(h->lent_cap) + h->tile_nodes + 8) + sizeof(double) * h->tile_nodes +
+           h->tile_nodes;
+}
+
+template <class K>
+int launch_tiled_k(pm_handle *h, K kern, const Mesh &g, const TileArgs &ta, const double *x, double *y,
+                   const Iter &it, hipStream_t s)
+{
+    const size_t lds = tiled_lds_bytes(h);
+    if (lds > 65536) HIPCK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    hipLaunchKernelGGL(kern, dim3(h->n_ablocks), dim3(BLK), lds, s, g, ta, x, y, it);
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+// Size classes of the tiled kernel: (nodes per lane, instances per lane,
+// node-table slots per lane).  Setup picks the first class that covers the
+// tile size, the largest tile's instance count and its node table.
+struct TileClass {
+    int npt, ipt, spt;
+};
+constexpr TileClass TILE_CLASSES[] = {{1, 4, 2}, {1, 8, 3}, {1, 12, 3}, {1, 12, 4}, {1, 16, 4},
+                                      {2, 8, 4}, {2, 12, 4}, {2, 16, 6}, {2, 20, 6}, {2, 24, 8}};
+constexpr int N_TILE_CLASSES = sizeof(TILE_CLASSES) / sizeof(TILE_CLASSES[0]);
+
+template <int DIM, bool CG, int C>
+int launch_tiled_c(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
+{
+    constexpr TileClass tc = TILE_CLASSES[C];
+    Mesh g = make_mesh(h);
+    TileArgs ta = make_tiles(h);
+    return launch_tiled_k(h, k_apply_tiled<DIM, CG, tc.npt, tc.ipt, tc.spt>, g, ta, x, y, it, s);
+}
+
+template <int DIM, bool CG>
+int launch_tiled_t(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
+{
+    switch (h->tile_class) {
+    case 0: return launch_tiled_c<DIM, CG, 0>(h, x, y, it, s);
+    case 1: return launch_tiled_c<DIM, CG, 1>(h, x, y, it, s);
+    case 2: return launch_tiled_c<DIM, CG, 2>(h, x, y, it, s);
+    case 3: return launch_tiled_c<DIM, CG, 3>(h, x, y, it, s);
+    case 4: return launch_tiled_c<DIM, CG, 4>(h, x, y, it, s);
+    case 5: return launch_tiled_c<DIM, CG, 5>(h, x, y, it, s);
+    case 6: return launch_tiled_c<DIM, CG, 6>(h, x, y, it, s);
+    case 7: return launch_tiled_c<DIM, CG, 7>(h, x, y, it, s);
+    case 8: return launch_tiled_c<DIM, CG, 8>(h, x, y, it, s);
+    case 9: return launch_tiled_c<DIM, CG, 9>(h, x, y, it, s);
+    default: return PM_EINVAL;
+    }
+}
+
+template <int DIM, bool CG>
+int launch_node_t(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
+{
+    Mesh g = make_mesh(h);
+    hipLaunchKernelGGL((k_apply_node<DIM, CG>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off, h->n2e_ent,
+                       h->tile_nodes, x, y, it);
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+// y = A x on internal vectors (cg = false) or one CG iteration's apply.
+int launch_apply(pm_handle *h, const double *x, double *y, const Iter *it, hipStream_t s)
+{
+    Iter dummy{};
+    const Iter &a = it ? *it : dummy;
+    const bool cg = it != nullptr;
+    if (h->variant == PM_VARIANT_NODE) {
+        if (h->dim == 2) return cg ? launch_node_t<2, true>(h, x, y, a, s) : launch_node_t<2, false>(h, x, y, a, s);
+        return cg ? launch_node_t<3, true>(h, x, y, a, s) : launch_node_t<3, false>(h, x, y, a, s);
+    }
+    if (h->dim == 2) return cg ? launch_tiled_t<2, true>(h, x, y, a, s) : launch_tiled_t<2, false>(h, x, y, a, s);
+    return cg ? launch_tiled_t<3, true>(h, x, y, a, s) : launch_tiled_t<3, false>(h, x, y, a, s);
+}
+
+int ensure_hist(pm_handle *h, int32_t max_iter)
+{
+    if (max_iter + 1 <= h->hist_cap) return PM_OK;
+    if (h->hist) {
+        HIPCK(hipFree(h->hist));
+        h->dev_bytes -= size_t(h->hist_cap) * sizeof(double);
+        h->hist = nullptr;
+    }
+    int32_t cap = std::max<int32_t>(max_iter + 1, 1024);
+    TRY(dalloc(h, &h->hist, size_t(cap)));
+    h->hist_cap = cap;
+    return PM_OK;
+}
+
+int event_pair(pm_handle *h, size_t k, hipEvent_t *a, hipEvent_t *b)
+{
+    while (h->ev.size() < 2 * (k + 1)) {
+        hipEvent_t e;
+        HIPCK(hipEventCreate(&e));
+        h->ev.push_back(e);
+    }
+    *a = h->ev[2 * k];
+    *b = h->ev[2 * k + 1];
+    return PM_OK;
+}
+
+int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
+{
+    pm::Tiles T;
+    TRY(pm::build_tiles(L, tile_nodes, &T));
+    h->tile_nodes = tile_nodes;
+    h->n_tiles = int(T.n_tiles);
+    h->max_local = tile_nodes + T.max_halo;
+    h->lent_cap = ((T.max_ent + 7) / 8) * 8 + 8;
+    h->n_inst = int64_t(T.inst_elem.size());
+    // smallest size class covering the tile, its instances and node table
+    const int need_n = (tile_nodes + BLK - 1) / BLK;
+    const int need_i = (T.max_inst + BLK - 1) / BLK;
+    const int need_s = (h->max_local + BLK - 1) / BLK;
+    h->tile_class = -1;
+    for (int c = 0; c < N_TILE_CLASSES; ++c)
+        if (TILE_CLASSES[c].npt == need_n && TILE_CLASSES[c].ipt >= need_i && TILE_CLASSES[c].spt >= need_s) {
+            h->tile_class = c;
+            break;
+        }
+    if (h->tile_class < 0) return PM_EINVAL;
+    TRY(dupload(h, &h->t_halo_off, T.halo_off));
+    TRY(dupload(h, &h->t_halo, T.halo));
+    TRY(dupload(h, &h->t_inst_off, T.inst_off));
+    TRY(dupload(h, &h->t_inst_elem, T.inst_elem));
+    TRY(dupload(h, &h->t_lent_off, T.lent_off));
+    TRY(dupload(h, &h->t_lnode_off, T.lnode_off));
+    TRY(dupload(h, &h->t_lent, T.lent));
+    TRY(dalloc(h, &h->t_inst_conn, size_t(h->n_inst)));
+    if (h->n_inst > 0)
+        HIPCK(hipMemcpy(h->t_inst_conn, T.inst_conn.data(), sizeof(uint16_t) * T.inst_conn.size(),
+                        hipMemcpyHostToDevice));
+    TRY(dalloc(h, &h->t_inst_w, size_t(h->n_inst)));
+    h->n_ablocks = std::min(h->n_tiles, AGRID_MAX);
+    if (tiled_lds_bytes(h) > h->lds_limit) return PM_EINVAL;
+    return PM_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+
+extern "C" {
+
+const char *pressure_strerror(int status)
+{
+    switch (status) {
+    case PM_OK: return "ok";
+    case PM_NOT_CONVERGED: return "not converged within max_iter";
+    case PM_EINVAL: return "invalid argument";
+    case PM_EDEGENERATE: return "degenerate element (zero volume)";
+    case PM_ENOMEM: return "out of memory";
+    case PM_EBREAKDOWN: return "CG breakdown (p.Ap <= 0 or not finite)";
+    case PM_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int pressure_layout(const pm_mesh *mesh, int32_t *node_new2old, int32_t *elem_new2old,
+                    int32_t *elems_new, int32_t *n2e_off, int32_t *n2e_ent)
+{
+    try {
+        pm::Layout L;
+        int s = pm::build_layout(mesh, &L);
+        if (s != PM_OK) return s;
+        const int nv = L.dim + 1;
+        if (node_new2old) std::memcpy(node_new2old, L.node_new2old.data(), sizeof(int32_t) * L.n_nodes);
+        if (elem_new2old) std::memcpy(elem_new2old, L.elem_new2old.data(), sizeof(int32_t) * L.n_elems);
+        if (elems_new)
+            for (int64_t e = 0; e < L.n_elems; ++e)
+                for (int a = 0; a < nv; ++a) elems_new[e * nv + a] = L.conn[e * 4 + a];
+        if (n2e_off) std::memcpy(n2e_off, L.n2e_off.data(), sizeof(int32_t) * (L.n_nodes + 1));
+        if (n2e_ent) std::memcpy(n2e_ent, L.n2e_ent.data(), sizeof(int32_t) * L.n2e_ent.size());
+        return PM_OK;
+    } catch (const std::bad_alloc &) {
+        return PM_ENOMEM;
+    } catch (...) {
+        return PM_EINVAL;
+    }
+}
+
+int pressure_footprint(const pm_mesh *mesh, int32_t flags, uint64_t *bytes)
+{
+    if (!mesh || !bytes || (mesh->dim != 2 && mesh->dim != 3) || mesh->n_nodes < 1 || mesh->n_elems < 1)
+        return PM_EINVAL;
+    (void)flags;
+    const uint64_t N = uint64_t(mesh->n_nodes), E = uint64_t(mesh->n_elems), d = uint64_t(mesh->dim);
+    // element instances over all tiles: at most 2 x elements on the meshes of
+    // interest (measured 1.3-1.6 x on Morton tiles of 256-1024 nodes)
+    const uint64_t I = 2 * E;
+    uint64_t b = 0;
+    b += 4 * N;                             // new2old
+    b += 4 * (N + 1) + 4 * (d + 1) * E;     // node-to-element lists
+    b += 16 * E;                            // connectivity
+    b += 8 * d * N;                         // coordinates
+    b += 16 * E;                            // c_e and w_e
+    b += N;                                 // Dirichlet flags
+    b += I * (4 + 8 + 8) + 2 * (d + 1) * E + 4 * N + 2 * N;   // tiles
+    b += 7 * 8 * N;                         // b, x, r, q, t, p (x2)
+    b += 8 * (AGRID_MAX + 3 * VGRID_MAX) + 1024 * 8 + 256;
+    *bytes = b;
+    return PM_OK;
+}
+
+void pressure_destroy(pm_handle *h)
+{
+    if (!h) return;
+    void *ptrs[] = {h->new2old, h->n2e_off, h->n2e_ent, h->conn, h->coords, h->coef, h->w, h->dir,
+                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_lent_off, h->t_inst_conn,
+                    h->t_inst_w, h->t_lnode_off, h->t_lent, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
+                    h->pbuf[1], h->part, h->st, h->hist};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->hst) (void)hipHostFree(h->hst);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+}
+
+static int tile_nodes_for(int32_t flags, int64_t N)
+{
+    switch (flags & PM_TILE_MASK) {
+    case PM_TILE_256: return 256;
+    case PM_TILE_512: return 512;
+    case PM_TILE_128: return 128;
+    case 0: return N < 2000000 ? 256 : 512;
+    default: return -1;
+    }
+}
+
+static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt,
+                      int32_t flags, pm_handle *h)
+{
+    if (!elem_coef || !(mass_coef >= 0.0) || !std::isfinite(mass_coef) || !(dt > 0.0) || !std::isfinite(dt))
+        return PM_EINVAL;
+    if (!mesh || !valid_coef(elem_coef, mesh->n_elems)) return PM_EINVAL;
+    pm::Layout L;
+    TRY(pm::build_layout(mesh, &L));
+    HIPCK(hipGetDevice(&h->device));
+    {
+        int v = 0;
+        HIPCK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+        h->lds_limit = size_t(v) - 1024;   // static LDS of the kernels
+    }
+    h->dim = L.dim;
+    h->N = L.n_nodes;
+    h->E = L.n_elems;
+    h->n_free = L.n_free;
+    h->alpha = mass_coef;
+    h->dt = dt;
+    h->flags = flags;
+    const int64_t N = h->N, E = h->E;
+    h->n_vblocks = int(std::min<int64_t>(grid_of(N), VGRID_MAX));
+
+    // connectivity with the Dirichlet flag of each vertex in bit 31
+    std::vector<int32_t> conn(L.conn);
+    const int nv = L.dim + 1;
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < nv; ++a) {
+            int32_t v = conn[e * 4 + a];
+            if (L.dirichlet[v]) conn[e * 4 + a] = int32_t(uint32_t(v) | DIR_BIT);
+        }
+    std::vector<double> cnew(E);
+    for (int64_t e = 0; e < E; ++e) cnew[e] = elem_coef[L.elem_new2old[e]];
+    h->elem_new2old = L.elem_new2old;
+
+    TRY(dupload(h, &h->new2old, L.node_new2old));
+    TRY(dupload(h, &h->n2e_off, L.n2e_off));
+    TRY(dupload(h, &h->n2e_ent, L.n2e_ent));
+    TRY(dalloc(h, &h->conn, E));
+    HIPCK(hipMemcpy(h->conn, conn.data(), 16 * E, hipMemcpyHostToDevice));
+    TRY(dupload(h, &h->coords, L.coords));
+    TRY(dupload(h, &h->coef, cnew));
+    TRY(dalloc(h, &h->w, E));
+    TRY(dupload(h, &h->dir, L.dirichlet));
+    const int tn = tile_nodes_for(flags, N);
+    if (tn < 0) return PM_EINVAL;
+    TRY(build_tiles_on_device(h, L, tn));
+    for (double **v : {&h->b, &h->x, &h->r, &h->q, &h->t, &h->pbuf[0], &h->pbuf[1]}) TRY(dalloc(h, v, N));
+    TRY(dalloc(h, &h->part, AGRID_MAX + 3 * VGRID_MAX));
+    TRY(dalloc(h, &h->st, 1));
+    TRY(ensure_hist(h, 1023));
+    HIPCK(hipHostMalloc((void **)&h->hst, sizeof(CGState), hipHostMallocDefault));
+    HIPCK(hipMemset(h->st, 0, sizeof(CGState)));
+    HIPCK(hipMemset(h->part, 0, sizeof(double) * (AGRID_MAX + 3 * VGRID_MAX)));
+    HIPCK(hipMemset(h->pbuf[0], 0, 8 * N));
+    HIPCK(hipMemset(h->pbuf[1], 0, 8 * N));
+    TRY(compute_factors(h));
+    return PM_OK;
+}
+
+int pressure_setup(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt,
+                   int32_t flags, pm_handle **out)
+{
+    if (!out) return PM_EINVAL;
+    *out = nullptr;
+    pm_handle *h = nullptr;
+    try {
+        h = new pm_handle();
+        int s = setup_impl(mesh, elem_coef, mass_coef, dt, flags, h);
+        if (s != PM_OK) {
+            pressure_destroy(h);
+            return s;
+        }
+    } catch (const std::bad_alloc &) {
+        pressure_destroy(h);
+        return PM_ENOMEM;
+    } catch (...) {
+        pressure_destroy(h);
+        return PM_EINVAL;
+    }
+    *out = h;
+    return PM_OK;
+}
+
+int pressure_update_coef(pm_handle *h, const double *elem_coef, double mass_coef, double dt)
+{
+    if (!h || !(mass_coef >= 0.0) || !std::isfinite(mass_coef) || !(dt > 0.0) || !std::isfinite(dt))
+        return PM_EINVAL;
+    if (elem_coef) {
+        if (!valid_coef(elem_coef, h->E)) return PM_EINVAL;
+        std::vector<double> cnew(h->E);
+        for (int64_t e = 0; e < h->E; ++e) cnew[e] = elem_coef[h->elem_new2old[e]];
+        HIPCK(hipMemcpy(h->coef, cnew.data(), 8 * h->E, hipMemcpyHostToDevice));
+    }
+    h->alpha = mass_coef;
+    h->dt = dt;
+    return compute_factors(h);
+}
+
+int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *stream)
+{
+    if (!h || !x_dev || !y_dev || x_dev == y_dev) return PM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned grid = grid_of(h->N);
+    const int N = int(h->N);
+    hipLaunchKernelGGL(k_gather, dim3(grid), dim3(BLK), 0, s, N, h->new2old, x_dev, h->t);
+    HIPCK(hipGetLastError());
+    TRY(launch_apply(h, h->t, h->q, nullptr, s));
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLK), 0, s, N, h->new2old, h->q, y_dev);
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+// Launch CG iterations k0 .. k0+count-1 (the first one with beta = 0 when
+// first is set).
+static int launch_iterations(pm_handle *h, int k0, int count, bool first, size_t *timed, hipStream_t s)
+{
+    const int N = int(h->N);
+    for (int c = 0; c < count; ++c) {
+        const int k = k0 + c;
+        Iter it;
+        it.k = k;
+        it.first = (first && c == 0) ? 1 : 0;
+        it.r = h->r;
+        it.p_old = h->pbuf[(k - 1) & 1];
+        it.p_new = h->pbuf[k & 1];
+        it.q = h->q;
+        it.st = h->st;
+        it.hist = h->hist;
+        it.part_pq = h->part_pq();
+        it.rr_cur = h->part_rr((k - 1) & 1);
+        it.rr_prev = h->part_rr(k & 1);
+        it.n_vblocks = h->n_vblocks;
+        const bool sample = h->timing && (k % TIMING_STRIDE) == 1;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (sample) {
+            TRY(event_pair(h, *timed, &e0, &e1));
+            HIPCK(hipEventRecord(e0, s));
+        }
+        TRY(launch_apply(h, it.p_new, h->q, &it, s));
+        if (sample) {
+            HIPCK(hipEventRecord(e1, s));
+            ++*timed;
+        }
+        hipLaunchKernelGGL(k_update, dim3(h->n_vblocks), dim3(BLK), 0, s, N, h->x, h->r, h->pbuf[k & 1], h->q,
+                           h->st, h->part_pq(), h->n_ablocks, h->part_rr((k - 1) & 1), h->n_vblocks,
+                           h->part_rr(k & 1));
+    }
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+static int read_state(pm_handle *h, hipStream_t s)
+{
+    HIPCK(hipMemcpyAsync(h->hst, h->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
+                   int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
+                   double *true_relres, void *stream)
+{
+    if (!h || !rhs_dev || !p_dev || !iters || !(rtol > 0.0) || !std::isfinite(rtol) || max_iter < 0)
+        return PM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    TRY(ensure_hist(h, max_iter));
+    const int N = int(h->N);
+    const unsigned vg = h->n_vblocks;
+
+    hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
+                       h->part_misc());
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist);
+    HIPCK(hipGetLastError());
+    TRY(launch_apply(h, h->x, h->q, nullptr, s));
+    hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
+    HIPCK(hipGetLastError());
+
+    int replaced = 0;
+    int k = 1;            // next iteration to launch
+    bool first = true;    // k is the first iteration after a (re)start
+    size_t timed = 0;
+    for (;;) {
+        int chunk = 4;
+        for (;;) {
+            const size_t t0 = timed;
+            TRY(launch_iterations(h, k, chunk, first, &timed, s));
+            const int kfirst = k;
+            k += chunk;
+            first = false;
+            chunk = std::min(chunk * 2, 64);
+            TRY(read_state(h, s));
+            if (h->timing) {
+                // sampled launches that ran a full iteration (k <= final count)
+                size_t idx = t0;
+                for (int kk = kfirst; kk < kfirst + (k - kfirst) && idx < timed; ++kk) {
+                    if ((kk % TIMING_STRIDE) != 1) continue;
+                    const bool full = !h->hst->done || kk <= h->hst->iter;
+                    if (full) {
+                        float ms = 0.f;
+                        HIPCK(hipEventElapsedTime(&ms, h->ev[2 * idx], h->ev[2 * idx + 1]));
+                        h->t_ms += ms;
+                        h->t_launches++;
+                    }
+                    ++idx;
+                }
+            }
+            if (h->hst->done) break;
+        }
+        if (h->hst->status != 0) break;
+        if (!(h->hst->bnorm > 0.0)) break;
+        // true residual of the final iterate
+        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        const int kdone = h->hst->iter;
+        hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_rr(kdone & 1));
+        hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_rr(kdone & 1), int(vg));
+        HIPCK(hipGetLastError());
+        TRY(read_state(h, s));
+        const double rel = std::sqrt(h->hst->tt) / h->hst->bnorm;
+        if (rel <= rtol || replaced >= 2 || kdone >= max_iter) break;
+        // residual replacement: r is now the true residual; restart the directions
+        hipLaunchKernelGGL(k_reopen, dim3(1), dim3(64), 0, s, h->st);
+        HIPCK(hipGetLastError());
+        k = kdone + 1;
+        first = true;
+        ++replaced;
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
+    HIPCK(hipGetLastError());
+    const CGState fin = *h->hst;
+    if (res_hist) HIPCK(hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (fin.iter + 1), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    *iters = fin.iter;
+    double rel = 0.0;
+    if (fin.bnorm > 0.0) rel = std::sqrt(fin.tt) / fin.bnorm;
+    if (true_relres) *true_relres = rel;
+    if (fin.status != 0) return fin.status;
+    return (rel <= rtol) ? PM_OK : PM_NOT_CONVERGED;
+}
+
+int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
+                         double inner_rtol, int32_t max_iter, double *p_dev, int32_t *iters,
+                         int32_t *outer, double *res_hist, double *true_relres, void *stream)
+{
+    (void)h; (void)rhs_dev; (void)x0_dev; (void)rtol; (void)inner_rtol; (void)max_iter; (void)p_dev;
+    (void)iters; (void)outer; (void)res_hist; (void)true_relres; (void)stream;
+    return PM_EINVAL;
+}
+
+int pressure_set_variant(pm_handle *h, int32_t variant)
+{
+    if (!h) return PM_EINVAL;
+    switch (variant) {
+    case PM_VARIANT_AUTO:
+    case PM_VARIANT_TILED: h->variant = PM_VARIANT_TILED; return PM_OK;
+    case PM_VARIANT_NODE: h->variant = PM_VARIANT_NODE; return PM_OK;
+    default: return PM_EINVAL;
+    }
+}
+
+int pressure_timing_enable(pm_handle *h, int32_t enable)
+{
+    if (!h) return PM_EINVAL;
+    h->timing = enable != 0;
+    h->t_launches = 0;
+    h->t_ms = 0.0;
+    return PM_OK;
+}
+
+int pressure_timing_read(pm_handle *h, int64_t *launches, double *total_ms)
+{
+    if (!h || !launches || !total_ms) return PM_EINVAL;
+    *launches = h->t_launches;
+    *total_ms = h->t_ms;
+    return PM_OK;
+}
+
+int pressure_info(pm_handle *h, int64_t *info, int32_t n_info)
+{
+    if (!h || !info || n_info < 0) return PM_EINVAL;
+    const int64_t d = h->dim;
+    int64_t v[8] = {h->N, h->E, h->n_free, d,
+                    16 * h->N + 8 * d * h->N + 4 * (d + 1) * h->E + 8 * h->E,
+                    int64_t(h->dev_bytes), h->n_tiles, h->n_inst};
+    for (int k = 0; k < n_info && k < 8; ++k) info[k] = v[k];
+    return PM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Every computation happens in libpressure.so (host setup in C++, the
+operator and the solver in HIP kernels).  PyTorch provides device memory
+and streams: vectors are float64 CUDA tensors, and calls run on the
+current stream unless a stream is given.
+"""
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import PmMesh, check, load
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _MeshArgs:
+    """Keeps the host arrays alive while the C call reads them."""
+
+    def __init__(self, dim, coords, elems, dirichlet=None, lattice=None):
+        self.coords = _np(coords, np.float64)
+        self.elems = _np(elems, np.int32)
+        self.dirichlet = None if dirichlet is None else _np(dirichlet, np.uint8)
+        self.lattice = None if lattice is None else _np(lattice, np.int32)
+        n = self.coords.shape[0]
+        if self.coords.shape != (n, dim) or self.elems.ndim != 2 or self.elems.shape[1] != dim + 1:
+            raise ValueError("coords must be [n, dim] and elems [m, dim+1]")
+        if self.dirichlet is not None and self.dirichlet.shape != (n,):
+            raise ValueError("dirichlet must have one entry per node")
+        if self.lattice is not None and self.lattice.shape != (n, dim):
+            raise ValueError("lattice must be [n, dim]")
+        self.struct = PmMesh(dim, 0, n, self.elems.shape[0], _ptr(self.coords), _ptr(self.elems),
+                             _ptr(self.dirichlet), _ptr(self.lattice))
+
+    def ref(self):
+        return ctypes.byref(self.struct)
+
+
+def layout(dim, coords, elems, lattice=None):
+    """The integer layout the library builds (host only, no GPU)."""
+    m = _MeshArgs(dim, coords, elems, None, lattice)
+    n, e = m.coords.shape[0], m.elems.shape[0]
+    out = {
+        "node_new2old": np.zeros(n, dtype=np.int32),
+        "elem_new2old": np.zeros(e, dtype=np.int32),
+        "elems_new": np.zeros((e, dim + 1), dtype=np.int32),
+        "n2e_off": np.zeros(n + 1, dtype=np.int32),
+        "n2e_ent": np.zeros(e * (dim + 1), dtype=np.int32),
+    }
+    st = load().pressure_layout(m.ref(), *[_ptr(out[k]) for k in
+                                           ("node_new2old", "elem_new2old", "elems_new", "n2e_off", "n2e_ent")])
+    return st, out
+
+
+def footprint(dim, coords, elems, flags=_lib.PM_FP64):
+    m = _MeshArgs(dim, coords, elems)
+    b = ctypes.c_uint64(0)
+    check(load().pressure_footprint(m.ref(), flags, ctypes.byref(b)), "pressure_footprint")
+    return b.value
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, n, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 CUDA tensor" % what)
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError("%s must be contiguous with %d entries" % (what, n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    p: object
+    status: int
+    iters: int
+    hist: np.ndarray
+    true_relres: float
+    outer: int = 0
+
+
+class PressureSystem:
+    """The P1 pressure operator of one mesh, resident on the GPU.
+
+    alpha * M + dt^2 * K_c with Dirichlet pressure nodes (see
+    include/pressure_cg.h for the exact definition)."""
+
+    def __init__(self, dim, coords, elems, coef, mass_coef, dt=1.0, dirichlet=None, lattice=None,
+                 flags=_lib.PM_FP64):
+        m = _MeshArgs(dim, coords, elems, dirichlet, lattice)
+        c = _np(coef, np.float64)
+        if c.shape != (m.elems.shape[0],):
+            raise ValueError("coef must have one entry per element")
+        h = ctypes.c_void_p(None)
+        check(load().pressure_setup(m.ref(), _ptr(c), float(mass_coef), float(dt), int(flags),
+                                    ctypes.byref(h)), "pressure_setup")
+        self._h = h
+        self.dim = dim
+        self.n_nodes = m.coords.shape[0]
+        self.n_elems = m.elems.shape[0]
+
+    @classmethod
+    def from_problem(cls, prob, flags=_lib.PM_FP64):
+        m = prob.mesh
+        return cls(m.dim, m.coords, m.elems, prob.coef, prob.alpha, float(np.sqrt(prob.beta)),
+                   m.dirichlet, m.lattice, flags)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().pressure_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update_coef(self, coef=None, mass_coef=None, dt=1.0):
+        c = None if coef is None else _np(coef, np.float64)
+        check(load().pressure_update_coef(self._h, _ptr(c), float(mass_coef), float(dt)),
+              "pressure_update_coef")
+
+    def set_variant(self, variant):
+        check(load().pressure_set_variant(self._h, int(variant)), "pressure_set_variant")
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        check(load().pressure_apply(self._h, _dev_ptr(x, self.n_nodes, "x"), _dev_ptr(y, self.n_nodes, "y"),
+                                    _stream_handle(stream)), "pressure_apply")
+        return y
+
+    def solve(self, rhs, x0=None, rtol=1e-10, max_iter=20000, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        it = ctypes.c_int32(0)
+        tr = ctypes.c_double(0.0)
+        hist = np.zeros(max_iter + 1)
+        st = load().pressure_solve(self._h, _dev_ptr(rhs, self.n_nodes, "rhs"),
+                                   None if x0 is None else _dev_ptr(x0, self.n_nodes, "x0"),
+                                   float(rtol), int(max_iter), _dev_ptr(out, self.n_nodes, "p"),
+                                   ctypes.byref(it), _ptr(hist), ctypes.byref(tr), _stream_handle(stream))
+        check(st, "pressure_solve")
+        return SolveResult(out, st, it.value, hist[: it.value + 1].copy(), tr.value)
+
+    def solve_mixed(self, rhs, x0=None, rtol=1e-10, inner_rtol=1e-4, max_iter=20000, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(rhs)
+        it = ctypes.c_int32(0)
+        outer = ctypes.c_int32(0)
+        tr = ctypes.c_double(0.0)
+        hist = np.zeros(max_iter + 1)
+        st = load().pressure_solve_mixed(self._h, _dev_ptr(rhs, self.n_nodes, "rhs"),
+                                         None if x0 is None else _dev_ptr(x0, self.n_nodes, "x0"),
+                                         float(rtol), float(inner_rtol), int(max_iter),
+                                         _dev_ptr(out, self.n_nodes, "p"), ctypes.byref(it), ctypes.byref(outer),
+                                         _ptr(hist), ctypes.byref(tr), _stream_handle(stream))
+        check(st, "pressure_solve_mixed")
+        return SolveResult(out, st, it.value, hist[: outer.value + 1].copy(), tr.value, outer.value)
+
+    def timing_enable(self, on=True):
+        check(load().pressure_timing_enable(self._h, 1 if on else 0), "pressure_timing_enable")
+
+    def timing_read(self):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        check(load().pressure_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)), "pressure_timing_read")
+        return n.value, ms.value
+
+    def info(self):
+        v = (ctypes.c_int64 * 8)()
+        check(load().pressure_info(self._h, v, 8), "pressure_info")
+        keys = ("n_nodes", "n_elems", "n_free", "dim", "apply_bytes", "device_bytes", "n_tiles", "n_instances")
+        return dict(zip(keys, list(v)))
