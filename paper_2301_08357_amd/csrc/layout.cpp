@@ -188,18 +188,18 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
     const int64_t nt = T->n_tiles;
     T->halo_off.assign(nt + 1, 0);
     T->inst_off.assign(nt + 1, 0);
-    T->lent_off.assign(nt + 1, 0);
-    T->lnode_off.assign(nt * (tile_nodes + 8), 0);
     T->halo.clear();
     T->inst_elem.clear();
     T->inst_conn.clear();
-    T->lent.clear();
+    T->inst_row.clear();
     T->inst_elem.reserve(size_t(E) * 3 / 2 + 16);
     T->inst_conn.reserve(size_t(E) * 6 + 64);
-    T->lent.reserve(size_t(E) * nv + 16);
+    T->inst_row.reserve(size_t(E) * 6 + 64);
     T->max_inst = 0;
     T->max_halo = 0;
-    T->max_ent = 0;
+    T->max_deg = 0;
+    for (int64_t i = 0; i < N; ++i) T->max_deg = std::max<int>(T->max_deg, L.n2e_off[i + 1] - L.n2e_off[i]);
+    if (T->max_deg > 254) return PM_EINVAL;
 
     // first element whose smallest vertex is >= v (elements are sorted by it)
     std::vector<int32_t> ebeg(N + 1, 0);
@@ -223,7 +223,6 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
         std::sort(halo_el.begin(), halo_el.end());
         halo_el.erase(std::unique(halo_el.begin(), halo_el.end()), halo_el.end());
         const int64_t ninst = int64_t(halo_el.size()) + (own1 - own0);
-        if (ninst >= 16384) return PM_EINVAL;
         // halo nodes: vertices of the instances outside [s, f)
         halo_nd.clear();
         auto add_halo = [&](int32_t e) {
@@ -244,37 +243,30 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
             if (v >= s && v < f) return uint16_t(v - s);
             return uint16_t(tile_nodes + (std::lower_bound(halo_nd.begin(), halo_nd.end(), v) - halo_nd.begin()));
         };
+        const size_t base = T->inst_elem.size();
         auto add_inst = [&](int32_t e) {
             T->inst_elem.push_back(e);
-            for (int a = 0; a < 4; ++a) T->inst_conn.push_back(a < nv ? local(L.conn[e * 4 + a]) : uint16_t(0));
+            for (int a = 0; a < 4; ++a) {
+                T->inst_conn.push_back(a < nv ? local(L.conn[e * 4 + a]) : uint16_t(0));
+                T->inst_row.push_back(0xFF);
+            }
         };
         for (int32_t e : halo_el) add_inst(e);
         for (int32_t e = own0; e < own1; ++e) add_inst(e);
-        T->inst_off[t + 1] = int32_t(T->inst_elem.size());
-        T->max_inst = std::max<int>(T->max_inst, int(ninst));
-
-        // each tile's incidence entries start on a 16-byte boundary
-        while (T->lent.size() % 8) T->lent.push_back(0);
-        T->lent_off[t] = int32_t(T->lent.size());
-        uint16_t *lo = T->lnode_off.data() + t * (tile_nodes + 8);
-        int64_t nent = 0;
-        for (int64_t i = s; i < s + tile_nodes; ++i) {
-            lo[i - s] = uint16_t(nent);
-            if (i >= f) continue;
-            for (int32_t k = L.n2e_off[i]; k < L.n2e_off[i + 1]; ++k) {
+        // rows: node i's incidence list is ascending in element id, and the
+        // instance index is ascending in element id too
+        for (int64_t i = s; i < f; ++i) {
+            int row = 0;
+            for (int32_t k = L.n2e_off[i]; k < L.n2e_off[i + 1]; ++k, ++row) {
                 int32_t e = L.n2e_ent[k] >> 2, a = L.n2e_ent[k] & 3;
                 int32_t li = (e >= own0) ? int32_t(halo_el.size()) + (e - own0)
                                          : int32_t(std::lower_bound(halo_el.begin(), halo_el.end(), e) - halo_el.begin());
-                T->lent.push_back(uint16_t((li << 2) | a));
-                ++nent;
+                T->inst_row[(base + li) * 4 + a] = uint8_t(row);
             }
         }
-        if (nent >= 65536) return PM_EINVAL;
-        lo[tile_nodes] = uint16_t(nent);
-        T->lent_off[t + 1] = T->lent_off[t] + int32_t(nent);
-        T->max_ent = std::max<int>(T->max_ent, int(nent));
+        T->inst_off[t + 1] = int32_t(T->inst_elem.size());
+        T->max_inst = std::max<int>(T->max_inst, int(ninst));
     }
-    while (T->lent.size() % 8) T->lent.push_back(0);
     return PM_OK;
 }
 

@@ -31,22 +31,22 @@ int build_layout(const pm_mesh *m, Layout *L);
 // then the contiguous run the tile owns), the outside vertices those
 // elements reach (its halo, ascending), each instance's vertices as
 // tile-local indices (own node i -> i - first node, halo node -> tile_nodes
-// + rank in the halo list), and for each own node its incidence list
-// (instance index << 2 | local vertex), ascending.
+// + rank in the halo list), and for each instance vertex that is an own
+// node the rank of the instance among that node's instances ("row";
+// 0xFF for halo vertices).  Node i's k-th element in ascending order is the
+// instance whose vertex i has row k.
 struct Tiles {
     int tile_nodes = 0;
     int64_t n_tiles = 0;
     int max_inst = 0;                     // largest instance count of a tile
     int max_halo = 0;                     // largest halo of a tile
-    int max_ent = 0;                      // largest incidence-entry count of a tile
+    int max_deg = 0;                      // largest number of elements at one node
     std::vector<int32_t> halo_off;        // n_tiles + 1
     std::vector<int32_t> halo;            // global node ids
     std::vector<int32_t> inst_off;        // n_tiles + 1
     std::vector<int32_t> inst_elem;       // element id of each instance
     std::vector<uint16_t> inst_conn;      // 4 local vertex ids per instance (slot 3 = 0 in 2D)
-    std::vector<int32_t> lent_off;        // n_tiles + 1; tile t's entries start at a multiple of 8
-    std::vector<uint16_t> lnode_off;      // n_tiles * (tile_nodes + 8): per-node offsets relative to lent_off[t]
-    std::vector<uint16_t> lent;           // instance << 2 | local vertex
+    std::vector<uint8_t> inst_row;        // 4 rows per instance (0xFF: halo vertex or unused)
 };
 
 int build_tiles(const Layout &L, int tile_nodes, Tiles *T);

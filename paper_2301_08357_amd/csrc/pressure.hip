@@ -50,7 +50,6 @@
 namespace {
 
 constexpr int BLK = 256;
-constexpr int CHUNK = 512;           // element instances per LDS pass of the tiled apply
 constexpr int VGRID_MAX = 1024;      // blocks of the vector kernels
 constexpr int AGRID_MAX = 2048;      // blocks of the tiled apply
 constexpr uint32_t DIR_BIT = 0x80000000u;
@@ -110,44 +109,44 @@ __device__ inline double sum_partials(const double *part, int n, double *red)
 // (alpha M_e + beta K_e) x_e for one simplex: out[a] for the local vertices.
 // xv are the nodal values (zero for Dirichlet vertices), w the element factor,
 // mscale = alpha / (d! (d+1) (d+2)).
-template <int DIM>
-__device__ __forceinline__ void elem_contrib(const double *X, const double *Y, const double *Z,
-                                             const double *xv, double w, double mscale, double out[4])
+template <int DIM, class R>
+__device__ __forceinline__ void elem_contrib(const R *X, const R *Y, const R *Z, const R *xv, R w, R mscale,
+                                             R out[4])
 {
     if (DIM == 2) {
-        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0];
-        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0];
-        const double det = e1x * e2y - e1y * e2x;
-        const double n1x = e2y, n1y = -e2x, n2x = -e1y, n2y = e1x;
-        const double d1 = xv[1] - xv[0], d2 = xv[2] - xv[0];
-        const double Gx = n1x * d1 + n2x * d2, Gy = n1y * d1 + n2y * d2;
-        const double r1 = n1x * Gx + n1y * Gy;
-        const double r2 = n2x * Gx + n2y * Gy;
-        const double r0 = -(r1 + r2);
-        const double S = xv[0] + xv[1] + xv[2];
-        const double m = mscale * det;
+        const R e1x = X[1] - X[0], e1y = Y[1] - Y[0];
+        const R e2x = X[2] - X[0], e2y = Y[2] - Y[0];
+        const R det = e1x * e2y - e1y * e2x;
+        const R n1x = e2y, n1y = -e2x, n2x = -e1y, n2y = e1x;
+        const R d1 = xv[1] - xv[0], d2 = xv[2] - xv[0];
+        const R Gx = n1x * d1 + n2x * d2, Gy = n1y * d1 + n2y * d2;
+        const R r1 = n1x * Gx + n1y * Gy;
+        const R r2 = n2x * Gx + n2y * Gy;
+        const R r0 = -(r1 + r2);
+        const R S = xv[0] + xv[1] + xv[2];
+        const R m = mscale * det;
         out[0] = w * r0 + m * (xv[0] + S);
         out[1] = w * r1 + m * (xv[1] + S);
         out[2] = w * r2 + m * (xv[2] + S);
-        out[3] = 0.0;
+        out[3] = R(0);
     } else {
-        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
-        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
-        const double e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
-        const double n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
-        const double n2x = e3y * e1z - e3z * e1y, n2y = e3z * e1x - e3x * e1z, n2z = e3x * e1y - e3y * e1x;
-        const double n3x = e1y * e2z - e1z * e2y, n3y = e1z * e2x - e1x * e2z, n3z = e1x * e2y - e1y * e2x;
-        const double det = e1x * n1x + e1y * n1y + e1z * n1z;
-        const double d1 = xv[1] - xv[0], d2 = xv[2] - xv[0], d3 = xv[3] - xv[0];
-        const double Gx = n1x * d1 + n2x * d2 + n3x * d3;
-        const double Gy = n1y * d1 + n2y * d2 + n3y * d3;
-        const double Gz = n1z * d1 + n2z * d2 + n3z * d3;
-        const double r1 = n1x * Gx + n1y * Gy + n1z * Gz;
-        const double r2 = n2x * Gx + n2y * Gy + n2z * Gz;
-        const double r3 = n3x * Gx + n3y * Gy + n3z * Gz;
-        const double r0 = -(r1 + r2 + r3);
-        const double S = xv[0] + xv[1] + xv[2] + xv[3];
-        const double m = mscale * det;
+        const R e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
+        const R e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
+        const R e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+        const R n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
+        const R n2x = e3y * e1z - e3z * e1y, n2y = e3z * e1x - e3x * e1z, n2z = e3x * e1y - e3y * e1x;
+        const R n3x = e1y * e2z - e1z * e2y, n3y = e1z * e2x - e1x * e2z, n3z = e1x * e2y - e1y * e2x;
+        const R det = e1x * n1x + e1y * n1y + e1z * n1z;
+        const R d1 = xv[1] - xv[0], d2 = xv[2] - xv[0], d3 = xv[3] - xv[0];
+        const R Gx = n1x * d1 + n2x * d2 + n3x * d3;
+        const R Gy = n1y * d1 + n2y * d2 + n3y * d3;
+        const R Gz = n1z * d1 + n2z * d2 + n3z * d3;
+        const R r1 = n1x * Gx + n1y * Gy + n1z * Gz;
+        const R r2 = n2x * Gx + n2y * Gy + n2z * Gz;
+        const R r3 = n3x * Gx + n3y * Gy + n3z * Gz;
+        const R r0 = -(r1 + r2 + r3);
+        const R S = xv[0] + xv[1] + xv[2] + xv[3];
+        const R m = mscale * det;
         out[0] = w * r0 + m * (xv[0] + S);
         out[1] = w * r1 + m * (xv[1] + S);
         out[2] = w * r2 + m * (xv[2] + S);
@@ -155,52 +154,55 @@ __device__ __forceinline__ void elem_contrib(const double *X, const double *Y, c
     }
 }
 
-template <int DIM>
-__device__ __forceinline__ double elem_det(const double *X, const double *Y, const double *Z)
+template <int DIM, class R>
+__device__ __forceinline__ R elem_det(const R *X, const R *Y, const R *Z)
 {
     if (DIM == 2) {
-        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0];
-        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0];
+        const R e1x = X[1] - X[0], e1y = Y[1] - Y[0];
+        const R e2x = X[2] - X[0], e2y = Y[2] - Y[0];
         return e1x * e2y - e1y * e2x;
     }
-    const double e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
-    const double e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
-    const double e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
-    const double n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
+    const R e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
+    const R e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
+    const R e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+    const R n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
     return e1x * n1x + e1y * n1y + e1z * n1z;
 }
 
-struct Mesh {
+template <class R>
+struct MeshT {
     int N, E;
     const int4 *conn;     // 4 vertex ids per element, bit 31 = Dirichlet vertex
-    const double *X, *Y, *Z;
-    const double *w;      // beta * c_e / (d! det_e), per element
+    const R *X, *Y, *Z;
+    const R *w;           // beta * c_e / (d! det_e), per element
     const uint8_t *dir;   // Dirichlet flag per node
-    double mscale;        // alpha / (d! (d+1) (d+2))
+    R mscale;             // alpha / (d! (d+1) (d+2))
 };
+using Mesh = MeshT<double>;
 
 // w_e = beta * c_e / (d! det_e)
-template <int DIM>
-__global__ void __launch_bounds__(BLK) k_factors(Mesh g, const double *__restrict__ coef, double beta,
-                                                 double *__restrict__ w)
+template <int DIM, class R>
+__global__ void __launch_bounds__(BLK) k_factors(MeshT<R> g, const double *__restrict__ coef, double beta,
+                                                 R *__restrict__ w)
 {
     const int e = blockIdx.x * BLK + threadIdx.x;
     if (e >= g.E) return;
     const int4 c = g.conn[e];
     const int v[4] = {c.x & 0x7fffffff, c.y & 0x7fffffff, c.z & 0x7fffffff, c.w & 0x7fffffff};
-    double X[4], Y[4], Z[4];
+    R X[4], Y[4], Z[4];
     for (int a = 0; a <= DIM; ++a) {
         X[a] = g.X[v[a]];
         Y[a] = g.Y[v[a]];
-        Z[a] = (DIM == 3) ? g.Z[v[a]] : 0.0;
+        Z[a] = (DIM == 3) ? g.Z[v[a]] : R(0);
     }
-    const double fact = (DIM == 2) ? 2.0 : 6.0;
-    w[e] = beta * coef[e] / (fact * elem_det<DIM>(X, Y, Z));
+    const R fact = (DIM == 2) ? R(2) : R(6);
+    w[e] = R(beta * coef[e]) / (fact * elem_det<DIM, R>(X, Y, Z));
 }
 
 // per-instance copy of the element factor, for the tiled apply
+template <class R>
 __global__ void __launch_bounds__(BLK) k_inst_factors(int n, const int *__restrict__ inst_elem,
-                                                      const double *__restrict__ w, double *__restrict__ iw)
+                                                      const R *__restrict__ w, R *__restrict__ iw)
 {
     const int j = blockIdx.x * BLK + threadIdx.x;
     if (j < n) iw[j] = w[inst_elem[j]];
@@ -209,13 +211,14 @@ __global__ void __launch_bounds__(BLK) k_inst_factors(int n, const int *__restri
 // ------------------------------------------------------------- CG plumbing
 
 // Arguments of one CG iteration (k >= 1).  With first set, beta = 0.
-struct Iter {
+template <class R>
+struct IterT {
     int k;
     int first;
-    const double *r;
-    const double *p_old;   // p_{k-1}
-    double *p_new;         // p_k
-    double *q;             // A p_k
+    const R *r;
+    const R *p_old;        // p_{k-1}
+    R *p_new;              // p_k
+    R *q;                  // A p_k
     CGState *st;
     double *hist;
     double *part_pq;       // apply partials (n_apply_blocks)
@@ -223,11 +226,13 @@ struct Iter {
     const double *rr_prev; // partials of r_{k-2}.r_{k-2}
     int n_vblocks;
 };
+using Iter = IterT<double>;
 
 // Prologue of apply(k): every block sums the partials of r_{k-1}.r_{k-1}
 // (and of the previous one for beta) and takes the convergence decision;
 // block 0 records it.  Returns false when the iteration must not run.
-__device__ inline bool iter_prologue(const Iter &it, double *red, double &beta)
+template <class R>
+__device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &beta)
 {
     if (block_done(it.st)) return false;
     const double rr = sum_partials(it.rr_cur, it.n_vblocks, red);
@@ -292,7 +297,7 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
                     xv[a] = (cv[a] < 0) ? 0.0 : val(v);
                 }
                 if (DIM == 2) xv[3] = 0.0;
-                elem_contrib<DIM>(X, Y, Z, xv, g.w[en >> 2], g.mscale, o);
+                elem_contrib<DIM, double>(X, Y, Z, xv, g.w[en >> 2], g.mscale, o);
                 const int a = en & 3;
                 yi += (a == 0) ? o[0] : (a == 1) ? o[1] : (a == 2) ? o[2] : o[3];
             }
@@ -309,78 +314,67 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
     }
 }
 
-struct TileArgs {
+template <class R>
+struct TileArgsT {
     int T;                        // nodes per tile
     int n_tiles;
     int max_local;                // T + largest halo (LDS node table size)
-    int lent_cap;                 // LDS capacity for one tile's incidence entries (multiple of 8)
+    int max_deg;                  // most elements at one node (rows of the LDS sum table)
     const int *halo_off, *halo;
     const int *inst_off;
     const uint2 *inst_conn;       // 4 x 16-bit local vertex ids
-    const double *inst_w;
-    const int *lent_off;          // 16-byte aligned per tile
-    const uint16_t *lnode_off;    // T + 8 per tile
-    const uint16_t *lent;
+    const uint32_t *inst_row;     // 4 x 8-bit rows (0xFF: not an own node)
+    const R *inst_w;
+    const uint8_t *deg;           // elements per node
 };
 
 // Morton-tiled apply.  One block per tile (grid-stride over tiles):
-//  1. load the tile's element instances (local connectivity and factor) into
-//     registers, its incidence lists into LDS, and the coordinates and nodal
-//     values of its nodes and halo into LDS (Dirichlet values as 0); under CG
-//     the values are p_k = r + beta p_{k-1} and the block stores p_k for its
-//     own nodes;
-//  2. in chunks of CHUNK instances: each lane computes whole elements from
-//     LDS and writes their d+1 contributions to LDS; then each own node adds
-//     the contributions of its incidence list that fall in the chunk
-//     (ascending instance = ascending element id).
+//  1. load the tile's element instances (local connectivity, rows and factor)
+//     into registers, and the coordinates and nodal values of its nodes and
+//     halo into LDS (Dirichlet values as 0); under CG the values are
+//     p_k = r + beta p_{k-1} and the block stores p_k for its own nodes;
+//  2. each lane computes whole elements from LDS and writes the contribution
+//     to each own vertex i into S[row][i], row = rank of the element among
+//     node i's elements;
+//  3. each own node sums S[0..deg-1][i] in row order (ascending element id).
 // Every element is computed once per tile that contains one of its vertices.
-// IPT instances per lane must cover the largest tile (checked at setup).
-template <int DIM, bool CG, int NPT, int IPT, int SPT>
-__global__ void __launch_bounds__(BLK) k_apply_tiled(Mesh g, TileArgs ta, const double *__restrict__ x,
-                                                     double *__restrict__ y, Iter it)
+// IPT instances and SPT node-table slots per lane cover the largest tile
+// (checked at setup).
+template <int DIM, bool CG, class R, int NPT, int IPT, int SPT>
+__global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
+                                                     R *__restrict__ y, IterT<R> it)
 {
-    constexpr int KPC = CHUNK / BLK;   // instances per lane per chunk
-    static_assert(IPT % KPC == 0, "IPT must be a multiple of CHUNK / BLK");
-    extern __shared__ double smem[];
+    extern __shared__ double smem_d[];
+    R *smem = reinterpret_cast<R *>(smem_d);
     __shared__ double red[BLK / 64];
     double beta = 0.0;
     if (CG && !iter_prologue(it, red, beta)) return;
-    const int L = ta.max_local;
-    double *sX = smem, *sY = smem + L, *sZ = smem + 2 * L;
-    double *sP = smem + (DIM == 3 ? 3 : 2) * L;
-    double *sC = sP + L;                                        // CHUNK x 4 contributions
-    uint16_t *sL = reinterpret_cast<uint16_t *>(sC + 4 * CHUNK);   // incidence entries
-    uint16_t *sO = sL + ta.lent_cap;                            // T + 8 node offsets
-    double *sQ = reinterpret_cast<double *>(sO + ta.T + 8);      // own p values (unmasked)
-    uint8_t *sD = reinterpret_cast<uint8_t *>(sQ + ta.T);        // own Dirichlet flags
+    const int L = ta.max_local, T = ta.T;
+    R *sX = smem, *sY = smem + L, *sZ = smem + 2 * L;
+    R *sP = smem + (DIM == 3 ? 3 : 2) * L;
+    R *sS = sP + L;                                               // max_deg x T
+    uint8_t *sD = reinterpret_cast<uint8_t *>(sS + ta.max_deg * T);   // own Dirichlet flags
+    uint8_t *sG = sD + T;                                         // own degrees
     double part = 0.0;
     for (int t = blockIdx.x; t < ta.n_tiles; t += gridDim.x) {
-        const int s = t * ta.T;
-        const int nt = min(ta.T, g.N - s);
+        const int s = t * T;
+        const int nt = min(T, g.N - s);
         const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
         const int i0 = ta.inst_off[t], ni = ta.inst_off[t + 1] - i0;
-        const int e0 = ta.lent_off[t], ne = ta.lent_off[t + 1] - e0;
         // 1a. instances into registers
         uint2 ic[IPT];
-        double iw[IPT];
+        uint32_t ir[IPT];
+        R iw[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
             const int j = threadIdx.x + k * BLK;
             if (j < ni) {
                 ic[k] = ta.inst_conn[i0 + j];
+                ir[k] = ta.inst_row[i0 + j];
                 iw[k] = ta.inst_w[i0 + j];
             }
         }
-        // 1b. incidence lists into LDS, 8 entries per load
-        {
-            const uint4 *src = reinterpret_cast<const uint4 *>(ta.lent + e0);
-            uint4 *dst = reinterpret_cast<uint4 *>(sL);
-            for (int q = threadIdx.x; q < (ne + 7) / 8; q += BLK) dst[q] = src[q];
-            const uint4 *osrc = reinterpret_cast<const uint4 *>(ta.lnode_off + (size_t)t * (ta.T + 8));
-            uint4 *odst = reinterpret_cast<uint4 *>(sO);
-            for (int q = threadIdx.x; q < (ta.T + 8) / 8; q += BLK) odst[q] = osrc[q];
-        }
-        // 1c. nodes: own node i at i - s, halo node of rank h at T + h (the
+        // 1b. nodes: own node i at i - s, halo node of rank h at T + h (the
         // local indices of the instance connectivity); slots nt..T-1 of a
         // ragged last tile are unused.  All global loads of a lane are issued
         // before its LDS writes.
@@ -391,19 +385,20 @@ __global__ void __launch_bounds__(BLK) k_apply_tiled(Mesh g, TileArgs ta, const 
                 const int l = threadIdx.x + q * BLK;
                 gidx[q] = -1;
                 if (l < nt) gidx[q] = s + l;
-                else if (l >= ta.T && l < ta.T + nh) gidx[q] = ta.halo[h0 + l - ta.T];
+                else if (l >= T && l < T + nh) gidx[q] = ta.halo[h0 + l - T];
             }
-            double vX[SPT], vY[SPT], vZ[SPT], vP[SPT];
-            uint8_t vD[SPT];
+            R vX[SPT], vY[SPT], vZ[SPT], vP[SPT];
+            uint8_t vD[SPT], vG[SPT];
 #pragma unroll
             for (int q = 0; q < SPT; ++q) {
                 const int gi = gidx[q];
                 if (gi >= 0) {
                     vX[q] = g.X[gi];
                     vY[q] = g.Y[gi];
-                    vZ[q] = (DIM == 3) ? g.Z[gi] : 0.0;
-                    vP[q] = CG ? (it.first ? it.r[gi] : it.r[gi] + beta * it.p_old[gi]) : x[gi];
+                    vZ[q] = (DIM == 3) ? g.Z[gi] : R(0);
+                    vP[q] = CG ? (it.first ? it.r[gi] : it.r[gi] + R(beta) * it.p_old[gi]) : x[gi];
                     vD[q] = g.dir[gi];
+                    vG[q] = (threadIdx.x + q * BLK < nt) ? ta.deg[gi] : 0;
                 }
             }
 #pragma unroll
@@ -414,82 +409,59 @@ __global__ void __launch_bounds__(BLK) k_apply_tiled(Mesh g, TileArgs ta, const 
                     sX[l] = vX[q];
                     sY[l] = vY[q];
                     if (DIM == 3) sZ[l] = vZ[q];
-                    sP[l] = vD[q] ? 0.0 : vP[q];
+                    sP[l] = vD[q] ? R(0) : vP[q];
                     if (l < nt) {
                         sD[l] = vD[q];
-                        if (CG) {
-                            it.p_new[gi] = vP[q];
-                            sQ[l] = vP[q];
-                        }
+                        sG[l] = vG[q];
+                        if (CG) it.p_new[gi] = vP[q];
                     }
                 }
             }
         }
         __syncthreads();
-        int kc[NPT], ke[NPT];
-        double acc[NPT];
+        // 2. element contributions into the row table
 #pragma unroll
-        for (int j = 0; j < NPT; ++j) {
-            const int l = threadIdx.x + j * BLK;
-            acc[j] = 0.0;
-            kc[j] = ke[j] = 0;
-            if (l < nt) {
-                kc[j] = sO[l];
-                ke[j] = sO[l + 1];
-            }
-        }
-        // 2. chunks of instances
+        for (int k = 0; k < IPT; ++k) {
+            const int j = threadIdx.x + k * BLK;
+            if (j < ni) {
+                const uint2 cc = ic[k];
+                const int lv[4] = {int(cc.x & 0xffffu), int(cc.x >> 16), int(cc.y & 0xffffu), int(cc.y >> 16)};
+                R X[4], Y[4], Z[4], xv[4], o[4];
 #pragma unroll
-        for (int k0 = 0; k0 < IPT; k0 += KPC) {
-            const int c0 = k0 * BLK;
-            if (c0 >= ni) break;
+                for (int a = 0; a <= DIM; ++a) {
+                    X[a] = sX[lv[a]];
+                    Y[a] = sY[lv[a]];
+                    Z[a] = (DIM == 3) ? sZ[lv[a]] : R(0);
+                    xv[a] = sP[lv[a]];
+                }
+                if (DIM == 2) xv[3] = R(0);
+                elem_contrib<DIM, R>(X, Y, Z, xv, iw[k], g.mscale, o);
 #pragma unroll
-            for (int kk = 0; kk < KPC; ++kk) {
-                const int k = k0 + kk;
-                const int j = threadIdx.x + k * BLK;
-                if (j < ni) {
-                    const uint2 cc = ic[k];
-                    const int lv[4] = {int(cc.x & 0xffffu), int(cc.x >> 16), int(cc.y & 0xffffu), int(cc.y >> 16)};
-                    double X[4], Y[4], Z[4], xv[4], o[4];
-#pragma unroll
-                    for (int a = 0; a <= DIM; ++a) {
-                        X[a] = sX[lv[a]];
-                        Y[a] = sY[lv[a]];
-                        Z[a] = (DIM == 3) ? sZ[lv[a]] : 0.0;
-                        xv[a] = sP[lv[a]];
-                    }
-                    if (DIM == 2) xv[3] = 0.0;
-                    elem_contrib<DIM>(X, Y, Z, xv, iw[k], g.mscale, o);
-                    double *dst = sC + 4 * (j - c0);
-                    dst[0] = o[0];
-                    dst[1] = o[1];
-                    dst[2] = o[2];
-                    if (DIM == 3) dst[3] = o[3];
+                for (int a = 0; a <= DIM; ++a) {
+                    const unsigned row = (ir[k] >> (8 * a)) & 0xffu;
+                    if (row != 0xffu) sS[row * T + lv[a]] = o[a];
                 }
             }
-            __syncthreads();
-            const int lim = (c0 + CHUNK) << 2;
-#pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                while (kc[j] < ke[j]) {
-                    const int en = sL[kc[j]];
-                    if (en >= lim) break;
-                    acc[j] += sC[en - (c0 << 2)];
-                    ++kc[j];
-                }
-            }
-            __syncthreads();
         }
+        __syncthreads();
+        // 3. row sums in ascending element order
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             const int l = threadIdx.x + j * BLK;
             if (l < nt) {
                 const int gi = s + l;
-                double yi = acc[j];
+                const int d = sG[l];
+                R yi = R(0);
+#pragma unroll 8
+                for (int k = 0; k < d; ++k) yi += sS[k * T + l];
                 if (CG) {
-                    const double pi = sQ[l];
-                    if (sD[l]) yi = pi;
-                    part += pi * yi;
+                    // free nodes: the staged value; Dirichlet rows: y = p
+                    R pi = sP[l];
+                    if (sD[l]) {
+                        pi = it.first ? it.r[gi] : it.r[gi] + R(beta) * it.p_old[gi];
+                        yi = pi;
+                    }
+                    part += double(pi) * double(yi);
                 } else if (sD[l]) {
                     yi = x[gi];
                 }
@@ -508,8 +480,9 @@ __global__ void __launch_bounds__(BLK) k_apply_tiled(Mesh g, TileArgs ta, const 
 
 // update(k): alpha = rr_{k-1} / p_k.q; x += alpha p_k; r -= alpha q;
 // partials of r_k.r_k.
-__global__ void __launch_bounds__(BLK) k_update(int N, double *__restrict__ x, double *__restrict__ r,
-                                                const double *__restrict__ p, const double *__restrict__ q,
+template <class R>
+__global__ void __launch_bounds__(BLK) k_update(int N, R *__restrict__ x, R *__restrict__ r,
+                                                const R *__restrict__ p, const R *__restrict__ q,
                                                 CGState *st, const double *part_pq, int n_ablocks,
                                                 const double *rr_cur, int n_vblocks, double *rr_out)
 {
@@ -524,13 +497,13 @@ __global__ void __launch_bounds__(BLK) k_update(int N, double *__restrict__ x, d
         }
         return;
     }
-    const double a = rr / pq;
+    const R a = R(rr / pq);
     double v = 0.0;
     for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
         x[i] += a * p[i];
-        const double ri = r[i] - a * q[i];
+        const R ri = r[i] - a * q[i];
         r[i] = ri;
-        v += ri * ri;
+        v += double(ri) * double(ri);
     }
     const double bs = block_sum_all(v, red);
     if (threadIdx.x == 0) rr_out[blockIdx.x] = bs;
@@ -629,6 +602,48 @@ __global__ void k_reopen(CGState *st)
     if (threadIdx.x == 0) st->done = 0;
 }
 
+// Mixed precision: r32 = r (rounded), d32 = 0, partials of r32.r32 (FP64).
+__global__ void __launch_bounds__(BLK) k_to_inner(int N, const double *__restrict__ r, float *__restrict__ r32,
+                                                  float *__restrict__ d32, double *part)
+{
+    __shared__ double red[BLK / 64];
+    double v = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+        const float ri = float(r[i]);
+        r32[i] = ri;
+        d32[i] = 0.0f;
+        v += double(ri) * double(ri);
+    }
+    const double bs = block_sum_all(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// One block: state of an inner solve (tolerance relative to its rhs).
+__global__ void __launch_bounds__(BLK) k_begin_inner(CGState *st, const double *part, int n, double rtol,
+                                                     int max_iter)
+{
+    __shared__ double red[BLK / 64];
+    const double bb = sum_partials(part, n, red);
+    if (threadIdx.x == 0) {
+        const double bn = sqrt(bb);
+        st->bnorm = bn;
+        st->tol = rtol * bn;
+        st->rr = bb;
+        st->tt = 0.0;
+        st->iter = 0;
+        st->max_iter = max_iter;
+        st->status = isfinite(bn) ? 0 : PM_EBREAKDOWN;
+        st->done = (!isfinite(bn) || !(bn > 0.0) || max_iter <= 0) ? 1 : 0;
+    }
+}
+
+// x += d (the inner correction, in FP64).
+__global__ void __launch_bounds__(BLK) k_correct(int N, double *__restrict__ x, const float *__restrict__ d32)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i < N) x[i] += double(d32[i]);
+}
+
 __global__ void __launch_bounds__(BLK) k_gather(int N, const int *__restrict__ new2old,
                                                 const double *__restrict__ src, double *__restrict__ dst)
 {
@@ -664,14 +679,20 @@ struct pm_handle {
     double *w = nullptr;        // beta c_e / (d! det_e)
     uint8_t *dir = nullptr;
     // tiles (device)
-    int tile_nodes = 0, n_tiles = 0, max_local = 0, lent_cap = 0, tile_class = -1;
+    int tile_nodes = 0, n_tiles = 0, max_local = 0, max_deg = 0, tile_class = -1;
     size_t lds_limit = 65536;
     int64_t n_inst = 0;
     int *t_halo_off = nullptr, *t_halo = nullptr, *t_inst_off = nullptr, *t_inst_elem = nullptr;
-    int *t_lent_off = nullptr;
     uint2 *t_inst_conn = nullptr;
+    uint32_t *t_inst_row = nullptr;
     double *t_inst_w = nullptr;
-    uint16_t *t_lnode_off = nullptr, *t_lent = nullptr;
+    uint8_t *t_deg = nullptr;
+    // FP32 operator data and inner-CG vectors (PM_FP32_INNER)
+    float *coords32 = nullptr, *w32 = nullptr, *t_inst_w32 = nullptr;
+    float *r32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    float *p32[2] = {nullptr, nullptr};
+    CGState *st_in = nullptr;
+    CGState *hst_in = nullptr;
     // CG vectors (device, internal order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
     double *pbuf[2] = {nullptr, nullptr};
@@ -733,9 +754,13 @@ int dupload(pm_handle *h, T **p, const std::vector<T> &v)
 
 inline unsigned grid_of(int64_t n) { return unsigned((n + BLK - 1) / BLK); }
 
-Mesh make_mesh(const pm_handle *h)
+template <class R>
+MeshT<R> make_mesh(const pm_handle *h);
+
+template <>
+MeshT<double> make_mesh<double>(const pm_handle *h)
 {
-    Mesh g;
+    MeshT<double> g;
     g.N = int(h->N);
     g.E = int(h->E);
     g.conn = h->conn;
@@ -749,21 +774,41 @@ Mesh make_mesh(const pm_handle *h)
     return g;
 }
 
-TileArgs make_tiles(const pm_handle *h)
+template <>
+MeshT<float> make_mesh<float>(const pm_handle *h)
 {
-    TileArgs ta;
+    MeshT<float> g;
+    g.N = int(h->N);
+    g.E = int(h->E);
+    g.conn = h->conn;
+    g.X = h->coords32;
+    g.Y = h->coords32 + h->N;
+    g.Z = (h->dim == 3) ? h->coords32 + 2 * h->N : h->coords32;
+    g.w = h->w32;
+    g.dir = h->dir;
+    const double denom = (h->dim == 2) ? 24.0 : 120.0;
+    g.mscale = float(h->alpha / denom);
+    return g;
+}
+
+template <class R>
+TileArgsT<R> make_tiles(const pm_handle *h)
+{
+    TileArgsT<R> ta;
     ta.T = h->tile_nodes;
     ta.n_tiles = h->n_tiles;
     ta.max_local = h->max_local;
-    ta.lent_cap = h->lent_cap;
+    ta.max_deg = h->max_deg;
     ta.halo_off = h->t_halo_off;
     ta.halo = h->t_halo;
     ta.inst_off = h->t_inst_off;
     ta.inst_conn = h->t_inst_conn;
-    ta.inst_w = h->t_inst_w;
-    ta.lent_off = h->t_lent_off;
-    ta.lnode_off = h->t_lnode_off;
-    ta.lent = h->t_lent;
+    ta.inst_row = h->t_inst_row;
+    if constexpr (sizeof(R) == 8)
+        ta.inst_w = h->t_inst_w;
+    else
+        ta.inst_w = h->t_inst_w32;
+    ta.deg = h->t_deg;
     return ta;
 }
 
@@ -774,36 +819,44 @@ bool valid_coef(const double *c, int64_t E)
     return true;
 }
 
-int compute_factors(pm_handle *h)
+template <class R>
+int compute_factors_t(pm_handle *h, R *w, R *inst_w)
 {
-    Mesh g = make_mesh(h);
+    MeshT<R> g = make_mesh<R>(h);
     const double beta = h->dt * h->dt;
     if (h->dim == 2)
-        hipLaunchKernelGGL(k_factors<2>, dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, h->w);
+        hipLaunchKernelGGL((k_factors<2, R>), dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, w);
     else
-        hipLaunchKernelGGL(k_factors<3>, dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, h->w);
+        hipLaunchKernelGGL((k_factors<3, R>), dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, w);
     HIPCK(hipGetLastError());
     if (h->n_inst > 0) {
-        hipLaunchKernelGGL(k_inst_factors, dim3(grid_of(h->n_inst)), dim3(BLK), 0, 0, int(h->n_inst),
-                           h->t_inst_elem, h->w, h->t_inst_w);
+        hipLaunchKernelGGL(k_inst_factors<R>, dim3(grid_of(h->n_inst)), dim3(BLK), 0, 0, int(h->n_inst),
+                           h->t_inst_elem, w, inst_w);
         HIPCK(hipGetLastError());
     }
+    return PM_OK;
+}
+
+int compute_factors(pm_handle *h)
+{
+    TRY(compute_factors_t<double>(h, h->w, h->t_inst_w));
+    if (h->w32) TRY(compute_factors_t<float>(h, h->w32, h->t_inst_w32));
     HIPCK(hipDeviceSynchronize());
     return PM_OK;
 }
 
+template <class R>
 size_t tiled_lds_bytes(const pm_handle *h)
 {
-    return sizeof(double) * (size_t(h->dim + 1) * h->max_local + 4 * CHUNK) +
-           sizeof(uint16_t) * (size_t(h->lent_cap) + h->tile_nodes + 8) + sizeof(double) * h->tile_nodes +
-           h->tile_nodes;
+    return sizeof(R) * (size_t(h->dim + 1) * h->max_local + size_t(h->max_deg) * h->tile_nodes) +
+           2 * size_t(h->tile_nodes);
 }
 
-template <class K>
-int launch_tiled_k(pm_handle *h, K kern, const Mesh &g, const TileArgs &ta, const double *x, double *y,
-                   const Iter &it, hipStream_t s)
+template <class R, class K>
+int launch_tiled_k(pm_handle *h, K kern, const MeshT<R> &g, const TileArgsT<R> &ta, const R *x, R *y,
+                   const IterT<R> &it, hipStream_t s)
 {
-    const size_t lds = tiled_lds_bytes(h);
+    const size_t lds = tiled_lds_bytes<R>(h);
     if (lds > 65536) HIPCK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(kern, dim3(h->n_ablocks), dim3(BLK), lds, s, g, ta, x, y, it);
     HIPCK(hipGetLastError());
@@ -816,33 +869,33 @@ int launch_tiled_k(pm_handle *h, K kern, const Mesh &g, const TileArgs &ta, cons
 struct TileClass {
     int npt, ipt, spt;
 };
-constexpr TileClass TILE_CLASSES[] = {{1, 4, 2}, {1, 8, 3}, {1, 12, 3}, {1, 12, 4}, {1, 16, 4},
-                                      {2, 8, 4}, {2, 12, 4}, {2, 16, 6}, {2, 20, 6}, {2, 24, 8}};
+constexpr TileClass TILE_CLASSES[] = {{1, 4, 2}, {1, 8, 2}, {1, 8, 3}, {1, 12, 3}, {1, 12, 4},
+                                      {1, 16, 4}, {2, 12, 4}, {2, 16, 6}, {2, 20, 6}, {2, 24, 8}};
 constexpr int N_TILE_CLASSES = sizeof(TILE_CLASSES) / sizeof(TILE_CLASSES[0]);
 
-template <int DIM, bool CG, int C>
-int launch_tiled_c(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
+template <int DIM, bool CG, class R, int C>
+int launch_tiled_c(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream_t s)
 {
     constexpr TileClass tc = TILE_CLASSES[C];
-    Mesh g = make_mesh(h);
-    TileArgs ta = make_tiles(h);
-    return launch_tiled_k(h, k_apply_tiled<DIM, CG, tc.npt, tc.ipt, tc.spt>, g, ta, x, y, it, s);
+    MeshT<R> g = make_mesh<R>(h);
+    TileArgsT<R> ta = make_tiles<R>(h);
+    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.npt, tc.ipt, tc.spt>, g, ta, x, y, it, s);
 }
 
-template <int DIM, bool CG>
-int launch_tiled_t(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
+template <int DIM, bool CG, class R>
+int launch_tiled_t(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream_t s)
 {
     switch (h->tile_class) {
-    case 0: return launch_tiled_c<DIM, CG, 0>(h, x, y, it, s);
-    case 1: return launch_tiled_c<DIM, CG, 1>(h, x, y, it, s);
-    case 2: return launch_tiled_c<DIM, CG, 2>(h, x, y, it, s);
-    case 3: return launch_tiled_c<DIM, CG, 3>(h, x, y, it, s);
-    case 4: return launch_tiled_c<DIM, CG, 4>(h, x, y, it, s);
-    case 5: return launch_tiled_c<DIM, CG, 5>(h, x, y, it, s);
-    case 6: return launch_tiled_c<DIM, CG, 6>(h, x, y, it, s);
-    case 7: return launch_tiled_c<DIM, CG, 7>(h, x, y, it, s);
-    case 8: return launch_tiled_c<DIM, CG, 8>(h, x, y, it, s);
-    case 9: return launch_tiled_c<DIM, CG, 9>(h, x, y, it, s);
+    case 0: return launch_tiled_c<DIM, CG, R, 0>(h, x, y, it, s);
+    case 1: return launch_tiled_c<DIM, CG, R, 1>(h, x, y, it, s);
+    case 2: return launch_tiled_c<DIM, CG, R, 2>(h, x, y, it, s);
+    case 3: return launch_tiled_c<DIM, CG, R, 3>(h, x, y, it, s);
+    case 4: return launch_tiled_c<DIM, CG, R, 4>(h, x, y, it, s);
+    case 5: return launch_tiled_c<DIM, CG, R, 5>(h, x, y, it, s);
+    case 6: return launch_tiled_c<DIM, CG, R, 6>(h, x, y, it, s);
+    case 7: return launch_tiled_c<DIM, CG, R, 7>(h, x, y, it, s);
+    case 8: return launch_tiled_c<DIM, CG, R, 8>(h, x, y, it, s);
+    case 9: return launch_tiled_c<DIM, CG, R, 9>(h, x, y, it, s);
     default: return PM_EINVAL;
     }
 }
@@ -850,7 +903,7 @@ int launch_tiled_t(pm_handle *h, const double *x, double *y, const Iter &it, hip
 template <int DIM, bool CG>
 int launch_node_t(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
 {
-    Mesh g = make_mesh(h);
+    Mesh g = make_mesh<double>(h);
     hipLaunchKernelGGL((k_apply_node<DIM, CG>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off, h->n2e_ent,
                        h->tile_nodes, x, y, it);
     HIPCK(hipGetLastError());
@@ -867,8 +920,16 @@ int launch_apply(pm_handle *h, const double *x, double *y, const Iter *it, hipSt
         if (h->dim == 2) return cg ? launch_node_t<2, true>(h, x, y, a, s) : launch_node_t<2, false>(h, x, y, a, s);
         return cg ? launch_node_t<3, true>(h, x, y, a, s) : launch_node_t<3, false>(h, x, y, a, s);
     }
-    if (h->dim == 2) return cg ? launch_tiled_t<2, true>(h, x, y, a, s) : launch_tiled_t<2, false>(h, x, y, a, s);
-    return cg ? launch_tiled_t<3, true>(h, x, y, a, s) : launch_tiled_t<3, false>(h, x, y, a, s);
+    if (h->dim == 2)
+        return cg ? launch_tiled_t<2, true, double>(h, x, y, a, s) : launch_tiled_t<2, false, double>(h, x, y, a, s);
+    return cg ? launch_tiled_t<3, true, double>(h, x, y, a, s) : launch_tiled_t<3, false, double>(h, x, y, a, s);
+}
+
+// One FP32 inner-CG iteration's apply (tiled kernel only).
+int launch_apply32(pm_handle *h, const IterT<float> &it, hipStream_t s)
+{
+    if (h->dim == 2) return launch_tiled_t<2, true, float>(h, it.p_new, it.q, it, s);
+    return launch_tiled_t<3, true, float>(h, it.p_new, it.q, it, s);
 }
 
 int ensure_hist(pm_handle *h, int32_t max_iter)
@@ -904,7 +965,7 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
     h->tile_nodes = tile_nodes;
     h->n_tiles = int(T.n_tiles);
     h->max_local = tile_nodes + T.max_halo;
-    h->lent_cap = ((T.max_ent + 7) / 8) * 8 + 8;
+    h->max_deg = T.max_deg;
     h->n_inst = int64_t(T.inst_elem.size());
     // smallest size class covering the tile, its instances and node table
     const int need_n = (tile_nodes + BLK - 1) / BLK;
@@ -917,20 +978,23 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
             break;
         }
     if (h->tile_class < 0) return PM_EINVAL;
+    std::vector<uint8_t> deg(L.n_nodes);
+    for (int64_t i = 0; i < L.n_nodes; ++i) deg[i] = uint8_t(L.n2e_off[i + 1] - L.n2e_off[i]);
     TRY(dupload(h, &h->t_halo_off, T.halo_off));
     TRY(dupload(h, &h->t_halo, T.halo));
     TRY(dupload(h, &h->t_inst_off, T.inst_off));
     TRY(dupload(h, &h->t_inst_elem, T.inst_elem));
-    TRY(dupload(h, &h->t_lent_off, T.lent_off));
-    TRY(dupload(h, &h->t_lnode_off, T.lnode_off));
-    TRY(dupload(h, &h->t_lent, T.lent));
+    TRY(dupload(h, &h->t_deg, deg));
     TRY(dalloc(h, &h->t_inst_conn, size_t(h->n_inst)));
-    if (h->n_inst > 0)
+    TRY(dalloc(h, &h->t_inst_row, size_t(h->n_inst)));
+    if (h->n_inst > 0) {
         HIPCK(hipMemcpy(h->t_inst_conn, T.inst_conn.data(), sizeof(uint16_t) * T.inst_conn.size(),
                         hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(h->t_inst_row, T.inst_row.data(), T.inst_row.size(), hipMemcpyHostToDevice));
+    }
     TRY(dalloc(h, &h->t_inst_w, size_t(h->n_inst)));
     h->n_ablocks = std::min(h->n_tiles, AGRID_MAX);
-    if (tiled_lds_bytes(h) > h->lds_limit) return PM_EINVAL;
+    if (tiled_lds_bytes<double>(h) > h->lds_limit) return PM_EINVAL;
     return PM_OK;
 }
 
@@ -1005,12 +1069,14 @@ void pressure_destroy(pm_handle *h)
 {
     if (!h) return;
     void *ptrs[] = {h->new2old, h->n2e_off, h->n2e_ent, h->conn, h->coords, h->coef, h->w, h->dir,
-                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_lent_off, h->t_inst_conn,
-                    h->t_inst_w, h->t_lnode_off, h->t_lent, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
-                    h->pbuf[1], h->part, h->st, h->hist};
+                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst_conn, h->t_inst_row,
+                    h->t_inst_w, h->t_deg, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
+                    h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
+                    h->d32, h->p32[0], h->p32[1], h->st_in};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
+    if (h->hst_in) (void)hipHostFree(h->hst_in);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
 }
@@ -1021,7 +1087,7 @@ static int tile_nodes_for(int32_t flags, int64_t N)
     case PM_TILE_256: return 256;
     case PM_TILE_512: return 512;
     case PM_TILE_128: return 128;
-    case 0: return N < 2000000 ? 256 : 512;
+    case 0: return 128;
     default: return -1;
     }
 }
@@ -1075,6 +1141,20 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     if (tn < 0) return PM_EINVAL;
     TRY(build_tiles_on_device(h, L, tn));
     for (double **v : {&h->b, &h->x, &h->r, &h->q, &h->t, &h->pbuf[0], &h->pbuf[1]}) TRY(dalloc(h, v, N));
+    if (flags & PM_FP32_INNER) {
+        std::vector<float> c32(L.coords.size());
+        for (size_t i = 0; i < c32.size(); ++i) c32[i] = float(L.coords[i]);
+        TRY(dupload(h, &h->coords32, c32));
+        TRY(dalloc(h, &h->w32, E));
+        TRY(dalloc(h, &h->t_inst_w32, size_t(std::max<int64_t>(h->n_inst, 1))));
+        for (float **v : {&h->r32, &h->q32, &h->d32, &h->p32[0], &h->p32[1]}) TRY(dalloc(h, v, N));
+        HIPCK(hipMemset(h->p32[0], 0, 4 * N));
+        HIPCK(hipMemset(h->p32[1], 0, 4 * N));
+        TRY(dalloc(h, &h->st_in, 1));
+        HIPCK(hipMemset(h->st_in, 0, sizeof(CGState)));
+        HIPCK(hipHostMalloc((void **)&h->hst_in, sizeof(CGState), hipHostMallocDefault));
+        if (tiled_lds_bytes<float>(h) > h->lds_limit) return PM_EINVAL;
+    }
     TRY(dalloc(h, &h->part, AGRID_MAX + 3 * VGRID_MAX));
     TRY(dalloc(h, &h->st, 1));
     TRY(ensure_hist(h, 1023));
@@ -1171,7 +1251,7 @@ static int launch_iterations(pm_handle *h, int k0, int count, bool first, size_t
             HIPCK(hipEventRecord(e1, s));
             ++*timed;
         }
-        hipLaunchKernelGGL(k_update, dim3(h->n_vblocks), dim3(BLK), 0, s, N, h->x, h->r, h->pbuf[k & 1], h->q,
+        hipLaunchKernelGGL(k_update<double>, dim3(h->n_vblocks), dim3(BLK), 0, s, N, h->x, h->r, h->pbuf[k & 1], h->q,
                            h->st, h->part_pq(), h->n_ablocks, h->part_rr((k - 1) & 1), h->n_vblocks,
                            h->part_rr(k & 1));
     }
@@ -1267,13 +1347,112 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
     return (rel <= rtol) ? PM_OK : PM_NOT_CONVERGED;
 }
 
+// Launch FP32 inner-CG iterations k0 .. k0+count-1.
+static int launch_iterations32(pm_handle *h, int k0, int count, bool first, hipStream_t s)
+{
+    const int N = int(h->N);
+    for (int c = 0; c < count; ++c) {
+        const int k = k0 + c;
+        IterT<float> it;
+        it.k = k;
+        it.first = (first && c == 0) ? 1 : 0;
+        it.r = h->r32;
+        it.p_old = h->p32[(k - 1) & 1];
+        it.p_new = h->p32[k & 1];
+        it.q = h->q32;
+        it.st = h->st_in;
+        it.hist = h->hist;
+        it.part_pq = h->part_pq();
+        it.rr_cur = h->part_rr((k - 1) & 1);
+        it.rr_prev = h->part_rr(k & 1);
+        it.n_vblocks = h->n_vblocks;
+        TRY(launch_apply32(h, it, s));
+        hipLaunchKernelGGL(k_update<float>, dim3(h->n_vblocks), dim3(BLK), 0, s, N, h->d32, h->r32, h->p32[k & 1],
+                           h->q32, h->st_in, h->part_pq(), h->n_ablocks, h->part_rr((k - 1) & 1), h->n_vblocks,
+                           h->part_rr(k & 1));
+    }
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
 int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                          double inner_rtol, int32_t max_iter, double *p_dev, int32_t *iters,
                          int32_t *outer, double *res_hist, double *true_relres, void *stream)
 {
-    (void)h; (void)rhs_dev; (void)x0_dev; (void)rtol; (void)inner_rtol; (void)max_iter; (void)p_dev;
-    (void)iters; (void)outer; (void)res_hist; (void)true_relres; (void)stream;
-    return PM_EINVAL;
+    constexpr int MAX_OUTER = 64;
+    if (!h || !rhs_dev || !p_dev || !iters || !(rtol > 0.0) || !std::isfinite(rtol) || max_iter < 0 ||
+        !(inner_rtol > 0.0) || !(inner_rtol < 1.0))
+        return PM_EINVAL;
+    if (!h->coords32) return PM_EINVAL;   // handle built without PM_FP32_INNER
+    hipStream_t s = (hipStream_t)stream;
+    TRY(ensure_hist(h, max_iter));
+    const int N = int(h->N);
+    const unsigned vg = h->n_vblocks;
+    std::vector<double> hist;
+
+    hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
+                       h->part_misc());
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist);
+    HIPCK(hipGetLastError());
+    TRY(read_state(h, s));
+    int status = h->hst->status;
+    const double bnorm = h->hst->bnorm;
+    int total = 0, n_outer = 0;
+    double rel = 0.0;
+    if (status == 0 && !(bnorm > 0.0)) {
+        // zero right-hand side: p = 0
+        HIPCK(hipMemsetAsync(h->x, 0, 8 * size_t(N), s));
+        hist.push_back(0.0);
+    }
+    while (status == 0 && bnorm > 0.0) {
+        // outer FP64 residual
+        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
+        hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
+        HIPCK(hipGetLastError());
+        TRY(read_state(h, s));
+        rel = std::sqrt(h->hst->tt) / bnorm;
+        hist.push_back(rel);
+        if (!std::isfinite(rel)) {
+            status = PM_EBREAKDOWN;
+            break;
+        }
+        if (rel <= rtol || total >= max_iter || n_outer >= MAX_OUTER) break;
+        // inner FP32 CG on A32 d = r32 from d = 0
+        hipLaunchKernelGGL(k_to_inner, dim3(vg), dim3(BLK), 0, s, N, h->r, h->r32, h->d32, h->part_rr(0));
+        hipLaunchKernelGGL(k_begin_inner, dim3(1), dim3(BLK), 0, s, h->st_in, h->part_rr(0), int(vg), inner_rtol,
+                           max_iter - total);
+        HIPCK(hipGetLastError());
+        int k = 1, chunk = 4;
+        bool first = true;
+        for (;;) {
+            TRY(launch_iterations32(h, k, chunk, first, s));
+            k += chunk;
+            first = false;
+            chunk = std::min(chunk * 2, 64);
+            HIPCK(hipMemcpyAsync(h->hst_in, h->st_in, sizeof(CGState), hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            if (h->hst_in->done) break;
+        }
+        total += h->hst_in->iter;
+        if (h->hst_in->status != 0) {
+            status = h->hst_in->status;
+            break;
+        }
+        hipLaunchKernelGGL(k_correct, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->x, h->d32);
+        HIPCK(hipGetLastError());
+        ++n_outer;
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(s));
+    *iters = total;
+    if (outer) *outer = n_outer;
+    if (res_hist)
+        for (size_t i = 0; i < hist.size() && i <= size_t(max_iter); ++i) res_hist[i] = hist[i];
+    if (true_relres) *true_relres = rel;
+    if (status != 0) return status;
+    return (rel <= rtol) ? PM_OK : PM_NOT_CONVERGED;
 }
 
 int pressure_set_variant(pm_handle *h, int32_t variant)

@@ -265,3 +265,51 @@ def test_tiled_and_node_kernels_agree_bitwise(tile):
         assert rt.iters == rn.iters
         assert np.array_equal(_host(rt.p).view(np.uint64), xn.view(np.uint64))
         s.close()
+
+
+# ------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("name,make", [PROBLEMS[0], PROBLEMS[1], PROBLEMS[3]])
+def test_mixed_precision_reaches_fp64_residual(name, make):
+    """FP32 inner CG inside FP64 defect correction: the oracle's FP64
+    operator accepts the result at the requested tolerance, and the result
+    agrees with the oracle's FP64 CG solution."""
+    prob = make()
+    m = prob.mesh
+    print("case", name, flush=True)
+    A = oracle.assemble_problem(prob)
+    b = _rhs_for(prob, A)
+    x_ref, st_ref, _, _, _ = oracle.cg(A, b, rtol=prob.rtol, max_iter=20000, dirichlet=m.dirichlet)
+    s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER)
+    res = s.solve_mixed(_dev(b), rtol=prob.rtol, inner_rtol=1e-4, max_iter=20000)
+    x = _host(res.p)
+    assert res.status == 0 and res.outer >= 1
+    accept = np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)
+    assert accept <= 1.05 * prob.rtol, accept
+    assert res.true_relres <= prob.rtol
+    assert np.all(np.diff(res.hist) < 0) and res.hist[-1] <= prob.rtol
+    rel = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    assert rel <= 1e-8, rel
+    # bitwise reproducible
+    res2 = s.solve_mixed(_dev(b), rtol=prob.rtol, inner_rtol=1e-4, max_iter=20000)
+    assert res2.iters == res.iters
+    assert np.array_equal(_host(res2.p).view(np.uint64), x.view(np.uint64))
+    s.close()
+
+
+def test_mixed_precision_edge_cases():
+    prob = workloads.cube(6, w=1e-2, jitter=0.2, rho="uniform")
+    m = prob.mesh
+    s64 = pm.PressureSystem.from_problem(prob)
+    with pytest.raises(pm.PressureError):
+        s64.solve_mixed(_dev(np.ones(m.n_nodes)), rtol=1e-10)
+    s64.close()
+    s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER)
+    r = s.solve_mixed(_dev(np.zeros(m.n_nodes)), rtol=1e-10)
+    assert r.status == 0 and r.iters == 0 and np.all(_host(r.p) == 0)
+    A = oracle.assemble_problem(prob)
+    b = _rhs_for(prob, A)
+    r = s.solve_mixed(_dev(b), rtol=1e-10, max_iter=5)
+    assert r.status == pm.PM_NOT_CONVERGED and r.iters <= 5
+    with pytest.raises(pm.PressureError):
+        s.solve_mixed(_dev(b), rtol=1e-10, inner_rtol=1.5)
+    s.close()
