@@ -36,6 +36,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--tile", type=int, default=0, help="Morton tile nodes (128/256/512; 0 = library default)")
+    ap.add_argument("--inner-rtol", type=float, default=1e-4, help="inner tolerance of the mixed solve")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -50,7 +53,9 @@ def main():
     ws = workloads.CUBE64_W
     probs = [workloads.cube64(w) for w in ws]
     m = probs[0].mesh
-    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    tile_flag = {0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
+    flags = pm.PM_FP64 | pm.PM_FP32_INNER | tile_flag
+    systems = [pm.PressureSystem.from_problem(p, flags=flags) for p in probs]
     for s in systems:
         s.set_variant(args.variant)
     info = systems[0].info()
@@ -128,11 +133,40 @@ def main():
             "launches": launches,
         },
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_comparison(systems, rhs, xstar, args, elapsed / len(lat))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(probs)
     print(json.dumps(out), flush=True)
     for s in systems:
         s.close()
+
+
+def mixed_comparison(systems, rhs, xstar, args, fp64_solve_s):
+    """The same solves by FP32-inner defect correction (FP64 outer residual,
+    dot accumulation and update), timed after the FP64 region."""
+    import torch
+    ref = [s.solve(b, rtol=args.rtol).p.clone() for s, b in zip(systems, rhs)]
+    for s, b in zip(systems, rhs):
+        s.solve_mixed(b, rtol=args.rtol, inner_rtol=args.inner_rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inner, outer, worst_res, worst_diff = [], [], 0.0, 0.0
+    for _ in range(args.steps):
+        for s, b, pr in zip(systems, rhs, ref):
+            r = s.solve_mixed(b, rtol=args.rtol, inner_rtol=args.inner_rtol)
+            if r.status != 0:
+                raise RuntimeError("mixed solve status %d" % r.status)
+            inner.append(r.iters)
+            outer.append(r.outer)
+            worst_res = max(worst_res, r.true_relres)
+            worst_diff = max(worst_diff, float(torch.linalg.norm(r.p - pr) / torch.linalg.norm(pr)))
+    torch.cuda.synchronize()
+    per_solve = (time.perf_counter() - t0) / len(inner)
+    return {"solve_ms": round(per_solve * 1e3, 3), "speedup_vs_fp64": round(fp64_solve_s / per_solve, 3),
+            "inner_iterations": inner[: len(systems)], "outer_corrections": outer[: len(systems)],
+            "inner_rtol": args.inner_rtol, "max_true_relres": worst_res,
+            "max_rel_diff_vs_fp64_solution": worst_diff}
 
 
 def cpu_baseline(probs):

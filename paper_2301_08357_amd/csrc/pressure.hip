@@ -251,6 +251,27 @@ __device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &be
     return !stop;
 }
 
+// Tile schedule: workgroups are dispatched round-robin over the 8 XCDs
+// (block b runs on XCD b mod 8), and each XCD has its own L2.  Block b takes
+// the tiles of XCD b mod 8's contiguous share of the Morton order, so blocks
+// running side by side on one XCD work on neighbouring tiles and share their
+// halo nodes in that L2.  tile_at(b, k) is the k-th tile of block b, or -1.
+constexpr int N_XCD = 8;
+
+__device__ __forceinline__ int tile_at(int b, int k, int n_blocks, int n_tiles)
+{
+    if (n_blocks < N_XCD || (n_blocks % N_XCD) != 0) {
+        const int t = b + k * n_blocks;
+        return t < n_tiles ? t : -1;
+    }
+    const int per_xcd_blocks = n_blocks / N_XCD;
+    const int share = (n_tiles + N_XCD - 1) / N_XCD;
+    const int x = b % N_XCD, j = b / N_XCD;
+    const int t = x * share + j + k * per_xcd_blocks;
+    const int end = min((x + 1) * share, n_tiles);
+    return t < end ? t : -1;
+}
+
 // ------------------------------------------------------------ apply kernels
 
 // One lane per node: y_i = sum over the node's elements (ascending) of the
@@ -275,7 +296,9 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
     };
     double part = 0.0;
     const int n_tiles = (g.N + T - 1) / T;
-    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x)
+    for (int kt = 0;; ++kt) {
+    const int t = tile_at(blockIdx.x, kt, gridDim.x, n_tiles);
+    if (t < 0) break;
     for (int jj = threadIdx.x; jj < T; jj += BLK) {
         const int i = t * T + jj;
         if (i >= g.N) break;
@@ -308,6 +331,7 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
             part += xi * yi;
         }
     }
+    }
     if (CG) {
         const double bs = block_sum_all(part, red);
         if (threadIdx.x == 0) it.part_pq[blockIdx.x] = bs;
@@ -328,7 +352,7 @@ struct TileArgsT {
     const uint8_t *deg;           // elements per node
 };
 
-// Morton-tiled apply.  One block per tile (grid-stride over tiles):
+// Morton-tiled apply.  Each block walks its tiles (tile_at); for every tile
 //  1. load the tile's element instances (local connectivity, rows and factor)
 //     into registers, and the coordinates and nodal values of its nodes and
 //     halo into LDS (Dirichlet values as 0); under CG the values are
@@ -339,7 +363,8 @@ struct TileArgsT {
 //  3. each own node sums S[0..deg-1][i] in row order (ascending element id).
 // Every element is computed once per tile that contains one of its vertices.
 // IPT instances and SPT node-table slots per lane cover the largest tile
-// (checked at setup).
+// (checked at setup).  Several blocks share a CU, so the loads of one block
+// overlap the arithmetic of another.
 template <int DIM, bool CG, class R, int NPT, int IPT, int SPT>
 __global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
                                                      R *__restrict__ y, IterT<R> it)
@@ -356,7 +381,9 @@ __global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta
     uint8_t *sD = reinterpret_cast<uint8_t *>(sS + ta.max_deg * T);   // own Dirichlet flags
     uint8_t *sG = sD + T;                                         // own degrees
     double part = 0.0;
-    for (int t = blockIdx.x; t < ta.n_tiles; t += gridDim.x) {
+    for (int kt = 0;; ++kt) {
+        const int t = tile_at(blockIdx.x, kt, gridDim.x, ta.n_tiles);
+        if (t < 0) break;
         const int s = t * T;
         const int nt = min(T, g.N - s);
         const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
@@ -697,7 +724,7 @@ struct pm_handle {
     double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
     double *pbuf[2] = {nullptr, nullptr};
     double *part = nullptr;     // [apply partials | rr partials x2 | misc partials]
-    int n_vblocks = 0, n_ablocks = 0;
+    int n_vblocks = 0, n_ablocks = 0, n_ablocks32 = 0, n_cu = 256;
     CGState *st = nullptr;
     double *hist = nullptr;
     int32_t hist_cap = 0;
@@ -858,7 +885,8 @@ int launch_tiled_k(pm_handle *h, K kern, const MeshT<R> &g, const TileArgsT<R> &
 {
     const size_t lds = tiled_lds_bytes<R>(h);
     if (lds > 65536) HIPCK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    hipLaunchKernelGGL(kern, dim3(h->n_ablocks), dim3(BLK), lds, s, g, ta, x, y, it);
+    const int grid = (sizeof(R) == 8) ? h->n_ablocks : h->n_ablocks32;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLK), lds, s, g, ta, x, y, it);
     HIPCK(hipGetLastError());
     return PM_OK;
 }
@@ -898,6 +926,51 @@ int launch_tiled_t(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream
     case 9: return launch_tiled_c<DIM, CG, R, 9>(h, x, y, it, s);
     default: return PM_EINVAL;
     }
+}
+
+// Resident blocks per CU of the CG apply kernel of the handle's size class.
+template <int DIM, class R, int C>
+int occupancy_c(pm_handle *h, int *per_cu)
+{
+    constexpr TileClass tc = TILE_CLASSES[C];
+    const void *kern = (const void *)k_apply_tiled<DIM, true, R, tc.npt, tc.ipt, tc.spt>;
+    const size_t lds = tiled_lds_bytes<R>(h);
+    if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, BLK, lds));
+    return PM_OK;
+}
+
+template <int DIM, class R>
+int occupancy_t(pm_handle *h, int *per_cu)
+{
+    switch (h->tile_class) {
+    case 0: return occupancy_c<DIM, R, 0>(h, per_cu);
+    case 1: return occupancy_c<DIM, R, 1>(h, per_cu);
+    case 2: return occupancy_c<DIM, R, 2>(h, per_cu);
+    case 3: return occupancy_c<DIM, R, 3>(h, per_cu);
+    case 4: return occupancy_c<DIM, R, 4>(h, per_cu);
+    case 5: return occupancy_c<DIM, R, 5>(h, per_cu);
+    case 6: return occupancy_c<DIM, R, 6>(h, per_cu);
+    case 7: return occupancy_c<DIM, R, 7>(h, per_cu);
+    case 8: return occupancy_c<DIM, R, 8>(h, per_cu);
+    case 9: return occupancy_c<DIM, R, 9>(h, per_cu);
+    default: return PM_EINVAL;
+    }
+}
+
+// Grid of the tiled apply: every block resident at once (one per resident
+// slot over all CUs), a multiple of the XCD count, at most one per tile.
+template <class R>
+int apply_grid(pm_handle *h, int *grid)
+{
+    int per_cu = 0;
+    const int st = (h->dim == 2) ? occupancy_t<2, R>(h, &per_cu) : occupancy_t<3, R>(h, &per_cu);
+    if (st != PM_OK) return st;
+    int g = std::max(1, per_cu) * h->n_cu;
+    g = std::min(g, AGRID_MAX);
+    if (g >= N_XCD) g -= g % N_XCD;
+    *grid = std::max(1, std::min(g, h->n_tiles));
+    return PM_OK;
 }
 
 template <int DIM, bool CG>
@@ -993,8 +1066,8 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
         HIPCK(hipMemcpy(h->t_inst_row, T.inst_row.data(), T.inst_row.size(), hipMemcpyHostToDevice));
     }
     TRY(dalloc(h, &h->t_inst_w, size_t(h->n_inst)));
-    h->n_ablocks = std::min(h->n_tiles, AGRID_MAX);
     if (tiled_lds_bytes<double>(h) > h->lds_limit) return PM_EINVAL;
+    TRY(apply_grid<double>(h, &h->n_ablocks));
     return PM_OK;
 }
 
@@ -1105,6 +1178,8 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
         int v = 0;
         HIPCK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
         h->lds_limit = size_t(v) - 1024;   // static LDS of the kernels
+        HIPCK(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, h->device));
+        h->n_cu = std::max(1, v);
     }
     h->dim = L.dim;
     h->N = L.n_nodes;
@@ -1154,6 +1229,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
         HIPCK(hipMemset(h->st_in, 0, sizeof(CGState)));
         HIPCK(hipHostMalloc((void **)&h->hst_in, sizeof(CGState), hipHostMallocDefault));
         if (tiled_lds_bytes<float>(h) > h->lds_limit) return PM_EINVAL;
+        TRY(apply_grid<float>(h, &h->n_ablocks32));
     }
     TRY(dalloc(h, &h->part, AGRID_MAX + 3 * VGRID_MAX));
     TRY(dalloc(h, &h->st, 1));
@@ -1368,7 +1444,7 @@ static int launch_iterations32(pm_handle *h, int k0, int count, bool first, hipS
         it.n_vblocks = h->n_vblocks;
         TRY(launch_apply32(h, it, s));
         hipLaunchKernelGGL(k_update<float>, dim3(h->n_vblocks), dim3(BLK), 0, s, N, h->d32, h->r32, h->p32[k & 1],
-                           h->q32, h->st_in, h->part_pq(), h->n_ablocks, h->part_rr((k - 1) & 1), h->n_vblocks,
+                           h->q32, h->st_in, h->part_pq(), h->n_ablocks32, h->part_rr((k - 1) & 1), h->n_vblocks,
                            h->part_rr(k & 1));
     }
     HIPCK(hipGetLastError());
