@@ -200,6 +200,47 @@ int pressure_timing_read(pm_handle *h, int64_t *launches, double *total_ms);
  *       instances over all tiles. */
 int pressure_info(pm_handle *h, int64_t *info, int32_t n_info);
 
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent meshes (2D and 3D mixed) solved together.
+ * Each CG iteration of all meshes is two kernel launches (the operator apply
+ * of every (mesh, tile slot), then the vector update of every (mesh, node
+ * slot)); chunks of iterations are captured once in a HIP graph and
+ * replayed, and meshes that have converged skip their slots.  This is the
+ * same classical CG as pressure_solve (paper Sec. 3.4), run for many systems
+ * at once.
+ */
+typedef struct pm_batch pm_batch;
+
+/* Group n handles (all from pressure_setup on the current device, each with
+ * the default or 128-node tiles) into a batch.
+ *   params   NULL for the defaults, else int32_t[2]:
+ *            params[0] Morton tiles per apply slot (>= 1, default 4),
+ *            params[1] nodes per lane of an update slot (>= 1, default 8).
+ * Joining a batch sets each handle's launch grids to the batch's; single
+ * pressure_solve calls on the handle then use the same grids, so a mesh's
+ * batched result equals its single-mesh result bit for bit.  The handles
+ * must outlive the batch and must not be used while a batched solve runs.
+ * Errors: PM_EINVAL (n < 1, NULL handle, unsupported tile size or mesh
+ * shape, handles on different devices), PM_ENOMEM, PM_EHIP. */
+int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *params, pm_batch **out);
+
+/* Solve all meshes of the batch.  rhs_dev, x0_dev and p_dev are host arrays
+ * of n device pointers (x0_dev may be NULL, or hold NULL entries, for a zero
+ * initial guess); iters, true_relres and status are host arrays of n
+ * (status[m] is the PM_* code of mesh m).  rtol and max_iter apply to every
+ * mesh.  Returns PM_OK when every mesh converged, PM_NOT_CONVERGED if some
+ * did not, or the first error.  Synchronises the stream before returning. */
+int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double *const *x0_dev, double rtol,
+                         int32_t max_iter, double *const *p_dev, int32_t *iters, double *true_relres,
+                         int32_t *status, void *stream);
+
+/* Number of CG iterations captured per graph replay (default 16, even, 2..256);
+ * 0 disables graph capture (iterations are launched one by one). */
+int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay);
+
+/* Release the batch (not its handles).  NULL is ignored. */
+void pressure_batch_destroy(pm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,10 @@ SIGNATURES = {
     "pressure_timing_enable": (ctypes.c_int, [_P, _i32]),
     "pressure_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
     "pressure_info": (ctypes.c_int, [_P, ctypes.POINTER(_i64), _i32]),
+    "pressure_batch_create": (ctypes.c_int, [_P, _i32, _P, ctypes.POINTER(_P)]),
+    "pressure_batch_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, _P, _P, _P, _P]),
+    "pressure_batch_set_graph": (ctypes.c_int, [_P, _i32]),
+    "pressure_batch_destroy": (None, [_P]),
 }
 
 _lib = None

@@ -232,7 +232,7 @@ using Iter = IterT<double>;
 // (and of the previous one for beta) and takes the convergence decision;
 // block 0 records it.  Returns false when the iteration must not run.
 template <class R>
-__device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &beta)
+__device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &beta, int vb)
 {
     if (block_done(it.st)) return false;
     const double rr = sum_partials(it.rr_cur, it.n_vblocks, red);
@@ -241,7 +241,7 @@ __device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &be
     const double nr = sqrt(rr);
     const bool bad = !isfinite(rr);
     const bool stop = bad || !(nr > it.st->tol) || (it.k - 1) >= it.st->max_iter;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (vb == 0 && threadIdx.x == 0) {
         if (!(it.first && it.k > 1)) it.hist[it.k - 1] = nr / it.st->bnorm;
         it.st->iter = it.k - 1;
         it.st->rr = rr;
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
 {
     __shared__ double red[BLK / 64];
     double beta = 0.0;
-    if (CG && !iter_prologue(it, red, beta)) return;
+    if (CG && !iter_prologue(it, red, beta, int(blockIdx.x))) return;
     auto val = [&](int v) -> double {
         if (!CG) return x[v];
         return it.first ? it.r[v] : it.r[v] + beta * it.p_old[v];
@@ -365,15 +365,15 @@ struct TileArgsT {
 // IPT instances and SPT node-table slots per lane cover the largest tile
 // (checked at setup).  Several blocks share a CU, so the loads of one block
 // overlap the arithmetic of another.
+// The body runs as virtual block vb of nvb (a real block of a single-mesh
+// launch, or one (mesh, slot) pair of a batched launch).
 template <int DIM, bool CG, class R, int NPT, int IPT, int SPT>
-__global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
-                                                     R *__restrict__ y, IterT<R> it)
+__device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileArgsT<R> &ta,
+                                                 const R *__restrict__ x, R *__restrict__ y, const IterT<R> &it,
+                                                 R *smem, double *red, int vb, int nvb)
 {
-    extern __shared__ double smem_d[];
-    R *smem = reinterpret_cast<R *>(smem_d);
-    __shared__ double red[BLK / 64];
     double beta = 0.0;
-    if (CG && !iter_prologue(it, red, beta)) return;
+    if (CG && !iter_prologue(it, red, beta, vb)) return;
     const int L = ta.max_local, T = ta.T;
     R *sX = smem, *sY = smem + L, *sZ = smem + 2 * L;
     R *sP = smem + (DIM == 3 ? 3 : 2) * L;
@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta
     uint8_t *sG = sD + T;                                         // own degrees
     double part = 0.0;
     for (int kt = 0;; ++kt) {
-        const int t = tile_at(blockIdx.x, kt, gridDim.x, ta.n_tiles);
+        const int t = tile_at(vb, kt, nvb, ta.n_tiles);
         if (t < 0) break;
         const int s = t * T;
         const int nt = min(T, g.N - s);
@@ -499,26 +499,35 @@ __global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta
     }
     if (CG) {
         const double bs = block_sum_all(part, red);
-        if (threadIdx.x == 0) it.part_pq[blockIdx.x] = bs;
+        if (threadIdx.x == 0) it.part_pq[vb] = bs;
     }
+}
+
+template <int DIM, bool CG, class R, int NPT, int IPT, int SPT>
+__global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
+                                                     R *__restrict__ y, IterT<R> it)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[BLK / 64];
+    apply_tiled_body<DIM, CG, R, NPT, IPT, SPT>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red,
+                                                int(blockIdx.x), int(gridDim.x));
 }
 
 // ------------------------------------------------------------- CG vectors
 
 // update(k): alpha = rr_{k-1} / p_k.q; x += alpha p_k; r -= alpha q;
-// partials of r_k.r_k.
+// partials of r_k.r_k.  Runs as virtual block vb of nvb.
 template <class R>
-__global__ void __launch_bounds__(BLK) k_update(int N, R *__restrict__ x, R *__restrict__ r,
-                                                const R *__restrict__ p, const R *__restrict__ q,
-                                                CGState *st, const double *part_pq, int n_ablocks,
-                                                const double *rr_cur, int n_vblocks, double *rr_out)
+__device__ __forceinline__ void update_body(int N, R *__restrict__ x, R *__restrict__ r, const R *__restrict__ p,
+                                            const R *__restrict__ q, CGState *st, const double *part_pq,
+                                            int n_ablocks, const double *rr_cur, double *rr_out, double *red,
+                                            int vb, int nvb)
 {
-    __shared__ double red[BLK / 64];
     if (block_done(st)) return;
     const double pq = sum_partials(part_pq, n_ablocks, red);
-    const double rr = sum_partials(rr_cur, n_vblocks, red);
+    const double rr = sum_partials(rr_cur, nvb, red);
     if (!(pq > 0.0) || !isfinite(pq)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (vb == 0 && threadIdx.x == 0) {
             st->status = PM_EBREAKDOWN;
             st->done = 1;
         }
@@ -526,14 +535,25 @@ __global__ void __launch_bounds__(BLK) k_update(int N, R *__restrict__ x, R *__r
     }
     const R a = R(rr / pq);
     double v = 0.0;
-    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+    for (int i = vb * BLK + threadIdx.x; i < N; i += nvb * BLK) {
         x[i] += a * p[i];
         const R ri = r[i] - a * q[i];
         r[i] = ri;
         v += double(ri) * double(ri);
     }
     const double bs = block_sum_all(v, red);
-    if (threadIdx.x == 0) rr_out[blockIdx.x] = bs;
+    if (threadIdx.x == 0) rr_out[vb] = bs;
+}
+
+template <class R>
+__global__ void __launch_bounds__(BLK) k_update(int N, R *__restrict__ x, R *__restrict__ r,
+                                                const R *__restrict__ p, const R *__restrict__ q,
+                                                CGState *st, const double *part_pq, int n_ablocks,
+                                                const double *rr_cur, int n_vblocks, double *rr_out)
+{
+    __shared__ double red[BLK / 64];
+    (void)n_vblocks;
+    update_body<R>(N, x, r, p, q, st, part_pq, n_ablocks, rr_cur, rr_out, red, int(blockIdx.x), int(gridDim.x));
 }
 
 // Gather the caller's rhs and initial guess into internal order; Dirichlet
@@ -629,6 +649,90 @@ __global__ void k_reopen(CGState *st)
     if (threadIdx.x == 0) st->done = 0;
 }
 
+// ----------------------------------------------------------- batched solve
+// Many meshes advance their CG iterations together: one launch runs the
+// apply of iteration k for every (mesh, slot) pair, the next the update.  The
+// iteration number lives in device memory (each kernel reads the field the
+// previous kernel wrote and writes the other one), so a sequence of
+// iterations can be captured once in a HIP graph and replayed.  Meshes that
+// have converged skip their slots.
+
+struct BatchMesh {
+    int dim, N;
+    MeshT<double> g;
+    TileArgsT<double> ta;
+    double *x, *r, *q, *p0, *p1, *hist;
+    CGState *st;
+    double *part_pq, *rr0, *rr1;
+    int n_ab, n_vb;   // apply / update virtual blocks of this mesh
+};
+
+struct BatchCtl {
+    int k_apply;   // iteration the next apply launch runs
+    int k_update;  // iteration the next update launch runs
+    int n_done;
+    int pad;
+};
+
+template <int IPT, int SPT>
+__global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMesh *__restrict__ meshes,
+                                                     const int2 *__restrict__ slots, BatchCtl *ctl)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[BLK / 64];
+    const int2 ms = slots[blockIdx.x];
+    const BatchMesh &M = meshes[ms.x];
+    const int k = ctl->k_apply;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_update = k;
+    IterT<double> it;
+    it.k = k;
+    it.first = (k == 1) ? 1 : 0;
+    it.r = M.r;
+    it.p_old = (k & 1) ? M.p0 : M.p1;   // p_{k-1}
+    it.p_new = (k & 1) ? M.p1 : M.p0;   // p_k
+    it.q = M.q;
+    it.st = M.st;
+    it.hist = M.hist;
+    it.part_pq = M.part_pq;
+    it.rr_cur = (k & 1) ? M.rr0 : M.rr1;
+    it.rr_prev = (k & 1) ? M.rr1 : M.rr0;
+    it.n_vblocks = M.n_vb;
+    if (M.dim == 3)
+        apply_tiled_body<3, true, double, 1, IPT, SPT>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
+    else
+        apply_tiled_body<2, true, double, 1, IPT, SPT>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
+}
+
+__global__ void __launch_bounds__(BLK) k_batch_update(const BatchMesh *__restrict__ meshes,
+                                                      const int2 *__restrict__ slots, BatchCtl *ctl)
+{
+    __shared__ double red[BLK / 64];
+    const int2 ms = slots[blockIdx.x];
+    const BatchMesh &M = meshes[ms.x];
+    const int k = ctl->k_update;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_apply = k + 1;
+    update_body<double>(M.N, M.x, M.r, (k & 1) ? M.p1 : M.p0, M.q, M.st, M.part_pq, M.n_ab,
+                        (k & 1) ? M.rr0 : M.rr1, (k & 1) ? M.rr1 : M.rr0, red, ms.y, M.n_vb);
+}
+
+// One block: number of finished meshes, and a copy of every state.
+__global__ void __launch_bounds__(BLK) k_batch_status(const BatchMesh *__restrict__ meshes, int n, BatchCtl *ctl,
+                                                      CGState *states)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int c = 0;
+    for (int m = threadIdx.x; m < n; m += BLK) {
+        const CGState s = *meshes[m].st;
+        states[m] = s;
+        c += s.done ? 1 : 0;
+    }
+    atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) ctl->n_done = cnt;
+}
+
 // Mixed precision: r32 = r (rounded), d32 = 0, partials of r32.r32 (FP64).
 __global__ void __launch_bounds__(BLK) k_to_inner(int N, const double *__restrict__ r, float *__restrict__ r32,
                                                   float *__restrict__ d32, double *part)
@@ -706,7 +810,7 @@ struct pm_handle {
     double *w = nullptr;        // beta c_e / (d! det_e)
     uint8_t *dir = nullptr;
     // tiles (device)
-    int tile_nodes = 0, n_tiles = 0, max_local = 0, max_deg = 0, tile_class = -1;
+    int tile_nodes = 0, n_tiles = 0, max_local = 0, max_deg = 0, max_inst = 0, tile_class = -1;
     size_t lds_limit = 65536;
     int64_t n_inst = 0;
     int *t_halo_off = nullptr, *t_halo = nullptr, *t_inst_off = nullptr, *t_inst_elem = nullptr;
@@ -1039,6 +1143,7 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
     h->n_tiles = int(T.n_tiles);
     h->max_local = tile_nodes + T.max_halo;
     h->max_deg = T.max_deg;
+    h->max_inst = T.max_inst;
     h->n_inst = int64_t(T.inst_elem.size());
     // smallest size class covering the tile, its instances and node table
     const int need_n = (tile_nodes + BLK - 1) / BLK;
@@ -1568,6 +1673,328 @@ int pressure_info(pm_handle *h, int64_t *info, int32_t n_info)
                     int64_t(h->dev_bytes), h->n_tiles, h->n_inst};
     for (int k = 0; k < n_info && k < 8; ++k) info[k] = v[k];
     return PM_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Batched solves
+
+struct pm_batch {
+    std::vector<pm_handle *> hs;
+    int device = 0;
+    int tiles_per_slot = 4, nodes_per_lane = 8;
+    BatchMesh *d_meshes = nullptr;
+    int2 *d_aslots = nullptr, *d_uslots = nullptr;
+    int n_aslots = 0, n_uslots = 0;
+    BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
+    CGState *d_states = nullptr, *h_states = nullptr;
+    int bclass = -1;
+    size_t lds = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_iters = 16;
+};
+
+namespace {
+
+// Size classes of the batched apply (instances per lane, node-table slots per lane).
+constexpr int2 BATCH_CLASSES[] = {{4, 2}, {8, 2}, {8, 3}, {12, 3}, {12, 4}, {16, 4}};
+constexpr int N_BATCH_CLASSES = sizeof(BATCH_CLASSES) / sizeof(BATCH_CLASSES[0]);
+
+template <int C>
+const void *batch_apply_fn()
+{
+    return (const void *)k_batch_apply<BATCH_CLASSES[C].x, BATCH_CLASSES[C].y>;
+}
+
+const void *batch_apply_kernel(int c)
+{
+    switch (c) {
+    case 0: return batch_apply_fn<0>();
+    case 1: return batch_apply_fn<1>();
+    case 2: return batch_apply_fn<2>();
+    case 3: return batch_apply_fn<3>();
+    case 4: return batch_apply_fn<4>();
+    case 5: return batch_apply_fn<5>();
+    default: return nullptr;
+    }
+}
+
+template <int C>
+void launch_batch_apply_c(pm_batch *b, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch_apply<BATCH_CLASSES[C].x, BATCH_CLASSES[C].y>), dim3(b->n_aslots), dim3(BLK),
+                       b->lds, s, b->d_meshes, b->d_aslots, b->d_ctl);
+}
+
+int launch_batch_iterations(pm_batch *b, int count, hipStream_t s)
+{
+    for (int i = 0; i < count; ++i) {
+        switch (b->bclass) {
+        case 0: launch_batch_apply_c<0>(b, s); break;
+        case 1: launch_batch_apply_c<1>(b, s); break;
+        case 2: launch_batch_apply_c<2>(b, s); break;
+        case 3: launch_batch_apply_c<3>(b, s); break;
+        case 4: launch_batch_apply_c<4>(b, s); break;
+        case 5: launch_batch_apply_c<5>(b, s); break;
+        default: return PM_EINVAL;
+        }
+        hipLaunchKernelGGL(k_batch_update, dim3(b->n_uslots), dim3(BLK), 0, s, b->d_meshes, b->d_uslots, b->d_ctl);
+    }
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+void batch_free(pm_batch *b)
+{
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *p : {(void *)b->d_meshes, (void *)b->d_aslots, (void *)b->d_uslots, (void *)b->d_ctl,
+                    (void *)b->d_states})
+        if (p) (void)hipFree(p);
+    if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+    if (b->h_states) (void)hipHostFree(b->h_states);
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const int32_t *params)
+{
+    if (params) {
+        if (params[0] < 1 || params[1] < 1) return PM_EINVAL;
+        b->tiles_per_slot = params[0];
+        b->nodes_per_lane = params[1];
+    }
+    HIPCK(hipGetDevice(&b->device));
+    int need_i = 1, need_s = 1;
+    std::vector<BatchMesh> meshes(n);
+    std::vector<int2> aslots, uslots;
+    for (int m = 0; m < n; ++m) {
+        pm_handle *h = handles[m];
+        if (!h || h->device != b->device || h->tile_nodes > BLK) return PM_EINVAL;
+        need_i = std::max(need_i, (h->max_inst + BLK - 1) / BLK);
+        need_s = std::max(need_s, (h->max_local + BLK - 1) / BLK);
+        b->lds = std::max(b->lds, tiled_lds_bytes<double>(h));
+        // the batch's grids become the handle's
+        h->n_ablocks = std::max(1, std::min(AGRID_MAX, (h->n_tiles + b->tiles_per_slot - 1) / b->tiles_per_slot));
+        h->n_vblocks = int(std::max<int64_t>(1, std::min<int64_t>(VGRID_MAX, (h->N + int64_t(BLK) * b->nodes_per_lane - 1) /
+                                                                                 (int64_t(BLK) * b->nodes_per_lane))));
+        BatchMesh &M = meshes[m];
+        M.dim = h->dim;
+        M.N = int(h->N);
+        M.g = make_mesh<double>(h);
+        M.ta = make_tiles<double>(h);
+        M.x = h->x;
+        M.r = h->r;
+        M.q = h->q;
+        M.p0 = h->pbuf[0];
+        M.p1 = h->pbuf[1];
+        M.hist = h->hist;
+        M.st = h->st;
+        M.part_pq = h->part_pq();
+        M.rr0 = h->part_rr(0);
+        M.rr1 = h->part_rr(1);
+        M.n_ab = h->n_ablocks;
+        M.n_vb = h->n_vblocks;
+        for (int j = 0; j < M.n_ab; ++j) aslots.push_back(make_int2(m, j));
+        for (int j = 0; j < M.n_vb; ++j) uslots.push_back(make_int2(m, j));
+        b->hs.push_back(h);
+    }
+    b->bclass = -1;
+    for (int c = 0; c < N_BATCH_CLASSES; ++c)
+        if (BATCH_CLASSES[c].x >= need_i && BATCH_CLASSES[c].y >= need_s) {
+            b->bclass = c;
+            break;
+        }
+    if (b->bclass < 0 || b->lds > b->hs[0]->lds_limit) return PM_EINVAL;
+    if (b->lds > 65536)
+        HIPCK(hipFuncSetAttribute(batch_apply_kernel(b->bclass), hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds)));
+    b->n_aslots = int(aslots.size());
+    b->n_uslots = int(uslots.size());
+    auto up = [&](auto **dst, const auto &vec) -> int {
+        using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+        if (hipMalloc((void **)dst, sizeof(T) * vec.size()) != hipSuccess) return PM_ENOMEM;
+        HIPCK(hipMemcpy(*dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice));
+        return PM_OK;
+    };
+    TRY(up(&b->d_meshes, meshes));
+    TRY(up(&b->d_aslots, aslots));
+    TRY(up(&b->d_uslots, uslots));
+    if (hipMalloc((void **)&b->d_ctl, sizeof(BatchCtl)) != hipSuccess) return PM_ENOMEM;
+    if (hipMalloc((void **)&b->d_states, sizeof(CGState) * n) != hipSuccess) return PM_ENOMEM;
+    HIPCK(hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault));
+    HIPCK(hipHostMalloc((void **)&b->h_states, sizeof(CGState) * n, hipHostMallocDefault));
+    HIPCK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIPCK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+    return PM_OK;
+}
+
+int batch_capture(pm_batch *b)
+{
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (b->graph_iters <= 0) return PM_OK;
+    HIPCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const int st = launch_batch_iterations(b, b->graph_iters, b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != PM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCK(e);
+    b->graph = g;
+    HIPCK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *params, pm_batch **out)
+{
+    if (!out || !handles || n < 1) return PM_EINVAL;
+    *out = nullptr;
+    pm_batch *b = nullptr;
+    try {
+        b = new pm_batch();
+        int s = batch_create_impl(b, handles, n, params);
+        if (s == PM_OK) s = batch_capture(b);
+        if (s != PM_OK) {
+            batch_free(b);
+            return s;
+        }
+    } catch (...) {
+        batch_free(b);
+        return PM_ENOMEM;
+    }
+    *out = b;
+    return PM_OK;
+}
+
+void pressure_batch_destroy(pm_batch *b) { batch_free(b); }
+
+int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
+{
+    if (!b || iterations_per_replay < 0 || iterations_per_replay > 256 || (iterations_per_replay % 2) != 0)
+        return PM_EINVAL;
+    b->graph_iters = iterations_per_replay;
+    return batch_capture(b);
+}
+
+int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double *const *x0_dev, double rtol,
+                         int32_t max_iter, double *const *p_dev, int32_t *iters, double *true_relres,
+                         int32_t *status, void *stream)
+{
+    if (!b || !rhs_dev || !p_dev || !iters || !true_relres || !status || !(rtol > 0.0) || !std::isfinite(rtol) ||
+        max_iter < 0)
+        return PM_EINVAL;
+    const int n = int(b->hs.size());
+    for (int m = 0; m < n; ++m)
+        if (!rhs_dev[m] || !p_dev[m]) return PM_EINVAL;
+    hipStream_t us = (hipStream_t)stream, s = b->stream;
+    HIPCK(hipEventRecord(b->ev, us));
+    HIPCK(hipStreamWaitEvent(s, b->ev, 0));
+    // start every mesh: rhs, guess, ||rhs||, r0 = b - A x0
+    for (int m = 0; m < n; ++m) {
+        pm_handle *h = b->hs[m];
+        TRY(ensure_hist(h, max_iter));
+        const int N = int(h->N);
+        const unsigned vg = h->n_vblocks;
+        hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev[m],
+                           x0_dev ? x0_dev[m] : nullptr, h->b, h->x, h->part_misc());
+        hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist);
+        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
+    }
+    HIPCK(hipGetLastError());
+    // the histories may have moved (ensure_hist): refresh the descriptors
+    {
+        bool moved = false;
+        std::vector<BatchMesh> meshes(n);
+        HIPCK(hipMemcpyAsync(meshes.data(), b->d_meshes, sizeof(BatchMesh) * n, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        for (int m = 0; m < n; ++m)
+            if (meshes[m].hist != b->hs[m]->hist) {
+                meshes[m].hist = b->hs[m]->hist;
+                moved = true;
+            }
+        if (moved) {
+            HIPCK(hipMemcpyAsync(b->d_meshes, meshes.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice, s));
+            HIPCK(hipStreamSynchronize(s));
+        }
+    }
+    b->h_ctl->k_apply = 1;
+    b->h_ctl->k_update = 0;
+    b->h_ctl->n_done = 0;
+    HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s));
+    // iterations until every mesh is done (each stops by itself at max_iter)
+    int64_t launched = 0;
+    for (;;) {
+        if (b->gexec) {
+            HIPCK(hipGraphLaunch(b->gexec, s));
+            launched += b->graph_iters;
+        } else {
+            TRY(launch_batch_iterations(b, 8, s));
+            launched += 8;
+        }
+        hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BLK), 0, s, b->d_meshes, n, b->d_ctl, b->d_states);
+        HIPCK(hipGetLastError());
+        HIPCK(hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (b->h_ctl->n_done >= n) break;
+        if (launched > int64_t(max_iter) + 2 * b->graph_iters + 16) return PM_EHIP;   // cannot happen: every mesh stops at max_iter
+    }
+    // true residuals and outputs
+    for (int m = 0; m < n; ++m) {
+        pm_handle *h = b->hs[m];
+        const int N = int(h->N);
+        const unsigned vg = h->n_vblocks;
+        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
+        hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
+        hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev[m]);
+    }
+    hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BLK), 0, s, b->d_meshes, n, b->d_ctl, b->d_states);
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(b->h_states, b->d_states, sizeof(CGState) * n, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    int worst = PM_OK;
+    for (int m = 0; m < n; ++m) {
+        const CGState &st = b->h_states[m];
+        iters[m] = st.iter;
+        const double rel = (st.bnorm > 0.0) ? std::sqrt(st.tt) / st.bnorm : 0.0;
+        true_relres[m] = rel;
+        int code = st.status;
+        if (code == 0 && !(rel <= rtol)) {
+            // residual replacement, as pressure_solve does: continue from the iterate
+            int32_t more = 0;
+            double rel2 = rel;
+            code = pressure_solve(b->hs[m], rhs_dev[m], p_dev[m], rtol, std::max(0, max_iter - st.iter), p_dev[m],
+                                  &more, nullptr, &rel2, (void *)s);
+            iters[m] += more;
+            true_relres[m] = rel2;
+        }
+        status[m] = code;
+        if (code < 0 && worst >= 0) worst = code;
+        else if (code == PM_NOT_CONVERGED && worst == PM_OK) worst = code;
+    }
+    HIPCK(hipEventRecord(b->ev, s));
+    HIPCK(hipStreamWaitEvent(us, b->ev, 0));
+    HIPCK(hipStreamSynchronize(us));
+    return worst;
 }
 
 }  // extern "C"

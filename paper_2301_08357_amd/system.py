@@ -190,3 +190,55 @@ class PressureSystem:
         check(load().pressure_info(self._h, v, 8), "pressure_info")
         keys = ("n_nodes", "n_elems", "n_free", "dim", "apply_bytes", "device_bytes", "n_tiles", "n_instances")
         return dict(zip(keys, list(v)))
+
+
+class PressureBatch:
+    """Several PressureSystem meshes solved together (batched launches
+    replayed from a HIP graph).  Joining a batch fixes each system's launch
+    grids to the batch's, so single solves on those systems reproduce the
+    batched results bit for bit."""
+
+    def __init__(self, systems, tiles_per_slot=4, nodes_per_lane=8):
+        self.systems = list(systems)
+        n = len(self.systems)
+        hs = (ctypes.c_void_p * n)(*[s._h.value for s in self.systems])
+        params = (ctypes.c_int32 * 2)(int(tiles_per_slot), int(nodes_per_lane))
+        b = ctypes.c_void_p(None)
+        check(load().pressure_batch_create(hs, n, params, ctypes.byref(b)), "pressure_batch_create")
+        self._b = b
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            load().pressure_batch_destroy(self._b)
+        self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, iterations_per_replay):
+        check(load().pressure_batch_set_graph(self._b, int(iterations_per_replay)), "pressure_batch_set_graph")
+
+    def solve(self, rhs, x0=None, rtol=1e-10, max_iter=20000, out=None, stream=None):
+        """rhs, x0, out: lists of float64 CUDA tensors (one per system).
+        Returns (overall status, list of SolveResult)."""
+        import torch
+        n = len(self.systems)
+        if out is None:
+            out = [torch.empty_like(r) for r in rhs]
+        rp = (ctypes.c_void_p * n)(*[_dev_ptr(r, s.n_nodes, "rhs").value for r, s in zip(rhs, self.systems)])
+        op = (ctypes.c_void_p * n)(*[_dev_ptr(o, s.n_nodes, "p").value for o, s in zip(out, self.systems)])
+        xp = None
+        if x0 is not None:
+            xp = (ctypes.c_void_p * n)(*[None if x is None else _dev_ptr(x, s.n_nodes, "x0").value
+                                         for x, s in zip(x0, self.systems)])
+        its = np.zeros(n, dtype=np.int32)
+        rel = np.zeros(n)
+        st = np.zeros(n, dtype=np.int32)
+        code = load().pressure_batch_solve(self._b, rp, xp, float(rtol), int(max_iter), op, _ptr(its), _ptr(rel),
+                                           _ptr(st), _stream_handle(stream))
+        check(code, "pressure_batch_solve")
+        res = [SolveResult(out[m], int(st[m]), int(its[m]), None, float(rel[m])) for m in range(n)]
+        return code, res

@@ -1,0 +1,106 @@
+"""Batched solves of many meshes (needs an MI355X).
+
+Every mesh of a batch must give exactly (bit for bit) what a single-mesh
+solve on the same handle gives, whether the iterations run from a replayed
+HIP graph or from direct launches, and the oracle's operator must accept
+each result at the requested tolerance.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2301_08357_amd as pm
+from synth import fields, workloads
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device=DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _small_mix():
+    """Meshes of the batched workload's distribution (2D and 3D, w spread
+    over [1e-6, 1]), limited to sizes the oracle assembles in a second."""
+    params = workloads.batch_params()
+    picked = [i for i, (d, n, w) in enumerate(params) if (n + 1) ** d <= 12000][:6]
+    probs = [workloads.batch_problem(i, params) for i in picked]
+    probs.append(workloads.cube(5, w=1.0, jitter=0.2, rho="uniform"))
+    probs.append(workloads.tgv2d(9))
+    return probs
+
+
+def _rhs(prob, A):
+    if "source" in prob.extra:
+        return oracle.mass_rhs(prob, prob.extra["source"])
+    return A.matvec(fields.sine_product(prob.mesh.coords))
+
+
+def test_batch_matches_single_and_oracle():
+    probs = _small_mix()
+    print("case meshes", [(p.mesh.dim, p.mesh.n_nodes) for p in probs], flush=True)
+    As = [oracle.assemble_problem(p) for p in probs]
+    bs = [_rhs(p, A) for p, A in zip(probs, As)]
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    batch = pm.PressureBatch(systems, tiles_per_slot=2, nodes_per_lane=4)
+    rhs = [_dev(b) for b in bs]
+    code, res = batch.solve(rhs, rtol=1e-10)
+    assert code == 0
+    xb = [_host(r.p).copy() for r in res]
+    for p, A, b, r, x in zip(probs, As, bs, res, xb):
+        assert r.status == 0
+        accept = np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)
+        assert accept <= 1.05e-10, (p.name, accept)
+    # eager single solves in between, then bitwise equality with them
+    for s, b, r, x in zip(systems, rhs, res, xb):
+        single = s.solve(b, rtol=1e-10)
+        assert single.iters == r.iters
+        assert np.array_equal(_host(single.p).view(np.uint64), x.view(np.uint64))
+    # a second replay of the same graphs gives the same bits
+    code2, res2 = batch.solve(rhs, rtol=1e-10)
+    assert code2 == 0
+    for r, x in zip(res2, xb):
+        assert np.array_equal(_host(r.p).view(np.uint64), x.view(np.uint64))
+    # direct launches (no graph) and another chunk length: same bits
+    for g in (0, 6):
+        batch.set_graph(g)
+        code3, res3 = batch.solve(rhs, rtol=1e-10)
+        assert code3 == 0
+        for r, x in zip(res3, xb):
+            assert np.array_equal(_host(r.p).view(np.uint64), x.view(np.uint64))
+    batch.close()
+    for s in systems:
+        s.close()
+
+
+def test_batch_edge_cases():
+    probs = [workloads.cube(4, w=1e-2, jitter=0.2, rho="uniform"), workloads.tgv2d(6)]
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    batch = pm.PressureBatch(systems)
+    As = [oracle.assemble_problem(p) for p in probs]
+    b0 = _dev(_rhs(probs[0], As[0]))
+    zero = _dev(np.zeros(probs[1].mesh.n_nodes))
+    code, res = batch.solve([b0, zero], rtol=1e-10)
+    assert code == 0 and res[1].iters == 0 and np.all(_host(res[1].p) == 0)
+    code, res = batch.solve([b0, _dev(_rhs(probs[1], As[1]))], rtol=1e-12, max_iter=3)
+    assert code == pm.PM_NOT_CONVERGED
+    assert all(r.status == pm.PM_NOT_CONVERGED and r.iters == 3 for r in res)
+    # warm start from the solution: no iterations
+    code, res = batch.solve([b0, zero], rtol=1e-11)
+    code, res2 = batch.solve([b0, zero], x0=[res[0].p.clone(), None], rtol=1e-10)
+    assert code == 0 and res2[0].iters == 0
+    with pytest.raises(pm.PressureError):
+        batch.set_graph(3)
+    batch.close()
+    for s in systems:
+        s.close()
