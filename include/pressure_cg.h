@@ -213,9 +213,13 @@ typedef struct pm_batch pm_batch;
 
 /* Group n handles (all from pressure_setup on the current device, each with
  * the default or 128-node tiles) into a batch.
- *   params   NULL for the defaults, else int32_t[2]:
+ *   params   NULL for the defaults, else int32_t[3]:
  *            params[0] Morton tiles per apply slot (>= 1, default 4),
- *            params[1] nodes per lane of an update slot (>= 1, default 8).
+ *            params[1] nodes per lane of an update slot (>= 1, default 8),
+ *            params[2] launch index of the batch's first step (>= 1,
+ *                      default 1); a batch rebuilt over a changed set of
+ *                      handles continues the solves in flight when it starts
+ *                      at the old batch's pressure_batch_next_index.
  * Joining a batch sets each handle's launch grids to the batch's; single
  * pressure_solve calls on the handle then use the same grids, so a mesh's
  * batched result equals its single-mesh result bit for bit.  The handles
@@ -233,6 +237,25 @@ int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *p
 int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double *const *x0_dev, double rtol,
                          int32_t max_iter, double *const *p_dev, int32_t *iters, double *true_relres,
                          int32_t *status, void *stream);
+
+/* Continuous batching: solves start and finish independently while the
+ * batch steps.  pressure_batch_begin starts the solve of mesh m (0-based)
+ * at the next step (rhs_dev, x0_dev as in pressure_solve; the solve must not
+ * be in flight); pressure_batch_step advances every solve in flight by one
+ * chunk of iterations and writes done[m] (host, n entries: nonzero = mesh m
+ * idle or finished); pressure_batch_finish computes mesh m's true residual,
+ * writes its solution to p_dev and returns its status (mesh m must be
+ * finished; rhs_dev and rtol as passed to begin).  A solve's arithmetic does
+ * not depend on the step at which it starts or on the other solves in
+ * flight, so each result equals the same solve run alone, bit for bit. */
+int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
+                         int32_t max_iter, void *stream);
+int pressure_batch_step(pm_batch *b, int32_t *done, void *stream);
+int pressure_batch_finish(pm_batch *b, int32_t m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
+                          double *true_relres, void *stream);
+
+/* Launch index of the batch's next step (see pressure_batch_create). */
+int pressure_batch_next_index(pm_batch *b, int32_t *k);
 
 /* Number of CG iterations captured per graph replay (default 16, even, 2..256);
  * 0 disables graph capture (iterations are launched one by one). */

@@ -46,6 +46,10 @@ SIGNATURES = {
     "pressure_batch_create": (ctypes.c_int, [_P, _i32, _P, ctypes.POINTER(_P)]),
     "pressure_batch_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, _P, _P, _P, _P]),
     "pressure_batch_set_graph": (ctypes.c_int, [_P, _i32]),
+    "pressure_batch_next_index": (ctypes.c_int, [_P, ctypes.POINTER(_i32)]),
+    "pressure_batch_begin": (ctypes.c_int, [_P, _i32, _P, _P, _dbl, _i32, _P]),
+    "pressure_batch_step": (ctypes.c_int, [_P, _P, _P]),
+    "pressure_batch_finish": (ctypes.c_int, [_P, _i32, _P, _dbl, _P, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _P]),
     "pressure_batch_destroy": (None, [_P]),
 }
 

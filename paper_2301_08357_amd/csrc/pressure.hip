@@ -63,6 +63,8 @@ struct CGState {
     int32_t max_iter;
     int32_t done;
     int32_t status;
+    int32_t k_first; // launch index of this solve's first iteration (batched solves)
+    int32_t pad;
 };
 
 // ------------------------------------------------------------------ reductions
@@ -581,7 +583,7 @@ __global__ void __launch_bounds__(BLK) k_prepare(int N, const int *__restrict__ 
 
 // One block: ||rhs|| and the solver state.
 __global__ void __launch_bounds__(BLK) k_begin(CGState *st, const double *part, int n, double rtol,
-                                               int max_iter, double *hist)
+                                               int max_iter, double *hist, int k_first)
 {
     __shared__ double red[BLK / 64];
     const double bb = sum_partials(part, n, red);
@@ -595,6 +597,7 @@ __global__ void __launch_bounds__(BLK) k_begin(CGState *st, const double *part, 
         st->max_iter = max_iter;
         st->status = isfinite(bn) ? 0 : PM_EINVAL;
         st->done = (!isfinite(bn) || !(bn > 0.0)) ? 1 : 0;
+        st->k_first = k_first;
         if (!(bn > 0.0)) hist[0] = 0.0;
     }
 }
@@ -684,9 +687,11 @@ __global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMesh *__restrict
     const BatchMesh &M = meshes[ms.x];
     const int k = ctl->k_apply;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_update = k;
+    // buffers alternate with the launch index k; the solve's own iteration
+    // number counts from its first launch
     IterT<double> it;
-    it.k = k;
-    it.first = (k == 1) ? 1 : 0;
+    it.k = k - M.st->k_first + 1;
+    it.first = (it.k == 1) ? 1 : 0;
     it.r = M.r;
     it.p_old = (k & 1) ? M.p0 : M.p1;   // p_{k-1}
     it.p_new = (k & 1) ? M.p1 : M.p0;   // p_k
@@ -713,6 +718,11 @@ __global__ void __launch_bounds__(BLK) k_batch_update(const BatchMesh *__restric
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_apply = k + 1;
     update_body<double>(M.N, M.x, M.r, (k & 1) ? M.p1 : M.p0, M.q, M.st, M.part_pq, M.n_ab,
                         (k & 1) ? M.rr0 : M.rr1, (k & 1) ? M.rr1 : M.rr0, red, ms.y, M.n_vb);
+}
+
+__global__ void k_set_done(CGState *st)
+{
+    if (threadIdx.x == 0) st->done = 1;
 }
 
 // One block: number of finished meshes, and a copy of every state.
@@ -1341,6 +1351,8 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     TRY(ensure_hist(h, 1023));
     HIPCK(hipHostMalloc((void **)&h->hst, sizeof(CGState), hipHostMallocDefault));
     HIPCK(hipMemset(h->st, 0, sizeof(CGState)));
+    hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, 0, h->st);   // idle until a solve starts
+    HIPCK(hipGetLastError());
     HIPCK(hipMemset(h->part, 0, sizeof(double) * (AGRID_MAX + 3 * VGRID_MAX)));
     HIPCK(hipMemset(h->pbuf[0], 0, 8 * N));
     HIPCK(hipMemset(h->pbuf[1], 0, 8 * N));
@@ -1460,7 +1472,7 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
 
     hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                        h->part_misc());
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist, 1);
     HIPCK(hipGetLastError());
     TRY(launch_apply(h, h->x, h->q, nullptr, s));
     hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
@@ -1573,7 +1585,7 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
 
     hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                        h->part_misc());
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist, 1);
     HIPCK(hipGetLastError());
     TRY(read_state(h, s));
     int status = h->hst->status;
@@ -1696,6 +1708,7 @@ struct pm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_iters = 16;
+    int k_next = 1;          // launch index of the next batched iteration
 };
 
 namespace {
@@ -1765,10 +1778,12 @@ void batch_free(pm_batch *b)
 
 int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const int32_t *params)
 {
+    int k_start = 1;
     if (params) {
-        if (params[0] < 1 || params[1] < 1) return PM_EINVAL;
+        if (params[0] < 1 || params[1] < 1 || params[2] < 1) return PM_EINVAL;
         b->tiles_per_slot = params[0];
         b->nodes_per_lane = params[1];
+        k_start = params[2];
     }
     HIPCK(hipGetDevice(&b->device));
     int need_i = 1, need_s = 1;
@@ -1831,6 +1846,13 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     HIPCK(hipHostMalloc((void **)&b->h_states, sizeof(CGState) * n, hipHostMallocDefault));
     HIPCK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIPCK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+    // solves of the handles that are in flight continue at launch index k_start
+    b->k_next = k_start;
+    b->h_ctl->k_apply = k_start;
+    b->h_ctl->k_update = k_start - 1;
+    b->h_ctl->n_done = 0;
+    HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
+    HIPCK(hipStreamSynchronize(b->stream));
     return PM_OK;
 }
 
@@ -1894,6 +1916,136 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
     return batch_capture(b);
 }
 
+// Start the solve of mesh m at the batch's next launch index: gather rhs and
+// guess, ||rhs||, r0 = rhs - A x0 (partials into the buffer that launch reads).
+static int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const double *x0_dev, double rtol,
+                            int32_t max_iter, hipStream_t s)
+{
+    pm_handle *h = b->hs[m];
+    TRY(ensure_hist(h, max_iter));
+    const int N = int(h->N);
+    const unsigned vg = h->n_vblocks;
+    hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
+                       h->part_misc());
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist,
+                       b->k_next);
+    TRY(launch_apply(h, h->x, h->q, nullptr, s));
+    hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st,
+                       h->part_rr((b->k_next - 1) & 1));
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+// The histories may have been reallocated (ensure_hist): refresh descriptors.
+static int batch_refresh(pm_batch *b, hipStream_t s)
+{
+    const int n = int(b->hs.size());
+    std::vector<BatchMesh> meshes(n);
+    HIPCK(hipMemcpyAsync(meshes.data(), b->d_meshes, sizeof(BatchMesh) * n, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    bool moved = false;
+    for (int m = 0; m < n; ++m)
+        if (meshes[m].hist != b->hs[m]->hist) {
+            meshes[m].hist = b->hs[m]->hist;
+            moved = true;
+        }
+    if (moved) {
+        HIPCK(hipMemcpyAsync(b->d_meshes, meshes.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice, s));
+        HIPCK(hipStreamSynchronize(s));
+    }
+    return PM_OK;
+}
+
+// Advance every solve in flight by one chunk; returns the number of meshes
+// that are idle or finished and copies the states to b->h_states.
+static int batch_step_impl(pm_batch *b, int *n_done, hipStream_t s)
+{
+    const int n = int(b->hs.size());
+    int its = 0;
+    if (b->gexec) {
+        HIPCK(hipGraphLaunch(b->gexec, s));
+        its = b->graph_iters;
+    } else {
+        its = 8;
+        TRY(launch_batch_iterations(b, its, s));
+    }
+    b->k_next += its;
+    hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BLK), 0, s, b->d_meshes, n, b->d_ctl, b->d_states);
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(b->h_states, b->d_states, sizeof(CGState) * n, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    *n_done = b->h_ctl->n_done;
+    return PM_OK;
+}
+
+// True residual and output of a finished mesh; residual replacement (as in
+// pressure_solve) when the recursive residual met rtol but the true one did not.
+static int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
+                             double *true_relres, hipStream_t s)
+{
+    pm_handle *h = b->hs[m];
+    const int N = int(h->N);
+    const unsigned vg = h->n_vblocks;
+    TRY(launch_apply(h, h->x, h->q, nullptr, s));
+    hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
+    hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
+    hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
+    HIPCK(hipGetLastError());
+    TRY(read_state(h, s));
+    const CGState st = *h->hst;
+    *iters = st.iter;
+    const double rel = (st.bnorm > 0.0) ? std::sqrt(st.tt) / st.bnorm : 0.0;
+    *true_relres = rel;
+    int code = st.status;
+    if (code == 0 && !(rel <= rtol)) {
+        if (st.iter >= st.max_iter) return PM_NOT_CONVERGED;
+        int32_t more = 0;
+        double rel2 = rel;
+        code = pressure_solve(h, rhs_dev, p_dev, rtol, std::max(0, st.max_iter - st.iter), p_dev, &more, nullptr,
+                              &rel2, (void *)s);
+        *iters += more;
+        *true_relres = rel2;
+        // the handle is idle again for the batch
+        hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, s, h->st);
+        HIPCK(hipGetLastError());
+    }
+    return code;
+}
+
+int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
+                         int32_t max_iter, void *stream)
+{
+    if (!b || m < 0 || m >= int(b->hs.size()) || !rhs_dev || !(rtol > 0.0) || !std::isfinite(rtol) || max_iter < 0)
+        return PM_EINVAL;
+    hipStream_t us = (hipStream_t)stream, s = b->stream;
+    HIPCK(hipEventRecord(b->ev, us));
+    HIPCK(hipStreamWaitEvent(s, b->ev, 0));
+    TRY(batch_begin_impl(b, m, rhs_dev, x0_dev, rtol, max_iter, s));
+    return batch_refresh(b, s);
+}
+
+int pressure_batch_step(pm_batch *b, int32_t *done, void *stream)
+{
+    if (!b || !done) return PM_EINVAL;
+    (void)stream;
+    int n_done = 0;
+    TRY(batch_step_impl(b, &n_done, b->stream));
+    for (size_t m = 0; m < b->hs.size(); ++m) done[m] = b->h_states[m].done;
+    return PM_OK;
+}
+
+int pressure_batch_finish(pm_batch *b, int32_t m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
+                          double *true_relres, void *stream)
+{
+    if (!b || m < 0 || m >= int(b->hs.size()) || !rhs_dev || !p_dev || !iters || !true_relres) return PM_EINVAL;
+    hipStream_t us = (hipStream_t)stream, s = b->stream;
+    const int code = batch_finish_impl(b, m, rhs_dev, rtol, p_dev, iters, true_relres, s);
+    HIPCK(hipEventRecord(b->ev, s));
+    HIPCK(hipStreamWaitEvent(us, b->ev, 0));
+    return code;
+}
+
 int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double *const *x0_dev, double rtol,
                          int32_t max_iter, double *const *p_dev, int32_t *iters, double *true_relres,
                          int32_t *status, void *stream)
@@ -1907,86 +2059,19 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
     hipStream_t us = (hipStream_t)stream, s = b->stream;
     HIPCK(hipEventRecord(b->ev, us));
     HIPCK(hipStreamWaitEvent(s, b->ev, 0));
-    // start every mesh: rhs, guess, ||rhs||, r0 = b - A x0
-    for (int m = 0; m < n; ++m) {
-        pm_handle *h = b->hs[m];
-        TRY(ensure_hist(h, max_iter));
-        const int N = int(h->N);
-        const unsigned vg = h->n_vblocks;
-        hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev[m],
-                           x0_dev ? x0_dev[m] : nullptr, h->b, h->x, h->part_misc());
-        hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist);
-        TRY(launch_apply(h, h->x, h->q, nullptr, s));
-        hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
-    }
-    HIPCK(hipGetLastError());
-    // the histories may have moved (ensure_hist): refresh the descriptors
-    {
-        bool moved = false;
-        std::vector<BatchMesh> meshes(n);
-        HIPCK(hipMemcpyAsync(meshes.data(), b->d_meshes, sizeof(BatchMesh) * n, hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        for (int m = 0; m < n; ++m)
-            if (meshes[m].hist != b->hs[m]->hist) {
-                meshes[m].hist = b->hs[m]->hist;
-                moved = true;
-            }
-        if (moved) {
-            HIPCK(hipMemcpyAsync(b->d_meshes, meshes.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice, s));
-            HIPCK(hipStreamSynchronize(s));
-        }
-    }
-    b->h_ctl->k_apply = 1;
-    b->h_ctl->k_update = 0;
-    b->h_ctl->n_done = 0;
-    HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s));
-    // iterations until every mesh is done (each stops by itself at max_iter)
-    int64_t launched = 0;
+    for (int m = 0; m < n; ++m) TRY(batch_begin_impl(b, m, rhs_dev[m], x0_dev ? x0_dev[m] : nullptr, rtol, max_iter, s));
+    TRY(batch_refresh(b, s));
+    // every solve stops by itself at max_iter, so this loop is bounded
+    const int64_t k_limit = int64_t(b->k_next) + max_iter + 2 * std::max(b->graph_iters, 8) + 2;
     for (;;) {
-        if (b->gexec) {
-            HIPCK(hipGraphLaunch(b->gexec, s));
-            launched += b->graph_iters;
-        } else {
-            TRY(launch_batch_iterations(b, 8, s));
-            launched += 8;
-        }
-        hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BLK), 0, s, b->d_meshes, n, b->d_ctl, b->d_states);
-        HIPCK(hipGetLastError());
-        HIPCK(hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        if (b->h_ctl->n_done >= n) break;
-        if (launched > int64_t(max_iter) + 2 * b->graph_iters + 16) return PM_EHIP;   // cannot happen: every mesh stops at max_iter
+        int n_done = 0;
+        TRY(batch_step_impl(b, &n_done, s));
+        if (n_done >= n) break;
+        if (b->k_next > k_limit) return PM_EHIP;
     }
-    // true residuals and outputs
-    for (int m = 0; m < n; ++m) {
-        pm_handle *h = b->hs[m];
-        const int N = int(h->N);
-        const unsigned vg = h->n_vblocks;
-        TRY(launch_apply(h, h->x, h->q, nullptr, s));
-        hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
-        hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
-        hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev[m]);
-    }
-    hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BLK), 0, s, b->d_meshes, n, b->d_ctl, b->d_states);
-    HIPCK(hipGetLastError());
-    HIPCK(hipMemcpyAsync(b->h_states, b->d_states, sizeof(CGState) * n, hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
     int worst = PM_OK;
     for (int m = 0; m < n; ++m) {
-        const CGState &st = b->h_states[m];
-        iters[m] = st.iter;
-        const double rel = (st.bnorm > 0.0) ? std::sqrt(st.tt) / st.bnorm : 0.0;
-        true_relres[m] = rel;
-        int code = st.status;
-        if (code == 0 && !(rel <= rtol)) {
-            // residual replacement, as pressure_solve does: continue from the iterate
-            int32_t more = 0;
-            double rel2 = rel;
-            code = pressure_solve(b->hs[m], rhs_dev[m], p_dev[m], rtol, std::max(0, max_iter - st.iter), p_dev[m],
-                                  &more, nullptr, &rel2, (void *)s);
-            iters[m] += more;
-            true_relres[m] = rel2;
-        }
+        const int code = batch_finish_impl(b, m, rhs_dev[m], rtol, p_dev[m], &iters[m], &true_relres[m], s);
         status[m] = code;
         if (code < 0 && worst >= 0) worst = code;
         else if (code == PM_NOT_CONVERGED && worst == PM_OK) worst = code;
@@ -1998,3 +2083,10 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
 }
 
 }  // extern "C"
+
+extern "C" int pressure_batch_next_index(pm_batch *b, int32_t *k)
+{
+    if (!b || !k) return PM_EINVAL;
+    *k = b->k_next;
+    return PM_OK;
+}

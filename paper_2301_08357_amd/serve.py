@@ -1,0 +1,197 @@
+"""Continuous-batching server for pressure solves on a pool of meshes.
+
+Requests (mesh, right-hand side) arrive over time.  The server keeps a set
+of meshes resident on the GPU within an HBM budget (each mesh's operator
+data, CG vectors and its last solution, sized by pressure_footprint),
+evicting the least recently used idle mesh when a new one must be loaded.
+Admitted requests join the running batch at the next step, so solves of
+different meshes overlap on the device; a mesh serves one request at a time
+because each request starts from that mesh's previous solution (the warm
+start of the paper's projection stage, Sec. 3.4).  A solve's result does not
+depend on when it joined or on the other solves in flight.
+
+The heavy lifting (setup, batched CG steps, residuals) happens in
+libpressure.so; this module only schedules calls.
+"""
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .system import PressureBatch, PressureSystem, footprint
+
+
+@dataclass
+class Request:
+    rid: int
+    mesh: int
+    arrival: float                  # seconds after the start of the run
+    rhs: object = None              # device tensor (filled at admission)
+    x0: object = None               # device tensor of the warm start, or None (cold)
+    start: float = -1.0
+    done: float = -1.0
+    iters: int = 0
+    status: int = 0
+    true_relres: float = 0.0
+    result: object = None
+    cold: bool = True
+
+
+@dataclass
+class ServeStats:
+    n: int = 0
+    makespan_s: float = 0.0
+    solves_per_s: float = 0.0
+    latency_ms: dict = field(default_factory=dict)
+    mean_iters_cold: float = 0.0
+    mean_iters_warm: float = 0.0
+    loads: int = 0
+    evictions: int = 0
+    rebuilds: int = 0
+    steps: int = 0
+    max_in_flight_seen: int = 0
+
+
+class PressureServer:
+    """problems: list of synth Problem (mesh id = index).  rhs_fn(req) must
+    return the request's right-hand side as a float64 CUDA tensor."""
+
+    def __init__(self, problems, budget_bytes, max_in_flight=64, rtol=1e-10, max_iter=20000,
+                 graph_iters=16, tiles_per_slot=4, nodes_per_lane=8, keep_x0=False):
+        self.problems = problems
+        self.budget = int(budget_bytes)
+        self.max_in_flight = int(max_in_flight)
+        self.rtol = rtol
+        self.max_iter = max_iter
+        self.graph_iters = graph_iters
+        self.tps = tiles_per_slot
+        self.npl = nodes_per_lane
+        self.keep_x0 = keep_x0
+        self.cost = [footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems) + 8 * p.mesh.n_nodes for p in problems]
+        self.resident = collections.OrderedDict()     # mesh -> PressureSystem, least recent first
+        self.last = {}                                # mesh -> last solution (device)
+        self.batch = None
+        self.members = []                             # mesh ids in batch order
+        self.dirty = False                            # resident set differs from the batch's
+        self.batch_next = 1                           # launch index carried over rebuilds
+        self.stats = ServeStats()
+
+    # -- residency ---------------------------------------------------------
+    def _used(self):
+        return sum(self.cost[m] for m in self.resident)
+
+    def _make_room(self, m, busy):
+        """Evict idle meshes (least recently used first) until mesh m fits."""
+        if self.cost[m] > self.budget:
+            raise ValueError("mesh %d needs %d bytes, more than the budget" % (m, self.cost[m]))
+        while self._used() + self.cost[m] > self.budget:
+            victim = next((v for v in self.resident if v not in busy), None)
+            if victim is None:
+                return False
+            # the batch must not step over a closed handle: drop it now and
+            # rebuild before the next step
+            if self.batch is not None:
+                self.batch_next = self.batch.next_index()
+                self.batch.close()
+                self.batch = None
+            self.resident.pop(victim).close()
+            self.last.pop(victim, None)
+            self.stats.evictions += 1
+            self.dirty = True
+        return True
+
+    def _load(self, m):
+        p = self.problems[m]
+        self.resident[m] = PressureSystem.from_problem(p)
+        self.stats.loads += 1
+
+    def _rebuild(self):
+        first = self.batch.next_index() if self.batch is not None else self.batch_next
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
+        self.batch_next = first
+        self.members = list(self.resident.keys())
+        self.dirty = False
+        if self.members:
+            self.batch = PressureBatch([self.resident[m] for m in self.members], self.tps, self.npl, first)
+            self.batch.set_graph(self.graph_iters)
+            self.stats.rebuilds += 1
+
+    # -- run ---------------------------------------------------------------
+    def run(self, requests, rhs_fn, clock=time.perf_counter):
+        """Serve the requests (sorted by arrival).  Returns the list of
+        finished requests and fills self.stats."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queues = collections.defaultdict(collections.deque)
+        in_flight = {}                     # mesh -> Request
+        finished = []
+        t0 = clock()
+        while pending or in_flight or any(queues.values()):
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                queues[r.mesh].append(r)
+            # admission: oldest waiting request first, one per mesh
+            waiting = sorted((q[0] for m, q in queues.items() if q and m not in in_flight), key=lambda r: r.arrival)
+            admit, changed = [], False
+            for r in waiting:
+                if len(in_flight) + len(admit) >= self.max_in_flight:
+                    break
+                if r.mesh not in self.resident:
+                    busy = set(in_flight) | {a.mesh for a in admit}
+                    if not self._make_room(r.mesh, busy):
+                        continue
+                    self._load(r.mesh)
+                    changed = True
+                admit.append(r)
+            if changed or self.dirty or (admit and self.batch is None):
+                self._rebuild()
+            for r in admit:
+                queues[r.mesh].popleft()
+                self.resident.move_to_end(r.mesh)
+                r.rhs = rhs_fn(r)
+                r.x0 = self.last.get(r.mesh)
+                r.cold = r.x0 is None
+                if self.keep_x0 and r.x0 is not None:
+                    r.x0 = r.x0.clone()
+                r.start = clock() - t0
+                self.batch.begin(self.members.index(r.mesh), r.rhs, r.x0, self.rtol, self.max_iter)
+                in_flight[r.mesh] = r
+            self.stats.max_in_flight_seen = max(self.stats.max_in_flight_seen, len(in_flight))
+            if in_flight:
+                done = self.batch.step()
+                self.stats.steps += 1
+                for m in [m for m in in_flight if done[self.members.index(m)]]:
+                    r = in_flight.pop(m)
+                    res = self.batch.finish(self.members.index(m), r.rhs, self.rtol)
+                    r.done = clock() - t0
+                    r.iters, r.status, r.true_relres, r.result = res.iters, res.status, res.true_relres, res.p
+                    self.last[m] = res.p
+                    finished.append(r)
+            elif pending:
+                time.sleep(max(0.0, min(1e-3, pending[0].arrival - (clock() - t0))))
+        st = self.stats
+        st.n = len(finished)
+        st.makespan_s = max(r.done for r in finished) if finished else 0.0
+        st.solves_per_s = st.n / st.makespan_s if st.makespan_s > 0 else 0.0
+        lat = np.array([r.done - r.arrival for r in finished]) * 1e3
+        if lat.size:
+            st.latency_ms = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "mean": float(lat.mean()), "max": float(lat.max())}
+        cold = [r.iters for r in finished if r.cold]
+        warm = [r.iters for r in finished if not r.cold]
+        st.mean_iters_cold = float(np.mean(cold)) if cold else 0.0
+        st.mean_iters_warm = float(np.mean(warm)) if warm else 0.0
+        return finished
+
+    def close(self):
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
+        for s in self.resident.values():
+            s.close()
+        self.resident.clear()
+        self.last.clear()

@@ -198,11 +198,11 @@ class PressureBatch:
     grids to the batch's, so single solves on those systems reproduce the
     batched results bit for bit."""
 
-    def __init__(self, systems, tiles_per_slot=4, nodes_per_lane=8):
+    def __init__(self, systems, tiles_per_slot=4, nodes_per_lane=8, first_index=1):
         self.systems = list(systems)
         n = len(self.systems)
         hs = (ctypes.c_void_p * n)(*[s._h.value for s in self.systems])
-        params = (ctypes.c_int32 * 2)(int(tiles_per_slot), int(nodes_per_lane))
+        params = (ctypes.c_int32 * 3)(int(tiles_per_slot), int(nodes_per_lane), int(first_index))
         b = ctypes.c_void_p(None)
         check(load().pressure_batch_create(hs, n, params, ctypes.byref(b)), "pressure_batch_create")
         self._b = b
@@ -242,3 +242,35 @@ class PressureBatch:
         check(code, "pressure_batch_solve")
         res = [SolveResult(out[m], int(st[m]), int(its[m]), None, float(rel[m])) for m in range(n)]
         return code, res
+
+    # -- continuous batching -------------------------------------------------
+    def next_index(self):
+        k = ctypes.c_int32(0)
+        check(load().pressure_batch_next_index(self._b, ctypes.byref(k)), "pressure_batch_next_index")
+        return k.value
+
+    def begin(self, m, rhs, x0=None, rtol=1e-10, max_iter=20000, stream=None):
+        s = self.systems[m]
+        check(load().pressure_batch_begin(self._b, int(m), _dev_ptr(rhs, s.n_nodes, "rhs"),
+                                          None if x0 is None else _dev_ptr(x0, s.n_nodes, "x0"),
+                                          float(rtol), int(max_iter), _stream_handle(stream)), "pressure_batch_begin")
+
+    def step(self, stream=None):
+        """One chunk of iterations for every solve in flight; returns the
+        done flags (numpy bool array, True = idle or finished)."""
+        done = np.zeros(len(self.systems), dtype=np.int32)
+        check(load().pressure_batch_step(self._b, _ptr(done), _stream_handle(stream)), "pressure_batch_step")
+        return done != 0
+
+    def finish(self, m, rhs, rtol=1e-10, out=None, stream=None):
+        import torch
+        s = self.systems[m]
+        if out is None:
+            out = torch.empty_like(rhs)
+        it = ctypes.c_int32(0)
+        tr = ctypes.c_double(0.0)
+        code = load().pressure_batch_finish(self._b, int(m), _dev_ptr(rhs, s.n_nodes, "rhs"), float(rtol),
+                                            _dev_ptr(out, s.n_nodes, "p"), ctypes.byref(it), ctypes.byref(tr),
+                                            _stream_handle(stream))
+        check(code, "pressure_batch_finish")
+        return SolveResult(out, code, it.value, None, tr.value)
