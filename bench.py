@@ -26,6 +26,20 @@ if ROOT not in sys.path:
 
 METRIC = "pressure-solve GDOF·iter/s + % HBM peak; solves/s & p50/p99 latency at rtol 1e-10"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_cube64_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2301_08357_amd", "csrc", "pressure.hip")
+
+
+def measured_traffic():
+    """HBM bytes per apply launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE measurement, if it was taken on the current kernel source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec.get("traffic_bytes_per_launch") if rec.get("source_sha256") == sha else None
 
 
 def main():
@@ -39,6 +53,10 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="Morton tile nodes (128/256/512; 0 = library default)")
     ap.add_argument("--inner-rtol", type=float, default=1e-4, help="inner tolerance of the mixed solve")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--workload", default="cube64", choices=["cube64", "cube160", "batch256", "serve", "copy"],
+                    help="cube64 (default line) or one of the other synthetic workloads")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
+    ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -49,6 +67,14 @@ def main():
     import paper_2301_08357_amd as pm
     from synth import workloads
 
+    if args.workload == "cube160":
+        return bench_cube160(args)
+    if args.workload == "batch256":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     dev = torch.device("cuda:0")
     ws = workloads.CUBE64_W
     probs = [workloads.cube64(w) for w in ws]
@@ -127,7 +153,7 @@ def main():
         "rel_error_vs_manufactured": err,
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
             "kernel": "operator apply (fused CG iteration)",
             "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg_ms * 1e3, 3),
             "launches": launches,
@@ -140,6 +166,164 @@ def main():
     print(json.dumps(out), flush=True)
     for s in systems:
         s.close()
+
+
+def _common(args, metric_value, unit, ms_per_step, config, extra):
+    out = {"metric": METRIC, "value": metric_value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_cube160(args):
+    """160^3 x 6 tets, jitter 0.2h, rho lognormal(0, 0.5), w = 1e-4: FP64 CG
+    and FP32-inner defect correction, both to rtol 1e-10."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from synth import workloads
+    prob = workloads.cube160()
+    tile_flag = {0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
+    s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER | tile_flag)
+    info = s.info()
+    xs = torch.tensor(prob.extra["xstar"], device="cuda")
+    b = s.apply(xs)
+    for _ in range(args.warmup):
+        s.solve(b, rtol=args.rtol)
+    s.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        r = s.solve(b, rtol=args.rtol)
+        its.append(r.iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n, ms = s.timing_read()
+    avg = ms / max(n, 1)
+    achieved = info["apply_bytes"] / (avg * 1e-3) / 1e9
+    value = info["n_free"] * sum(its) / el / 1e9
+    mixed = None if args.no_mixed else mixed_comparison([s], [b], xs, args, el / args.steps)
+    err = float(torch.linalg.norm(r.p - xs) / torch.linalg.norm(xs))
+    _common(args, round(value, 4), "GDOF*iter/s", round(el / args.steps * 1e3, 3),
+            {"workload": "cube160: unit cube 160^3 x 6 tets (24,576,000 tets, 4,173,281 nodes), jitter 0.2h, "
+                         "rho~lognormal(0,0.5), w=1e-4, FP64 CG to rtol %g; one step = one solve" % args.rtol,
+             "n_free": info["n_free"], "iterations": its[0]},
+            {"solves_per_s": round(args.steps / el, 3), "rel_error_vs_manufactured": err,
+             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                          "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg * 1e3, 3)},
+             "mixed": mixed})
+    s.close()
+
+
+def bench_copy(args):
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 2 ** 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"workload": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
+                      "GB_per_s": round(16 * n / el / 1e9, 1)}), flush=True)
+
+
+def _batch_problems(n):
+    from synth import workloads
+    params = workloads.batch_params(n)
+    return [workloads.batch_problem(i, params) for i in range(n)]
+
+
+def bench_batch(args):
+    """256 meshes (2D and 3D), nodes log-uniform in [2e3, 2e5], w log-uniform
+    in [1e-6, 1]: one batched FP64 solve of all of them per step."""
+    import torch
+    import paper_2301_08357_amd as pm
+    probs = _batch_problems(256)
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    rhs = [s.apply(torch.tensor(p.extra["xstar"], device="cuda")) for s, p in zip(systems, probs)]
+    batch = pm.PressureBatch(systems, tiles_per_slot=8, nodes_per_lane=8)
+    nfree = np.array([int((p.mesh.dirichlet == 0).sum()) for p in probs])
+    for _ in range(args.warmup):
+        batch.solve(rhs, rtol=args.rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dofit = 0.0
+    for _ in range(args.steps):
+        code, res = batch.solve(rhs, rtol=args.rtol)
+        if code != 0:
+            raise RuntimeError("batch status %d" % code)
+        dofit += float((nfree * np.array([r.iters for r in res])).sum())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    its = np.array([r.iters for r in res])
+    _common(args, round(dofit / el / 1e9, 4), "GDOF*iter/s", round(el / args.steps * 1e3, 3),
+            {"workload": "batch256: 256 meshes (129 2D, 127 3D), nodes log-uniform [2e3,2e5] (10.9M total), "
+                         "w log-uniform [1e-6,1], jitter 0.2h, rho~U[0.5,2], FP64 CG to rtol %g; one step = one "
+                         "batched solve of all meshes" % args.rtol,
+             "n_nodes_total": int(sum(p.mesh.n_nodes for p in probs))},
+            {"solves_per_s": round(256 * args.steps / el, 2), "iterations_max": int(its.max()),
+             "iterations_mean": float(its.mean()), "graph_iterations_per_replay": 16})
+    batch.close()
+    for s in systems:
+        s.close()
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals over the 256-mesh pool (uniform mesh choice),
+    each request warm-started from its mesh's previous solution with the rhs
+    perturbed by 1 % (normal noise scaled to ||rhs|| / sqrt(N_free)).  The rate
+    is 0.8 x the saturated rate measured in a closed-loop pass."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from paper_2301_08357_amd.serve import PressureServer, Request
+    from synth import fields, workloads
+    probs = _batch_problems(256)
+    base = []
+    for p in probs:
+        s = pm.PressureSystem.from_problem(p)
+        base.append(s.apply(torch.tensor(p.extra["xstar"], device="cuda")).clone())
+        s.close()
+    free = [torch.tensor((p.mesh.dirichlet == 0).astype(np.float64), device="cuda") for p in probs]
+    scale = [0.01 * float(torch.linalg.norm(b)) / float(f.sum()) ** 0.5 for b, f in zip(base, free)]
+
+    def rhs_fn(req):
+        xi = torch.tensor(fields.perturbation(workloads.MASTER_SEED, req.rid, probs[req.mesh].mesh.n_nodes),
+                          device="cuda")
+        return base[req.mesh] + scale[req.mesh] * free[req.mesh] * xi
+
+    budget = int(args.budget_gb * 2 ** 30) if args.budget_gb > 0 else int(0.8 * torch.cuda.mem_get_info()[0])
+    # closed loop: saturation rate
+    n_cal = min(2000, args.requests)
+    _, choice = workloads.arrivals(n_cal, 1.0, 256)
+    srv = PressureServer(probs, budget, max_in_flight=256, rtol=args.rtol, tiles_per_slot=8, nodes_per_lane=8)
+    srv.run([Request(rid=10 ** 6 + i, mesh=int(m), arrival=0.0) for i, m in enumerate(choice)], rhs_fn)
+    sat = srv.stats.solves_per_s
+    srv.close()
+    rate = 0.8 * sat
+    times, choice = workloads.arrivals(args.requests, rate, 256)
+    srv = PressureServer(probs, budget, max_in_flight=256, rtol=args.rtol, tiles_per_slot=8, nodes_per_lane=8)
+    done = srv.run([Request(rid=i, mesh=int(m), arrival=float(t)) for i, (t, m) in enumerate(zip(times, choice))],
+                   rhs_fn)
+    st = srv.stats
+    bad = sum(1 for r in done if r.status != 0 or r.true_relres > args.rtol)
+    srv.close()
+    _common(args, round(st.solves_per_s, 3), "solves/s", round(st.makespan_s * 1e3, 3),
+            {"workload": "serve: %d requests, Poisson arrivals at 0.8 x saturation over the 256-mesh pool, warm "
+                         "starts, 1%% rhs perturbation, rtol %g" % (args.requests, args.rtol),
+             "rate_per_s": round(rate, 2), "saturation_solves_per_s": round(sat, 2), "budget_bytes": budget},
+            {"latency_ms_p50": round(st.latency_ms["p50"], 3), "latency_ms_p99": round(st.latency_ms["p99"], 3),
+             "mean_iterations_cold": round(st.mean_iters_cold, 1), "mean_iterations_warm": round(st.mean_iters_warm, 1),
+             "loads": st.loads, "evictions": st.evictions, "batch_rebuilds": st.rebuilds,
+             "max_in_flight": st.max_in_flight_seen, "failed": bad})
 
 
 def mixed_comparison(systems, rhs, xstar, args, fp64_solve_s):

@@ -35,6 +35,7 @@
 // p alternates between two buffers, so no kernel overwrites data that another
 // block of the same kernel still reads.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -993,6 +994,10 @@ size_t tiled_lds_bytes(const pm_handle *h)
            2 * size_t(h->tile_nodes);
 }
 
+// Events of the next apply launch to time (start and stop are recorded by
+// the command processor at the kernel's begin and end), or null.
+thread_local hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
+
 template <class R, class K>
 int launch_tiled_k(pm_handle *h, K kern, const MeshT<R> &g, const TileArgsT<R> &ta, const R *x, R *y,
                    const IterT<R> &it, hipStream_t s)
@@ -1000,7 +1005,13 @@ int launch_tiled_k(pm_handle *h, K kern, const MeshT<R> &g, const TileArgsT<R> &
     const size_t lds = tiled_lds_bytes<R>(h);
     if (lds > 65536) HIPCK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     const int grid = (sizeof(R) == 8) ? h->n_ablocks : h->n_ablocks32;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLK), lds, s, g, ta, x, y, it);
+    if (g_time_start) {
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BLK), uint32_t(lds), s, g_time_start, g_time_stop, 0u, g, ta, x,
+                              y, it);
+        g_time_start = g_time_stop = nullptr;
+    } else {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLK), lds, s, g, ta, x, y, it);
+    }
     HIPCK(hipGetLastError());
     return PM_OK;
 }
@@ -1433,17 +1444,15 @@ static int launch_iterations(pm_handle *h, int k0, int count, bool first, size_t
         it.rr_cur = h->part_rr((k - 1) & 1);
         it.rr_prev = h->part_rr(k & 1);
         it.n_vblocks = h->n_vblocks;
-        const bool sample = h->timing && (k % TIMING_STRIDE) == 1;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const bool sample = h->timing && (k % TIMING_STRIDE) == 1 && h->variant != PM_VARIANT_NODE;
         if (sample) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             TRY(event_pair(h, *timed, &e0, &e1));
-            HIPCK(hipEventRecord(e0, s));
-        }
-        TRY(launch_apply(h, it.p_new, h->q, &it, s));
-        if (sample) {
-            HIPCK(hipEventRecord(e1, s));
+            g_time_start = e0;
+            g_time_stop = e1;
             ++*timed;
         }
+        TRY(launch_apply(h, it.p_new, h->q, &it, s));
         hipLaunchKernelGGL(k_update<double>, dim3(h->n_vblocks), dim3(BLK), 0, s, N, h->x, h->r, h->pbuf[k & 1], h->q,
                            h->st, h->part_pq(), h->n_ablocks, h->part_rr((k - 1) & 1), h->n_vblocks,
                            h->part_rr(k & 1));
