@@ -264,6 +264,38 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay);
 /* Release the batch (not its handles).  NULL is ignored. */
 void pressure_batch_destroy(pm_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Autotuners.  Each times short runs of the real CG iterations on the
+ * caller's own operators (right-hand side of ones; a tolerance no run can
+ * meet, so every candidate runs the same iterations) and returns the
+ * fastest candidate with its time per iteration.  cache_path (NULL = no
+ * cache) names a text file of earlier choices, one line each, keyed by a
+ * 64-bit hash of the tuner, the device (architecture name and compute-unit
+ * count), the library build and the mesh sizes: a key that is present is
+ * returned at once (with the time recorded for it); a new choice is
+ * appended.  Errors: PM_EINVAL (arguments), PM_ENOMEM, PM_EHIP, and those of
+ * the calls the tuner makes.
+ */
+
+/* Launch shape of a batch over n handles: Morton tiles per apply slot in
+ * {1, 2, 4, 8} and nodes per lane of an update slot in {2, 4, 8, 16}, each
+ * candidate timed over `iters` iterations (rounded up to whole 16-iteration
+ * graph replays) of a batched solve of all n meshes.  params_out[0..1] take
+ * the choice (params[0..1] of pressure_batch_create).  The runs overwrite
+ * the handles' solver state and set their launch grids as
+ * pressure_batch_create does; create the batch afterwards. */
+int pressure_batch_tune(pm_handle *const *handles, int32_t n, int32_t iters, const char *cache_path,
+                        int32_t *params_out, double *ms_per_iter);
+
+/* Morton tile size of one mesh: the mesh is set up with each of
+ * PM_TILE_128, PM_TILE_256 and PM_TILE_512 (sizes whose tables do not fit
+ * the kernel are skipped) and `iters` CG iterations of each are timed.
+ * *flags_out receives `flags` with the fastest PM_TILE_* bits.  Arguments as
+ * pressure_setup; the key hashes dim, n_nodes, n_elems and the precision
+ * flags. */
+int pressure_tune_tile(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt, int32_t flags,
+                       int32_t iters, const char *cache_path, int32_t *flags_out, double *ms_per_iter);
+
 #ifdef __cplusplus
 }
 #endif

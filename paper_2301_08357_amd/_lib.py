@@ -51,6 +51,9 @@ SIGNATURES = {
     "pressure_batch_step": (ctypes.c_int, [_P, _P, _P]),
     "pressure_batch_finish": (ctypes.c_int, [_P, _i32, _P, _dbl, _P, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _P]),
     "pressure_batch_destroy": (None, [_P]),
+    "pressure_batch_tune": (ctypes.c_int, [_P, _i32, _i32, ctypes.c_char_p, _P, ctypes.POINTER(_dbl)]),
+    "pressure_tune_tile": (ctypes.c_int, [_PMESH, _P, _dbl, _dbl, _i32, _i32, ctypes.c_char_p,
+                                          ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]),
 }
 
 _lib = None

@@ -9,10 +9,10 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUTDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUTDIR, "libpressure.so")
 
-SOURCES = ["pressure.hip", "layout.cpp"]
+SOURCES = ["pressure.hip", "layout.cpp", "tune.cpp"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",

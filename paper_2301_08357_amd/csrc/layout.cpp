@@ -190,16 +190,16 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
     T->inst_off.assign(nt + 1, 0);
     T->halo.clear();
     T->inst_elem.clear();
-    T->inst_conn.clear();
-    T->inst_row.clear();
+    T->inst.clear();
     T->inst_elem.reserve(size_t(E) * 3 / 2 + 16);
-    T->inst_conn.reserve(size_t(E) * 6 + 64);
-    T->inst_row.reserve(size_t(E) * 6 + 64);
+    T->inst.reserve(size_t(E) * 6 + 64);
+    T->lvb = (tile_nodes <= 256) ? 10 : 11;
+    const int max_rows = 1 << (16 - T->lvb), max_local = 1 << T->lvb;
     T->max_inst = 0;
     T->max_halo = 0;
     T->max_deg = 0;
     for (int64_t i = 0; i < N; ++i) T->max_deg = std::max<int>(T->max_deg, L.n2e_off[i + 1] - L.n2e_off[i]);
-    if (T->max_deg > 254) return PM_EINVAL;
+    if (T->max_deg > max_rows) return TILES_TOO_WIDE;
 
     // first element whose smallest vertex is >= v (elements are sorted by it)
     std::vector<int32_t> ebeg(N + 1, 0);
@@ -235,7 +235,7 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
         for (int32_t e = own0; e < own1; ++e) add_halo(e);
         std::sort(halo_nd.begin(), halo_nd.end());
         halo_nd.erase(std::unique(halo_nd.begin(), halo_nd.end()), halo_nd.end());
-        if (int64_t(tile_nodes) + int64_t(halo_nd.size()) >= 65536) return PM_EINVAL;
+        if (int64_t(tile_nodes) + int64_t(halo_nd.size()) > max_local) return TILES_TOO_WIDE;
         T->halo.insert(T->halo.end(), halo_nd.begin(), halo_nd.end());
         T->halo_off[t + 1] = int32_t(T->halo.size());
         T->max_halo = std::max<int>(T->max_halo, int(halo_nd.size()));
@@ -246,10 +246,7 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
         const size_t base = T->inst_elem.size();
         auto add_inst = [&](int32_t e) {
             T->inst_elem.push_back(e);
-            for (int a = 0; a < 4; ++a) {
-                T->inst_conn.push_back(a < nv ? local(L.conn[e * 4 + a]) : uint16_t(0));
-                T->inst_row.push_back(0xFF);
-            }
+            for (int a = 0; a < 4; ++a) T->inst.push_back(a < nv ? local(L.conn[e * 4 + a]) : uint16_t(0));
         };
         for (int32_t e : halo_el) add_inst(e);
         for (int32_t e = own0; e < own1; ++e) add_inst(e);
@@ -261,7 +258,7 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
                 int32_t e = L.n2e_ent[k] >> 2, a = L.n2e_ent[k] & 3;
                 int32_t li = (e >= own0) ? int32_t(halo_el.size()) + (e - own0)
                                          : int32_t(std::lower_bound(halo_el.begin(), halo_el.end(), e) - halo_el.begin());
-                T->inst_row[(base + li) * 4 + a] = uint8_t(row);
+                T->inst[(base + li) * 4 + a] |= uint16_t(row << T->lvb);
             }
         }
         T->inst_off[t + 1] = int32_t(T->inst_elem.size());

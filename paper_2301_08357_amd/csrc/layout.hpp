@@ -28,15 +28,18 @@ int build_layout(const pm_mesh *m, Layout *L);
 // Morton tiles: runs of `tile_nodes` consecutive internal nodes.  A tile
 // holds every element touching one of its nodes (its "instances", ascending
 // element id: first those whose smallest vertex lies in an earlier tile,
-// then the contiguous run the tile owns), the outside vertices those
-// elements reach (its halo, ascending), each instance's vertices as
-// tile-local indices (own node i -> i - first node, halo node -> tile_nodes
-// + rank in the halo list), and for each instance vertex that is an own
-// node the rank of the instance among that node's instances ("row";
-// 0xFF for halo vertices).  Node i's k-th element in ascending order is the
-// instance whose vertex i has row k.
+// then the contiguous run the tile owns) and the outside vertices those
+// elements reach (its halo, ascending).  Each instance is one record of four
+// 16-bit fields, one per vertex (the fourth is 0 for a triangle):
+//   bits 0 .. lvb-1   tile-local index: own node i -> i - first node,
+//                     halo node -> tile_nodes + rank in the halo list;
+//   bits lvb .. 15    for an own node, the rank of the instance among that
+//                     node's instances ("row"); 0 for a halo vertex.
+// Node i's k-th element in ascending order is the instance whose vertex i
+// has row k.  lvb = 10 for tiles of up to 256 nodes, 11 for larger ones.
 struct Tiles {
     int tile_nodes = 0;
+    int lvb = 0;
     int64_t n_tiles = 0;
     int max_inst = 0;                     // largest instance count of a tile
     int max_halo = 0;                     // largest halo of a tile
@@ -45,9 +48,12 @@ struct Tiles {
     std::vector<int32_t> halo;            // global node ids
     std::vector<int32_t> inst_off;        // n_tiles + 1
     std::vector<int32_t> inst_elem;       // element id of each instance
-    std::vector<uint16_t> inst_conn;      // 4 local vertex ids per instance (slot 3 = 0 in 2D)
-    std::vector<uint8_t> inst_row;        // 4 rows per instance (0xFF: halo vertex or unused)
+    std::vector<uint16_t> inst;           // 4 fields per instance
 };
+
+// Returned by build_tiles when a node has more elements, or a tile more
+// own and halo nodes, than a record can name at this tile size.
+constexpr int TILES_TOO_WIDE = 100;
 
 int build_tiles(const Layout &L, int tile_nodes, Tiles *T);
 

@@ -341,164 +341,242 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
     }
 }
 
-template <class R>
-struct TileArgsT {
-    int T;                        // nodes per tile
-    int n_tiles;
-    int max_local;                // T + largest halo (LDS node table size)
-    int max_deg;                  // most elements at one node (rows of the LDS sum table)
-    const int *halo_off, *halo;
-    const int *inst_off;
-    const uint2 *inst_conn;       // 4 x 16-bit local vertex ids
-    const uint32_t *inst_row;     // 4 x 8-bit rows (0xFF: not an own node)
-    const R *inst_w;
-    const uint8_t *deg;           // elements per node
+// Tile-local instance record: 4 x 16 bits, vertex a in bits 16a..16a+15 of
+// the (x, y) pair; the low LVB bits are the vertex's local index (own node
+// i -> i - first node of the tile, halo node -> T + rank in the tile's halo
+// list), the high bits its row (rank of the element among the own node's
+// elements, ascending element id; 0 for halo vertices and the unused
+// fourth vertex of a triangle).
+template <int T>
+struct TileGeom {
+    static_assert(T == 128 || T == 256 || T == 512, "tile sizes are powers of two");
+    static constexpr int NPT = (T + BLK - 1) / BLK;        // own nodes per lane
+    static constexpr int LVB = (T <= 256) ? 10 : 11;       // bits of a local index
+    static constexpr unsigned LV_MASK = (1u << LVB) - 1u;
+    static constexpr int MAX_ROWS = 1 << (16 - LVB);       // rows a record can name
+    static constexpr int MAX_LOCAL = 1 << LVB;             // own + halo nodes a record can name
+    static constexpr int RS = T + 1;                       // row stride of the sums table (padded)
+    static constexpr int DUMMY = 64;                       // per-lane sink for halo-vertex writes
 };
 
+// Size classes of the tiled kernel: (tile nodes, instances per lane,
+// node-table entries).  Setup picks the first class of the tile size that
+// covers the largest tile's instance count and node table.
+struct TileClass {
+    int t, ipt, lm;
+};
+constexpr TileClass TILE_CLASSES[] = {{128, 2, 256},  {128, 4, 256},  {128, 4, 384},   {128, 6, 448},
+                                      {128, 8, 512},  {128, 12, 768}, {256, 6, 512},   {256, 8, 768},
+                                      {256, 12, 768}, {256, 12, 1024}, {512, 16, 1024}, {512, 20, 1536},
+                                      {512, 24, 2048}};
+constexpr int N_TILE_CLASSES = sizeof(TILE_CLASSES) / sizeof(TILE_CLASSES[0]);
+
+template <class R>
+struct TileArgsT {
+    int n_tiles;
+    int max_deg;                  // rows of the LDS sums table
+    const int *halo_off, *halo;
+    const int *inst_off;
+    const uint2 *inst;            // packed instance records
+    const R *inst_w;              // element factor per instance
+    const uint8_t *nflag;         // per node: element count | Dirichlet << 7
+};
+
+// LDS bytes of the tiled kernel: node table (DIM+1 fields of LM entries)
+// and the sums table (max_deg rows of RS, plus the halo-write sink).
+template <class R, int T>
+constexpr size_t tile_lds_bytes(int dim, int lm, int max_deg)
+{
+    return sizeof(R) * (size_t(dim + 1) * size_t(lm) + size_t(max_deg) * TileGeom<T>::RS + TileGeom<T>::DUMMY);
+}
+
 // Morton-tiled apply.  Each block walks its tiles (tile_at); for every tile
-//  1. load the tile's element instances (local connectivity, rows and factor)
-//     into registers, and the coordinates and nodal values of its nodes and
-//     halo into LDS (Dirichlet values as 0); under CG the values are
+//  1. the coordinates and nodal values of the tile's own and halo nodes go
+//     to the LDS node table (Dirichlet values as 0); under CG the value is
 //     p_k = r + beta p_{k-1} and the block stores p_k for its own nodes;
-//  2. each lane computes whole elements from LDS and writes the contribution
-//     to each own vertex i into S[row][i], row = rank of the element among
-//     node i's elements;
+//  2. each lane computes whole elements (its instances, held in registers)
+//     from the node table and writes the contribution to each own vertex i
+//     into S[row][i], row = rank of the element among node i's elements
+//     (writes for halo vertices go to a sink);
 //  3. each own node sums S[0..deg-1][i] in row order (ascending element id).
 // Every element is computed once per tile that contains one of its vertices.
-// IPT instances and SPT node-table slots per lane cover the largest tile
-// (checked at setup).  Several blocks share a CU, so the loads of one block
-// overlap the arithmetic of another.
+// The loads of tile k+1 (instances, node data) are issued as soon as tile
+// k's elements are done, and its halo ids and offsets one step earlier, so
+// their latency overlaps the row sums of tile k and the other blocks of the
+// CU.  IPT instances per lane and LM node-table entries cover the largest
+// tile (checked at setup).  Own node l of the tile is staged by lane
+// l mod BLK in slot l / BLK, which is also the lane that sums its row, so the
+// own values stay in registers between the phases.
 // The body runs as virtual block vb of nvb (a real block of a single-mesh
 // launch, or one (mesh, slot) pair of a batched launch).
-template <int DIM, bool CG, class R, int NPT, int IPT, int SPT>
+template <int DIM, bool CG, class R, int T, int IPT, int LM>
 __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileArgsT<R> &ta,
                                                  const R *__restrict__ x, R *__restrict__ y, const IterT<R> &it,
                                                  R *smem, double *red, int vb, int nvb)
 {
+    using G = TileGeom<T>;
+    constexpr int NPT = G::NPT, SPT = (LM + BLK - 1) / BLK, NF = DIM + 1, RS = G::RS;
+    static_assert(LM >= T && LM <= G::MAX_LOCAL, "node table");
     double beta = 0.0;
     if (CG && !iter_prologue(it, red, beta, vb)) return;
-    const int L = ta.max_local, T = ta.T;
-    R *sX = smem, *sY = smem + L, *sZ = smem + 2 * L;
-    R *sP = smem + (DIM == 3 ? 3 : 2) * L;
-    R *sS = sP + L;                                               // max_deg x T
-    uint8_t *sD = reinterpret_cast<uint8_t *>(sS + ta.max_deg * T);   // own Dirichlet flags
-    uint8_t *sG = sD + T;                                         // own degrees
+    R *const sN = smem;                      // NF x LM: X, Y, (Z,) value
+    R *const sS = smem + NF * LM;            // max_deg x RS sums, then the sink
+    R *const sink = sS + ta.max_deg * RS + (threadIdx.x & (G::DUMMY - 1));
+    const R rbeta = R(beta);
+
+    // -- loads of one tile, into registers
+    int gidx[SPT];
+    uint2 ic[IPT];
+    R iw[IPT];
+    R vX[SPT], vY[SPT], vZ[SPT], vP[SPT];
+    uint8_t vF[SPT];
+    auto load_ids = [&](int t, int h0, int nh, int *gi) {
+        const int s = t * T, nt = min(T, g.N - s);
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int l = threadIdx.x + q * BLK;
+            gi[q] = -1;
+            if (l < nt) gi[q] = s + l;
+            else if (l >= T && l < T + nh) gi[q] = ta.halo[h0 + l - T];
+        }
+    };
+    auto load_inst = [&](int k, int i0, int ni) {
+        const int j = threadIdx.x + k * BLK;
+        if (j < ni) {
+            ic[k] = ta.inst[i0 + j];
+            iw[k] = ta.inst_w[i0 + j];
+        }
+    };
+    auto load_nodes = [&](const int *gi) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int v = gi[q];
+            if (v >= 0) {
+                vX[q] = g.X[v];
+                vY[q] = g.Y[v];
+                if (DIM == 3) vZ[q] = g.Z[v];
+                if (CG) vP[q] = it.first ? it.r[v] : it.r[v] + rbeta * it.p_old[v];
+                else vP[q] = x[v];
+                vF[q] = ta.nflag[v];
+            }
+        }
+    };
+
     double part = 0.0;
-    for (int kt = 0;; ++kt) {
-        const int t = tile_at(vb, kt, nvb, ta.n_tiles);
-        if (t < 0) break;
-        const int s = t * T;
-        const int nt = min(T, g.N - s);
+    // offsets of tile tt as vector loads (lanes 0-3 of each wave), read out
+    // with readlane when needed: unlike scalar loads they do not hold up the
+    // waits on LDS operations
+    const int lane = threadIdx.x & 63;
+    auto load_offsets = [&](int tt) -> int {
+        int v = 0;
+        if (tt >= 0 && lane < 4) v = (lane < 2) ? ta.halo_off[tt + lane] : ta.inst_off[tt + lane - 2];
+        return v;
+    };
+    int t = tile_at(vb, 0, nvb, ta.n_tiles);
+    int ni = 0;
+    if (t >= 0) {
         const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
-        const int i0 = ta.inst_off[t], ni = ta.inst_off[t + 1] - i0;
-        // 1a. instances into registers
-        uint2 ic[IPT];
-        uint32_t ir[IPT];
-        R iw[IPT];
+        const int i0 = ta.inst_off[t];
+        ni = ta.inst_off[t + 1] - i0;
+        load_ids(t, h0, nh, gidx);
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const int j = threadIdx.x + k * BLK;
-            if (j < ni) {
-                ic[k] = ta.inst_conn[i0 + j];
-                ir[k] = ta.inst_row[i0 + j];
-                iw[k] = ta.inst_w[i0 + j];
+        for (int k = 0; k < IPT; ++k) load_inst(k, i0, ni);
+        load_nodes(gidx);
+    }
+    int tn = tile_at(vb, 1, nvb, ta.n_tiles);
+    int vo = load_offsets(tn);
+    for (int kt = 0; t >= 0; ++kt) {
+        const int s = t * T, nt = min(T, g.N - s);
+        // 1. node table; own values kept for the row sums
+        R ownP[NPT];
+        uint8_t ownF[NPT];
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int l = threadIdx.x + q * BLK;
+            if (gidx[q] >= 0) {
+                const bool d = (vF[q] & 0x80u) != 0;
+                sN[l] = vX[q];
+                sN[LM + l] = vY[q];
+                if (DIM == 3) sN[2 * LM + l] = vZ[q];
+                sN[(NF - 1) * LM + l] = d ? R(0) : vP[q];
+                if (CG && l < nt) it.p_new[gidx[q]] = vP[q];
+            }
+            if (q < NPT) {
+                ownP[q] = vP[q];
+                ownF[q] = vF[q];
             }
         }
-        // 1b. nodes: own node i at i - s, halo node of rank h at T + h (the
-        // local indices of the instance connectivity); slots nt..T-1 of a
-        // ragged last tile are unused.  All global loads of a lane are issued
-        // before its LDS writes.
-        {
-            int gidx[SPT];
-#pragma unroll
-            for (int q = 0; q < SPT; ++q) {
-                const int l = threadIdx.x + q * BLK;
-                gidx[q] = -1;
-                if (l < nt) gidx[q] = s + l;
-                else if (l >= T && l < T + nh) gidx[q] = ta.halo[h0 + l - T];
-            }
-            R vX[SPT], vY[SPT], vZ[SPT], vP[SPT];
-            uint8_t vD[SPT], vG[SPT];
-#pragma unroll
-            for (int q = 0; q < SPT; ++q) {
-                const int gi = gidx[q];
-                if (gi >= 0) {
-                    vX[q] = g.X[gi];
-                    vY[q] = g.Y[gi];
-                    vZ[q] = (DIM == 3) ? g.Z[gi] : R(0);
-                    vP[q] = CG ? (it.first ? it.r[gi] : it.r[gi] + R(beta) * it.p_old[gi]) : x[gi];
-                    vD[q] = g.dir[gi];
-                    vG[q] = (threadIdx.x + q * BLK < nt) ? ta.deg[gi] : 0;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < SPT; ++q) {
-                const int l = threadIdx.x + q * BLK;
-                const int gi = gidx[q];
-                if (gi >= 0) {
-                    sX[l] = vX[q];
-                    sY[l] = vY[q];
-                    if (DIM == 3) sZ[l] = vZ[q];
-                    sP[l] = vD[q] ? R(0) : vP[q];
-                    if (l < nt) {
-                        sD[l] = vD[q];
-                        sG[l] = vG[q];
-                        if (CG) it.p_new[gi] = vP[q];
-                    }
-                }
-            }
-        }
+        // offsets and halo ids of the next tile
+        const int h0n = __builtin_amdgcn_readlane(vo, 0), nhn = __builtin_amdgcn_readlane(vo, 1) - h0n;
+        const int i0n = __builtin_amdgcn_readlane(vo, 2), nin = __builtin_amdgcn_readlane(vo, 3) - i0n;
+        int gidn[SPT];
+        if (tn >= 0) load_ids(tn, h0n, nhn, gidn);
         __syncthreads();
-        // 2. element contributions into the row table
+        // 2. element contributions into the sums table.  The next tile's
+        // loads go into the registers as this tile frees them: its instances
+        // slot by slot, its node data once its halo ids have arrived.
+        constexpr int NODES_AT = (IPT > 2) ? 2 : IPT - 1;
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
             const int j = threadIdx.x + k * BLK;
             if (j < ni) {
-                const uint2 cc = ic[k];
-                const int lv[4] = {int(cc.x & 0xffffu), int(cc.x >> 16), int(cc.y & 0xffffu), int(cc.y >> 16)};
+                const unsigned u[4] = {ic[k].x & 0xffffu, ic[k].x >> 16, ic[k].y & 0xffffu, ic[k].y >> 16};
                 R X[4], Y[4], Z[4], xv[4], o[4];
 #pragma unroll
                 for (int a = 0; a <= DIM; ++a) {
-                    X[a] = sX[lv[a]];
-                    Y[a] = sY[lv[a]];
-                    Z[a] = (DIM == 3) ? sZ[lv[a]] : R(0);
-                    xv[a] = sP[lv[a]];
+                    const int lv = int(u[a] & G::LV_MASK);
+                    X[a] = sN[lv];
+                    Y[a] = sN[LM + lv];
+                    Z[a] = (DIM == 3) ? sN[2 * LM + lv] : R(0);
+                    xv[a] = sN[(NF - 1) * LM + lv];
                 }
                 if (DIM == 2) xv[3] = R(0);
                 elem_contrib<DIM, R>(X, Y, Z, xv, iw[k], g.mscale, o);
 #pragma unroll
                 for (int a = 0; a <= DIM; ++a) {
-                    const unsigned row = (ir[k] >> (8 * a)) & 0xffu;
-                    if (row != 0xffu) sS[row * T + lv[a]] = o[a];
+                    const int lv = int(u[a] & G::LV_MASK);
+                    R *dst = (lv < T) ? sS + int(u[a] >> G::LVB) * RS + lv : sink;
+                    *dst = o[a];
+                }
+            }
+            if (tn >= 0) {
+                load_inst(k, i0n, nin);
+                if (k == NODES_AT) {
+#pragma unroll
+                    for (int q = 0; q < SPT; ++q) gidx[q] = gidn[q];
+                    load_nodes(gidx);
                 }
             }
         }
+        const int tn2 = (tn >= 0) ? tile_at(vb, kt + 2, nvb, ta.n_tiles) : -1;
+        vo = load_offsets(tn2);
         __syncthreads();
         // 3. row sums in ascending element order
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             const int l = threadIdx.x + j * BLK;
             if (l < nt) {
-                const int gi = s + l;
-                const int d = sG[l];
+                const int d = ownF[j] & 0x7f;
                 R yi = R(0);
-#pragma unroll 8
-                for (int k = 0; k < d; ++k) yi += sS[k * T + l];
-                if (CG) {
-                    // free nodes: the staged value; Dirichlet rows: y = p
-                    R pi = sP[l];
-                    if (sD[l]) {
-                        pi = it.first ? it.r[gi] : it.r[gi] + R(beta) * it.p_old[gi];
-                        yi = pi;
-                    }
-                    part += double(pi) * double(yi);
-                } else if (sD[l]) {
-                    yi = x[gi];
+                // rows in chunks of 8: the reads of a chunk are issued together
+                for (int k0 = 0; k0 < d; k0 += 8) {
+                    R v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < d) v[u] = sS[(k0 + u) * RS + l];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < d) yi += v[u];
                 }
-                y[gi] = yi;
+                // Dirichlet rows: y = x (p_k under CG)
+                if (ownF[j] & 0x80u) yi = ownP[j];
+                if (CG) part += double(ownP[j]) * double(yi);
+                y[s + l] = yi;
             }
         }
-        __syncthreads();
+        t = tn;
+        ni = nin;
+        tn = tn2;
     }
     if (CG) {
         const double bs = block_sum_all(part, red);
@@ -506,14 +584,14 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     }
 }
 
-template <int DIM, bool CG, class R, int NPT, int IPT, int SPT>
+template <int DIM, bool CG, class R, int T, int IPT, int LM>
 __global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
                                                      R *__restrict__ y, IterT<R> it)
 {
     extern __shared__ double smem_d[];
     __shared__ double red[BLK / 64];
-    apply_tiled_body<DIM, CG, R, NPT, IPT, SPT>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red,
-                                                int(blockIdx.x), int(gridDim.x));
+    apply_tiled_body<DIM, CG, R, T, IPT, LM>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red, int(blockIdx.x),
+                                             int(gridDim.x));
 }
 
 // ------------------------------------------------------------- CG vectors
@@ -678,7 +756,8 @@ struct BatchCtl {
     int pad;
 };
 
-template <int IPT, int SPT>
+// C: size class (128-node tiles) covering every mesh of the batch
+template <int C>
 __global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMesh *__restrict__ meshes,
                                                      const int2 *__restrict__ slots, BatchCtl *ctl)
 {
@@ -703,10 +782,12 @@ __global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMesh *__restrict
     it.rr_cur = (k & 1) ? M.rr0 : M.rr1;
     it.rr_prev = (k & 1) ? M.rr1 : M.rr0;
     it.n_vblocks = M.n_vb;
+    constexpr TileClass tc = TILE_CLASSES[C];
+    static_assert(tc.t == 128, "batched meshes use 128-node tiles");
     if (M.dim == 3)
-        apply_tiled_body<3, true, double, 1, IPT, SPT>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
+        apply_tiled_body<3, true, double, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
     else
-        apply_tiled_body<2, true, double, 1, IPT, SPT>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
+        apply_tiled_body<2, true, double, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
 }
 
 __global__ void __launch_bounds__(BLK) k_batch_update(const BatchMesh *__restrict__ meshes,
@@ -825,10 +906,9 @@ struct pm_handle {
     size_t lds_limit = 65536;
     int64_t n_inst = 0;
     int *t_halo_off = nullptr, *t_halo = nullptr, *t_inst_off = nullptr, *t_inst_elem = nullptr;
-    uint2 *t_inst_conn = nullptr;
-    uint32_t *t_inst_row = nullptr;
+    uint2 *t_inst = nullptr;
     double *t_inst_w = nullptr;
-    uint8_t *t_deg = nullptr;
+    uint8_t *t_nflag = nullptr;
     // FP32 operator data and inner-CG vectors (PM_FP32_INNER)
     float *coords32 = nullptr, *w32 = nullptr, *t_inst_w32 = nullptr;
     float *r32 = nullptr, *q32 = nullptr, *d32 = nullptr;
@@ -937,20 +1017,17 @@ template <class R>
 TileArgsT<R> make_tiles(const pm_handle *h)
 {
     TileArgsT<R> ta;
-    ta.T = h->tile_nodes;
     ta.n_tiles = h->n_tiles;
-    ta.max_local = h->max_local;
     ta.max_deg = h->max_deg;
     ta.halo_off = h->t_halo_off;
     ta.halo = h->t_halo;
     ta.inst_off = h->t_inst_off;
-    ta.inst_conn = h->t_inst_conn;
-    ta.inst_row = h->t_inst_row;
+    ta.inst = h->t_inst;
     if constexpr (sizeof(R) == 8)
         ta.inst_w = h->t_inst_w;
     else
         ta.inst_w = h->t_inst_w32;
-    ta.deg = h->t_deg;
+    ta.nflag = h->t_nflag;
     return ta;
 }
 
@@ -988,10 +1065,20 @@ int compute_factors(pm_handle *h)
 }
 
 template <class R>
+size_t tiled_lds_bytes(int dim, int c, int max_deg)
+{
+    const TileClass tc = TILE_CLASSES[c];
+    switch (tc.t) {
+    case 128: return tile_lds_bytes<R, 128>(dim, tc.lm, max_deg);
+    case 256: return tile_lds_bytes<R, 256>(dim, tc.lm, max_deg);
+    default: return tile_lds_bytes<R, 512>(dim, tc.lm, max_deg);
+    }
+}
+
+template <class R>
 size_t tiled_lds_bytes(const pm_handle *h)
 {
-    return sizeof(R) * (size_t(h->dim + 1) * h->max_local + size_t(h->max_deg) * h->tile_nodes) +
-           2 * size_t(h->tile_nodes);
+    return tiled_lds_bytes<R>(h->dim, h->tile_class, h->max_deg);
 }
 
 // Events of the next apply launch to time (start and stop are recorded by
@@ -1016,71 +1103,56 @@ int launch_tiled_k(pm_handle *h, K kern, const MeshT<R> &g, const TileArgsT<R> &
     return PM_OK;
 }
 
-// Size classes of the tiled kernel: (nodes per lane, instances per lane,
-// node-table slots per lane).  Setup picks the first class that covers the
-// tile size, the largest tile's instance count and its node table.
-struct TileClass {
-    int npt, ipt, spt;
-};
-constexpr TileClass TILE_CLASSES[] = {{1, 4, 2}, {1, 8, 2}, {1, 8, 3}, {1, 12, 3}, {1, 12, 4},
-                                      {1, 16, 4}, {2, 12, 4}, {2, 16, 6}, {2, 20, 6}, {2, 24, 8}};
-constexpr int N_TILE_CLASSES = sizeof(TILE_CLASSES) / sizeof(TILE_CLASSES[0]);
-
 template <int DIM, bool CG, class R, int C>
 int launch_tiled_c(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream_t s)
 {
     constexpr TileClass tc = TILE_CLASSES[C];
     MeshT<R> g = make_mesh<R>(h);
     TileArgsT<R> ta = make_tiles<R>(h);
-    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.npt, tc.ipt, tc.spt>, g, ta, x, y, it, s);
+    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.t, tc.ipt, tc.lm>, g, ta, x, y, it, s);
 }
+
+// f.template operator()<C>() for the handle's class C
+template <class F>
+int with_class(int c, F &&f)
+{
+    switch (c) {
+    case 0: return f.template operator()<0>();
+    case 1: return f.template operator()<1>();
+    case 2: return f.template operator()<2>();
+    case 3: return f.template operator()<3>();
+    case 4: return f.template operator()<4>();
+    case 5: return f.template operator()<5>();
+    case 6: return f.template operator()<6>();
+    case 7: return f.template operator()<7>();
+    case 8: return f.template operator()<8>();
+    case 9: return f.template operator()<9>();
+    case 10: return f.template operator()<10>();
+    case 11: return f.template operator()<11>();
+    case 12: return f.template operator()<12>();
+    default: return PM_EINVAL;
+    }
+}
+static_assert(N_TILE_CLASSES == 13, "with_class covers every class");
 
 template <int DIM, bool CG, class R>
 int launch_tiled_t(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream_t s)
 {
-    switch (h->tile_class) {
-    case 0: return launch_tiled_c<DIM, CG, R, 0>(h, x, y, it, s);
-    case 1: return launch_tiled_c<DIM, CG, R, 1>(h, x, y, it, s);
-    case 2: return launch_tiled_c<DIM, CG, R, 2>(h, x, y, it, s);
-    case 3: return launch_tiled_c<DIM, CG, R, 3>(h, x, y, it, s);
-    case 4: return launch_tiled_c<DIM, CG, R, 4>(h, x, y, it, s);
-    case 5: return launch_tiled_c<DIM, CG, R, 5>(h, x, y, it, s);
-    case 6: return launch_tiled_c<DIM, CG, R, 6>(h, x, y, it, s);
-    case 7: return launch_tiled_c<DIM, CG, R, 7>(h, x, y, it, s);
-    case 8: return launch_tiled_c<DIM, CG, R, 8>(h, x, y, it, s);
-    case 9: return launch_tiled_c<DIM, CG, R, 9>(h, x, y, it, s);
-    default: return PM_EINVAL;
-    }
+    return with_class(h->tile_class, [&]<int C>() { return launch_tiled_c<DIM, CG, R, C>(h, x, y, it, s); });
 }
 
 // Resident blocks per CU of the CG apply kernel of the handle's size class.
-template <int DIM, class R, int C>
-int occupancy_c(pm_handle *h, int *per_cu)
-{
-    constexpr TileClass tc = TILE_CLASSES[C];
-    const void *kern = (const void *)k_apply_tiled<DIM, true, R, tc.npt, tc.ipt, tc.spt>;
-    const size_t lds = tiled_lds_bytes<R>(h);
-    if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, BLK, lds));
-    return PM_OK;
-}
-
 template <int DIM, class R>
 int occupancy_t(pm_handle *h, int *per_cu)
 {
-    switch (h->tile_class) {
-    case 0: return occupancy_c<DIM, R, 0>(h, per_cu);
-    case 1: return occupancy_c<DIM, R, 1>(h, per_cu);
-    case 2: return occupancy_c<DIM, R, 2>(h, per_cu);
-    case 3: return occupancy_c<DIM, R, 3>(h, per_cu);
-    case 4: return occupancy_c<DIM, R, 4>(h, per_cu);
-    case 5: return occupancy_c<DIM, R, 5>(h, per_cu);
-    case 6: return occupancy_c<DIM, R, 6>(h, per_cu);
-    case 7: return occupancy_c<DIM, R, 7>(h, per_cu);
-    case 8: return occupancy_c<DIM, R, 8>(h, per_cu);
-    case 9: return occupancy_c<DIM, R, 9>(h, per_cu);
-    default: return PM_EINVAL;
-    }
+    return with_class(h->tile_class, [&]<int C>() {
+        constexpr TileClass tc = TILE_CLASSES[C];
+        const void *kern = (const void *)k_apply_tiled<DIM, true, R, tc.t, tc.ipt, tc.lm>;
+        const size_t lds = tiled_lds_bytes<R>(h);
+        if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+        HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, BLK, lds));
+        return PM_OK;
+    });
 }
 
 // Grid of the tiled apply: every block resident at once (one per resident
@@ -1156,6 +1228,10 @@ int event_pair(pm_handle *h, size_t k, hipEvent_t *a, hipEvent_t *b)
     return PM_OK;
 }
 
+// Tiles of the tiled apply.  Returns pm::TILES_TOO_WIDE when the mesh does
+// not fit the tiled kernel at this tile size (a node with more elements, or
+// a tile with more own and halo nodes, than a record names; no size class
+// or not enough LDS for the largest tile).
 int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
 {
     pm::Tiles T;
@@ -1167,33 +1243,46 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
     h->max_inst = T.max_inst;
     h->n_inst = int64_t(T.inst_elem.size());
     // smallest size class covering the tile, its instances and node table
-    const int need_n = (tile_nodes + BLK - 1) / BLK;
-    const int need_i = (T.max_inst + BLK - 1) / BLK;
-    const int need_s = (h->max_local + BLK - 1) / BLK;
     h->tile_class = -1;
     for (int c = 0; c < N_TILE_CLASSES; ++c)
-        if (TILE_CLASSES[c].npt == need_n && TILE_CLASSES[c].ipt >= need_i && TILE_CLASSES[c].spt >= need_s) {
+        if (TILE_CLASSES[c].t == tile_nodes && TILE_CLASSES[c].ipt * BLK >= T.max_inst &&
+            TILE_CLASSES[c].lm >= h->max_local) {
             h->tile_class = c;
             break;
         }
-    if (h->tile_class < 0) return PM_EINVAL;
-    std::vector<uint8_t> deg(L.n_nodes);
-    for (int64_t i = 0; i < L.n_nodes; ++i) deg[i] = uint8_t(L.n2e_off[i + 1] - L.n2e_off[i]);
+    if (h->tile_class < 0 || tiled_lds_bytes<double>(h) > h->lds_limit) {
+        h->tile_class = -1;
+        return pm::TILES_TOO_WIDE;
+    }
+    std::vector<uint8_t> nflag(L.n_nodes);
+    for (int64_t i = 0; i < L.n_nodes; ++i)
+        nflag[i] = uint8_t((L.n2e_off[i + 1] - L.n2e_off[i]) | (L.dirichlet[i] ? 0x80 : 0));
     TRY(dupload(h, &h->t_halo_off, T.halo_off));
     TRY(dupload(h, &h->t_halo, T.halo));
     TRY(dupload(h, &h->t_inst_off, T.inst_off));
     TRY(dupload(h, &h->t_inst_elem, T.inst_elem));
-    TRY(dupload(h, &h->t_deg, deg));
-    TRY(dalloc(h, &h->t_inst_conn, size_t(h->n_inst)));
-    TRY(dalloc(h, &h->t_inst_row, size_t(h->n_inst)));
-    if (h->n_inst > 0) {
-        HIPCK(hipMemcpy(h->t_inst_conn, T.inst_conn.data(), sizeof(uint16_t) * T.inst_conn.size(),
-                        hipMemcpyHostToDevice));
-        HIPCK(hipMemcpy(h->t_inst_row, T.inst_row.data(), T.inst_row.size(), hipMemcpyHostToDevice));
-    }
+    TRY(dupload(h, &h->t_nflag, nflag));
+    TRY(dalloc(h, &h->t_inst, size_t(h->n_inst)));
+    if (h->n_inst > 0)
+        HIPCK(hipMemcpy(h->t_inst, T.inst.data(), sizeof(uint16_t) * T.inst.size(), hipMemcpyHostToDevice));
     TRY(dalloc(h, &h->t_inst_w, size_t(h->n_inst)));
-    if (tiled_lds_bytes<double>(h) > h->lds_limit) return PM_EINVAL;
     TRY(apply_grid<double>(h, &h->n_ablocks));
+    return PM_OK;
+}
+
+// Meshes the tiled kernel does not take (see build_tiles_on_device) run on
+// the node kernel alone, over 128-node runs in the same block order.
+int setup_node_only(pm_handle *h)
+{
+    h->variant = PM_VARIANT_NODE;
+    h->tile_class = -1;
+    h->tile_nodes = 128;
+    h->n_tiles = int((h->N + 127) / 128);
+    h->n_inst = 0;
+    h->max_inst = 0;
+    int g = std::min(AGRID_MAX, 8 * h->n_cu);
+    if (g >= N_XCD) g -= g % N_XCD;
+    h->n_ablocks = std::max(1, std::min(g, h->n_tiles));
     return PM_OK;
 }
 
@@ -1257,7 +1346,7 @@ int pressure_footprint(const pm_mesh *mesh, int32_t flags, uint64_t *bytes)
     b += 8 * d * N;                         // coordinates
     b += 16 * E;                            // c_e and w_e
     b += N;                                 // Dirichlet flags
-    b += I * (4 + 8 + 8) + 2 * (d + 1) * E + 4 * N + 2 * N;   // tiles
+    b += I * (8 + 8 + 4) + 8 * N + 8 * N;   // tiles: records, factors, element ids; halo lists, flags
     b += 7 * 8 * N;                         // b, x, r, q, t, p (x2)
     b += 8 * (AGRID_MAX + 3 * VGRID_MAX) + 1024 * 8 + 256;
     *bytes = b;
@@ -1268,8 +1357,8 @@ void pressure_destroy(pm_handle *h)
 {
     if (!h) return;
     void *ptrs[] = {h->new2old, h->n2e_off, h->n2e_ent, h->conn, h->coords, h->coef, h->w, h->dir,
-                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst_conn, h->t_inst_row,
-                    h->t_inst_w, h->t_deg, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
+                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst, h->t_inst_w,
+                    h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in};
     for (void *p : ptrs)
@@ -1340,7 +1429,15 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     TRY(dupload(h, &h->dir, L.dirichlet));
     const int tn = tile_nodes_for(flags, N);
     if (tn < 0) return PM_EINVAL;
-    TRY(build_tiles_on_device(h, L, tn));
+    {
+        int st = build_tiles_on_device(h, L, tn);
+        if (st == pm::TILES_TOO_WIDE) {
+            // an explicit tile size is an error; the default runs the node kernel
+            if ((flags & PM_TILE_MASK) != 0 || (flags & PM_FP32_INNER)) return PM_EINVAL;
+            st = setup_node_only(h);
+        }
+        TRY(st);
+    }
     for (double **v : {&h->b, &h->x, &h->r, &h->q, &h->t, &h->pbuf[0], &h->pbuf[1]}) TRY(dalloc(h, v, N));
     if (flags & PM_FP32_INNER) {
         std::vector<float> c32(L.coords.size());
@@ -1661,8 +1758,11 @@ int pressure_set_variant(pm_handle *h, int32_t variant)
 {
     if (!h) return PM_EINVAL;
     switch (variant) {
-    case PM_VARIANT_AUTO:
-    case PM_VARIANT_TILED: h->variant = PM_VARIANT_TILED; return PM_OK;
+    case PM_VARIANT_AUTO: h->variant = (h->tile_class >= 0) ? PM_VARIANT_TILED : PM_VARIANT_NODE; return PM_OK;
+    case PM_VARIANT_TILED:
+        if (h->tile_class < 0) return PM_EINVAL;   // mesh on the node kernel only
+        h->variant = PM_VARIANT_TILED;
+        return PM_OK;
     case PM_VARIANT_NODE: h->variant = PM_VARIANT_NODE; return PM_OK;
     default: return PM_EINVAL;
     }
@@ -1722,25 +1822,21 @@ struct pm_batch {
 
 namespace {
 
-// Size classes of the batched apply (instances per lane, node-table slots per lane).
-constexpr int2 BATCH_CLASSES[] = {{4, 2}, {8, 2}, {8, 3}, {12, 3}, {12, 4}, {16, 4}};
-constexpr int N_BATCH_CLASSES = sizeof(BATCH_CLASSES) / sizeof(BATCH_CLASSES[0]);
-
-template <int C>
-const void *batch_apply_fn()
-{
-    return (const void *)k_batch_apply<BATCH_CLASSES[C].x, BATCH_CLASSES[C].y>;
-}
+// The batched apply runs the size classes of 128-node tiles (the first
+// N_BATCH_CLASSES entries of TILE_CLASSES).
+constexpr int N_BATCH_CLASSES = 6;
+static_assert(TILE_CLASSES[N_BATCH_CLASSES - 1].t == 128 && TILE_CLASSES[N_BATCH_CLASSES].t != 128,
+              "batch classes are the 128-node classes");
 
 const void *batch_apply_kernel(int c)
 {
     switch (c) {
-    case 0: return batch_apply_fn<0>();
-    case 1: return batch_apply_fn<1>();
-    case 2: return batch_apply_fn<2>();
-    case 3: return batch_apply_fn<3>();
-    case 4: return batch_apply_fn<4>();
-    case 5: return batch_apply_fn<5>();
+    case 0: return (const void *)k_batch_apply<0>;
+    case 1: return (const void *)k_batch_apply<1>;
+    case 2: return (const void *)k_batch_apply<2>;
+    case 3: return (const void *)k_batch_apply<3>;
+    case 4: return (const void *)k_batch_apply<4>;
+    case 5: return (const void *)k_batch_apply<5>;
     default: return nullptr;
     }
 }
@@ -1748,8 +1844,8 @@ const void *batch_apply_kernel(int c)
 template <int C>
 void launch_batch_apply_c(pm_batch *b, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch_apply<BATCH_CLASSES[C].x, BATCH_CLASSES[C].y>), dim3(b->n_aslots), dim3(BLK),
-                       b->lds, s, b->d_meshes, b->d_aslots, b->d_ctl);
+    hipLaunchKernelGGL((k_batch_apply<C>), dim3(b->n_aslots), dim3(BLK), b->lds, s, b->d_meshes, b->d_aslots,
+                       b->d_ctl);
 }
 
 int launch_batch_iterations(pm_batch *b, int count, hipStream_t s)
@@ -1795,15 +1891,15 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
         k_start = params[2];
     }
     HIPCK(hipGetDevice(&b->device));
-    int need_i = 1, need_s = 1;
+    int max_inst = 1, max_local = 1;
     std::vector<BatchMesh> meshes(n);
     std::vector<int2> aslots, uslots;
     for (int m = 0; m < n; ++m) {
         pm_handle *h = handles[m];
-        if (!h || h->device != b->device || h->tile_nodes > BLK) return PM_EINVAL;
-        need_i = std::max(need_i, (h->max_inst + BLK - 1) / BLK);
-        need_s = std::max(need_s, (h->max_local + BLK - 1) / BLK);
-        b->lds = std::max(b->lds, tiled_lds_bytes<double>(h));
+        if (!h || h->device != b->device || h->tile_class < 0 || TILE_CLASSES[h->tile_class].t != 128)
+            return PM_EINVAL;
+        max_inst = std::max(max_inst, h->max_inst);
+        max_local = std::max(max_local, h->max_local);
         // the batch's grids become the handle's
         h->n_ablocks = std::max(1, std::min(AGRID_MAX, (h->n_tiles + b->tiles_per_slot - 1) / b->tiles_per_slot));
         h->n_vblocks = int(std::max<int64_t>(1, std::min<int64_t>(VGRID_MAX, (h->N + int64_t(BLK) * b->nodes_per_lane - 1) /
@@ -1831,11 +1927,13 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     }
     b->bclass = -1;
     for (int c = 0; c < N_BATCH_CLASSES; ++c)
-        if (BATCH_CLASSES[c].x >= need_i && BATCH_CLASSES[c].y >= need_s) {
+        if (TILE_CLASSES[c].ipt * BLK >= max_inst && TILE_CLASSES[c].lm >= max_local) {
             b->bclass = c;
             break;
         }
-    if (b->bclass < 0 || b->lds > b->hs[0]->lds_limit) return PM_EINVAL;
+    if (b->bclass < 0) return PM_EINVAL;
+    for (pm_handle *h : b->hs) b->lds = std::max(b->lds, tiled_lds_bytes<double>(h->dim, b->bclass, h->max_deg));
+    if (b->lds > b->hs[0]->lds_limit) return PM_EINVAL;
     if (b->lds > 65536)
         HIPCK(hipFuncSetAttribute(batch_apply_kernel(b->bclass), hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds)));
     b->n_aslots = int(aslots.size());

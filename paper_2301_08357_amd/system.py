@@ -274,3 +274,48 @@ class PressureBatch:
                                             _stream_handle(stream))
         check(code, "pressure_batch_finish")
         return SolveResult(out, code, it.value, None, tr.value)
+
+
+def default_tune_cache():
+    """Path of the autotuners' cache file: $PM_TUNE_CACHE, else
+    ~/.cache/paper_2301_08357_amd/tune.txt."""
+    import os
+    p = os.environ.get("PM_TUNE_CACHE")
+    if p:
+        return p
+    d = os.path.join(os.path.expanduser("~"), ".cache", "paper_2301_08357_amd")
+    os.makedirs(d, exist_ok=True)
+    return os.path.join(d, "tune.txt")
+
+
+def _cache_arg(cache):
+    if cache is False:
+        return None
+    return (default_tune_cache() if cache is None else str(cache)).encode()
+
+
+def tune_batch(systems, iters=64, cache=None):
+    """Batch launch shape picked by the library's autotuner.  Returns
+    (tiles_per_slot, nodes_per_lane, ms_per_iteration).  cache: None for the
+    default file, False for none, or a path."""
+    n = len(systems)
+    hs = (ctypes.c_void_p * n)(*[s._h.value for s in systems])
+    out = (ctypes.c_int32 * 2)()
+    ms = ctypes.c_double(0.0)
+    check(load().pressure_batch_tune(hs, n, int(iters), _cache_arg(cache), out, ctypes.byref(ms)),
+          "pressure_batch_tune")
+    return int(out[0]), int(out[1]), ms.value
+
+
+def tune_tile(prob, flags=_lib.PM_FP64, iters=32, cache=None):
+    """Tile-size flags picked by the library's autotuner for a synth
+    Problem.  Returns (flags, ms_per_iteration)."""
+    m = prob.mesh
+    a = _MeshArgs(m.dim, m.coords, m.elems, m.dirichlet, m.lattice)
+    c = _np(prob.coef, np.float64)
+    f = ctypes.c_int32(0)
+    ms = ctypes.c_double(0.0)
+    check(load().pressure_tune_tile(a.ref(), _ptr(c), float(prob.alpha), float(np.sqrt(prob.beta)), int(flags),
+                                    int(iters), _cache_arg(cache), ctypes.byref(f), ctypes.byref(ms)),
+          "pressure_tune_tile")
+    return int(f.value), ms.value

@@ -131,3 +131,25 @@ def structured_mesh(dim, n, jitter=0.0, seed=0):
     dirichlet = (~interior).astype(np.uint8)
     return Mesh(dim=dim, n=n, coords=np.ascontiguousarray(coords), elems=elems,
                 dirichlet=dirichlet, lattice=lat)
+
+
+def fan_mesh(k=80):
+    """An unstructured 2D mesh with one high-degree node: the centre of a
+    disk joined to a ring of k nodes at radius 1 (k triangles meet there),
+    and a second ring of k nodes at radius 2 joined to the first by 2k
+    triangles.  The outer ring is Dirichlet.  Counter-clockwise triangles;
+    no lattice (Morton keys come from the coordinates)."""
+    ang = 2.0 * np.pi * np.arange(k) / k
+    ring1 = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    ring2 = 2.0 * np.stack([np.cos(ang + np.pi / k), np.sin(ang + np.pi / k)], axis=1)
+    coords = np.concatenate([np.zeros((1, 2)), ring1, ring2]).astype(np.float64)
+    a = 1 + np.arange(k)
+    b = 1 + (np.arange(k) + 1) % k
+    c = 1 + k + np.arange(k)
+    tri = [np.stack([np.zeros(k, dtype=np.int64), a, b], axis=1),
+           np.stack([a, c, b], axis=1),
+           np.stack([b, c, 1 + k + (np.arange(k) + 1) % k], axis=1)]
+    elems = np.concatenate(tri).astype(np.int32)
+    dirichlet = np.zeros(coords.shape[0], dtype=np.uint8)
+    dirichlet[1 + k:] = 1
+    return Mesh(2, 0, coords, elems, dirichlet, None)
