@@ -149,13 +149,26 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
 /* Same system by FP64 defect correction around an FP32 inner CG: the outer
  * residual, the dot-product accumulation and the solution update are FP64;
  * the inner operator data, vectors and apply are FP32.  Requires a handle
- * built with PM_FP32_INNER.  inner_rtol in (0,1) is the inner relative
- * tolerance; iters receives the total number of inner iterations and
- * outer (may be NULL) the number of outer corrections; res_hist (may be
- * NULL, capacity max_iter+1) receives the outer relative residuals. */
+ * built with PM_FP32_INNER.  Each correction step computes the FP64
+ * residual r = rhs - A x, runs the FP32 CG on A d = r until its residual has
+ * dropped by inner_rtol (in (0,1)), and adds d to x in FP64.  In the default
+ * mode (PM_MIXED_KEEP_DIRECTION, see pressure_set_mixed_mode) the inner CG
+ * is not restarted at a correction: its residual is replaced by the
+ * rounded FP64 residual and its search direction is kept (the "reliable
+ * update" form of mixed-precision CG, Clark et al., Comput. Phys. Commun.
+ * 181 (2010) 1517), so the inner iteration count stays close to a plain
+ * CG's; PM_MIXED_RESTART starts a fresh inner CG at every correction.
+ * iters receives the total number of inner iterations and outer (may be
+ * NULL) the number of corrections; res_hist (may be NULL, capacity
+ * max_iter+1) receives the FP64 relative residual at each correction. */
 int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                          double inner_rtol, int32_t max_iter, double *p_dev, int32_t *iters,
                          int32_t *outer, double *res_hist, double *true_relres, void *stream);
+
+/* Inner-solve mode of pressure_solve_mixed for this handle. */
+#define PM_MIXED_KEEP_DIRECTION 0
+#define PM_MIXED_RESTART 1
+int pressure_set_mixed_mode(pm_handle *h, int32_t mode);
 
 /* Device bytes pressure_setup would allocate for this mesh (operator
  * data, CG vectors and scratch), for admission control.  Host only. */

@@ -13,6 +13,7 @@ PM_OK, PM_NOT_CONVERGED, PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EBREAKDOWN, PM
 PM_FP64, PM_FP32_INNER = 1, 2
 PM_TILE_256, PM_TILE_512, PM_TILE_128 = 0x10, 0x20, 0x30
 PM_VARIANT_AUTO, PM_VARIANT_NODE, PM_VARIANT_TILED = 0, 1, 2
+PM_MIXED_KEEP_DIRECTION, PM_MIXED_RESTART = 0, 1
 
 # every symbol the header declares, with (restype, argtypes)
 _P = ctypes.c_void_p
@@ -40,6 +41,7 @@ SIGNATURES = {
     "pressure_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pressure_layout": (ctypes.c_int, [_PMESH, _P, _P, _P, _P, _P]),
     "pressure_set_variant": (ctypes.c_int, [_P, _i32]),
+    "pressure_set_mixed_mode": (ctypes.c_int, [_P, _i32]),
     "pressure_timing_enable": (ctypes.c_int, [_P, _i32]),
     "pressure_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
     "pressure_info": (ctypes.c_int, [_P, ctypes.POINTER(_i64), _i32]),

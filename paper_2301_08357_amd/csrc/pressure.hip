@@ -860,6 +860,22 @@ __global__ void __launch_bounds__(BLK) k_begin_inner(CGState *st, const double *
     }
 }
 
+// One block: the inner solve continues after an FP64 correction.  The
+// residual was just replaced (its partials are in part); the tolerance is
+// relative to it; iteration count, budget and search direction carry on.
+__global__ void __launch_bounds__(BLK) k_resume_inner(CGState *st, const double *part, int n, double rtol)
+{
+    __shared__ double red[BLK / 64];
+    const double bb = sum_partials(part, n, red);
+    if (threadIdx.x == 0) {
+        const double bn = sqrt(bb);
+        st->tol = rtol * bn;
+        st->rr = bb;
+        st->status = isfinite(bn) ? 0 : PM_EBREAKDOWN;
+        st->done = (!isfinite(bn) || !(bn > 0.0) || st->iter >= st->max_iter) ? 1 : 0;
+    }
+}
+
 // x += d (the inner correction, in FP64).
 __global__ void __launch_bounds__(BLK) k_correct(int N, double *__restrict__ x, const float *__restrict__ d32)
 {
@@ -892,6 +908,7 @@ struct pm_handle {
     double alpha = 0.0, dt = 0.0;
     int32_t flags = 0;
     int variant = PM_VARIANT_TILED;
+    int mixed_mode = PM_MIXED_KEEP_DIRECTION;
     int device = 0;
     // operator data (device)
     int *new2old = nullptr;
@@ -1696,7 +1713,8 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
     TRY(read_state(h, s));
     int status = h->hst->status;
     const double bnorm = h->hst->bnorm;
-    int total = 0, n_outer = 0;
+    int total = 0, n_outer = 0, k = 1;
+    const bool keep = h->mixed_mode == PM_MIXED_KEEP_DIRECTION;
     double rel = 0.0;
     if (status == 0 && !(bnorm > 0.0)) {
         // zero right-hand side: p = 0
@@ -1717,13 +1735,22 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
             break;
         }
         if (rel <= rtol || total >= max_iter || n_outer >= MAX_OUTER) break;
-        // inner FP32 CG on A32 d = r32 from d = 0
-        hipLaunchKernelGGL(k_to_inner, dim3(vg), dim3(BLK), 0, s, N, h->r, h->r32, h->d32, h->part_rr(0));
-        hipLaunchKernelGGL(k_begin_inner, dim3(1), dim3(BLK), 0, s, h->st_in, h->part_rr(0), int(vg), inner_rtol,
-                           max_iter - total);
+        // inner FP32 CG on A32 d = r32 from d = 0: a fresh CG (restart mode,
+        // and the first correction), or the running one with its residual
+        // replaced by the rounded FP64 residual and its direction kept
+        const bool resume = keep && n_outer > 0;
+        if (!resume) k = 1;
+        double *rr_next = h->part_rr((k - 1) & 1);   // r.r partials the next apply reads
+        hipLaunchKernelGGL(k_to_inner, dim3(vg), dim3(BLK), 0, s, N, h->r, h->r32, h->d32, rr_next);
+        if (resume)
+            hipLaunchKernelGGL(k_resume_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), inner_rtol);
+        else
+            hipLaunchKernelGGL(k_begin_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), inner_rtol,
+                               keep ? max_iter : max_iter - total);
         HIPCK(hipGetLastError());
-        int k = 1, chunk = 4;
-        bool first = true;
+        const int iter0 = resume ? h->hst_in->iter : 0;
+        int chunk = 4;
+        bool first = !resume;
         for (;;) {
             TRY(launch_iterations32(h, k, chunk, first, s));
             k += chunk;
@@ -1733,11 +1760,15 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
             HIPCK(hipStreamSynchronize(s));
             if (h->hst_in->done) break;
         }
-        total += h->hst_in->iter;
+        const int done_iter = h->hst_in->iter;   // last completed inner iteration
+        k = done_iter + 1;
+        total = keep ? done_iter : total + done_iter;
         if (h->hst_in->status != 0) {
             status = h->hst_in->status;
             break;
         }
+        // no inner progress (the rounded residual is zero, d = 0): x is final
+        if (done_iter == iter0) break;
         hipLaunchKernelGGL(k_correct, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->x, h->d32);
         HIPCK(hipGetLastError());
         ++n_outer;
@@ -1766,6 +1797,13 @@ int pressure_set_variant(pm_handle *h, int32_t variant)
     case PM_VARIANT_NODE: h->variant = PM_VARIANT_NODE; return PM_OK;
     default: return PM_EINVAL;
     }
+}
+
+int pressure_set_mixed_mode(pm_handle *h, int32_t mode)
+{
+    if (!h || (mode != PM_MIXED_KEEP_DIRECTION && mode != PM_MIXED_RESTART)) return PM_EINVAL;
+    h->mixed_mode = mode;
+    return PM_OK;
 }
 
 int pressure_timing_enable(pm_handle *h, int32_t enable)

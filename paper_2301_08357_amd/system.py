@@ -138,6 +138,9 @@ class PressureSystem:
     def set_variant(self, variant):
         check(load().pressure_set_variant(self._h, int(variant)), "pressure_set_variant")
 
+    def set_mixed_mode(self, mode):
+        check(load().pressure_set_mixed_mode(self._h, int(mode)), "pressure_set_mixed_mode")
+
     def apply(self, x, y=None, stream=None):
         import torch
         if y is None:
@@ -160,7 +163,7 @@ class PressureSystem:
         check(st, "pressure_solve")
         return SolveResult(out, st, it.value, hist[: it.value + 1].copy(), tr.value)
 
-    def solve_mixed(self, rhs, x0=None, rtol=1e-10, inner_rtol=1e-4, max_iter=20000, out=None, stream=None):
+    def solve_mixed(self, rhs, x0=None, rtol=1e-10, inner_rtol=1e-2, max_iter=20000, out=None, stream=None):
         import torch
         if out is None:
             out = torch.empty_like(rhs)

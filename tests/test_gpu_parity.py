@@ -268,19 +268,24 @@ def test_tiled_and_node_kernels_agree_bitwise(tile):
 
 
 # ------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("mode", [pm.PM_MIXED_KEEP_DIRECTION, pm.PM_MIXED_RESTART])
 @pytest.mark.parametrize("name,make", [PROBLEMS[0], PROBLEMS[1], PROBLEMS[3]])
-def test_mixed_precision_reaches_fp64_residual(name, make):
+def test_mixed_precision_reaches_fp64_residual(name, make, mode):
     """FP32 inner CG inside FP64 defect correction: the oracle's FP64
     operator accepts the result at the requested tolerance, and the result
-    agrees with the oracle's FP64 CG solution."""
+    agrees with the oracle's FP64 CG solution.  Keeping the inner search
+    direction across corrections keeps the inner iteration count close to
+    the FP64 CG's."""
     prob = make()
     m = prob.mesh
-    print("case", name, flush=True)
+    print("case", name, "mode", mode, flush=True)
     A = oracle.assemble_problem(prob)
     b = _rhs_for(prob, A)
-    x_ref, st_ref, _, _, _ = oracle.cg(A, b, rtol=prob.rtol, max_iter=20000, dirichlet=m.dirichlet)
+    x_ref, st_ref, it_ref, _, _ = oracle.cg(A, b, rtol=prob.rtol, max_iter=20000, dirichlet=m.dirichlet)
     s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER)
-    res = s.solve_mixed(_dev(b), rtol=prob.rtol, inner_rtol=1e-4, max_iter=20000)
+    s.set_mixed_mode(mode)
+    eta = 1e-2 if mode == pm.PM_MIXED_KEEP_DIRECTION else 1e-4
+    res = s.solve_mixed(_dev(b), rtol=prob.rtol, inner_rtol=eta, max_iter=20000)
     x = _host(res.p)
     assert res.status == 0 and res.outer >= 1
     accept = np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)
@@ -289,8 +294,10 @@ def test_mixed_precision_reaches_fp64_residual(name, make):
     assert np.all(np.diff(res.hist) < 0) and res.hist[-1] <= prob.rtol
     rel = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
     assert rel <= 1e-8, rel
+    if mode == pm.PM_MIXED_KEEP_DIRECTION:
+        assert res.iters <= 1.5 * it_ref + 20, (res.iters, it_ref)
     # bitwise reproducible
-    res2 = s.solve_mixed(_dev(b), rtol=prob.rtol, inner_rtol=1e-4, max_iter=20000)
+    res2 = s.solve_mixed(_dev(b), rtol=prob.rtol, inner_rtol=eta, max_iter=20000)
     assert res2.iters == res.iters
     assert np.array_equal(_host(res2.p).view(np.uint64), x.view(np.uint64))
     s.close()
