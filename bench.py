@@ -58,6 +58,7 @@ def main():
                     help="cube64 (default line) or one of the other synthetic workloads")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
+    ap.add_argument("--serve-mixed", action="store_true", help="serving: mixed-precision solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -245,35 +246,58 @@ def _batch_problems(n):
 
 def bench_batch(args):
     """256 meshes (2D and 3D), nodes log-uniform in [2e3, 2e5], w log-uniform
-    in [1e-6, 1]: one batched FP64 solve of all of them per step."""
+    in [1e-6, 1]: one batched FP64 solve of all of them per step, in the
+    launch shape picked by the library's autotuner; then the same batch as
+    mixed-precision solves (FP32 inner CG, FP64 corrections), timed after."""
     import torch
     import paper_2301_08357_amd as pm
     probs = _batch_problems(256)
-    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    systems = [pm.PressureSystem.from_problem(p, flags=pm.PM_FP64 | pm.PM_FP32_INNER) for p in probs]
     rhs = [s.apply(torch.tensor(p.extra["xstar"], device="cuda")) for s, p in zip(systems, probs)]
-    batch = pm.PressureBatch(systems, tiles_per_slot=8, nodes_per_lane=8)
-    nfree = np.array([int((p.mesh.dirichlet == 0).sum()) for p in probs])
-    for _ in range(args.warmup):
-        batch.solve(rhs, rtol=args.rtol)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dofit = 0.0
-    for _ in range(args.steps):
-        code, res = batch.solve(rhs, rtol=args.rtol)
-        if code != 0:
-            raise RuntimeError("batch status %d" % code)
-        dofit += float((nfree * np.array([r.iters for r in res])).sum())
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    tps, npl, tuned_ms = pm.tune_batch(systems, iters=32)
+    tune_s = time.perf_counter() - t0
+    nfree = np.array([int((p.mesh.dirichlet == 0).sum()) for p in probs])
+
+    def timed(batch):
+        for _ in range(args.warmup):
+            batch.solve(rhs, rtol=args.rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dofit = 0.0
+        for _ in range(args.steps):
+            code, res = batch.solve(rhs, rtol=args.rtol)
+            if code != 0:
+                raise RuntimeError("batch status %d" % code)
+            dofit += float((nfree * np.array([r.iters for r in res])).sum())
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, dofit, res
+
+    batch = pm.PressureBatch(systems, tiles_per_slot=tps, nodes_per_lane=npl)
+    el, dofit, res = timed(batch)
     its = np.array([r.iters for r in res])
+    ref = [r.p.clone() for r in res]
+    batch.close()
+    mixed = {}
+    if not args.no_mixed:
+        mb = pm.PressureBatch(systems, tiles_per_slot=tps, nodes_per_lane=npl, mixed=True, inner_rtol=args.inner_rtol)
+        el_m, dofit_m, res_m = timed(mb)
+        diff = max(float(torch.linalg.norm(r.p - q) / torch.linalg.norm(q)) for r, q in zip(res_m, ref))
+        mixed = {"mixed_batch_ms": round(el_m / args.steps * 1e3, 3),
+                 "mixed_speedup_vs_fp64_batch": round(el / el_m, 3),
+                 "mixed_inner_iterations_mean": float(np.mean([r.iters for r in res_m])),
+                 "mixed_max_true_relres": max(r.true_relres for r in res_m),
+                 "mixed_max_rel_diff_vs_fp64": diff, "mixed_inner_rtol": args.inner_rtol}
+        mb.close()
     _common(args, round(dofit / el / 1e9, 4), "GDOF*iter/s", round(el / args.steps * 1e3, 3),
             {"workload": "batch256: 256 meshes (129 2D, 127 3D), nodes log-uniform [2e3,2e5] (10.9M total), "
                          "w log-uniform [1e-6,1], jitter 0.2h, rho~U[0.5,2], FP64 CG to rtol %g; one step = one "
                          "batched solve of all meshes" % args.rtol,
              "n_nodes_total": int(sum(p.mesh.n_nodes for p in probs))},
-            {"solves_per_s": round(256 * args.steps / el, 2), "iterations_max": int(its.max()),
-             "iterations_mean": float(its.mean()), "graph_iterations_per_replay": 16})
-    batch.close()
+            dict({"solves_per_s": round(256 * args.steps / el, 2), "iterations_max": int(its.max()),
+                  "iterations_mean": float(its.mean()), "graph_iterations_per_replay": 16,
+                  "tuned_tiles_per_slot": tps, "tuned_nodes_per_lane": npl,
+                  "tuned_ms_per_iteration": round(tuned_ms, 4), "tuning_s": round(tune_s, 2)}, **mixed))
     for s in systems:
         s.close()
 
@@ -281,50 +305,99 @@ def bench_batch(args):
 def bench_serve(args):
     """Serving: Poisson arrivals over the 256-mesh pool (uniform mesh choice),
     each request warm-started from its mesh's previous solution with the rhs
-    perturbed by 1 % (normal noise scaled to ||rhs|| / sqrt(N_free)).  The rate
-    is 0.8 x the saturated rate measured in a closed-loop pass."""
+    perturbed by 1 % (normal noise scaled to ||rhs|| / sqrt(N_free)).  The
+    main rate is 0.8 x the saturated rate measured in a closed-loop pass;
+    0.5 x and 0.95 x are extra points on fewer requests.  The same requests
+    served one at a time by single FP64 solves give the sequential rate."""
     import torch
     import paper_2301_08357_amd as pm
     from paper_2301_08357_amd.serve import PressureServer, Request
     from synth import fields, workloads
     probs = _batch_problems(256)
-    base = []
+    flags = pm.PM_FP64 | (pm.PM_FP32_INNER if args.serve_mixed else 0)
+    base, pool = [], []
     for p in probs:
-        s = pm.PressureSystem.from_problem(p)
+        s = pm.PressureSystem.from_problem(p, flags=flags)
         base.append(s.apply(torch.tensor(p.extra["xstar"], device="cuda")).clone())
-        s.close()
+        pool.append(s)
     free = [torch.tensor((p.mesh.dirichlet == 0).astype(np.float64), device="cuda") for p in probs]
     scale = [0.01 * float(torch.linalg.norm(b)) / float(f.sum()) ** 0.5 for b, f in zip(base, free)]
 
     def rhs_fn(req):
-        xi = torch.tensor(fields.perturbation(workloads.MASTER_SEED, req.rid, probs[req.mesh].mesh.n_nodes),
-                          device="cuda")
+        xi = fields.perturbation_torch(workloads.MASTER_SEED, req.rid, probs[req.mesh].mesh.n_nodes, "cuda")
         return base[req.mesh] + scale[req.mesh] * free[req.mesh] * xi
 
+    # sequential baseline: single solves (each handle with its own launch
+    # grids), one request at a time, warm starts
+    n_seq = min(500, args.requests)
+    _, choice = workloads.arrivals(n_seq, 1.0, 256)
+
+    def single(m, b, x0):
+        if args.serve_mixed:
+            return pool[m].solve_mixed(b, x0=x0, rtol=args.rtol, inner_rtol=args.inner_rtol)
+        return pool[m].solve(b, x0=x0, rtol=args.rtol)
+
+    single(0, rhs_fn(Request(rid=4 * 10 ** 6, mesh=0, arrival=0.0)), None)
+    last = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, m in enumerate(choice):
+        m = int(m)
+        r = single(m, rhs_fn(Request(rid=2 * 10 ** 6 + i, mesh=m, arrival=0.0)), last.get(m))
+        last[m] = r.p
+    torch.cuda.synchronize()
+    seq_rate = n_seq / (time.perf_counter() - t0)
+    del last
+    tps, npl, _ = pm.tune_batch(pool, iters=32)
+    for s in pool:
+        s.close()
+
     budget = int(args.budget_gb * 2 ** 30) if args.budget_gb > 0 else int(0.8 * torch.cuda.mem_get_info()[0])
+
+    def server():
+        return PressureServer(probs, budget, max_in_flight=256, rtol=args.rtol, tiles_per_slot=tps,
+                              nodes_per_lane=npl, mixed=args.serve_mixed, inner_rtol=args.inner_rtol)
+
     # closed loop: saturation rate
     n_cal = min(2000, args.requests)
     _, choice = workloads.arrivals(n_cal, 1.0, 256)
-    srv = PressureServer(probs, budget, max_in_flight=256, rtol=args.rtol, tiles_per_slot=8, nodes_per_lane=8)
+    srv = server()
     srv.run([Request(rid=10 ** 6 + i, mesh=int(m), arrival=0.0) for i, m in enumerate(choice)], rhs_fn)
     sat = srv.stats.solves_per_s
     srv.close()
-    rate = 0.8 * sat
-    times, choice = workloads.arrivals(args.requests, rate, 256)
-    srv = PressureServer(probs, budget, max_in_flight=256, rtol=args.rtol, tiles_per_slot=8, nodes_per_lane=8)
-    done = srv.run([Request(rid=i, mesh=int(m), arrival=float(t)) for i, (t, m) in enumerate(zip(times, choice))],
-                   rhs_fn)
-    st = srv.stats
-    bad = sum(1 for r in done if r.status != 0 or r.true_relres > args.rtol)
-    srv.close()
+
+    def point(factor, n_req, rid0):
+        times, choice = workloads.arrivals(n_req, factor * sat, 256)
+        srv = server()
+        done = srv.run([Request(rid=rid0 + i, mesh=int(m), arrival=float(t))
+                        for i, (t, m) in enumerate(zip(times, choice))], rhs_fn)
+        st = srv.stats
+        bad = sum(1 for r in done if r.status != 0 or r.true_relres > args.rtol)
+        srv.close()
+        return st, bad
+
+    st, bad = point(0.8, args.requests, 0)
+    extra_points = []
+    for f in (0.5, 0.95):
+        e, eb = point(f, min(2000, args.requests), 3 * 10 ** 6 + int(f * 100) * 10 ** 4)
+        extra_points.append({"rate_factor": f, "rate_per_s": round(f * sat, 2), "requests": e.n,
+                             "solves_per_s": round(e.solves_per_s, 3), "latency_ms_p50": round(e.latency_ms["p50"], 3),
+                             "latency_ms_p99": round(e.latency_ms["p99"], 3), "failed": eb})
+    kind = "mixed-precision (FP32 inner, FP64 corrections)" if args.serve_mixed else "FP64"
     _common(args, round(st.solves_per_s, 3), "solves/s", round(st.makespan_s * 1e3, 3),
             {"workload": "serve: %d requests, Poisson arrivals at 0.8 x saturation over the 256-mesh pool, warm "
-                         "starts, 1%% rhs perturbation, rtol %g" % (args.requests, args.rtol),
-             "rate_per_s": round(rate, 2), "saturation_solves_per_s": round(sat, 2), "budget_bytes": budget},
+                         "starts, 1%% rhs perturbation, %s solves to rtol %g" % (args.requests, kind, args.rtol),
+             "rate_per_s": round(0.8 * sat, 2), "saturation_solves_per_s": round(sat, 2), "budget_bytes": budget,
+             "tiles_per_slot": tps, "nodes_per_lane": npl},
             {"latency_ms_p50": round(st.latency_ms["p50"], 3), "latency_ms_p99": round(st.latency_ms["p99"], 3),
              "mean_iterations_cold": round(st.mean_iters_cold, 1), "mean_iterations_warm": round(st.mean_iters_warm, 1),
              "loads": st.loads, "evictions": st.evictions, "batch_rebuilds": st.rebuilds,
-             "max_in_flight": st.max_in_flight_seen, "failed": bad})
+             "max_in_flight": st.max_in_flight_seen, "failed": bad,
+             "host_time_s": {"steps": round(st.t_step, 2), "finish": round(st.t_finish, 2),
+                             "admit": round(st.t_admit, 2), "rebuild": round(st.t_rebuild, 2)},
+             "sequential_solves_per_s": round(seq_rate, 3),
+             "speedup_vs_sequential_single_solves": round(st.solves_per_s / seq_rate, 3),
+             "extra_points": extra_points})
 
 
 def mixed_comparison(systems, rhs, xstar, args, fp64_solve_s):

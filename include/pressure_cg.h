@@ -241,6 +241,19 @@ typedef struct pm_batch pm_batch;
  * shape, handles on different devices), PM_ENOMEM, PM_EHIP. */
 int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *params, pm_batch **out);
 
+/* A batch of mixed-precision solves (pressure_solve_mixed for every mesh):
+ * the FP32 inner CG iterations of all meshes run in the batched launches;
+ * when a mesh's inner solve has dropped its residual by inner_rtol (in
+ * (0,1)) the next step computes that mesh's FP64 correction and residual
+ * and, unless it has converged, continues its inner solve (in the handle's
+ * pressure_set_mixed_mode).  Every handle must be built with PM_FP32_INNER;
+ * params and errors as pressure_batch_create.  pressure_batch_solve, _begin,
+ * _step and _finish then run mixed solves (iters counts inner iterations;
+ * done[m] is set when mesh m's whole solve has finished), and each result
+ * equals pressure_solve_mixed on the same handle bit for bit. */
+int pressure_batch_create_mixed(pm_handle *const *handles, int32_t n, const int32_t *params, double inner_rtol,
+                                pm_batch **out);
+
 /* Solve all meshes of the batch.  rhs_dev, x0_dev and p_dev are host arrays
  * of n device pointers (x0_dev may be NULL, or hold NULL entries, for a zero
  * initial guess); iters, true_relres and status are host arrays of n

@@ -46,6 +46,7 @@ SIGNATURES = {
     "pressure_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
     "pressure_info": (ctypes.c_int, [_P, ctypes.POINTER(_i64), _i32]),
     "pressure_batch_create": (ctypes.c_int, [_P, _i32, _P, ctypes.POINTER(_P)]),
+    "pressure_batch_create_mixed": (ctypes.c_int, [_P, _i32, _P, _dbl, ctypes.POINTER(_P)]),
     "pressure_batch_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, _P, _P, _P, _P]),
     "pressure_batch_set_graph": (ctypes.c_int, [_P, _i32]),
     "pressure_batch_next_index": (ctypes.c_int, [_P, ctypes.POINTER(_i32)]),

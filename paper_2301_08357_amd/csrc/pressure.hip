@@ -739,15 +739,18 @@ __global__ void k_reopen(CGState *st)
 // iterations can be captured once in a HIP graph and replayed.  Meshes that
 // have converged skip their slots.
 
-struct BatchMesh {
+template <class R>
+struct BatchMeshT {
     int dim, N;
-    MeshT<double> g;
-    TileArgsT<double> ta;
-    double *x, *r, *q, *p0, *p1, *hist;
+    MeshT<R> g;
+    TileArgsT<R> ta;
+    R *x, *r, *q, *p0, *p1;   // FP32 batches: the inner solve's d, r, q, p
+    double *hist;
     CGState *st;
     double *part_pq, *rr0, *rr1;
     int n_ab, n_vb;   // apply / update virtual blocks of this mesh
 };
+using BatchMesh = BatchMeshT<double>;
 
 struct BatchCtl {
     int k_apply;   // iteration the next apply launch runs
@@ -756,50 +759,55 @@ struct BatchCtl {
     int pad;
 };
 
-// C: size class (128-node tiles) covering every mesh of the batch
-template <int C>
-__global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMesh *__restrict__ meshes,
+// C: size class (128-node tiles) covering every mesh of the batch.  Each
+// solve numbers its iterations from its first launch (k_first) and picks
+// its p and r.r buffers by the parity of that number, as a single-mesh
+// solve does; so a solve may start, or continue, at any launch.
+template <int C, class R>
+__global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
                                                      const int2 *__restrict__ slots, BatchCtl *ctl)
 {
     extern __shared__ double smem_d[];
     __shared__ double red[BLK / 64];
     const int2 ms = slots[blockIdx.x];
-    const BatchMesh &M = meshes[ms.x];
+    const BatchMeshT<R> &M = meshes[ms.x];
     const int k = ctl->k_apply;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_update = k;
-    // buffers alternate with the launch index k; the solve's own iteration
-    // number counts from its first launch
-    IterT<double> it;
-    it.k = k - M.st->k_first + 1;
-    it.first = (it.k == 1) ? 1 : 0;
+    const int kl = k - M.st->k_first + 1;
+    IterT<R> it;
+    it.k = kl;
+    it.first = (kl == 1) ? 1 : 0;
     it.r = M.r;
-    it.p_old = (k & 1) ? M.p0 : M.p1;   // p_{k-1}
-    it.p_new = (k & 1) ? M.p1 : M.p0;   // p_k
+    it.p_old = (kl & 1) ? M.p0 : M.p1;   // p_{k-1}
+    it.p_new = (kl & 1) ? M.p1 : M.p0;   // p_k
     it.q = M.q;
     it.st = M.st;
     it.hist = M.hist;
     it.part_pq = M.part_pq;
-    it.rr_cur = (k & 1) ? M.rr0 : M.rr1;
-    it.rr_prev = (k & 1) ? M.rr1 : M.rr0;
+    it.rr_cur = (kl & 1) ? M.rr0 : M.rr1;
+    it.rr_prev = (kl & 1) ? M.rr1 : M.rr0;
     it.n_vblocks = M.n_vb;
     constexpr TileClass tc = TILE_CLASSES[C];
     static_assert(tc.t == 128, "batched meshes use 128-node tiles");
+    R *smem = reinterpret_cast<R *>(smem_d);
     if (M.dim == 3)
-        apply_tiled_body<3, true, double, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
+        apply_tiled_body<3, true, R, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y, M.n_ab);
     else
-        apply_tiled_body<2, true, double, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem_d, red, ms.y, M.n_ab);
+        apply_tiled_body<2, true, R, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y, M.n_ab);
 }
 
-__global__ void __launch_bounds__(BLK) k_batch_update(const BatchMesh *__restrict__ meshes,
+template <class R>
+__global__ void __launch_bounds__(BLK) k_batch_update(const BatchMeshT<R> *__restrict__ meshes,
                                                       const int2 *__restrict__ slots, BatchCtl *ctl)
 {
     __shared__ double red[BLK / 64];
     const int2 ms = slots[blockIdx.x];
-    const BatchMesh &M = meshes[ms.x];
+    const BatchMeshT<R> &M = meshes[ms.x];
     const int k = ctl->k_update;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_apply = k + 1;
-    update_body<double>(M.N, M.x, M.r, (k & 1) ? M.p1 : M.p0, M.q, M.st, M.part_pq, M.n_ab,
-                        (k & 1) ? M.rr0 : M.rr1, (k & 1) ? M.rr1 : M.rr0, red, ms.y, M.n_vb);
+    const int kl = k - M.st->k_first + 1;
+    update_body<R>(M.N, M.x, M.r, (kl & 1) ? M.p1 : M.p0, M.q, M.st, M.part_pq, M.n_ab,
+                   (kl & 1) ? M.rr0 : M.rr1, (kl & 1) ? M.rr1 : M.rr0, red, ms.y, M.n_vb);
 }
 
 __global__ void k_set_done(CGState *st)
@@ -808,7 +816,8 @@ __global__ void k_set_done(CGState *st)
 }
 
 // One block: number of finished meshes, and a copy of every state.
-__global__ void __launch_bounds__(BLK) k_batch_status(const BatchMesh *__restrict__ meshes, int n, BatchCtl *ctl,
+template <class R>
+__global__ void __launch_bounds__(BLK) k_batch_status(const BatchMeshT<R> *__restrict__ meshes, int n, BatchCtl *ctl,
                                                       CGState *states)
 {
     __shared__ int cnt;
@@ -843,7 +852,7 @@ __global__ void __launch_bounds__(BLK) k_to_inner(int N, const double *__restric
 
 // One block: state of an inner solve (tolerance relative to its rhs).
 __global__ void __launch_bounds__(BLK) k_begin_inner(CGState *st, const double *part, int n, double rtol,
-                                                     int max_iter)
+                                                     int max_iter, int k_first)
 {
     __shared__ double red[BLK / 64];
     const double bb = sum_partials(part, n, red);
@@ -857,13 +866,15 @@ __global__ void __launch_bounds__(BLK) k_begin_inner(CGState *st, const double *
         st->max_iter = max_iter;
         st->status = isfinite(bn) ? 0 : PM_EBREAKDOWN;
         st->done = (!isfinite(bn) || !(bn > 0.0) || max_iter <= 0) ? 1 : 0;
+        st->k_first = k_first;
     }
 }
 
 // One block: the inner solve continues after an FP64 correction.  The
 // residual was just replaced (its partials are in part); the tolerance is
 // relative to it; iteration count, budget and search direction carry on.
-__global__ void __launch_bounds__(BLK) k_resume_inner(CGState *st, const double *part, int n, double rtol)
+__global__ void __launch_bounds__(BLK) k_resume_inner(CGState *st, const double *part, int n, double rtol,
+                                                      int k_first)
 {
     __shared__ double red[BLK / 64];
     const double bb = sum_partials(part, n, red);
@@ -873,6 +884,7 @@ __global__ void __launch_bounds__(BLK) k_resume_inner(CGState *st, const double 
         st->rr = bb;
         st->status = isfinite(bn) ? 0 : PM_EBREAKDOWN;
         st->done = (!isfinite(bn) || !(bn > 0.0) || st->iter >= st->max_iter) ? 1 : 0;
+        st->k_first = k_first;
     }
 }
 
@@ -1366,6 +1378,8 @@ int pressure_footprint(const pm_mesh *mesh, int32_t flags, uint64_t *bytes)
     b += I * (8 + 8 + 4) + 8 * N + 8 * N;   // tiles: records, factors, element ids; halo lists, flags
     b += 7 * 8 * N;                         // b, x, r, q, t, p (x2)
     b += 8 * (AGRID_MAX + 3 * VGRID_MAX) + 1024 * 8 + 256;
+    if (flags & PM_FP32_INNER)   // FP32 coordinates, factors and inner-CG vectors
+        b += 4 * d * N + 4 * E + 4 * I + 5 * 4 * N + 256;
     *bytes = b;
     return PM_OK;
 }
@@ -1743,10 +1757,10 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
         double *rr_next = h->part_rr((k - 1) & 1);   // r.r partials the next apply reads
         hipLaunchKernelGGL(k_to_inner, dim3(vg), dim3(BLK), 0, s, N, h->r, h->r32, h->d32, rr_next);
         if (resume)
-            hipLaunchKernelGGL(k_resume_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), inner_rtol);
+            hipLaunchKernelGGL(k_resume_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), inner_rtol, 1);
         else
             hipLaunchKernelGGL(k_begin_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), inner_rtol,
-                               keep ? max_iter : max_iter - total);
+                               keep ? max_iter : max_iter - total, 1);
         HIPCK(hipGetLastError());
         const int iter0 = resume ? h->hst_in->iter : 0;
         int chunk = 4;
@@ -1842,8 +1856,10 @@ int pressure_info(pm_handle *h, int64_t *info, int32_t n_info)
 struct pm_batch {
     std::vector<pm_handle *> hs;
     int device = 0;
+    bool mixed = false;            // FP32 inner solves with FP64 corrections
+    double inner_rtol = 1e-2;
     int tiles_per_slot = 4, nodes_per_lane = 8;
-    BatchMesh *d_meshes = nullptr;
+    void *d_meshes = nullptr;      // BatchMeshT<double> or BatchMeshT<float>
     int2 *d_aslots = nullptr, *d_uslots = nullptr;
     int n_aslots = 0, n_uslots = 0;
     BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
@@ -1856,9 +1872,20 @@ struct pm_batch {
     hipGraphExec_t gexec = nullptr;
     int graph_iters = 16;
     int k_next = 1;          // launch index of the next batched iteration
+    // mixed batches: host bookkeeping of each mesh's solve
+    struct Mixed {
+        int phase = 0;       // MX_IDLE, MX_RESIDUAL, MX_INNER, MX_FINISHED
+        double rtol = 0.0, rel = 0.0;
+        int max_iter = 0, iters = 0, n_outer = 0, status = 0, iter0 = 0;
+    };
+    std::vector<Mixed> mx;
+    std::vector<double *> hist_seen;   // history pointers in the uploaded descriptors
 };
 
 namespace {
+
+enum { MX_IDLE = 0, MX_RESIDUAL = 1, MX_INNER = 2, MX_FINISHED = 3 };
+constexpr int MAX_CORRECTIONS = 64;
 
 // The batched apply runs the size classes of 128-node tiles (the first
 // N_BATCH_CLASSES entries of TILE_CLASSES).
@@ -1866,42 +1893,50 @@ constexpr int N_BATCH_CLASSES = 6;
 static_assert(TILE_CLASSES[N_BATCH_CLASSES - 1].t == 128 && TILE_CLASSES[N_BATCH_CLASSES].t != 128,
               "batch classes are the 128-node classes");
 
+template <class R>
 const void *batch_apply_kernel(int c)
 {
     switch (c) {
-    case 0: return (const void *)k_batch_apply<0>;
-    case 1: return (const void *)k_batch_apply<1>;
-    case 2: return (const void *)k_batch_apply<2>;
-    case 3: return (const void *)k_batch_apply<3>;
-    case 4: return (const void *)k_batch_apply<4>;
-    case 5: return (const void *)k_batch_apply<5>;
+    case 0: return (const void *)k_batch_apply<0, R>;
+    case 1: return (const void *)k_batch_apply<1, R>;
+    case 2: return (const void *)k_batch_apply<2, R>;
+    case 3: return (const void *)k_batch_apply<3, R>;
+    case 4: return (const void *)k_batch_apply<4, R>;
+    case 5: return (const void *)k_batch_apply<5, R>;
     default: return nullptr;
     }
 }
 
-template <int C>
+template <int C, class R>
 void launch_batch_apply_c(pm_batch *b, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch_apply<C>), dim3(b->n_aslots), dim3(BLK), b->lds, s, b->d_meshes, b->d_aslots,
-                       b->d_ctl);
+    hipLaunchKernelGGL((k_batch_apply<C, R>), dim3(b->n_aslots), dim3(BLK), b->lds, s,
+                       (const BatchMeshT<R> *)b->d_meshes, b->d_aslots, b->d_ctl);
+}
+
+template <class R>
+int launch_batch_iterations_t(pm_batch *b, int count, hipStream_t s)
+{
+    for (int i = 0; i < count; ++i) {
+        switch (b->bclass) {
+        case 0: launch_batch_apply_c<0, R>(b, s); break;
+        case 1: launch_batch_apply_c<1, R>(b, s); break;
+        case 2: launch_batch_apply_c<2, R>(b, s); break;
+        case 3: launch_batch_apply_c<3, R>(b, s); break;
+        case 4: launch_batch_apply_c<4, R>(b, s); break;
+        case 5: launch_batch_apply_c<5, R>(b, s); break;
+        default: return PM_EINVAL;
+        }
+        hipLaunchKernelGGL(k_batch_update<R>, dim3(b->n_uslots), dim3(BLK), 0, s,
+                           (const BatchMeshT<R> *)b->d_meshes, b->d_uslots, b->d_ctl);
+    }
+    HIPCK(hipGetLastError());
+    return PM_OK;
 }
 
 int launch_batch_iterations(pm_batch *b, int count, hipStream_t s)
 {
-    for (int i = 0; i < count; ++i) {
-        switch (b->bclass) {
-        case 0: launch_batch_apply_c<0>(b, s); break;
-        case 1: launch_batch_apply_c<1>(b, s); break;
-        case 2: launch_batch_apply_c<2>(b, s); break;
-        case 3: launch_batch_apply_c<3>(b, s); break;
-        case 4: launch_batch_apply_c<4>(b, s); break;
-        case 5: launch_batch_apply_c<5>(b, s); break;
-        default: return PM_EINVAL;
-        }
-        hipLaunchKernelGGL(k_batch_update, dim3(b->n_uslots), dim3(BLK), 0, s, b->d_meshes, b->d_uslots, b->d_ctl);
-    }
-    HIPCK(hipGetLastError());
-    return PM_OK;
+    return b->mixed ? launch_batch_iterations_t<float>(b, count, s) : launch_batch_iterations_t<double>(b, count, s);
 }
 
 void batch_free(pm_batch *b)
@@ -1919,6 +1954,74 @@ void batch_free(pm_batch *b)
     delete b;
 }
 
+// Descriptor of one mesh of the batch: its FP64 solve, or (mixed) its FP32
+// inner solve.
+template <class R>
+BatchMeshT<R> batch_mesh(pm_handle *h);
+
+template <>
+BatchMeshT<double> batch_mesh<double>(pm_handle *h)
+{
+    BatchMeshT<double> M;
+    M.dim = h->dim;
+    M.N = int(h->N);
+    M.g = make_mesh<double>(h);
+    M.ta = make_tiles<double>(h);
+    M.x = h->x;
+    M.r = h->r;
+    M.q = h->q;
+    M.p0 = h->pbuf[0];
+    M.p1 = h->pbuf[1];
+    M.hist = h->hist;
+    M.st = h->st;
+    M.part_pq = h->part_pq();
+    M.rr0 = h->part_rr(0);
+    M.rr1 = h->part_rr(1);
+    M.n_ab = h->n_ablocks;
+    M.n_vb = h->n_vblocks;
+    return M;
+}
+
+template <>
+BatchMeshT<float> batch_mesh<float>(pm_handle *h)
+{
+    BatchMeshT<float> M;
+    M.dim = h->dim;
+    M.N = int(h->N);
+    M.g = make_mesh<float>(h);
+    M.ta = make_tiles<float>(h);
+    M.x = h->d32;
+    M.r = h->r32;
+    M.q = h->q32;
+    M.p0 = h->p32[0];
+    M.p1 = h->p32[1];
+    M.hist = h->hist;
+    M.st = h->st_in;
+    M.part_pq = h->part_pq();
+    M.rr0 = h->part_rr(0);
+    M.rr1 = h->part_rr(1);
+    M.n_ab = h->n_ablocks32;
+    M.n_vb = h->n_vblocks;
+    return M;
+}
+
+template <class R>
+int upload_meshes(pm_batch *b)
+{
+    std::vector<BatchMeshT<R>> meshes;
+    b->hist_seen.clear();
+    for (pm_handle *h : b->hs) {
+        meshes.push_back(batch_mesh<R>(h));
+        b->hist_seen.push_back(h->hist);
+    }
+    if (!b->d_meshes && hipMalloc(&b->d_meshes, sizeof(BatchMeshT<R>) * meshes.size()) != hipSuccess)
+        return PM_ENOMEM;
+    HIPCK(hipMemcpyAsync(b->d_meshes, meshes.data(), sizeof(BatchMeshT<R>) * meshes.size(), hipMemcpyHostToDevice,
+                         b->stream));
+    HIPCK(hipStreamSynchronize(b->stream));
+    return PM_OK;
+}
+
 int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const int32_t *params)
 {
     int k_start = 1;
@@ -1930,39 +2033,24 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     }
     HIPCK(hipGetDevice(&b->device));
     int max_inst = 1, max_local = 1;
-    std::vector<BatchMesh> meshes(n);
     std::vector<int2> aslots, uslots;
     for (int m = 0; m < n; ++m) {
         pm_handle *h = handles[m];
         if (!h || h->device != b->device || h->tile_class < 0 || TILE_CLASSES[h->tile_class].t != 128)
             return PM_EINVAL;
+        if (b->mixed && !h->coords32) return PM_EINVAL;   // handle built without PM_FP32_INNER
         max_inst = std::max(max_inst, h->max_inst);
         max_local = std::max(max_local, h->max_local);
         // the batch's grids become the handle's
         h->n_ablocks = std::max(1, std::min(AGRID_MAX, (h->n_tiles + b->tiles_per_slot - 1) / b->tiles_per_slot));
+        h->n_ablocks32 = h->n_ablocks;
         h->n_vblocks = int(std::max<int64_t>(1, std::min<int64_t>(VGRID_MAX, (h->N + int64_t(BLK) * b->nodes_per_lane - 1) /
                                                                                  (int64_t(BLK) * b->nodes_per_lane))));
-        BatchMesh &M = meshes[m];
-        M.dim = h->dim;
-        M.N = int(h->N);
-        M.g = make_mesh<double>(h);
-        M.ta = make_tiles<double>(h);
-        M.x = h->x;
-        M.r = h->r;
-        M.q = h->q;
-        M.p0 = h->pbuf[0];
-        M.p1 = h->pbuf[1];
-        M.hist = h->hist;
-        M.st = h->st;
-        M.part_pq = h->part_pq();
-        M.rr0 = h->part_rr(0);
-        M.rr1 = h->part_rr(1);
-        M.n_ab = h->n_ablocks;
-        M.n_vb = h->n_vblocks;
-        for (int j = 0; j < M.n_ab; ++j) aslots.push_back(make_int2(m, j));
-        for (int j = 0; j < M.n_vb; ++j) uslots.push_back(make_int2(m, j));
+        for (int j = 0; j < h->n_ablocks; ++j) aslots.push_back(make_int2(m, j));
+        for (int j = 0; j < h->n_vblocks; ++j) uslots.push_back(make_int2(m, j));
         b->hs.push_back(h);
     }
+    b->mx.assign(size_t(n), pm_batch::Mixed());
     b->bclass = -1;
     for (int c = 0; c < N_BATCH_CLASSES; ++c)
         if (TILE_CLASSES[c].ipt * BLK >= max_inst && TILE_CLASSES[c].lm >= max_local) {
@@ -1970,10 +2058,14 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
             break;
         }
     if (b->bclass < 0) return PM_EINVAL;
-    for (pm_handle *h : b->hs) b->lds = std::max(b->lds, tiled_lds_bytes<double>(h->dim, b->bclass, h->max_deg));
+    for (pm_handle *h : b->hs)
+        b->lds = std::max(b->lds, b->mixed ? tiled_lds_bytes<float>(h->dim, b->bclass, h->max_deg)
+                                           : tiled_lds_bytes<double>(h->dim, b->bclass, h->max_deg));
     if (b->lds > b->hs[0]->lds_limit) return PM_EINVAL;
-    if (b->lds > 65536)
-        HIPCK(hipFuncSetAttribute(batch_apply_kernel(b->bclass), hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds)));
+    if (b->lds > 65536) {
+        const void *k = b->mixed ? batch_apply_kernel<float>(b->bclass) : batch_apply_kernel<double>(b->bclass);
+        HIPCK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds)));
+    }
     b->n_aslots = int(aslots.size());
     b->n_uslots = int(uslots.size());
     auto up = [&](auto **dst, const auto &vec) -> int {
@@ -1982,7 +2074,6 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
         HIPCK(hipMemcpy(*dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice));
         return PM_OK;
     };
-    TRY(up(&b->d_meshes, meshes));
     TRY(up(&b->d_aslots, aslots));
     TRY(up(&b->d_uslots, uslots));
     if (hipMalloc((void **)&b->d_ctl, sizeof(BatchCtl)) != hipSuccess) return PM_ENOMEM;
@@ -1991,12 +2082,16 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     HIPCK(hipHostMalloc((void **)&b->h_states, sizeof(CGState) * n, hipHostMallocDefault));
     HIPCK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIPCK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+    TRY(b->mixed ? upload_meshes<float>(b) : upload_meshes<double>(b));
     // solves of the handles that are in flight continue at launch index k_start
     b->k_next = k_start;
     b->h_ctl->k_apply = k_start;
     b->h_ctl->k_update = k_start - 1;
     b->h_ctl->n_done = 0;
     HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
+    if (b->mixed)   // the inner solves are idle until a mixed solve starts
+        for (pm_handle *h : b->hs) hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, b->stream, h->st_in);
+    HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(b->stream));
     return PM_OK;
 }
@@ -2026,17 +2121,16 @@ int batch_capture(pm_batch *b)
     return PM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *params, pm_batch **out)
+int batch_create_common(pm_handle *const *handles, int32_t n, const int32_t *params, bool mixed, double inner_rtol,
+                        pm_batch **out)
 {
     if (!out || !handles || n < 1) return PM_EINVAL;
     *out = nullptr;
     pm_batch *b = nullptr;
     try {
         b = new pm_batch();
+        b->mixed = mixed;
+        b->inner_rtol = inner_rtol;
         int s = batch_create_impl(b, handles, n, params);
         if (s == PM_OK) s = batch_capture(b);
         if (s != PM_OK) {
@@ -2051,20 +2145,21 @@ int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *p
     return PM_OK;
 }
 
-void pressure_batch_destroy(pm_batch *b) { batch_free(b); }
-
-int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
+// The histories may have been reallocated (ensure_hist): refresh descriptors.
+int batch_refresh(pm_batch *b)
 {
-    if (!b || iterations_per_replay < 0 || iterations_per_replay > 256 || (iterations_per_replay % 2) != 0)
-        return PM_EINVAL;
-    b->graph_iters = iterations_per_replay;
-    return batch_capture(b);
+    bool moved = false;
+    for (size_t m = 0; m < b->hs.size(); ++m) moved |= (b->hs[m]->hist != b->hist_seen[m]);
+    if (!moved) return PM_OK;
+    return b->mixed ? upload_meshes<float>(b) : upload_meshes<double>(b);
 }
 
-// Start the solve of mesh m at the batch's next launch index: gather rhs and
-// guess, ||rhs||, r0 = rhs - A x0 (partials into the buffer that launch reads).
-static int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const double *x0_dev, double rtol,
-                            int32_t max_iter, hipStream_t s)
+// Start the FP64 solve of mesh m at the batch's next launch index: gather rhs
+// and guess, ||rhs||, r0 = rhs - A x0 (partials into the buffer its first
+// apply reads).  A mixed solve only gathers here; its FP64 residual is
+// computed by the next step's correction pass.
+int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const double *x0_dev, double rtol,
+                     int32_t max_iter, hipStream_t s)
 {
     pm_handle *h = b->hs[m];
     TRY(ensure_hist(h, max_iter));
@@ -2074,38 +2169,114 @@ static int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const dou
                        h->part_misc());
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist,
                        b->k_next);
+    if (b->mixed) {
+        pm_batch::Mixed &X = b->mx[m];
+        X = pm_batch::Mixed();
+        X.phase = MX_RESIDUAL;
+        X.rtol = rtol;
+        X.max_iter = max_iter;
+        HIPCK(hipGetLastError());
+        return PM_OK;
+    }
     TRY(launch_apply(h, h->x, h->q, nullptr, s));
-    hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st,
-                       h->part_rr((b->k_next - 1) & 1));
+    hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
     HIPCK(hipGetLastError());
     return PM_OK;
 }
 
-// The histories may have been reallocated (ensure_hist): refresh descriptors.
-static int batch_refresh(pm_batch *b, hipStream_t s)
+// Mixed batches: FP64 residual r = b - A x for every mesh whose inner solve
+// has stopped (after x += d) or that has just begun, then the decision per
+// mesh: finished, or (re)start its inner solve at the next launch.
+int batch_corrections(pm_batch *b, hipStream_t s)
 {
     const int n = int(b->hs.size());
-    std::vector<BatchMesh> meshes(n);
-    HIPCK(hipMemcpyAsync(meshes.data(), b->d_meshes, sizeof(BatchMesh) * n, hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
-    bool moved = false;
-    for (int m = 0; m < n; ++m)
-        if (meshes[m].hist != b->hs[m]->hist) {
-            meshes[m].hist = b->hs[m]->hist;
-            moved = true;
-        }
-    if (moved) {
-        HIPCK(hipMemcpyAsync(b->d_meshes, meshes.data(), sizeof(BatchMesh) * n, hipMemcpyHostToDevice, s));
-        HIPCK(hipStreamSynchronize(s));
+    std::vector<int> due;
+    for (int m = 0; m < n; ++m) {
+        pm_batch::Mixed &X = b->mx[m];
+        if (X.phase == MX_RESIDUAL) due.push_back(m);
+        else if (X.phase == MX_INNER && b->h_states[m].done) due.push_back(m);
     }
+    if (due.empty()) return PM_OK;
+    for (int m : due) {
+        pm_handle *h = b->hs[m];
+        pm_batch::Mixed &X = b->mx[m];
+        const int N = int(h->N);
+        const unsigned vg = h->n_vblocks;
+        if (X.phase == MX_INNER) {
+            const CGState &in = b->h_states[m];
+            const bool keep = h->mixed_mode == PM_MIXED_KEEP_DIRECTION;
+            X.iters = keep ? in.iter : X.iters + in.iter;
+            if (in.status != 0) {
+                X.status = in.status;
+                X.phase = MX_FINISHED;
+                continue;
+            }
+            if (in.iter == X.iter0) {   // no inner progress: x is final
+                X.phase = MX_FINISHED;
+                continue;
+            }
+            hipLaunchKernelGGL(k_correct, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->x, h->d32);
+            ++X.n_outer;
+        }
+        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
+        hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
+        HIPCK(hipMemcpyAsync(h->hst, h->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    }
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(s));
+    for (int m : due) {
+        pm_handle *h = b->hs[m];
+        pm_batch::Mixed &X = b->mx[m];
+        if (X.phase == MX_FINISHED) continue;
+        const int N = int(h->N);
+        const unsigned vg = h->n_vblocks;
+        const CGState &st = *h->hst;
+        if (st.status != 0) {   // not finite rhs
+            X.status = st.status;
+            X.phase = MX_FINISHED;
+            continue;
+        }
+        if (!(st.bnorm > 0.0)) {   // zero right-hand side: p = 0
+            HIPCK(hipMemsetAsync(h->x, 0, 8 * size_t(N), s));
+            X.rel = 0.0;
+            X.phase = MX_FINISHED;
+            continue;
+        }
+        X.rel = std::sqrt(st.tt) / st.bnorm;
+        if (!std::isfinite(X.rel)) {
+            X.status = PM_EBREAKDOWN;
+            X.phase = MX_FINISHED;
+            continue;
+        }
+        if (X.rel <= X.rtol || X.iters >= X.max_iter || X.n_outer >= MAX_CORRECTIONS) {
+            X.phase = MX_FINISHED;
+            continue;
+        }
+        const bool keep = h->mixed_mode == PM_MIXED_KEEP_DIRECTION;
+        const bool resume = keep && X.phase == MX_INNER;
+        const int K = resume ? b->h_states[m].iter : 0;   // last completed inner iteration
+        double *rr_next = h->part_rr(K & 1);              // r.r partials of iteration K+1's apply
+        hipLaunchKernelGGL(k_to_inner, dim3(vg), dim3(BLK), 0, s, N, h->r, h->r32, h->d32, rr_next);
+        if (resume)
+            hipLaunchKernelGGL(k_resume_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), b->inner_rtol,
+                               b->k_next - K);
+        else
+            hipLaunchKernelGGL(k_begin_inner, dim3(1), dim3(BLK), 0, s, h->st_in, rr_next, int(vg), b->inner_rtol,
+                               keep ? X.max_iter : X.max_iter - X.iters, b->k_next);
+        X.iter0 = K;
+        X.phase = MX_INNER;
+    }
+    HIPCK(hipGetLastError());
     return PM_OK;
 }
 
-// Advance every solve in flight by one chunk; returns the number of meshes
-// that are idle or finished and copies the states to b->h_states.
-static int batch_step_impl(pm_batch *b, int *n_done, hipStream_t s)
+// Advance every solve in flight by one chunk of iterations (mixed batches:
+// after the correction pass); copies the states to b->h_states.
+int batch_step_impl(pm_batch *b, hipStream_t s)
 {
     const int n = int(b->hs.size());
+    if (b->mixed) TRY(batch_corrections(b, s));
     int its = 0;
     if (b->gexec) {
         HIPCK(hipGraphLaunch(b->gexec, s));
@@ -2115,23 +2286,45 @@ static int batch_step_impl(pm_batch *b, int *n_done, hipStream_t s)
         TRY(launch_batch_iterations(b, its, s));
     }
     b->k_next += its;
-    hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(BLK), 0, s, b->d_meshes, n, b->d_ctl, b->d_states);
+    if (b->mixed)
+        hipLaunchKernelGGL(k_batch_status<float>, dim3(1), dim3(BLK), 0, s, (const BatchMeshT<float> *)b->d_meshes, n,
+                           b->d_ctl, b->d_states);
+    else
+        hipLaunchKernelGGL(k_batch_status<double>, dim3(1), dim3(BLK), 0, s, (const BatchMeshT<double> *)b->d_meshes,
+                           n, b->d_ctl, b->d_states);
     HIPCK(hipGetLastError());
     HIPCK(hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
     HIPCK(hipMemcpyAsync(b->h_states, b->d_states, sizeof(CGState) * n, hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    *n_done = b->h_ctl->n_done;
     return PM_OK;
 }
 
-// True residual and output of a finished mesh; residual replacement (as in
-// pressure_solve) when the recursive residual met rtol but the true one did not.
-static int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
-                             double *true_relres, hipStream_t s)
+bool batch_mesh_done(const pm_batch *b, int m)
+{
+    if (b->mixed) return b->mx[m].phase == MX_IDLE || b->mx[m].phase == MX_FINISHED;
+    return b->h_states[m].done != 0;
+}
+
+// True residual and output of a finished mesh; for FP64 solves, residual
+// replacement (as in pressure_solve) when the recursive residual met rtol
+// but the true one did not.
+int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
+                      double *true_relres, hipStream_t s)
 {
     pm_handle *h = b->hs[m];
     const int N = int(h->N);
     const unsigned vg = h->n_vblocks;
+    if (b->mixed) {
+        pm_batch::Mixed &X = b->mx[m];
+        hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
+        HIPCK(hipGetLastError());
+        HIPCK(hipStreamSynchronize(s));
+        *iters = X.iters;
+        *true_relres = X.rel;
+        X.phase = MX_IDLE;
+        if (X.status != 0) return X.status;
+        return (X.rel <= rtol) ? PM_OK : PM_NOT_CONVERGED;
+    }
     TRY(launch_apply(h, h->x, h->q, nullptr, s));
     hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
     hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
@@ -2158,6 +2351,32 @@ static int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double r
     return code;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pressure_batch_create(pm_handle *const *handles, int32_t n, const int32_t *params, pm_batch **out)
+{
+    return batch_create_common(handles, n, params, false, 0.0, out);
+}
+
+int pressure_batch_create_mixed(pm_handle *const *handles, int32_t n, const int32_t *params, double inner_rtol,
+                                pm_batch **out)
+{
+    if (!(inner_rtol > 0.0) || !(inner_rtol < 1.0)) return PM_EINVAL;
+    return batch_create_common(handles, n, params, true, inner_rtol, out);
+}
+
+void pressure_batch_destroy(pm_batch *b) { batch_free(b); }
+
+int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
+{
+    if (!b || iterations_per_replay < 0 || iterations_per_replay > 256 || (iterations_per_replay % 2) != 0)
+        return PM_EINVAL;
+    b->graph_iters = iterations_per_replay;
+    return batch_capture(b);
+}
+
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
                          int32_t max_iter, void *stream)
 {
@@ -2167,16 +2386,15 @@ int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const do
     HIPCK(hipEventRecord(b->ev, us));
     HIPCK(hipStreamWaitEvent(s, b->ev, 0));
     TRY(batch_begin_impl(b, m, rhs_dev, x0_dev, rtol, max_iter, s));
-    return batch_refresh(b, s);
+    return batch_refresh(b);
 }
 
 int pressure_batch_step(pm_batch *b, int32_t *done, void *stream)
 {
     if (!b || !done) return PM_EINVAL;
     (void)stream;
-    int n_done = 0;
-    TRY(batch_step_impl(b, &n_done, b->stream));
-    for (size_t m = 0; m < b->hs.size(); ++m) done[m] = b->h_states[m].done;
+    TRY(batch_step_impl(b, b->stream));
+    for (size_t m = 0; m < b->hs.size(); ++m) done[m] = batch_mesh_done(b, int(m)) ? 1 : 0;
     return PM_OK;
 }
 
@@ -2205,12 +2423,15 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
     HIPCK(hipEventRecord(b->ev, us));
     HIPCK(hipStreamWaitEvent(s, b->ev, 0));
     for (int m = 0; m < n; ++m) TRY(batch_begin_impl(b, m, rhs_dev[m], x0_dev ? x0_dev[m] : nullptr, rtol, max_iter, s));
-    TRY(batch_refresh(b, s));
-    // every solve stops by itself at max_iter, so this loop is bounded
-    const int64_t k_limit = int64_t(b->k_next) + max_iter + 2 * std::max(b->graph_iters, 8) + 2;
+    TRY(batch_refresh(b));
+    // every solve stops by itself at max_iter (mixed: within MAX_CORRECTIONS
+    // corrections), so this loop is bounded
+    const int chunk = std::max(b->graph_iters, 8);
+    const int64_t k_limit = int64_t(b->k_next) + int64_t(max_iter) + int64_t(chunk) * (b->mixed ? MAX_CORRECTIONS + 2 : 2) + 2;
     for (;;) {
+        TRY(batch_step_impl(b, s));
         int n_done = 0;
-        TRY(batch_step_impl(b, &n_done, s));
+        for (int m = 0; m < n; ++m) n_done += batch_mesh_done(b, m) ? 1 : 0;
         if (n_done >= n) break;
         if (b->k_next > k_limit) return PM_EHIP;
     }
@@ -2227,11 +2448,11 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
     return worst;
 }
 
-}  // extern "C"
-
-extern "C" int pressure_batch_next_index(pm_batch *b, int32_t *k)
+int pressure_batch_next_index(pm_batch *b, int32_t *k)
 {
     if (!b || !k) return PM_EINVAL;
     *k = b->k_next;
     return PM_OK;
 }
+
+}  // extern "C"

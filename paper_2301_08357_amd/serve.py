@@ -1,6 +1,7 @@
 """Continuous-batching server for pressure solves on a pool of meshes.
 
-Requests (mesh, right-hand side) arrive over time.  The server keeps a set
+Requests (mesh, right-hand side) arrive over time; each is an FP64 solve, or
+with mixed=True an FP32-inner mixed-precision solve to the same tolerance.  The server keeps a set
 of meshes resident on the GPU within an HBM budget (each mesh's operator
 data, CG vectors and its last solution, sized by pressure_footprint),
 evicting the least recently used idle mesh when a new one must be loaded.
@@ -20,6 +21,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import _lib
 from .system import PressureBatch, PressureSystem, footprint
 
 
@@ -52,6 +54,13 @@ class ServeStats:
     rebuilds: int = 0
     steps: int = 0
     max_in_flight_seen: int = 0
+    # host wall time by activity (seconds): batched steps (GPU iterations and
+    # status read), finishing solves, admitting requests (rhs, begin),
+    # rebuilding the batch
+    t_step: float = 0.0
+    t_finish: float = 0.0
+    t_admit: float = 0.0
+    t_rebuild: float = 0.0
 
 
 class PressureServer:
@@ -59,7 +68,8 @@ class PressureServer:
     return the request's right-hand side as a float64 CUDA tensor."""
 
     def __init__(self, problems, budget_bytes, max_in_flight=64, rtol=1e-10, max_iter=20000,
-                 graph_iters=16, tiles_per_slot=4, nodes_per_lane=8, keep_x0=False):
+                 graph_iters=16, tiles_per_slot=4, nodes_per_lane=8, keep_x0=False, mixed=False,
+                 inner_rtol=1e-2):
         self.problems = problems
         self.budget = int(budget_bytes)
         self.max_in_flight = int(max_in_flight)
@@ -69,11 +79,16 @@ class PressureServer:
         self.tps = tiles_per_slot
         self.npl = nodes_per_lane
         self.keep_x0 = keep_x0
-        self.cost = [footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems) + 8 * p.mesh.n_nodes for p in problems]
+        self.mixed = bool(mixed)
+        self.inner_rtol = inner_rtol
+        self.flags = _lib.PM_FP64 | (_lib.PM_FP32_INNER if self.mixed else 0)
+        self.cost = [footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems, self.flags) + 8 * p.mesh.n_nodes
+                     for p in problems]
         self.resident = collections.OrderedDict()     # mesh -> PressureSystem, least recent first
         self.last = {}                                # mesh -> last solution (device)
         self.batch = None
         self.members = []                             # mesh ids in batch order
+        self.slot = {}                                # mesh id -> position in the batch
         self.dirty = False                            # resident set differs from the batch's
         self.batch_next = 1                           # launch index carried over rebuilds
         self.stats = ServeStats()
@@ -104,7 +119,7 @@ class PressureServer:
 
     def _load(self, m):
         p = self.problems[m]
-        self.resident[m] = PressureSystem.from_problem(p)
+        self.resident[m] = PressureSystem.from_problem(p, flags=self.flags)
         self.stats.loads += 1
 
     def _rebuild(self):
@@ -114,9 +129,11 @@ class PressureServer:
             self.batch = None
         self.batch_next = first
         self.members = list(self.resident.keys())
+        self.slot = {m: j for j, m in enumerate(self.members)}
         self.dirty = False
         if self.members:
-            self.batch = PressureBatch([self.resident[m] for m in self.members], self.tps, self.npl, first)
+            self.batch = PressureBatch([self.resident[m] for m in self.members], self.tps, self.npl, first,
+                                       mixed=self.mixed, inner_rtol=self.inner_rtol)
             self.batch.set_graph(self.graph_iters)
             self.stats.rebuilds += 1
 
@@ -147,8 +164,11 @@ class PressureServer:
                     self._load(r.mesh)
                     changed = True
                 admit.append(r)
+            t_a = clock()
             if changed or self.dirty or (admit and self.batch is None):
                 self._rebuild()
+            t_b = clock()
+            self.stats.t_rebuild += t_b - t_a
             for r in admit:
                 queues[r.mesh].popleft()
                 self.resident.move_to_end(r.mesh)
@@ -158,19 +178,24 @@ class PressureServer:
                 if self.keep_x0 and r.x0 is not None:
                     r.x0 = r.x0.clone()
                 r.start = clock() - t0
-                self.batch.begin(self.members.index(r.mesh), r.rhs, r.x0, self.rtol, self.max_iter)
+                self.batch.begin(self.slot[r.mesh], r.rhs, r.x0, self.rtol, self.max_iter)
                 in_flight[r.mesh] = r
+            t_c = clock()
+            self.stats.t_admit += t_c - t_b
             self.stats.max_in_flight_seen = max(self.stats.max_in_flight_seen, len(in_flight))
             if in_flight:
                 done = self.batch.step()
+                t_d = clock()
+                self.stats.t_step += t_d - t_c
                 self.stats.steps += 1
-                for m in [m for m in in_flight if done[self.members.index(m)]]:
+                for m in [m for m in in_flight if done[self.slot[m]]]:
                     r = in_flight.pop(m)
-                    res = self.batch.finish(self.members.index(m), r.rhs, self.rtol)
+                    res = self.batch.finish(self.slot[m], r.rhs, self.rtol)
                     r.done = clock() - t0
                     r.iters, r.status, r.true_relres, r.result = res.iters, res.status, res.true_relres, res.p
                     self.last[m] = res.p
                     finished.append(r)
+                self.stats.t_finish += clock() - t_d
             elif pending:
                 time.sleep(max(0.0, min(1e-3, pending[0].arrival - (clock() - t0))))
         st = self.stats

@@ -201,13 +201,18 @@ class PressureBatch:
     grids to the batch's, so single solves on those systems reproduce the
     batched results bit for bit."""
 
-    def __init__(self, systems, tiles_per_slot=4, nodes_per_lane=8, first_index=1):
+    def __init__(self, systems, tiles_per_slot=4, nodes_per_lane=8, first_index=1, mixed=False, inner_rtol=1e-2):
         self.systems = list(systems)
+        self.mixed = bool(mixed)
         n = len(self.systems)
         hs = (ctypes.c_void_p * n)(*[s._h.value for s in self.systems])
         params = (ctypes.c_int32 * 3)(int(tiles_per_slot), int(nodes_per_lane), int(first_index))
         b = ctypes.c_void_p(None)
-        check(load().pressure_batch_create(hs, n, params, ctypes.byref(b)), "pressure_batch_create")
+        if self.mixed:
+            check(load().pressure_batch_create_mixed(hs, n, params, float(inner_rtol), ctypes.byref(b)),
+                  "pressure_batch_create_mixed")
+        else:
+            check(load().pressure_batch_create(hs, n, params, ctypes.byref(b)), "pressure_batch_create")
         self._b = b
 
     def close(self):

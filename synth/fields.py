@@ -45,3 +45,11 @@ def perturbation(seed, request_id, n_nodes):
     index request_id * 2**32 + node)."""
     idx = np.uint64(request_id) * np.uint64(1 << 32) + np.arange(n_nodes, dtype=np.uint64)
     return normal(seed, STREAM_PERTURB, idx)
+
+
+def perturbation_torch(seed, request_id, n_nodes, device):
+    """perturbation() generated on a torch device."""
+    import torch
+    from .rng import normal_torch
+    idx = torch.arange(n_nodes, dtype=torch.int64, device=device) + (int(request_id) << 32)
+    return normal_torch(seed, STREAM_PERTURB, idx)

@@ -67,3 +67,40 @@ def normal(seed, stream, idx):
     u1 = uniform(seed, stream, np.uint64(2) * idx)
     u2 = uniform(seed, stream, np.uint64(2) * idx + np.uint64(1))
     return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def _i64(c):
+    """A uint64 constant as the int64 with the same bits."""
+    c = int(c)
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def uniform_torch(seed, stream, idx):
+    """uniform() computed with torch int64 arithmetic on idx's device (the
+    same bits: products wrap mod 2**64, right shifts are masked to logical
+    shifts)."""
+    import torch
+    idx = idx.to(torch.int64)
+
+    def srl(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    ctr = idx + (_i64(stream) << 40) + 1
+    z = ctr * _i64(GOLDEN) + _i64(seed)
+    z = z ^ srl(z, 30)
+    z = z * _i64(M1)
+    z = z ^ srl(z, 27)
+    z = z * _i64(M2)
+    z = z ^ srl(z, 31)
+    return srl(z, 11).to(torch.float64) * (2.0 ** -53)
+
+
+def normal_torch(seed, stream, idx):
+    """normal() with torch on idx's device (Box-Muller with torch's log1p and
+    cos, which may differ from numpy's in the last bit)."""
+    import math
+    import torch
+    idx = idx.to(torch.int64)
+    u1 = uniform_torch(seed, stream, 2 * idx)
+    u2 = uniform_torch(seed, stream, 2 * idx + 1)
+    return torch.sqrt(-2.0 * torch.log1p(-u1)) * torch.cos((2.0 * math.pi) * u2)

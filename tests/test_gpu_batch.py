@@ -104,3 +104,51 @@ def test_batch_edge_cases():
     batch.close()
     for s in systems:
         s.close()
+
+
+def test_mixed_batch_matches_single_mixed():
+    """Batched mixed-precision solves (FP32 inner CG of every mesh in the
+    batched launches, FP64 corrections per mesh) give each mesh's
+    pressure_solve_mixed result bit for bit, in both inner modes, and solves
+    may start at different steps."""
+    probs = _small_mix()[:5]
+    print("case mixed batch", [(p.mesh.dim, p.mesh.n_nodes) for p in probs], flush=True)
+    As = [oracle.assemble_problem(p) for p in probs]
+    bs = [_rhs(p, A) for p, A in zip(probs, As)]
+    systems = [pm.PressureSystem.from_problem(p, flags=pm.PM_FP64 | pm.PM_FP32_INNER) for p in probs]
+    systems[1].set_mixed_mode(pm.PM_MIXED_RESTART)
+    batch = pm.PressureBatch(systems, tiles_per_slot=2, nodes_per_lane=4, mixed=True, inner_rtol=1e-2)
+    rhs = [_dev(b) for b in bs]
+    code, res = batch.solve(rhs, rtol=1e-10)
+    assert code == 0
+    xb = [_host(r.p).copy() for r in res]
+    for p, A, b, r, x in zip(probs, As, bs, res, xb):
+        assert r.status == 0 and r.true_relres <= 1e-10
+        accept = np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)
+        assert accept <= 1.05e-10, (p.name, accept)
+    for s, b, r, x in zip(systems, rhs, res, xb):
+        single = s.solve_mixed(b, rtol=1e-10, inner_rtol=1e-2)
+        assert single.iters == r.iters
+        assert np.array_equal(_host(single.p).view(np.uint64), x.view(np.uint64))
+    # continuous batching: mesh 2 joins two steps after mesh 0
+    outs = {}
+    batch.begin(0, rhs[0], rtol=1e-10)
+    started, steps = {0}, 0
+    while True:
+        done = batch.step()
+        steps += 1
+        for m in sorted(started):
+            if done[m] and m not in outs:
+                outs[m] = batch.finish(m, rhs[m], rtol=1e-10)
+        if steps == 2:
+            batch.begin(2, rhs[2], rtol=1e-10)
+            started.add(2)
+        if len(outs) == 2:
+            break
+        assert steps < 10000
+    for m in (0, 2):
+        assert outs[m].iters == res[m].iters
+        assert np.array_equal(_host(outs[m].p).view(np.uint64), xb[m].view(np.uint64))
+    batch.close()
+    for s in systems:
+        s.close()
