@@ -234,10 +234,10 @@ using Iter = IterT<double>;
 // Prologue of apply(k): every block sums the partials of r_{k-1}.r_{k-1}
 // (and of the previous one for beta) and takes the convergence decision;
 // block 0 records it.  Returns false when the iteration must not run.
+// iter_decide is the part after the test of st->done.
 template <class R>
-__device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &beta, int vb)
+__device__ inline bool iter_decide(const IterT<R> &it, double *red, double &beta, int vb)
 {
-    if (block_done(it.st)) return false;
     const double rr = sum_partials(it.rr_cur, it.n_vblocks, red);
     beta = 0.0;
     if (!it.first) beta = rr / sum_partials(it.rr_prev, it.n_vblocks, red);
@@ -252,6 +252,13 @@ __device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &be
         if (stop) it.st->done = 1;
     }
     return !stop;
+}
+
+template <class R>
+__device__ inline bool iter_prologue(const IterT<R> &it, double *red, double &beta, int vb)
+{
+    if (block_done(it.st)) return false;
+    return iter_decide(it, red, beta, vb);
 }
 
 // Tile schedule: workgroups are dispatched round-robin over the 8 XCDs
@@ -417,18 +424,17 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     using G = TileGeom<T>;
     constexpr int NPT = G::NPT, SPT = (LM + BLK - 1) / BLK, NF = DIM + 1, RS = G::RS;
     static_assert(LM >= T && LM <= G::MAX_LOCAL, "node table");
-    double beta = 0.0;
-    if (CG && !iter_prologue(it, red, beta, vb)) return;
+    if (CG && block_done(it.st)) return;
     R *const sN = smem;                      // NF x LM: X, Y, (Z,) value
     R *const sS = smem + NF * LM;            // max_deg x RS sums, then the sink
     R *const sink = sS + ta.max_deg * RS + (threadIdx.x & (G::DUMMY - 1));
-    const R rbeta = R(beta);
 
-    // -- loads of one tile, into registers
+    // -- loads of one tile, into registers (under CG: r and p_{k-1}; p_k is
+    // formed when staging, once beta is known)
     int gidx[SPT];
     uint2 ic[IPT];
     R iw[IPT];
-    R vX[SPT], vY[SPT], vZ[SPT], vP[SPT];
+    R vX[SPT], vY[SPT], vZ[SPT], vP[SPT], vQ[SPT];
     uint8_t vF[SPT];
     auto load_ids = [&](int t, int h0, int nh, int *gi) {
         const int s = t * T, nt = min(T, g.N - s);
@@ -455,8 +461,12 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
                 vX[q] = g.X[v];
                 vY[q] = g.Y[v];
                 if (DIM == 3) vZ[q] = g.Z[v];
-                if (CG) vP[q] = it.first ? it.r[v] : it.r[v] + rbeta * it.p_old[v];
-                else vP[q] = x[v];
+                if (CG) {
+                    vP[q] = it.r[v];
+                    vQ[q] = it.first ? R(0) : it.p_old[v];
+                } else {
+                    vP[q] = x[v];
+                }
                 vF[q] = ta.nflag[v];
             }
         }
@@ -485,6 +495,10 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     }
     int tn = tile_at(vb, 1, nvb, ta.n_tiles);
     int vo = load_offsets(tn);
+    // the sums of the prologue run while the first tile's loads are in flight
+    double beta = 0.0;
+    if (CG && !iter_decide(it, red, beta, vb)) return;
+    const R rbeta = R(beta);
     for (int kt = 0; t >= 0; ++kt) {
         const int s = t * T, nt = min(T, g.N - s);
         // 1. node table; own values kept for the row sums
@@ -493,6 +507,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int l = threadIdx.x + q * BLK;
+            if (CG && !it.first) vP[q] = vP[q] + rbeta * vQ[q];   // p_k = r + beta p_{k-1}
             if (gidx[q] >= 0) {
                 const bool d = (vF[q] & 0x80u) != 0;
                 sN[l] = vX[q];
@@ -584,8 +599,13 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     }
 }
 
+// Waves per SIMD the register budget is held to: four for the classes whose
+// LDS tables admit four blocks per CU (128-node tiles, node table <= 448).
+template <int T, int LM>
+constexpr int tile_waves() { return (T == 128 && LM <= 448) ? 4 : 1; }
+
 template <int DIM, bool CG, class R, int T, int IPT, int LM>
-__global__ void __launch_bounds__(BLK) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
+__global__ void __launch_bounds__(BLK, (tile_waves<T, LM>())) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
                                                      R *__restrict__ y, IterT<R> it)
 {
     extern __shared__ double smem_d[];
@@ -764,7 +784,7 @@ struct BatchCtl {
 // its p and r.r buffers by the parity of that number, as a single-mesh
 // solve does; so a solve may start, or continue, at any launch.
 template <int C, class R>
-__global__ void __launch_bounds__(BLK) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
+__global__ void __launch_bounds__(BLK, (tile_waves<TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
                                                      const int2 *__restrict__ slots, BatchCtl *ctl)
 {
     extern __shared__ double smem_d[];
@@ -1435,7 +1455,9 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     h->dt = dt;
     h->flags = flags;
     const int64_t N = h->N, E = h->E;
-    h->n_vblocks = int(std::min<int64_t>(grid_of(N), VGRID_MAX));
+    // vector kernels: about 4 nodes per lane (fewer blocks also means fewer
+    // partials for the next kernel's prologue to sum)
+    h->n_vblocks = int(std::max<int64_t>(1, std::min<int64_t>((N + 4 * BLK - 1) / (4 * BLK), VGRID_MAX)));
 
     // connectivity with the Dirichlet flag of each vertex in bit 31
     std::vector<int32_t> conn(L.conn);
