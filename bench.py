@@ -439,10 +439,19 @@ def cpu_baseline(probs):
         x, st, it, _, _ = oracle.cg(A, b, rtol=1e-10, max_iter=20000, dirichlet=p.mesh.dirichlet)
         total_t += time.perf_counter() - t0
         total_dofiter += float((p.mesh.dirichlet == 0).sum()) * it
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(total_dofiter / total_t / 1e9, 5), "unit": "GDOF*iter/s", "cores": 1,
             "kind": "oracle",
             "sample": "one FP64 CG solve per w in {1e-6,1e-3,1} on the same 64^3 mesh "
-                      "(%.1f s of CPU time, assembly excluded)" % total_t}
+                      "(%.1f s of CPU time, assembly excluded; one thread of %d available, %s)"
+                      % (total_t, len(os.sched_getaffinity(0)), cpu)}
 
 
 if __name__ == "__main__":

@@ -599,13 +599,15 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     }
 }
 
-// Waves per SIMD the register budget is held to: four for the classes whose
-// LDS tables admit four blocks per CU (128-node tiles, node table <= 448).
-template <int T, int LM>
-constexpr int tile_waves() { return (T == 128 && LM <= 448) ? 4 : 1; }
+// Waves per SIMD the register budget is held to: four for the FP64 classes
+// whose LDS tables admit four blocks per CU (128-node tiles, node table
+// <= 448).  The FP32 kernels fit five waves without a bound (forcing six
+// spills registers and was measured slower).
+template <class R, int T, int LM>
+constexpr int tile_waves() { return (sizeof(R) == 8 && T == 128 && LM <= 448) ? 4 : 1; }
 
 template <int DIM, bool CG, class R, int T, int IPT, int LM>
-__global__ void __launch_bounds__(BLK, (tile_waves<T, LM>())) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
+__global__ void __launch_bounds__(BLK, (tile_waves<R, T, LM>())) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
                                                      R *__restrict__ y, IterT<R> it)
 {
     extern __shared__ double smem_d[];
@@ -784,7 +786,7 @@ struct BatchCtl {
 // its p and r.r buffers by the parity of that number, as a single-mesh
 // solve does; so a solve may start, or continue, at any launch.
 template <int C, class R>
-__global__ void __launch_bounds__(BLK, (tile_waves<TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
+__global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
                                                      const int2 *__restrict__ slots, BatchCtl *ctl)
 {
     extern __shared__ double smem_d[];
