@@ -76,14 +76,16 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// Block sum in a fixed order; the result is valid in every thread.
+// Block sum in a fixed order; the result is valid in every thread.  NTH is
+// the block size; red holds NTH / 64 doubles.
+template <int NTH = BLK>
 __device__ inline double block_sum_all(double v, double *red)
 {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = red[0];
-    for (int k = 1; k < BLK / 64; ++k) s += red[k];
+    for (int k = 1; k < NTH / 64; ++k) s += red[k];
     __syncthreads();
     return s;
 }
@@ -99,12 +101,17 @@ __device__ inline bool block_done(const CGState *st)
     return d;
 }
 
-// Sum of n block partials, in the same fixed order in every block.
+// Sum of n block partials, in the same fixed order in every block.  The
+// first BLK threads do the summing whatever the block size NTH, so every
+// kernel that sums the same partials gets the same bits (the lanes past BLK
+// add exact zeros).
+template <int NTH = BLK>
 __device__ inline double sum_partials(const double *part, int n, double *red)
 {
     double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += BLK) v += part[k];
-    return block_sum_all(v, red);
+    if (threadIdx.x < BLK)
+        for (int k = threadIdx.x; k < n; k += BLK) v += part[k];
+    return block_sum_all<NTH>(v, red);
 }
 
 // ----------------------------------------------------------- element kernel
@@ -235,12 +242,12 @@ using Iter = IterT<double>;
 // (and of the previous one for beta) and takes the convergence decision;
 // block 0 records it.  Returns false when the iteration must not run.
 // iter_decide is the part after the test of st->done.
-template <class R>
+template <class R, int NTH = BLK>
 __device__ inline bool iter_decide(const IterT<R> &it, double *red, double &beta, int vb)
 {
-    const double rr = sum_partials(it.rr_cur, it.n_vblocks, red);
+    const double rr = sum_partials<NTH>(it.rr_cur, it.n_vblocks, red);
     beta = 0.0;
-    if (!it.first) beta = rr / sum_partials(it.rr_prev, it.n_vblocks, red);
+    if (!it.first) beta = rr / sum_partials<NTH>(it.rr_prev, it.n_vblocks, red);
     const double nr = sqrt(rr);
     const bool bad = !isfinite(rr);
     const bool stop = bad || !(nr > it.st->tol) || (it.k - 1) >= it.st->max_iter;
@@ -357,7 +364,6 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
 template <int T>
 struct TileGeom {
     static_assert(T == 128 || T == 256 || T == 512, "tile sizes are powers of two");
-    static constexpr int NPT = (T + BLK - 1) / BLK;        // own nodes per lane
     static constexpr int LVB = (T <= 256) ? 10 : 11;       // bits of a local index
     static constexpr unsigned LV_MASK = (1u << LVB) - 1u;
     static constexpr int MAX_ROWS = 1 << (16 - LVB);       // rows a record can name
@@ -367,15 +373,17 @@ struct TileGeom {
 };
 
 // Size classes of the tiled kernel: (tile nodes, instances per lane,
-// node-table entries).  Setup picks the first class of the tile size that
-// covers the largest tile's instance count and node table.
+// node-table entries, threads per block).  Setup picks the first class of
+// the tile size that covers the largest tile's instance count and node
+// table.  256-node tiles run 512 threads: two such blocks fill a CU's LDS
+// with the same 16 waves as four 128-node blocks.
 struct TileClass {
-    int t, ipt, lm;
+    int t, ipt, lm, nth;
 };
-constexpr TileClass TILE_CLASSES[] = {{128, 2, 256},  {128, 4, 256},  {128, 4, 384},   {128, 6, 448},
-                                      {128, 8, 512},  {128, 12, 768}, {256, 6, 512},   {256, 8, 768},
-                                      {256, 12, 768}, {256, 12, 1024}, {512, 16, 1024}, {512, 20, 1536},
-                                      {512, 24, 2048}};
+constexpr TileClass TILE_CLASSES[] = {
+    {128, 2, 256, 256},   {128, 4, 256, 256},   {128, 4, 384, 256},  {128, 6, 448, 256},  {128, 8, 512, 256},
+    {128, 12, 768, 256},  {256, 3, 512, 512},   {256, 4, 768, 512},  {256, 6, 768, 512},  {256, 8, 1024, 512},
+    {512, 16, 1024, 256}, {512, 20, 1536, 256}, {512, 24, 2048, 256}};
 constexpr int N_TILE_CLASSES = sizeof(TILE_CLASSES) / sizeof(TILE_CLASSES[0]);
 
 template <class R>
@@ -416,13 +424,13 @@ constexpr size_t tile_lds_bytes(int dim, int lm, int max_deg)
 // own values stay in registers between the phases.
 // The body runs as virtual block vb of nvb (a real block of a single-mesh
 // launch, or one (mesh, slot) pair of a batched launch).
-template <int DIM, bool CG, class R, int T, int IPT, int LM>
+template <int DIM, bool CG, class R, int T, int IPT, int LM, int NTH = BLK>
 __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileArgsT<R> &ta,
                                                  const R *__restrict__ x, R *__restrict__ y, const IterT<R> &it,
                                                  R *smem, double *red, int vb, int nvb)
 {
     using G = TileGeom<T>;
-    constexpr int NPT = G::NPT, SPT = (LM + BLK - 1) / BLK, NF = DIM + 1, RS = G::RS;
+    constexpr int NPT = (T + NTH - 1) / NTH, SPT = (LM + NTH - 1) / NTH, NF = DIM + 1, RS = G::RS;
     static_assert(LM >= T && LM <= G::MAX_LOCAL, "node table");
     if (CG && block_done(it.st)) return;
     R *const sN = smem;                      // NF x LM: X, Y, (Z,) value
@@ -440,14 +448,14 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         const int s = t * T, nt = min(T, g.N - s);
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
-            const int l = threadIdx.x + q * BLK;
+            const int l = threadIdx.x + q * NTH;
             gi[q] = -1;
             if (l < nt) gi[q] = s + l;
             else if (l >= T && l < T + nh) gi[q] = ta.halo[h0 + l - T];
         }
     };
     auto load_inst = [&](int k, int i0, int ni) {
-        const int j = threadIdx.x + k * BLK;
+        const int j = threadIdx.x + k * NTH;
         if (j < ni) {
             ic[k] = ta.inst[i0 + j];
             iw[k] = ta.inst_w[i0 + j];
@@ -497,7 +505,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     int vo = load_offsets(tn);
     // the sums of the prologue run while the first tile's loads are in flight
     double beta = 0.0;
-    if (CG && !iter_decide(it, red, beta, vb)) return;
+    if (CG && !iter_decide<R, NTH>(it, red, beta, vb)) return;
     const R rbeta = R(beta);
     for (int kt = 0; t >= 0; ++kt) {
         const int s = t * T, nt = min(T, g.N - s);
@@ -506,7 +514,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         uint8_t ownF[NPT];
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
-            const int l = threadIdx.x + q * BLK;
+            const int l = threadIdx.x + q * NTH;
             if (CG && !it.first) vP[q] = vP[q] + rbeta * vQ[q];   // p_k = r + beta p_{k-1}
             if (gidx[q] >= 0) {
                 const bool d = (vF[q] & 0x80u) != 0;
@@ -533,7 +541,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         constexpr int NODES_AT = (IPT > 2) ? 2 : IPT - 1;
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-            const int j = threadIdx.x + k * BLK;
+            const int j = threadIdx.x + k * NTH;
             if (j < ni) {
                 const unsigned u[4] = {ic[k].x & 0xffffu, ic[k].x >> 16, ic[k].y & 0xffffu, ic[k].y >> 16};
                 R X[4], Y[4], Z[4], xv[4], o[4];
@@ -569,7 +577,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         // 3. row sums in ascending element order
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
-            const int l = threadIdx.x + j * BLK;
+            const int l = threadIdx.x + j * NTH;
             if (l < nt) {
                 const int d = ownF[j] & 0x7f;
                 R yi = R(0);
@@ -594,7 +602,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         tn = tn2;
     }
     if (CG) {
-        const double bs = block_sum_all(part, red);
+        const double bs = block_sum_all<NTH>(part, red);
         if (threadIdx.x == 0) it.part_pq[vb] = bs;
     }
 }
@@ -604,16 +612,20 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
 // <= 448).  The FP32 kernels fit five waves without a bound (forcing six
 // spills registers and was measured slower).
 template <class R, int T, int LM>
-constexpr int tile_waves() { return (sizeof(R) == 8 && T == 128 && LM <= 448) ? 4 : 1; }
+constexpr int tile_waves()
+{
+    return (sizeof(R) == 8 && ((T == 128 && LM <= 448) || (T == 256 && LM <= 768))) ? 4 : 1;
+}
 
-template <int DIM, bool CG, class R, int T, int IPT, int LM>
-__global__ void __launch_bounds__(BLK, (tile_waves<R, T, LM>())) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta, const R *__restrict__ x,
-                                                     R *__restrict__ y, IterT<R> it)
+template <int DIM, bool CG, class R, int T, int IPT, int LM, int NTH>
+__global__ void __launch_bounds__(NTH, (tile_waves<R, T, LM>())) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta,
+                                                                             const R *__restrict__ x,
+                                                                             R *__restrict__ y, IterT<R> it)
 {
     extern __shared__ double smem_d[];
-    __shared__ double red[BLK / 64];
-    apply_tiled_body<DIM, CG, R, T, IPT, LM>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red, int(blockIdx.x),
-                                             int(gridDim.x));
+    __shared__ double red[NTH / 64];
+    apply_tiled_body<DIM, CG, R, T, IPT, LM, NTH>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red,
+                                                  int(blockIdx.x), int(gridDim.x));
 }
 
 // ------------------------------------------------------------- CG vectors
@@ -1137,18 +1149,18 @@ size_t tiled_lds_bytes(const pm_handle *h)
 thread_local hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
 
 template <class R, class K>
-int launch_tiled_k(pm_handle *h, K kern, const MeshT<R> &g, const TileArgsT<R> &ta, const R *x, R *y,
+int launch_tiled_k(pm_handle *h, K kern, int nth, const MeshT<R> &g, const TileArgsT<R> &ta, const R *x, R *y,
                    const IterT<R> &it, hipStream_t s)
 {
     const size_t lds = tiled_lds_bytes<R>(h);
     if (lds > 65536) HIPCK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     const int grid = (sizeof(R) == 8) ? h->n_ablocks : h->n_ablocks32;
     if (g_time_start) {
-        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(BLK), uint32_t(lds), s, g_time_start, g_time_stop, 0u, g, ta, x,
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(nth), uint32_t(lds), s, g_time_start, g_time_stop, 0u, g, ta, x,
                               y, it);
         g_time_start = g_time_stop = nullptr;
     } else {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLK), lds, s, g, ta, x, y, it);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(nth), lds, s, g, ta, x, y, it);
     }
     HIPCK(hipGetLastError());
     return PM_OK;
@@ -1160,7 +1172,7 @@ int launch_tiled_c(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream
     constexpr TileClass tc = TILE_CLASSES[C];
     MeshT<R> g = make_mesh<R>(h);
     TileArgsT<R> ta = make_tiles<R>(h);
-    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.t, tc.ipt, tc.lm>, g, ta, x, y, it, s);
+    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.t, tc.ipt, tc.lm, tc.nth>, tc.nth, g, ta, x, y, it, s);
 }
 
 // f.template operator()<C>() for the handle's class C
@@ -1198,10 +1210,10 @@ int occupancy_t(pm_handle *h, int *per_cu)
 {
     return with_class(h->tile_class, [&]<int C>() {
         constexpr TileClass tc = TILE_CLASSES[C];
-        const void *kern = (const void *)k_apply_tiled<DIM, true, R, tc.t, tc.ipt, tc.lm>;
+        const void *kern = (const void *)k_apply_tiled<DIM, true, R, tc.t, tc.ipt, tc.lm, tc.nth>;
         const size_t lds = tiled_lds_bytes<R>(h);
         if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-        HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, BLK, lds));
+        HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, tc.nth, lds));
         return PM_OK;
     });
 }
@@ -1296,7 +1308,7 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
     // smallest size class covering the tile, its instances and node table
     h->tile_class = -1;
     for (int c = 0; c < N_TILE_CLASSES; ++c)
-        if (TILE_CLASSES[c].t == tile_nodes && TILE_CLASSES[c].ipt * BLK >= T.max_inst &&
+        if (TILE_CLASSES[c].t == tile_nodes && TILE_CLASSES[c].ipt * TILE_CLASSES[c].nth >= T.max_inst &&
             TILE_CLASSES[c].lm >= h->max_local) {
             h->tile_class = c;
             break;
@@ -1914,7 +1926,8 @@ constexpr int MAX_CORRECTIONS = 64;
 // The batched apply runs the size classes of 128-node tiles (the first
 // N_BATCH_CLASSES entries of TILE_CLASSES).
 constexpr int N_BATCH_CLASSES = 6;
-static_assert(TILE_CLASSES[N_BATCH_CLASSES - 1].t == 128 && TILE_CLASSES[N_BATCH_CLASSES].t != 128,
+static_assert(TILE_CLASSES[N_BATCH_CLASSES - 1].t == 128 && TILE_CLASSES[N_BATCH_CLASSES].t != 128 &&
+                  TILE_CLASSES[N_BATCH_CLASSES - 1].nth == BLK,
               "batch classes are the 128-node classes");
 
 template <class R>
