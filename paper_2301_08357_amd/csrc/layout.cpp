@@ -199,7 +199,7 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
     T->max_halo = 0;
     T->max_deg = 0;
     for (int64_t i = 0; i < N; ++i) T->max_deg = std::max<int>(T->max_deg, L.n2e_off[i + 1] - L.n2e_off[i]);
-    if (T->max_deg > max_rows) return TILES_TOO_WIDE;
+    if (T->max_deg >= max_rows) return TILES_TOO_WIDE;   // row max_deg takes the halo vertices
 
     // first element whose smallest vertex is >= v (elements are sorted by it)
     std::vector<int32_t> ebeg(N + 1, 0);
@@ -246,7 +246,14 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
         const size_t base = T->inst_elem.size();
         auto add_inst = [&](int32_t e) {
             T->inst_elem.push_back(e);
-            for (int a = 0; a < 4; ++a) T->inst.push_back(a < nv ? local(L.conn[e * 4 + a]) : uint16_t(0));
+            for (int a = 0; a < 4; ++a) {
+                uint16_t f = 0;
+                if (a < nv) {
+                    f = local(L.conn[e * 4 + a]);
+                    if (f >= tile_nodes) f = uint16_t(f | (T->max_deg << T->lvb));   // halo vertex: the extra row
+                }
+                T->inst.push_back(f);
+            }
         };
         for (int32_t e : halo_el) add_inst(e);
         for (int32_t e = own0; e < own1; ++e) add_inst(e);

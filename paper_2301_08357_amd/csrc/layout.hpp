@@ -34,7 +34,7 @@ int build_layout(const pm_mesh *m, Layout *L);
 //   bits 0 .. lvb-1   tile-local index: own node i -> i - first node,
 //                     halo node -> tile_nodes + rank in the halo list;
 //   bits lvb .. 15    for an own node, the rank of the instance among that
-//                     node's instances ("row"); 0 for a halo vertex.
+//                     node's instances ("row"); max_deg for a halo vertex.
 // Node i's k-th element in ascending order is the instance whose vertex i
 // has row k.  lvb = 10 for tiles of up to 256 nodes, 11 for larger ones.
 struct Tiles {

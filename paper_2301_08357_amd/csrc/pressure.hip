@@ -13,7 +13,8 @@
 //     G   = sum_k n_k (x_k - x_0)                 (= det * grad x_h)
 //     (K x)_k = c |T| grad(phi_k) . grad(x_h) = w n_k . G,  w = c / (d! det)
 //     (K x)_0 = -sum_k (K x)_k
-//     (M x)_a = |T| / ((d+1)(d+2)) * (x_a + sum_b x_b).
+//     (M x)_a = |T| / ((d+1)(d+2)) * (x_a + sum_b x_b)
+// (evaluated as fma(m, x_a, m * sum_b x_b) with m = |T| / ((d+1)(d+2))).
 // The per-element factor beta * c_e / (d! det_e) is precomputed; the geometry
 // is recomputed from the vertex coordinates on every apply.
 //
@@ -134,10 +135,10 @@ __device__ __forceinline__ void elem_contrib(const R *X, const R *Y, const R *Z,
         const R r2 = n2x * Gx + n2y * Gy;
         const R r0 = -(r1 + r2);
         const R S = xv[0] + xv[1] + xv[2];
-        const R m = mscale * det;
-        out[0] = w * r0 + m * (xv[0] + S);
-        out[1] = w * r1 + m * (xv[1] + S);
-        out[2] = w * r2 + m * (xv[2] + S);
+        const R m = mscale * det, mS = m * S;
+        out[0] = fma(w, r0, fma(m, xv[0], mS));
+        out[1] = fma(w, r1, fma(m, xv[1], mS));
+        out[2] = fma(w, r2, fma(m, xv[2], mS));
         out[3] = R(0);
     } else {
         const R e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
@@ -156,11 +157,11 @@ __device__ __forceinline__ void elem_contrib(const R *X, const R *Y, const R *Z,
         const R r3 = n3x * Gx + n3y * Gy + n3z * Gz;
         const R r0 = -(r1 + r2 + r3);
         const R S = xv[0] + xv[1] + xv[2] + xv[3];
-        const R m = mscale * det;
-        out[0] = w * r0 + m * (xv[0] + S);
-        out[1] = w * r1 + m * (xv[1] + S);
-        out[2] = w * r2 + m * (xv[2] + S);
-        out[3] = w * r3 + m * (xv[3] + S);
+        const R m = mscale * det, mS = m * S;
+        out[0] = fma(w, r0, fma(m, xv[0], mS));
+        out[1] = fma(w, r1, fma(m, xv[1], mS));
+        out[2] = fma(w, r2, fma(m, xv[2], mS));
+        out[3] = fma(w, r3, fma(m, xv[3], mS));
     }
 }
 
@@ -359,17 +360,18 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
 // the (x, y) pair; the low LVB bits are the vertex's local index (own node
 // i -> i - first node of the tile, halo node -> T + rank in the tile's halo
 // list), the high bits its row (rank of the element among the own node's
-// elements, ascending element id; 0 for halo vertices and the unused
-// fourth vertex of a triangle).
+// elements, ascending element id).  Halo vertices carry the row max_deg,
+// an extra row of the sums table that no node reads, so every vertex's
+// contribution is written to row * RS + (local index mod T) without a test;
+// the unused fourth vertex of a triangle is 0 and never processed.
 template <int T>
 struct TileGeom {
     static_assert(T == 128 || T == 256 || T == 512, "tile sizes are powers of two");
     static constexpr int LVB = (T <= 256) ? 10 : 11;       // bits of a local index
     static constexpr unsigned LV_MASK = (1u << LVB) - 1u;
-    static constexpr int MAX_ROWS = 1 << (16 - LVB);       // rows a record can name
+    static constexpr int MAX_ROWS = 1 << (16 - LVB);       // rows a record can name (incl. the extra row)
     static constexpr int MAX_LOCAL = 1 << LVB;             // own + halo nodes a record can name
     static constexpr int RS = T + 1;                       // row stride of the sums table (padded)
-    static constexpr int DUMMY = 64;                       // per-lane sink for halo-vertex writes
 };
 
 // Size classes of the tiled kernel: (tile nodes, instances per lane,
@@ -398,11 +400,11 @@ struct TileArgsT {
 };
 
 // LDS bytes of the tiled kernel: node table (DIM+1 fields of LM entries)
-// and the sums table (max_deg rows of RS, plus the halo-write sink).
+// and the sums table (max_deg rows of RS plus the row of halo writes).
 template <class R, int T>
 constexpr size_t tile_lds_bytes(int dim, int lm, int max_deg)
 {
-    return sizeof(R) * (size_t(dim + 1) * size_t(lm) + size_t(max_deg) * TileGeom<T>::RS + TileGeom<T>::DUMMY);
+    return sizeof(R) * (size_t(dim + 1) * size_t(lm) + size_t(max_deg + 1) * TileGeom<T>::RS);
 }
 
 // Morton-tiled apply.  Each block walks its tiles (tile_at); for every tile
@@ -434,8 +436,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     static_assert(LM >= T && LM <= G::MAX_LOCAL, "node table");
     if (CG && block_done(it.st)) return;
     R *const sN = smem;                      // NF x LM: X, Y, (Z,) value
-    R *const sS = smem + NF * LM;            // max_deg x RS sums, then the sink
-    R *const sink = sS + ta.max_deg * RS + (threadIdx.x & (G::DUMMY - 1));
+    R *const sS = smem + NF * LM;            // (max_deg + 1) x RS sums
 
     // -- loads of one tile, into registers (under CG: r and p_{k-1}; p_k is
     // formed when staging, once beta is known)
@@ -556,11 +557,8 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
                 if (DIM == 2) xv[3] = R(0);
                 elem_contrib<DIM, R>(X, Y, Z, xv, iw[k], g.mscale, o);
 #pragma unroll
-                for (int a = 0; a <= DIM; ++a) {
-                    const int lv = int(u[a] & G::LV_MASK);
-                    R *dst = (lv < T) ? sS + int(u[a] >> G::LVB) * RS + lv : sink;
-                    *dst = o[a];
-                }
+                for (int a = 0; a <= DIM; ++a)
+                    sS[int(u[a] >> G::LVB) * RS + int(u[a] & unsigned(T - 1))] = o[a];
             }
             if (tn >= 0) {
                 load_inst(k, i0n, nin);
