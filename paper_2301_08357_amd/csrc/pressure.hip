@@ -976,6 +976,13 @@ struct pm_handle {
     float *p32[2] = {nullptr, nullptr};
     CGState *st_in = nullptr;
     CGState *hst_in = nullptr;
+    // host bookkeeping of a mixed-precision solve run by a batch; it lives
+    // with the handle so that a rebuilt batch continues the solve
+    struct MixedSolve {
+        int phase = 0;       // MX_IDLE, MX_RESIDUAL, MX_INNER, MX_FINISHED
+        double rtol = 0.0, rel = 0.0;
+        int max_iter = 0, iters = 0, n_outer = 0, status = 0, iter0 = 0;
+    } mx;
     // CG vectors (device, internal order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
     double *pbuf[2] = {nullptr, nullptr};
@@ -1515,6 +1522,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
         HIPCK(hipMemset(h->p32[1], 0, 4 * N));
         TRY(dalloc(h, &h->st_in, 1));
         HIPCK(hipMemset(h->st_in, 0, sizeof(CGState)));
+        hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, 0, h->st_in);   // idle until a mixed solve starts
         HIPCK(hipHostMalloc((void **)&h->hst_in, sizeof(CGState), hipHostMallocDefault));
         if (tiled_lds_bytes<float>(h) > h->lds_limit) return PM_EINVAL;
         TRY(apply_grid<float>(h, &h->n_ablocks32));
@@ -1906,13 +1914,6 @@ struct pm_batch {
     hipGraphExec_t gexec = nullptr;
     int graph_iters = 16;
     int k_next = 1;          // launch index of the next batched iteration
-    // mixed batches: host bookkeeping of each mesh's solve
-    struct Mixed {
-        int phase = 0;       // MX_IDLE, MX_RESIDUAL, MX_INNER, MX_FINISHED
-        double rtol = 0.0, rel = 0.0;
-        int max_iter = 0, iters = 0, n_outer = 0, status = 0, iter0 = 0;
-    };
-    std::vector<Mixed> mx;
     std::vector<double *> hist_seen;   // history pointers in the uploaded descriptors
 };
 
@@ -2085,7 +2086,6 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
         for (int j = 0; j < h->n_vblocks; ++j) uslots.push_back(make_int2(m, j));
         b->hs.push_back(h);
     }
-    b->mx.assign(size_t(n), pm_batch::Mixed());
     b->bclass = -1;
     for (int c = 0; c < N_BATCH_CLASSES; ++c)
         if (TILE_CLASSES[c].ipt * BLK >= max_inst && TILE_CLASSES[c].lm >= max_local) {
@@ -2115,6 +2115,7 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     if (hipMalloc((void **)&b->d_states, sizeof(CGState) * n) != hipSuccess) return PM_ENOMEM;
     HIPCK(hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault));
     HIPCK(hipHostMalloc((void **)&b->h_states, sizeof(CGState) * n, hipHostMallocDefault));
+    std::memset(b->h_states, 0, sizeof(CGState) * n);   // no inner solve is seen as stopped before a step
     HIPCK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIPCK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
     TRY(b->mixed ? upload_meshes<float>(b) : upload_meshes<double>(b));
@@ -2124,8 +2125,6 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     b->h_ctl->k_update = k_start - 1;
     b->h_ctl->n_done = 0;
     HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
-    if (b->mixed)   // the inner solves are idle until a mixed solve starts
-        for (pm_handle *h : b->hs) hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, b->stream, h->st_in);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(b->stream));
     return PM_OK;
@@ -2205,8 +2204,8 @@ int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const double *x0
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist,
                        b->k_next);
     if (b->mixed) {
-        pm_batch::Mixed &X = b->mx[m];
-        X = pm_batch::Mixed();
+        pm_handle::MixedSolve &X = b->hs[m]->mx;
+        X = pm_handle::MixedSolve();
         X.phase = MX_RESIDUAL;
         X.rtol = rtol;
         X.max_iter = max_iter;
@@ -2227,14 +2226,14 @@ int batch_corrections(pm_batch *b, hipStream_t s)
     const int n = int(b->hs.size());
     std::vector<int> due;
     for (int m = 0; m < n; ++m) {
-        pm_batch::Mixed &X = b->mx[m];
+        pm_handle::MixedSolve &X = b->hs[m]->mx;
         if (X.phase == MX_RESIDUAL) due.push_back(m);
         else if (X.phase == MX_INNER && b->h_states[m].done) due.push_back(m);
     }
     if (due.empty()) return PM_OK;
     for (int m : due) {
         pm_handle *h = b->hs[m];
-        pm_batch::Mixed &X = b->mx[m];
+        pm_handle::MixedSolve &X = b->hs[m]->mx;
         const int N = int(h->N);
         const unsigned vg = h->n_vblocks;
         if (X.phase == MX_INNER) {
@@ -2262,7 +2261,7 @@ int batch_corrections(pm_batch *b, hipStream_t s)
     HIPCK(hipStreamSynchronize(s));
     for (int m : due) {
         pm_handle *h = b->hs[m];
-        pm_batch::Mixed &X = b->mx[m];
+        pm_handle::MixedSolve &X = b->hs[m]->mx;
         if (X.phase == MX_FINISHED) continue;
         const int N = int(h->N);
         const unsigned vg = h->n_vblocks;
@@ -2336,7 +2335,7 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
 
 bool batch_mesh_done(const pm_batch *b, int m)
 {
-    if (b->mixed) return b->mx[m].phase == MX_IDLE || b->mx[m].phase == MX_FINISHED;
+    if (b->mixed) return b->hs[m]->mx.phase == MX_IDLE || b->hs[m]->mx.phase == MX_FINISHED;
     return b->h_states[m].done != 0;
 }
 
@@ -2350,7 +2349,7 @@ int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, do
     const int N = int(h->N);
     const unsigned vg = h->n_vblocks;
     if (b->mixed) {
-        pm_batch::Mixed &X = b->mx[m];
+        pm_handle::MixedSolve &X = b->hs[m]->mx;
         hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
         HIPCK(hipGetLastError());
         HIPCK(hipStreamSynchronize(s));

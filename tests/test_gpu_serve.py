@@ -27,8 +27,10 @@ def _pool():
     return probs
 
 
-def test_serving_results_equal_alone_and_in_the_mix():
+@pytest.mark.parametrize("mixed", [False, True])
+def test_serving_results_equal_alone_and_in_the_mix(mixed):
     probs = _pool()
+    flags = pm.PM_FP64 | (pm.PM_FP32_INNER if mixed else 0)
     base = []
     for p in probs:
         s = pm.PressureSystem.from_problem(p)
@@ -43,14 +45,15 @@ def test_serving_results_equal_alone_and_in_the_mix():
         scale = 0.01 * float(torch.linalg.norm(b)) / np.sqrt(free.sum())
         return b + torch.tensor(np.where(free, scale * xi, 0.0), device="cuda")
 
+    print("case serve mixed=%s" % mixed, flush=True)
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(0.002, size=30))
     meshes = rng.integers(0, len(probs), size=30)
     reqs = [Request(rid=i, mesh=int(m), arrival=float(t)) for i, (t, m) in enumerate(zip(arrivals, meshes))]
-    costs = [pm.footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems) + 8 * p.mesh.n_nodes for p in probs]
+    costs = [pm.footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems, flags) + 8 * p.mesh.n_nodes for p in probs]
     budget = sum(sorted(costs)[-3:])           # at most ~3 meshes resident: forces evictions
     srv = PressureServer(probs, budget, max_in_flight=3, rtol=1e-10, graph_iters=4, tiles_per_slot=2,
-                         nodes_per_lane=4, keep_x0=True)
+                         nodes_per_lane=4, keep_x0=True, mixed=mixed, inner_rtol=1e-2)
     done = srv.run(reqs, rhs_fn)
     st = srv.stats
     print("stats", st, flush=True)
@@ -60,10 +63,13 @@ def test_serving_results_equal_alone_and_in_the_mix():
     # replay every request alone on a fresh handle with the same grids
     srv.close()
     for m, p in enumerate(probs):
-        s = pm.PressureSystem.from_problem(p)
+        s = pm.PressureSystem.from_problem(p, flags=flags)
         pm.PressureBatch([s], tiles_per_slot=2, nodes_per_lane=4).close()   # same launch grids
         for r in [r for r in done if r.mesh == m]:
-            alone = s.solve(r.rhs, x0=r.x0, rtol=1e-10)
+            if mixed:
+                alone = s.solve_mixed(r.rhs, x0=r.x0, rtol=1e-10, inner_rtol=1e-2)
+            else:
+                alone = s.solve(r.rhs, x0=r.x0, rtol=1e-10)
             assert alone.iters == r.iters, (r.rid, alone.iters, r.iters)
             a = alone.p.cpu().numpy()
             b = r.result.cpu().numpy()
