@@ -164,7 +164,18 @@ def main():
     if not args.no_mixed:
         out["mixed"] = mixed_comparison(systems, rhs, xstar, args, elapsed / len(lat))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(probs)
+        out["cpu_baseline"], x_oracle, b_oracle = cpu_baseline(probs)
+        # error of each GPU solve against the oracle's FP64 solution of the
+        # same system (the oracle's right-hand side), per w
+        def vs_oracle(xg, xo):
+            return float(np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo))
+        bo = [torch.tensor(b, device=dev) for b in b_oracle]
+        out["error_vs_oracle"] = {
+            "fp64": [vs_oracle(s.solve(b, rtol=args.rtol).p, xo) for s, b, xo in zip(systems, bo, x_oracle)]}
+        if not args.no_mixed:
+            out["error_vs_oracle"]["mixed"] = [
+                vs_oracle(s.solve_mixed(b, rtol=args.rtol, inner_rtol=args.inner_rtol).p, xo)
+                for s, b, xo in zip(systems, bo, x_oracle)]
     print(json.dumps(out), flush=True)
     for s in systems:
         s.close()
@@ -429,15 +440,20 @@ def mixed_comparison(systems, rhs, xstar, args, fp64_solve_s):
 
 def cpu_baseline(probs):
     """The CPU oracle (assembled CSR + textbook CG, one thread) on the same
-    three systems, one solve each; assembly is not timed."""
+    three systems, one solve each; assembly is not timed.  Returns the
+    baseline record, the oracle's solutions and its right-hand sides
+    (caller's node order)."""
     import oracle
     total_dofiter, total_t = 0.0, 0.0
+    xs, bs = [], []
     for p in probs:
         A = oracle.assemble_problem(p)
         b = A.matvec(p.extra["xstar"])
         t0 = time.perf_counter()
         x, st, it, _, _ = oracle.cg(A, b, rtol=1e-10, max_iter=20000, dirichlet=p.mesh.dirichlet)
         total_t += time.perf_counter() - t0
+        xs.append(x)
+        bs.append(b)
         total_dofiter += float((p.mesh.dirichlet == 0).sum()) * it
     cpu = "unknown CPU"
     try:
@@ -451,7 +467,7 @@ def cpu_baseline(probs):
             "kind": "oracle",
             "sample": "one FP64 CG solve per w in {1e-6,1e-3,1} on the same 64^3 mesh "
                       "(%.1f s of CPU time, assembly excluded; one thread of %d available, %s)"
-                      % (total_t, len(os.sched_getaffinity(0)), cpu)}
+                      % (total_t, len(os.sched_getaffinity(0)), cpu)}, xs, bs
 
 
 if __name__ == "__main__":

@@ -71,14 +71,19 @@ extern "C" {
 /* Precision flags for pressure_setup / pressure_footprint. */
 #define PM_FP64 1             /* FP64 operator data (always present)               */
 #define PM_FP32_INNER 2       /* also keep FP32 operator data for pressure_solve_mixed */
-/* Morton tile size of the tiled apply (bits 4..7 of flags); 0 = automatic. */
+/* Morton tile size of the tiled apply (bits 4..7 of flags).  0 = the
+ * default, 128 nodes; a mesh that the tiled kernel cannot take at the
+ * default size (a node in more than 63 elements, or a tile reaching more
+ * than 1024 own and halo nodes) then runs on the node kernel, while an
+ * explicit size returns PM_EINVAL for it.  pressure_tune_tile picks the
+ * fastest size for a mesh. */
 #define PM_TILE_MASK 0xF0
 #define PM_TILE_256 0x10
 #define PM_TILE_512 0x20
 #define PM_TILE_128 0x30
 
 /* Apply-kernel variants (pressure_set_variant). */
-#define PM_VARIANT_AUTO 0     /* the tuned default                                 */
+#define PM_VARIANT_AUTO 0     /* tiled when the mesh has tiles, else node           */
 #define PM_VARIANT_NODE 1     /* one lane per node, element factors recomputed per incidence */
 #define PM_VARIANT_TILED 2    /* Morton tiles: each element computed once per tile in LDS */
 
@@ -194,7 +199,10 @@ const char *pressure_strerror(int status);
 int pressure_layout(const pm_mesh *mesh, int32_t *node_new2old, int32_t *elem_new2old,
                     int32_t *elems_new, int32_t *n2e_off, int32_t *n2e_ent);
 
-/* Select the apply kernel used by pressure_apply / pressure_solve. */
+/* Select the apply kernel used by pressure_apply / pressure_solve.  Both
+ * kernels give the same bits.  PM_VARIANT_TILED returns PM_EINVAL for a
+ * handle without tiles (see PM_TILE_MASK); PM_EINVAL also for an unknown
+ * variant. */
 int pressure_set_variant(pm_handle *h, int32_t variant);
 
 /* Kernel timing with HIP events on the solve stream.  enable != 0 starts

@@ -1439,7 +1439,7 @@ void pressure_destroy(pm_handle *h)
     delete h;
 }
 
-static int tile_nodes_for(int32_t flags, int64_t N)
+static int tile_nodes_for(int32_t flags)
 {
     switch (flags & PM_TILE_MASK) {
     case PM_TILE_256: return 256;
@@ -1499,7 +1499,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     TRY(dupload(h, &h->coef, cnew));
     TRY(dalloc(h, &h->w, E));
     TRY(dupload(h, &h->dir, L.dirichlet));
-    const int tn = tile_nodes_for(flags, N);
+    const int tn = tile_nodes_for(flags);
     if (tn < 0) return PM_EINVAL;
     {
         int st = build_tiles_on_device(h, L, tn);
