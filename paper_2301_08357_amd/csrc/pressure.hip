@@ -637,6 +637,20 @@ __device__ __forceinline__ void update_body(int N, R *__restrict__ x, R *__restr
                                             int vb, int nvb)
 {
     if (block_done(st)) return;
+    // the lane's first PF nodes are loaded while the partials are summed
+    constexpr int PF = 4;
+    const int i0 = vb * BLK + threadIdx.x, stride = nvb * BLK;
+    R vx[PF], vp[PF], vr[PF], vq[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int i = i0 + u * stride;
+        if (i < N) {
+            vx[u] = x[i];
+            vp[u] = p[i];
+            vr[u] = r[i];
+            vq[u] = q[i];
+        }
+    }
     const double pq = sum_partials(part_pq, n_ablocks, red);
     const double rr = sum_partials(rr_cur, nvb, red);
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -648,7 +662,17 @@ __device__ __forceinline__ void update_body(int N, R *__restrict__ x, R *__restr
     }
     const R a = R(rr / pq);
     double v = 0.0;
-    for (int i = vb * BLK + threadIdx.x; i < N; i += nvb * BLK) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int i = i0 + u * stride;
+        if (i < N) {
+            x[i] = vx[u] + a * vp[u];
+            const R ri = vr[u] - a * vq[u];
+            r[i] = ri;
+            v += double(ri) * double(ri);
+        }
+    }
+    for (int i = i0 + PF * stride; i < N; i += stride) {
         x[i] += a * p[i];
         const R ri = r[i] - a * q[i];
         r[i] = ri;
