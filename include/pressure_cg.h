@@ -281,7 +281,10 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
  * writes its solution to p_dev and returns its status (mesh m must be
  * finished; rhs_dev and rtol as passed to begin).  A solve's arithmetic does
  * not depend on the step at which it starts or on the other solves in
- * flight, so each result equals the same solve run alone, bit for bit. */
+ * flight, so each result equals the same solve run alone, bit for bit.
+ * The batch runs on a stream of its own: _begin and _step start after the
+ * work already queued on `stream`, _finish's output is ready in `stream`
+ * order, and _step returns with the batch's work complete. */
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
                          int32_t max_iter, void *stream);
 int pressure_batch_step(pm_batch *b, int32_t *done, void *stream);

@@ -2450,7 +2450,9 @@ int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const do
 int pressure_batch_step(pm_batch *b, int32_t *done, void *stream)
 {
     if (!b || !done) return PM_EINVAL;
-    (void)stream;
+    // the batch runs on its own stream, after the caller's work so far
+    HIPCK(hipEventRecord(b->ev, (hipStream_t)stream));
+    HIPCK(hipStreamWaitEvent(b->stream, b->ev, 0));
     TRY(batch_step_impl(b, b->stream));
     for (size_t m = 0; m < b->hs.size(); ++m) done[m] = batch_mesh_done(b, int(m)) ? 1 : 0;
     return PM_OK;
