@@ -25,7 +25,19 @@
  *     A_D = P_I (alpha M + beta K_c) P_I + P_B,
  *
  * symmetric positive definite when alpha >= 0, beta > 0, every c_e > 0 and
- * (alpha > 0 or at least one Dirichlet node).  An inhomogeneous value g is
+ * (alpha > 0 or at least one Dirichlet node).
+ *
+ * With alpha = 0 and no Dirichlet node (the zero Mach number limit, where
+ * the system becomes the pressure Poisson problem of the incompressible
+ * scheme, Sec. 1 and 3.4) the operator is singular: its kernel is the
+ * constants.  The handle detects this case and solves the weak problem posed
+ * in V_0 = {z : int z = 0} (Sec. 3.4): with the lumped weights
+ * m_i = int phi_i and |Omega| = sum_i m_i it replaces rhs by the compatible
+ * rhs - (sum_i rhs_i / |Omega|) m, runs CG on it (the operator is positive
+ * definite on the complement of the constants, and CG stays in it), and
+ * returns the solution shifted so that int p_h = sum_i m_i p_i = 0.
+ * Stopping test, iters, res_hist and true_relres then refer to the
+ * projected rhs.  An inhomogeneous value g is
  * imposed by passing rhs_B = g and rhs_I = f_I - A_IB g; the solver then
  * returns p_B = g exactly.
  *

@@ -18,6 +18,13 @@ What each function follows in the paper:
                   the paper; pinned only through the FP64 oracle's residual).
   layout          Morton renumbering and node-to-element lists (not in the
                   paper; integer definitions compared bit for bit).
+  lumped_mass     m_i = integral of the P1 basis function of node i (sum of
+                  |T|/(d+1) over its elements): the weights of the
+                  constraint of the space V_0 (Sec. 3.4).
+  solve_v0        the weak problem posed in V_0 = {z : int z = 0}
+                  (Sec. 3.4) when the operator is singular (no mass term,
+                  no Dirichlet node): the bordered system
+                  [A m; m^T 0][p; lam] = [b; 0], solved densely (NumPy).
 """
 
 import ctypes
@@ -246,3 +253,29 @@ def mass_rhs(prob, f):
     fi = np.where(m.dirichlet.astype(bool), 0.0, f)
     y = apply_elements(m.dim, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, m.dirichlet, fi)
     return np.where(m.dirichlet.astype(bool), f, y)
+
+
+def lumped_mass(dim, coords, elems):
+    """m_i = sum over the elements containing node i of |T| / (d+1), with
+    |T| = |det J| / d! from NumPy's determinant of the edge matrix."""
+    coords = _f64(coords)
+    elems = np.asarray(elems, dtype=np.int64)
+    x = coords[elems]                                   # [E, d+1, d]
+    J = x[:, 1:, :] - x[:, :1, :]                       # rows e_k = x_k - x_0
+    vol = np.abs(np.linalg.det(J)) / (2.0 if dim == 2 else 6.0)
+    return np.bincount(elems.ravel(), weights=np.repeat(vol / (dim + 1), dim + 1), minlength=coords.shape[0])
+
+
+def solve_v0(A, b, m):
+    """The solution in V_0 (Sec. 3.4) of the singular system: p with
+    A p = b - lam m and m^T p = 0, from the dense bordered system."""
+    n = A.n
+    S = A.to_scipy().toarray()
+    B = np.zeros((n + 1, n + 1))
+    B[:n, :n] = S
+    B[:n, n] = m
+    B[n, :n] = m
+    rhs = np.concatenate([_f64(b), [0.0]])
+    sol = np.linalg.solve(B, rhs)
+    return sol[:n]
+

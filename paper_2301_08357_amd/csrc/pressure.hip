@@ -787,6 +787,66 @@ __global__ void k_reopen(CGState *st)
     if (threadIdx.x == 0) st->done = 0;
 }
 
+// ------------------------------------------------- the space V_0 (Sec. 3.4)
+// With no Dirichlet node and alpha = 0 the operator beta K_c is singular
+// (its kernel is the constants) and the weak problem is posed in
+// V_0 = {z : int z = 0}.  Testing with z in V_0 gives K p = b - (sum_i b_i /
+// |Omega|) m, with m_i = int phi_i (the lumped mass weights, |Omega| =
+// sum_i m_i), and the solution is the one with sum_i m_i p_i = 0.
+
+// m_i = sum over node i's elements (ascending) of |T_e| / (d+1)
+template <int DIM>
+__global__ void __launch_bounds__(BLK) k_lumped_mass(Mesh g, const int *__restrict__ off,
+                                                     const int *__restrict__ ent, double *__restrict__ mw)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= g.N) return;
+    constexpr double fact = (DIM == 2) ? 2.0 * 3.0 : 6.0 * 4.0;   // d! (d+1)
+    double sum = 0.0;
+    for (int k = off[i]; k < off[i + 1]; ++k) {
+        const int4 c = g.conn[ent[k] >> 2];
+        const int v[4] = {c.x & 0x7fffffff, c.y & 0x7fffffff, c.z & 0x7fffffff, c.w & 0x7fffffff};
+        double X[4], Y[4], Z[4];
+        for (int a = 0; a <= DIM; ++a) {
+            X[a] = g.X[v[a]];
+            Y[a] = g.Y[v[a]];
+            Z[a] = (DIM == 3) ? g.Z[v[a]] : 0.0;
+        }
+        sum += elem_det<DIM, double>(X, Y, Z) / fact;
+    }
+    mw[i] = sum;
+}
+
+// block partials of sum_i w_i v_i (w = null: sum_i v_i)
+__global__ void __launch_bounds__(BLK) k_wsum(int N, const double *__restrict__ w, const double *__restrict__ v,
+                                              double *part)
+{
+    __shared__ double red[BLK / 64];
+    double acc = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) acc += w ? w[i] * v[i] : v[i];
+    const double bs = block_sum_all(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// v -= (sum of the n partials / denom) * (w ? w_i : 1); partials of v.v
+// into bb (may be null)
+__global__ void __launch_bounds__(BLK) k_sub_mean(int N, double *__restrict__ v, const double *__restrict__ w,
+                                                  const double *part, int n, double denom, double *bb)
+{
+    __shared__ double red[BLK / 64];
+    const double c = sum_partials(part, n, red) / denom;
+    double acc = 0.0;
+    for (int i = blockIdx.x * BLK + threadIdx.x; i < N; i += gridDim.x * BLK) {
+        const double vi = v[i] - c * (w ? w[i] : 1.0);
+        v[i] = vi;
+        acc += vi * vi;
+    }
+    if (bb) {
+        const double bs = block_sum_all(acc, red);
+        if (threadIdx.x == 0) bb[blockIdx.x] = bs;
+    }
+}
+
 // ----------------------------------------------------------- batched solve
 // Many meshes advance their CG iterations together: one launch runs the
 // apply of iteration k for every (mesh, slot) pair, the next the update.  The
@@ -1009,6 +1069,10 @@ struct pm_handle {
     } mx;
     // CG vectors (device, internal order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
+    // alpha = 0 and no Dirichlet node: the solve is posed in V_0
+    bool singular = false;
+    double *mw = nullptr;       // m_i = int phi_i
+    double m_total = 0.0;       // |Omega| = sum_i m_i
     double *pbuf[2] = {nullptr, nullptr};
     double *part = nullptr;     // [apply partials | rr partials x2 | misc partials]
     int n_vblocks = 0, n_ablocks = 0, n_ablocks32 = 0, n_cu = 256;
@@ -1454,13 +1518,35 @@ void pressure_destroy(pm_handle *h)
                     h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst, h->t_inst_w,
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
-                    h->d32, h->p32[0], h->p32[1], h->st_in};
+                    h->d32, h->p32[0], h->p32[1], h->st_in, h->mw};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
     if (h->hst_in) (void)hipHostFree(h->hst_in);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
+}
+
+// No Dirichlet node and alpha = 0: the solve is posed in V_0, which needs the
+// lumped mass weights m_i = int phi_i and |Omega| (computed once).
+static int update_v0(pm_handle *h)
+{
+    h->singular = (h->n_free == h->N && h->alpha == 0.0);
+    if (!h->singular || h->mw) return PM_OK;
+    const int64_t N = h->N;
+    TRY(dalloc(h, &h->mw, N));
+    Mesh g = make_mesh<double>(h);
+    if (h->dim == 2)
+        hipLaunchKernelGGL(k_lumped_mass<2>, dim3(grid_of(N)), dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+    else
+        hipLaunchKernelGGL(k_lumped_mass<3>, dim3(grid_of(N)), dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+    HIPCK(hipGetLastError());
+    std::vector<double> mw(N);
+    HIPCK(hipMemcpy(mw.data(), h->mw, 8 * N, hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (double v : mw) tot += v;
+    h->m_total = tot;
+    return PM_OK;
 }
 
 static int tile_nodes_for(int32_t flags)
@@ -1562,7 +1648,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     HIPCK(hipMemset(h->pbuf[0], 0, 8 * N));
     HIPCK(hipMemset(h->pbuf[1], 0, 8 * N));
     TRY(compute_factors(h));
-    return PM_OK;
+    return update_v0(h);
 }
 
 int pressure_setup(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt,
@@ -1601,7 +1687,8 @@ int pressure_update_coef(pm_handle *h, const double *elem_coef, double mass_coef
     }
     h->alpha = mass_coef;
     h->dt = dt;
-    return compute_factors(h);
+    TRY(compute_factors(h));
+    return update_v0(h);
 }
 
 int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *stream)
@@ -1655,6 +1742,33 @@ static int launch_iterations(pm_handle *h, int k0, int count, bool first, size_t
     return PM_OK;
 }
 
+// V_0 (singular handles only): b -= (sum b / |Omega|) m, with the partials of
+// b.b for ||b|| where k_prepare left them; and, after the solve, the shift
+// x -= (sum_i m_i x_i / |Omega|) that makes int x_h = 0.
+static int project_rhs(pm_handle *h, hipStream_t s)
+{
+    if (!h->singular) return PM_OK;
+    const int N = int(h->N);
+    const unsigned vg = h->n_vblocks;
+    hipLaunchKernelGGL(k_wsum, dim3(vg), dim3(BLK), 0, s, N, nullptr, h->b, h->part_rr(0));
+    hipLaunchKernelGGL(k_sub_mean, dim3(vg), dim3(BLK), 0, s, N, h->b, h->mw, h->part_rr(0), int(vg), h->m_total,
+                       h->part_misc());
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
+static int shift_mean(pm_handle *h, hipStream_t s)
+{
+    if (!h->singular) return PM_OK;
+    const int N = int(h->N);
+    const unsigned vg = h->n_vblocks;
+    hipLaunchKernelGGL(k_wsum, dim3(vg), dim3(BLK), 0, s, N, h->mw, h->x, h->part_misc());
+    hipLaunchKernelGGL(k_sub_mean, dim3(vg), dim3(BLK), 0, s, N, h->x, nullptr, h->part_misc(), int(vg), h->m_total,
+                       nullptr);
+    HIPCK(hipGetLastError());
+    return PM_OK;
+}
+
 static int read_state(pm_handle *h, hipStream_t s)
 {
     HIPCK(hipMemcpyAsync(h->hst, h->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -1675,6 +1789,7 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
 
     hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                        h->part_misc());
+    TRY(project_rhs(h, s));
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist, 1);
     HIPCK(hipGetLastError());
     TRY(launch_apply(h, h->x, h->q, nullptr, s));
@@ -1730,6 +1845,7 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
         first = true;
         ++replaced;
     }
+    TRY(shift_mean(h, s));
     hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
     HIPCK(hipGetLastError());
     const CGState fin = *h->hst;
@@ -1788,6 +1904,7 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
 
     hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                        h->part_misc());
+    TRY(project_rhs(h, s));
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist, 1);
     HIPCK(hipGetLastError());
     TRY(read_state(h, s));
@@ -1853,6 +1970,7 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
         HIPCK(hipGetLastError());
         ++n_outer;
     }
+    TRY(shift_mean(h, s));
     hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(s));
@@ -2225,6 +2343,7 @@ int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const double *x0
     const unsigned vg = h->n_vblocks;
     hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                        h->part_misc());
+    TRY(project_rhs(h, s));
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist,
                        b->k_next);
     if (b->mixed) {
@@ -2374,6 +2493,7 @@ int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, do
     const unsigned vg = h->n_vblocks;
     if (b->mixed) {
         pm_handle::MixedSolve &X = b->hs[m]->mx;
+        TRY(shift_mean(h, s));
         hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
         HIPCK(hipGetLastError());
         HIPCK(hipStreamSynchronize(s));
@@ -2386,6 +2506,7 @@ int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, do
     TRY(launch_apply(h, h->x, h->q, nullptr, s));
     hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_misc());
     hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg));
+    TRY(shift_mean(h, s));
     hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
     HIPCK(hipGetLastError());
     TRY(read_state(h, s));

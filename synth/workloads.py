@@ -98,3 +98,26 @@ def arrivals(n_requests, rate, n_meshes, seed=MASTER_SEED):
     gaps = -np.log1p(-uniform(seed, STREAM_ARRIVAL, k)) / rate
     choice = np.minimum((uniform(seed, STREAM_CHOICE, k) * n_meshes).astype(np.int64), n_meshes - 1)
     return np.cumsum(gaps), choice
+
+
+def neumann_square(n=32, seed=MASTER_SEED, jitter=0.2):
+    """The zero-Mach limit of the pressure system: alpha = 0, no Dirichlet
+    node (the solve is posed in V_0), c = 1 on the unit square.  Source of
+    p = cos(pi x) cos(pi y), which has zero mean and zero normal derivative:
+    f = 2 pi^2 p.  rtol 1e-12."""
+    m = structured_mesh(2, n, jitter=jitter, seed=seed)
+    m.dirichlet[:] = 0
+    p = np.cos(np.pi * m.coords[:, 0]) * np.cos(np.pi * m.coords[:, 1])
+    return Problem("neumann_square_%d" % n, m, np.ones(m.n_elems), 0.0, 1.0, 1e-12, seed,
+                   extra={"source": 2.0 * np.pi ** 2 * p, "exact": p})
+
+
+def neumann_cube(n=10, seed=MASTER_SEED, jitter=0.2, rho="lognormal"):
+    """alpha = 0 and no Dirichlet node on the unit cube, c = 1/rho; the rhs
+    is b = A x* with x* = prod cos(pi x_i) (so b is compatible)."""
+    m = structured_mesh(3, n, jitter=jitter, seed=seed)
+    m.dirichlet[:] = 0
+    r = fields.rho_lognormal(seed, m.n_elems, 0.5) if rho == "lognormal" else fields.rho_uniform(seed, m.n_elems)
+    xs = np.prod(np.cos(np.pi * m.coords), axis=1)
+    return Problem("neumann_cube_%d" % n, m, 1.0 / r, 0.0, 1.0, 1e-12, seed, extra={"xstar": xs})
+

@@ -370,3 +370,39 @@ def test_orientation_repair_and_errors():
     bad = m.elems.copy()
     bad[0, 0] = m.n_nodes
     assert oracle.orient(3, m.coords, bad)[0] == oracle.EINVAL
+
+
+# ---------------------------------------------------------------- V_0 (Sec. 3.4)
+
+def test_lumped_mass_weights_pins():
+    """m_i = int phi_i: the weights sum to |Omega| = 1 on the unit square and
+    cube, and equal the row sums of the consistent mass matrix."""
+    for dim, n in ((2, 7), (3, 4)):
+        m = smesh.structured_mesh(dim, n, jitter=0.2, seed=5)
+        mw = oracle.lumped_mass(dim, m.coords, m.elems)
+        assert abs(mw.sum() - 1.0) < 1e-13
+        M = oracle.assemble(dim, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, None)
+        assert np.max(np.abs(M.matvec(np.ones(m.n_nodes)) - mw)) < 1e-15
+
+
+def test_v0_solution_pins():
+    """The weak problem in V_0 with no mass term and no Dirichlet node: the
+    bordered solution is mean-zero (int p_h = 0), solves A p = b - lam m with
+    lam = sum b / |Omega|, and converges at second order in L2 to
+    p = cos(pi x) cos(pi y), the Neumann solution of -Laplace p = 2 pi^2 p."""
+    errs = []
+    for n in (8, 16, 32):
+        prob = workloads.neumann_square(n)
+        m = prob.mesh
+        mw = oracle.lumped_mass(2, m.coords, m.elems)
+        K = oracle.assemble_problem(prob)
+        b = oracle.mass_rhs(prob, prob.extra["source"])
+        p = oracle.solve_v0(K, b, mw)
+        assert abs(mw @ p) < 1e-14
+        lam = b.sum() / mw.sum()
+        assert np.max(np.abs(K.matvec(p) - (b - lam * mw))) < 1e-11 * np.max(np.abs(b))
+        M = oracle.assemble(2, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, None)
+        e = p - prob.extra["exact"]
+        errs.append(np.sqrt(e @ M.matvec(e)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.85) and np.all(rates < 2.15), rates
