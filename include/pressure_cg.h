@@ -25,7 +25,9 @@
  *     A_D = P_I (alpha M + beta K_c) P_I + P_B,
  *
  * symmetric positive definite when alpha >= 0, beta > 0, every c_e > 0 and
- * (alpha > 0 or at least one Dirichlet node).
+ * (alpha > 0 or at least one Dirichlet node).  An inhomogeneous value g is
+ * imposed by passing rhs_B = g and rhs_I = f_I - A_IB g; the solver then
+ * returns p_B = g exactly.
  *
  * With alpha = 0 and no Dirichlet node (the zero Mach number limit, where
  * the system becomes the pressure Poisson problem of the incompressible
@@ -37,9 +39,7 @@
  * definite on the complement of the constants, and CG stays in it), and
  * returns the solution shifted so that int p_h = sum_i m_i p_i = 0.
  * Stopping test, iters, res_hist and true_relres then refer to the
- * projected rhs.  An inhomogeneous value g is
- * imposed by passing rhs_B = g and rhs_I = f_I - A_IB g; the solver then
- * returns p_B = g exactly.
+ * projected rhs.
  *
  * The solve is the classical conjugate gradient method the paper names for
  * this system (abstract; Sec. 3.4), matrix-free: the operator is never
@@ -110,7 +110,20 @@ typedef struct pm_handle pm_handle;
  *   dirichlet  n_nodes bytes, nonzero = Dirichlet pressure node; NULL = none
  *   lattice    optional n_nodes * dim integer coordinates in [0, 2^21) used
  *              as Morton keys; NULL = coordinates quantised to 21 bits per
- *              axis over the bounding box. */
+ *              axis over the bounding box.
+ *   period     optional dim doubles: period[ax] > 0 makes the mesh periodic
+ *              along axis ax with that length, 0 leaves the axis open; NULL
+ *              = not periodic.  Periodic boundary conditions (Sec. 3.6): the
+ *              caller provides a periodic mesh whose matching boundary
+ *              vertices are already merged, so each pair (or group) of
+ *              periodic images is one node, one pressure unknown, and the
+ *              elements reference the merged nodes.  Every element then
+ *              takes the minimum image of its edge vectors: along a periodic
+ *              axis each component of x_k - x_0 is shifted by a multiple of
+ *              the period into [-period/2, period/2].  This requires every
+ *              element's extent along a periodic axis to stay below half the
+ *              period (three or more cells across it).  Translations along
+ *              the coordinate axes only. */
 typedef struct {
     int32_t dim;
     int32_t reserved;
@@ -120,6 +133,7 @@ typedef struct {
     const int32_t *elems;
     const uint8_t *dirichlet;
     const int32_t *lattice;
+    const double *period;
 } pm_mesh;
 
 /* Build the device-resident operator of one mesh (Sec. 3.4 operator with
@@ -130,7 +144,8 @@ typedef struct {
  *   flags      PM_FP64, optionally | PM_FP32_INNER, optionally one PM_TILE_*
  *   out        receives the handle (NULL on failure)
  * Validation: dim in {2,3}, n_nodes in [1, 2^31-1), n_elems in
- * [1, 2^29), indices in range, finite coordinates, nonzero element volume.
+ * [1, 2^29), indices in range, finite coordinates, nonzero element volume
+ * (after the minimum image on periodic axes), each period finite and >= 0.
  * Errors: PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EHIP.  Synchronous. */
 int pressure_setup(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt,
                    int32_t flags, pm_handle **out);

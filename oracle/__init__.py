@@ -21,6 +21,10 @@ What each function follows in the paper:
   lumped_mass     m_i = integral of the P1 basis function of node i (sum of
                   |T|/(d+1) over its elements): the weights of the
                   constraint of the space V_0 (Sec. 3.4).
+  assemble_periodic  the operator of a periodic mesh whose matching
+                  boundary vertices are merged (Sec. 3.6): P^T A P with A
+                  assembled on the unmerged mesh and P the 0/1 merge matrix,
+                  then Dirichlet elimination.
   solve_v0        the weak problem posed in V_0 = {z : int z = 0}
                   (Sec. 3.4) when the operator is singular (no mass term,
                   no Dirichlet node): the bordered system
@@ -75,6 +79,8 @@ def lib():
     L.orc_csr_export.argtypes = [P, P, P, P]
     L.orc_csr_free.restype = None
     L.orc_csr_free.argtypes = [P]
+    L.orc_csr_from.restype = P
+    L.orc_csr_from.argtypes = [i64, P, P, P]
     L.orc_spmv.restype = None
     L.orc_spmv.argtypes = [P, P, P]
     L.orc_cg.restype = ctypes.c_int
@@ -146,6 +152,20 @@ class CSR:
         lib().orc_csr_export(self._h, _p(rp), _p(ci), _p(va))
         return rp, ci, va
 
+    @classmethod
+    def from_scipy(cls, S):
+        """A handle holding a copy of the SciPy matrix S (rows sorted)."""
+        S = S.tocsr()
+        S.sort_indices()
+        n = S.shape[0]
+        rp = np.ascontiguousarray(S.indptr, dtype=np.int64)
+        ci = _i32(S.indices)
+        va = _f64(S.data)
+        h = lib().orc_csr_from(n, _p(rp), _p(ci), _p(va))
+        if not h:
+            raise MemoryError("oracle CSR copy failed")
+        return cls(h, n)
+
     def to_scipy(self):
         import scipy.sparse as sp
         rp, ci, va = self.export()
@@ -171,8 +191,39 @@ def assemble(dim, coords, elems, coef, alpha, beta, dirichlet=None):
     return CSR(h, coords.shape[0])
 
 
+def merge_matrix(rep, n_merged):
+    """P with P[i, rep[i]] = 1: the merged P1 basis function of node j is
+    the sum of the unmerged basis functions of its images (Sec. 3.6,
+    periodic vertices merged), so merged nodal values v give the unmerged
+    ones P v."""
+    import scipy.sparse as sp
+    rep = np.asarray(rep, dtype=np.int64)
+    return sp.csr_matrix((np.ones(rep.shape[0]), (np.arange(rep.shape[0]), rep)), shape=(rep.shape[0], n_merged))
+
+
+def assemble_periodic(mesh, coef, alpha, beta):
+    """The operator of a periodic mesh with merged vertices (Sec. 3.6): the
+    Galerkin matrix of the merged P1 space, P^T A P, where A is the matrix
+    of the same weak problem (Sec. 3.4) on the unmerged mesh, whose images
+    carry their own coordinates; then the Dirichlet nodes of the merged mesh
+    are eliminated symmetrically as in ``assemble``."""
+    import scipy.sparse as sp
+    u = mesh.unmerged
+    full = assemble(u.dim, u.coords, u.elems, coef, alpha, beta, None).to_scipy()
+    P = merge_matrix(mesh.rep, mesh.n_nodes)
+    S = (P.T @ full @ P).tocsr()
+    d = np.asarray(mesh.dirichlet, dtype=bool)
+    if d.any():
+        keep = sp.diags((~d).astype(np.float64))
+        S = (keep @ S @ keep + sp.diags(d.astype(np.float64))).tocsr()
+    S.eliminate_zeros()
+    return CSR.from_scipy(S)
+
+
 def assemble_problem(prob):
     m = prob.mesh
+    if getattr(m, "period", None) is not None:
+        return assemble_periodic(m, prob.coef, prob.alpha, prob.beta)
     return assemble(m.dim, m.coords, m.elems, prob.coef, prob.alpha, prob.beta, m.dirichlet)
 
 
@@ -251,8 +302,21 @@ def mass_rhs(prob, f):
     source of the manufactured 2D problem)."""
     m = prob.mesh
     fi = np.where(m.dirichlet.astype(bool), 0.0, f)
-    y = apply_elements(m.dim, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, m.dirichlet, fi)
+    if getattr(m, "period", None) is not None:
+        y = assemble_periodic(m, np.ones(m.n_elems), 1.0, 0.0).matvec(fi)
+    else:
+        y = apply_elements(m.dim, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, m.dirichlet, fi)
     return np.where(m.dirichlet.astype(bool), f, y)
+
+
+def lumped_mass_mesh(mesh):
+    """lumped_mass of a mesh; for a periodic mesh the weights of the
+    unmerged mesh summed over the images of each merged node (P^T m)."""
+    if getattr(mesh, "period", None) is not None:
+        u = mesh.unmerged
+        mu = lumped_mass(u.dim, u.coords, u.elems)
+        return np.bincount(np.asarray(mesh.rep, dtype=np.int64), weights=mu, minlength=mesh.n_nodes)
+    return lumped_mass(mesh.dim, mesh.coords, mesh.elems)
 
 
 def lumped_mass(dim, coords, elems):

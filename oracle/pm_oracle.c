@@ -293,6 +293,27 @@ void orc_csr_export(const void *h, int64_t *rowptr, int32_t *col, double *val)
     memcpy(val, A->val, sizeof(double) * (size_t)A->rowptr[A->n]);
 }
 
+/* A CSR handle holding a copy of the given arrays (an operator formed
+ * outside this file, e.g. the merged operator of a periodic mesh). */
+void *orc_csr_from(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val)
+{
+    orc_csr *A = calloc(1, sizeof(orc_csr));
+    if (!A) return NULL;
+    const int64_t nnz = rowptr[n];
+    A->n = n;
+    A->rowptr = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    A->col = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    A->val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!A->rowptr || !A->col || !A->val) {
+        orc_csr_free(A);
+        return NULL;
+    }
+    memcpy(A->rowptr, rowptr, sizeof(int64_t) * (size_t)(n + 1));
+    memcpy(A->col, col, sizeof(int32_t) * (size_t)nnz);
+    memcpy(A->val, val, sizeof(double) * (size_t)nnz);
+    return A;
+}
+
 void orc_csr_free(void *h)
 {
     orc_csr *A = h;

@@ -23,7 +23,7 @@ _i32, _i64, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 class PmMesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64),
-                ("coords", _P), ("elems", _P), ("dirichlet", _P), ("lattice", _P)]
+                ("coords", _P), ("elems", _P), ("dirichlet", _P), ("lattice", _P), ("period", _P)]
 
 
 _PMESH = ctypes.POINTER(PmMesh)

@@ -34,23 +34,31 @@ inline uint64_t spread2(uint64_t v)
     return v;
 }
 
-// Signed Jacobian determinant: (X1-X0) x (X2-X0) in 2D,
-// (X1-X0) . ((X2-X0) x (X3-X0)) in 3D.
-inline double simplex_det(int dim, const double *c, const int32_t *v)
+// Component c of the edge vector p_k - p_0, shifted along a periodic axis
+// (L > 0, iL = 1/L) by the multiple of L that brings it into [-L/2, L/2].
+inline double edge(const double *pk, const double *p0, int c, const double *L, const double *iL)
+{
+    const double d = pk[c] - p0[c];
+    return L[c] > 0.0 ? std::fma(-L[c], std::nearbyint(d * iL[c]), d) : d;
+}
+
+// Signed Jacobian determinant of the (minimum-image) edge vectors:
+// e1 x e2 in 2D, e1 . (e2 x e3) in 3D.
+inline double simplex_det(int dim, const double *c, const int32_t *v, const double *L, const double *iL)
 {
     if (dim == 2) {
         const double *p0 = c + 2 * (int64_t)v[0], *p1 = c + 2 * (int64_t)v[1], *p2 = c + 2 * (int64_t)v[2];
-        double ax = p1[0] - p0[0], ay = p1[1] - p0[1];
-        double bx = p2[0] - p0[0], by = p2[1] - p0[1];
+        double ax = edge(p1, p0, 0, L, iL), ay = edge(p1, p0, 1, L, iL);
+        double bx = edge(p2, p0, 0, L, iL), by = edge(p2, p0, 1, L, iL);
         return ax * by - ay * bx;
     }
     const double *p0 = c + 3 * (int64_t)v[0], *p1 = c + 3 * (int64_t)v[1];
     const double *p2 = c + 3 * (int64_t)v[2], *p3 = c + 3 * (int64_t)v[3];
     double a[3], b[3], d[3];
     for (int k = 0; k < 3; ++k) {
-        a[k] = p1[k] - p0[k];
-        b[k] = p2[k] - p0[k];
-        d[k] = p3[k] - p0[k];
+        a[k] = edge(p1, p0, k, L, iL);
+        b[k] = edge(p2, p0, k, L, iL);
+        d[k] = edge(p3, p0, k, L, iL);
     }
     double cx = b[1] * d[2] - b[2] * d[1];
     double cy = b[2] * d[0] - b[0] * d[2];
@@ -70,6 +78,19 @@ int build_layout(const pm_mesh *m, Layout *L)
     const int nv = dim + 1;
     for (int64_t i = 0; i < N * dim; ++i)
         if (!std::isfinite(m->coords[i])) return PM_EINVAL;
+    double per[3] = {0.0, 0.0, 0.0}, iper[3] = {0.0, 0.0, 0.0};
+    L->periodic = false;
+    if (m->period)
+        for (int ax = 0; ax < dim; ++ax) {
+            const double p = m->period[ax];
+            if (!std::isfinite(p) || p < 0.0) return PM_EINVAL;
+            if (p > 0.0) {
+                per[ax] = p;
+                iper[ax] = 1.0 / p;
+                L->periodic = true;
+            }
+        }
+    for (int ax = 0; ax < 3; ++ax) L->period[ax] = per[ax];
 
     // 1. indices and orientation
     std::vector<int32_t> el(m->elems, m->elems + E * nv);
@@ -77,7 +98,7 @@ int build_layout(const pm_mesh *m, Layout *L)
         int32_t *v = el.data() + e * nv;
         for (int a = 0; a < nv; ++a)
             if (v[a] < 0 || v[a] >= N) return PM_EINVAL;
-        double det = simplex_det(dim, m->coords, v);
+        double det = simplex_det(dim, m->coords, v, per, iper);
         if (det == 0.0 || !std::isfinite(det)) return PM_EDEGENERATE;
         if (det < 0.0) std::swap(v[1], v[2]);
     }

@@ -20,6 +20,8 @@ struct Layout {
     std::vector<int32_t> n2e_ent;        // 4*e + a, ascending e
     std::vector<uint8_t> dirichlet;      // internal order
     std::vector<double> coords;          // internal order, SoA: coords[ax * n_nodes + i]
+    bool periodic = false;               // some period[ax] > 0
+    double period[3] = {0.0, 0.0, 0.0};  // 0 = open axis
 };
 
 // Validate, orient and renumber.  Returns a PM_* status.

@@ -117,16 +117,49 @@ __device__ inline double sum_partials(const double *part, int n, double *red)
 
 // ----------------------------------------------------------- element kernel
 
+template <class R>
+struct MeshT {
+    int N, E;
+    const int4 *conn;     // 4 vertex ids per element, bit 31 = Dirichlet vertex
+    const R *X, *Y, *Z;
+    const R *w;           // beta * c_e / (d! det_e), per element
+    const uint8_t *dir;   // Dirichlet flag per node
+    R mscale;             // alpha / (d! (d+1) (d+2))
+    R per[3], iper[3];    // period and 1/period per axis; 0 = open axis
+};
+using Mesh = MeshT<double>;
+
+// Edge vectors e[k-1] = x_k - x_0, k = 1..DIM, of one simplex.  With PER (a
+// periodic mesh, whose matching boundary vertices are merged) each component
+// takes its minimum image: the multiple of the period nearest to it is
+// subtracted, which brings it into [-per/2, per/2].  Open axes carry
+// per = iper = 0, for which the subtraction is an exact no-op; a wrapped
+// component d, |d| in [per/2, 2 per], loses exactly one period.
+template <int DIM, bool PER, class R>
+__device__ __forceinline__ void elem_edges(const R *X, const R *Y, const R *Z, const MeshT<R> &g, R e[3][3])
+{
+#pragma unroll
+    for (int k = 1; k <= DIM; ++k) {
+        e[k - 1][0] = X[k] - X[0];
+        e[k - 1][1] = Y[k] - Y[0];
+        e[k - 1][2] = (DIM == 3) ? Z[k] - Z[0] : R(0);
+        if (PER) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) e[k - 1][c] = fma(-g.per[c], rint(e[k - 1][c] * g.iper[c]), e[k - 1][c]);
+        }
+    }
+}
+
+
 // (alpha M_e + beta K_e) x_e for one simplex: out[a] for the local vertices.
 // xv are the nodal values (zero for Dirichlet vertices), w the element factor,
 // mscale = alpha / (d! (d+1) (d+2)).
 template <int DIM, class R>
-__device__ __forceinline__ void elem_contrib(const R *X, const R *Y, const R *Z, const R *xv, R w, R mscale,
-                                             R out[4])
+__device__ __forceinline__ void elem_contrib(const R e[3][3], const R *xv, R w, R mscale, R out[4])
 {
     if (DIM == 2) {
-        const R e1x = X[1] - X[0], e1y = Y[1] - Y[0];
-        const R e2x = X[2] - X[0], e2y = Y[2] - Y[0];
+        const R e1x = e[0][0], e1y = e[0][1];
+        const R e2x = e[1][0], e2y = e[1][1];
         const R det = e1x * e2y - e1y * e2x;
         const R n1x = e2y, n1y = -e2x, n2x = -e1y, n2y = e1x;
         const R d1 = xv[1] - xv[0], d2 = xv[2] - xv[0];
@@ -141,9 +174,9 @@ __device__ __forceinline__ void elem_contrib(const R *X, const R *Y, const R *Z,
         out[2] = fma(w, r2, fma(m, xv[2], mS));
         out[3] = R(0);
     } else {
-        const R e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
-        const R e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
-        const R e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+        const R e1x = e[0][0], e1y = e[0][1], e1z = e[0][2];
+        const R e2x = e[1][0], e2y = e[1][1], e2z = e[1][2];
+        const R e3x = e[2][0], e3y = e[2][1], e3z = e[2][2];
         const R n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
         const R n2x = e3y * e1z - e3z * e1y, n2y = e3z * e1x - e3x * e1z, n2z = e3x * e1y - e3y * e1x;
         const R n3x = e1y * e2z - e1z * e2y, n3y = e1z * e2x - e1x * e2z, n3z = e1x * e2y - e1y * e2x;
@@ -166,33 +199,23 @@ __device__ __forceinline__ void elem_contrib(const R *X, const R *Y, const R *Z,
 }
 
 template <int DIM, class R>
-__device__ __forceinline__ R elem_det(const R *X, const R *Y, const R *Z)
+__device__ __forceinline__ R elem_det(const R e[3][3])
 {
     if (DIM == 2) {
-        const R e1x = X[1] - X[0], e1y = Y[1] - Y[0];
-        const R e2x = X[2] - X[0], e2y = Y[2] - Y[0];
+        const R e1x = e[0][0], e1y = e[0][1];
+        const R e2x = e[1][0], e2y = e[1][1];
         return e1x * e2y - e1y * e2x;
     }
-    const R e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
-    const R e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
-    const R e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+    const R e1x = e[0][0], e1y = e[0][1], e1z = e[0][2];
+    const R e2x = e[1][0], e2y = e[1][1], e2z = e[1][2];
+    const R e3x = e[2][0], e3y = e[2][1], e3z = e[2][2];
     const R n1x = e2y * e3z - e2z * e3y, n1y = e2z * e3x - e2x * e3z, n1z = e2x * e3y - e2y * e3x;
     return e1x * n1x + e1y * n1y + e1z * n1z;
 }
 
-template <class R>
-struct MeshT {
-    int N, E;
-    const int4 *conn;     // 4 vertex ids per element, bit 31 = Dirichlet vertex
-    const R *X, *Y, *Z;
-    const R *w;           // beta * c_e / (d! det_e), per element
-    const uint8_t *dir;   // Dirichlet flag per node
-    R mscale;             // alpha / (d! (d+1) (d+2))
-};
-using Mesh = MeshT<double>;
 
 // w_e = beta * c_e / (d! det_e)
-template <int DIM, class R>
+template <int DIM, class R, bool PER>
 __global__ void __launch_bounds__(BLK) k_factors(MeshT<R> g, const double *__restrict__ coef, double beta,
                                                  R *__restrict__ w)
 {
@@ -206,8 +229,10 @@ __global__ void __launch_bounds__(BLK) k_factors(MeshT<R> g, const double *__res
         Y[a] = g.Y[v[a]];
         Z[a] = (DIM == 3) ? g.Z[v[a]] : R(0);
     }
+    R ed[3][3];
+    elem_edges<DIM, PER>(X, Y, Z, g, ed);
     const R fact = (DIM == 2) ? R(2) : R(6);
-    w[e] = R(beta * coef[e]) / (fact * elem_det<DIM, R>(X, Y, Z));
+    w[e] = R(beta * coef[e]) / (fact * elem_det<DIM, R>(ed));
 }
 
 // per-instance copy of the element factor, for the tiled apply
@@ -299,7 +324,7 @@ __device__ __forceinline__ int tile_at(int b, int k, int n_blocks, int n_tiles)
 // Nodes are visited in the tiled kernel's order (tile t by block t mod grid,
 // node t*T + j*BLK + lane), so the block partials of p.Ap, and hence whole
 // solves, agree bit for bit between the two kernels.
-template <int DIM, bool CG>
+template <int DIM, bool CG, bool PER>
 __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restrict__ off,
                                                     const int *__restrict__ ent, int T,
                                                     const double *__restrict__ x, double *__restrict__ y,
@@ -338,7 +363,9 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
                     xv[a] = (cv[a] < 0) ? 0.0 : val(v);
                 }
                 if (DIM == 2) xv[3] = 0.0;
-                elem_contrib<DIM, double>(X, Y, Z, xv, g.w[en >> 2], g.mscale, o);
+                double ed[3][3];
+                elem_edges<DIM, PER>(X, Y, Z, g, ed);
+                elem_contrib<DIM, double>(ed, xv, g.w[en >> 2], g.mscale, o);
                 const int a = en & 3;
                 yi += (a == 0) ? o[0] : (a == 1) ? o[1] : (a == 2) ? o[2] : o[3];
             }
@@ -426,7 +453,7 @@ constexpr size_t tile_lds_bytes(int dim, int lm, int max_deg)
 // own values stay in registers between the phases.
 // The body runs as virtual block vb of nvb (a real block of a single-mesh
 // launch, or one (mesh, slot) pair of a batched launch).
-template <int DIM, bool CG, class R, int T, int IPT, int LM, int NTH = BLK>
+template <int DIM, bool CG, class R, int T, int IPT, int LM, int NTH, bool PER>
 __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileArgsT<R> &ta,
                                                  const R *__restrict__ x, R *__restrict__ y, const IterT<R> &it,
                                                  R *smem, double *red, int vb, int nvb)
@@ -555,7 +582,9 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
                     xv[a] = sN[(NF - 1) * LM + lv];
                 }
                 if (DIM == 2) xv[3] = R(0);
-                elem_contrib<DIM, R>(X, Y, Z, xv, iw[k], g.mscale, o);
+                R ed[3][3];
+                elem_edges<DIM, PER>(X, Y, Z, g, ed);
+                elem_contrib<DIM, R>(ed, xv, iw[k], g.mscale, o);
 #pragma unroll
                 for (int a = 0; a <= DIM; ++a)
                     sS[int(u[a] >> G::LVB) * RS + int(u[a] & unsigned(T - 1))] = o[a];
@@ -615,15 +644,15 @@ constexpr int tile_waves()
     return (sizeof(R) == 8 && ((T == 128 && LM <= 448) || (T == 256 && LM <= 768))) ? 4 : 1;
 }
 
-template <int DIM, bool CG, class R, int T, int IPT, int LM, int NTH>
+template <int DIM, bool CG, class R, int T, int IPT, int LM, int NTH, bool PER>
 __global__ void __launch_bounds__(NTH, (tile_waves<R, T, LM>())) k_apply_tiled(MeshT<R> g, TileArgsT<R> ta,
                                                                              const R *__restrict__ x,
                                                                              R *__restrict__ y, IterT<R> it)
 {
     extern __shared__ double smem_d[];
     __shared__ double red[NTH / 64];
-    apply_tiled_body<DIM, CG, R, T, IPT, LM, NTH>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red,
-                                                  int(blockIdx.x), int(gridDim.x));
+    apply_tiled_body<DIM, CG, R, T, IPT, LM, NTH, PER>(g, ta, x, y, it, reinterpret_cast<R *>(smem_d), red,
+                                                       int(blockIdx.x), int(gridDim.x));
 }
 
 // ------------------------------------------------------------- CG vectors
@@ -795,7 +824,7 @@ __global__ void k_reopen(CGState *st)
 // sum_i m_i), and the solution is the one with sum_i m_i p_i = 0.
 
 // m_i = sum over node i's elements (ascending) of |T_e| / (d+1)
-template <int DIM>
+template <int DIM, bool PER>
 __global__ void __launch_bounds__(BLK) k_lumped_mass(Mesh g, const int *__restrict__ off,
                                                      const int *__restrict__ ent, double *__restrict__ mw)
 {
@@ -812,7 +841,9 @@ __global__ void __launch_bounds__(BLK) k_lumped_mass(Mesh g, const int *__restri
             Y[a] = g.Y[v[a]];
             Z[a] = (DIM == 3) ? g.Z[v[a]] : 0.0;
         }
-        sum += elem_det<DIM, double>(X, Y, Z) / fact;
+        double ed[3][3];
+        elem_edges<DIM, PER>(X, Y, Z, g, ed);
+        sum += elem_det<DIM, double>(ed) / fact;
     }
     mw[i] = sum;
 }
@@ -879,7 +910,7 @@ struct BatchCtl {
 // solve numbers its iterations from its first launch (k_first) and picks
 // its p and r.r buffers by the parity of that number, as a single-mesh
 // solve does; so a solve may start, or continue, at any launch.
-template <int C, class R>
+template <int C, class R, bool PER>
 __global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
                                                      const int2 *__restrict__ slots, BatchCtl *ctl)
 {
@@ -907,9 +938,11 @@ __global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CL
     static_assert(tc.t == 128, "batched meshes use 128-node tiles");
     R *smem = reinterpret_cast<R *>(smem_d);
     if (M.dim == 3)
-        apply_tiled_body<3, true, R, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y, M.n_ab);
+        apply_tiled_body<3, true, R, 128, tc.ipt, tc.lm, BLK, PER>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y,
+                                                                  M.n_ab);
     else
-        apply_tiled_body<2, true, R, 128, tc.ipt, tc.lm>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y, M.n_ab);
+        apply_tiled_body<2, true, R, 128, tc.ipt, tc.lm, BLK, PER>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y,
+                                                                  M.n_ab);
 }
 
 template <class R>
@@ -1069,6 +1102,9 @@ struct pm_handle {
     } mx;
     // CG vectors (device, internal order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
+    // periodic mesh (merged images): period per axis, 0 = open
+    bool periodic = false;
+    double period[3] = {0.0, 0.0, 0.0};
     // alpha = 0 and no Dirichlet node: the solve is posed in V_0
     bool singular = false;
     double *mw = nullptr;       // m_i = int phi_i
@@ -1149,6 +1185,10 @@ MeshT<double> make_mesh<double>(const pm_handle *h)
     g.dir = h->dir;
     const double denom = (h->dim == 2) ? 24.0 : 120.0;   // d! (d+1) (d+2)
     g.mscale = h->alpha / denom;
+    for (int ax = 0; ax < 3; ++ax) {
+        g.per[ax] = h->period[ax];
+        g.iper[ax] = h->period[ax] > 0.0 ? 1.0 / h->period[ax] : 0.0;
+    }
     return g;
 }
 
@@ -1166,6 +1206,10 @@ MeshT<float> make_mesh<float>(const pm_handle *h)
     g.dir = h->dir;
     const double denom = (h->dim == 2) ? 24.0 : 120.0;
     g.mscale = float(h->alpha / denom);
+    for (int ax = 0; ax < 3; ++ax) {
+        g.per[ax] = float(h->period[ax]);
+        g.iper[ax] = h->period[ax] > 0.0 ? float(1.0 / h->period[ax]) : 0.0f;
+    }
     return g;
 }
 
@@ -1199,10 +1243,15 @@ int compute_factors_t(pm_handle *h, R *w, R *inst_w)
 {
     MeshT<R> g = make_mesh<R>(h);
     const double beta = h->dt * h->dt;
-    if (h->dim == 2)
-        hipLaunchKernelGGL((k_factors<2, R>), dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, w);
+    const dim3 grid(grid_of(h->E));
+    if (h->dim == 2 && h->periodic)
+        hipLaunchKernelGGL((k_factors<2, R, true>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
+    else if (h->dim == 2)
+        hipLaunchKernelGGL((k_factors<2, R, false>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
+    else if (h->periodic)
+        hipLaunchKernelGGL((k_factors<3, R, true>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
     else
-        hipLaunchKernelGGL((k_factors<3, R>), dim3(grid_of(h->E)), dim3(BLK), 0, 0, g, h->coef, beta, w);
+        hipLaunchKernelGGL((k_factors<3, R, false>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
     HIPCK(hipGetLastError());
     if (h->n_inst > 0) {
         hipLaunchKernelGGL(k_inst_factors<R>, dim3(grid_of(h->n_inst)), dim3(BLK), 0, 0, int(h->n_inst),
@@ -1265,7 +1314,11 @@ int launch_tiled_c(pm_handle *h, const R *x, R *y, const IterT<R> &it, hipStream
     constexpr TileClass tc = TILE_CLASSES[C];
     MeshT<R> g = make_mesh<R>(h);
     TileArgsT<R> ta = make_tiles<R>(h);
-    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.t, tc.ipt, tc.lm, tc.nth>, tc.nth, g, ta, x, y, it, s);
+    if (h->periodic)
+        return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.t, tc.ipt, tc.lm, tc.nth, true>, tc.nth, g, ta, x,
+                                 y, it, s);
+    return launch_tiled_k<R>(h, k_apply_tiled<DIM, CG, R, tc.t, tc.ipt, tc.lm, tc.nth, false>, tc.nth, g, ta, x, y,
+                             it, s);
 }
 
 // f.template operator()<C>() for the handle's class C
@@ -1303,7 +1356,8 @@ int occupancy_t(pm_handle *h, int *per_cu)
 {
     return with_class(h->tile_class, [&]<int C>() {
         constexpr TileClass tc = TILE_CLASSES[C];
-        const void *kern = (const void *)k_apply_tiled<DIM, true, R, tc.t, tc.ipt, tc.lm, tc.nth>;
+        const void *kern = h->periodic ? (const void *)k_apply_tiled<DIM, true, R, tc.t, tc.ipt, tc.lm, tc.nth, true>
+                                       : (const void *)k_apply_tiled<DIM, true, R, tc.t, tc.ipt, tc.lm, tc.nth, false>;
         const size_t lds = tiled_lds_bytes<R>(h);
         if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
         HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, tc.nth, lds));
@@ -1330,8 +1384,12 @@ template <int DIM, bool CG>
 int launch_node_t(pm_handle *h, const double *x, double *y, const Iter &it, hipStream_t s)
 {
     Mesh g = make_mesh<double>(h);
-    hipLaunchKernelGGL((k_apply_node<DIM, CG>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off, h->n2e_ent,
-                       h->tile_nodes, x, y, it);
+    if (h->periodic)
+        hipLaunchKernelGGL((k_apply_node<DIM, CG, true>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off,
+                           h->n2e_ent, h->tile_nodes, x, y, it);
+    else
+        hipLaunchKernelGGL((k_apply_node<DIM, CG, false>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off,
+                           h->n2e_ent, h->tile_nodes, x, y, it);
     HIPCK(hipGetLastError());
     return PM_OK;
 }
@@ -1536,10 +1594,15 @@ static int update_v0(pm_handle *h)
     const int64_t N = h->N;
     TRY(dalloc(h, &h->mw, N));
     Mesh g = make_mesh<double>(h);
-    if (h->dim == 2)
-        hipLaunchKernelGGL(k_lumped_mass<2>, dim3(grid_of(N)), dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+    const dim3 grid(grid_of(N));
+    if (h->dim == 2 && h->periodic)
+        hipLaunchKernelGGL((k_lumped_mass<2, true>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+    else if (h->dim == 2)
+        hipLaunchKernelGGL((k_lumped_mass<2, false>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+    else if (h->periodic)
+        hipLaunchKernelGGL((k_lumped_mass<3, true>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
     else
-        hipLaunchKernelGGL(k_lumped_mass<3>, dim3(grid_of(N)), dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+        hipLaunchKernelGGL((k_lumped_mass<3, false>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
     HIPCK(hipGetLastError());
     std::vector<double> mw(N);
     HIPCK(hipMemcpy(mw.data(), h->mw, 8 * N, hipMemcpyDeviceToHost));
@@ -1580,6 +1643,8 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     h->N = L.n_nodes;
     h->E = L.n_elems;
     h->n_free = L.n_free;
+    h->periodic = L.periodic;
+    for (int ax = 0; ax < 3; ++ax) h->period[ax] = L.period[ax];
     h->alpha = mass_coef;
     h->dt = dt;
     h->flags = flags;
@@ -2041,6 +2106,7 @@ struct pm_batch {
     std::vector<pm_handle *> hs;
     int device = 0;
     bool mixed = false;            // FP32 inner solves with FP64 corrections
+    bool periodic = false;         // some mesh is periodic: the apply takes minimum images
     double inner_rtol = 1e-2;
     int tiles_per_slot = 4, nodes_per_lane = 8;
     void *d_meshes = nullptr;      // BatchMeshT<double> or BatchMeshT<float>
@@ -2071,25 +2137,38 @@ static_assert(TILE_CLASSES[N_BATCH_CLASSES - 1].t == 128 && TILE_CLASSES[N_BATCH
                   TILE_CLASSES[N_BATCH_CLASSES - 1].nth == BLK,
               "batch classes are the 128-node classes");
 
-template <class R>
+// A batch with a periodic mesh runs the minimum-image kernels for all its
+// meshes (exact no-ops on the open axes, so the other meshes get the same
+// bits as alone).
+template <class R, bool PER>
 const void *batch_apply_kernel(int c)
 {
     switch (c) {
-    case 0: return (const void *)k_batch_apply<0, R>;
-    case 1: return (const void *)k_batch_apply<1, R>;
-    case 2: return (const void *)k_batch_apply<2, R>;
-    case 3: return (const void *)k_batch_apply<3, R>;
-    case 4: return (const void *)k_batch_apply<4, R>;
-    case 5: return (const void *)k_batch_apply<5, R>;
+    case 0: return (const void *)k_batch_apply<0, R, PER>;
+    case 1: return (const void *)k_batch_apply<1, R, PER>;
+    case 2: return (const void *)k_batch_apply<2, R, PER>;
+    case 3: return (const void *)k_batch_apply<3, R, PER>;
+    case 4: return (const void *)k_batch_apply<4, R, PER>;
+    case 5: return (const void *)k_batch_apply<5, R, PER>;
     default: return nullptr;
     }
+}
+
+template <class R>
+const void *batch_apply_kernel(const pm_batch *b)
+{
+    return b->periodic ? batch_apply_kernel<R, true>(b->bclass) : batch_apply_kernel<R, false>(b->bclass);
 }
 
 template <int C, class R>
 void launch_batch_apply_c(pm_batch *b, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch_apply<C, R>), dim3(b->n_aslots), dim3(BLK), b->lds, s,
-                       (const BatchMeshT<R> *)b->d_meshes, b->d_aslots, b->d_ctl);
+    if (b->periodic)
+        hipLaunchKernelGGL((k_batch_apply<C, R, true>), dim3(b->n_aslots), dim3(BLK), b->lds, s,
+                           (const BatchMeshT<R> *)b->d_meshes, b->d_aslots, b->d_ctl);
+    else
+        hipLaunchKernelGGL((k_batch_apply<C, R, false>), dim3(b->n_aslots), dim3(BLK), b->lds, s,
+                           (const BatchMeshT<R> *)b->d_meshes, b->d_aslots, b->d_ctl);
 }
 
 template <class R>
@@ -2219,6 +2298,7 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
         if (b->mixed && !h->coords32) return PM_EINVAL;   // handle built without PM_FP32_INNER
         max_inst = std::max(max_inst, h->max_inst);
         max_local = std::max(max_local, h->max_local);
+        b->periodic = b->periodic || h->periodic;
         // the batch's grids become the handle's
         h->n_ablocks = std::max(1, std::min(AGRID_MAX, (h->n_tiles + b->tiles_per_slot - 1) / b->tiles_per_slot));
         h->n_ablocks32 = h->n_ablocks;
@@ -2240,7 +2320,7 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
                                            : tiled_lds_bytes<double>(h->dim, b->bclass, h->max_deg));
     if (b->lds > b->hs[0]->lds_limit) return PM_EINVAL;
     if (b->lds > 65536) {
-        const void *k = b->mixed ? batch_apply_kernel<float>(b->bclass) : batch_apply_kernel<double>(b->bclass);
+        const void *k = b->mixed ? batch_apply_kernel<float>(b) : batch_apply_kernel<double>(b);
         HIPCK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds)));
     }
     b->n_aslots = int(aslots.size());

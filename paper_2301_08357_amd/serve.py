@@ -82,7 +82,8 @@ class PressureServer:
         self.mixed = bool(mixed)
         self.inner_rtol = inner_rtol
         self.flags = _lib.PM_FP64 | (_lib.PM_FP32_INNER if self.mixed else 0)
-        self.cost = [footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems, self.flags) + 8 * p.mesh.n_nodes
+        self.cost = [footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems, self.flags,
+                               getattr(p.mesh, "period", None)) + 8 * p.mesh.n_nodes
                      for p in problems]
         self.resident = collections.OrderedDict()     # mesh -> PressureSystem, least recent first
         self.last = {}                                # mesh -> last solution (device)

@@ -26,11 +26,12 @@ def _ptr(a):
 class _MeshArgs:
     """Keeps the host arrays alive while the C call reads them."""
 
-    def __init__(self, dim, coords, elems, dirichlet=None, lattice=None):
+    def __init__(self, dim, coords, elems, dirichlet=None, lattice=None, period=None):
         self.coords = _np(coords, np.float64)
         self.elems = _np(elems, np.int32)
         self.dirichlet = None if dirichlet is None else _np(dirichlet, np.uint8)
         self.lattice = None if lattice is None else _np(lattice, np.int32)
+        self.period = None if period is None else _np(period, np.float64)
         n = self.coords.shape[0]
         if self.coords.shape != (n, dim) or self.elems.ndim != 2 or self.elems.shape[1] != dim + 1:
             raise ValueError("coords must be [n, dim] and elems [m, dim+1]")
@@ -38,16 +39,18 @@ class _MeshArgs:
             raise ValueError("dirichlet must have one entry per node")
         if self.lattice is not None and self.lattice.shape != (n, dim):
             raise ValueError("lattice must be [n, dim]")
+        if self.period is not None and self.period.shape != (dim,):
+            raise ValueError("period must have dim entries")
         self.struct = PmMesh(dim, 0, n, self.elems.shape[0], _ptr(self.coords), _ptr(self.elems),
-                             _ptr(self.dirichlet), _ptr(self.lattice))
+                             _ptr(self.dirichlet), _ptr(self.lattice), _ptr(self.period))
 
     def ref(self):
         return ctypes.byref(self.struct)
 
 
-def layout(dim, coords, elems, lattice=None):
+def layout(dim, coords, elems, lattice=None, period=None):
     """The integer layout the library builds (host only, no GPU)."""
-    m = _MeshArgs(dim, coords, elems, None, lattice)
+    m = _MeshArgs(dim, coords, elems, None, lattice, period)
     n, e = m.coords.shape[0], m.elems.shape[0]
     out = {
         "node_new2old": np.zeros(n, dtype=np.int32),
@@ -61,8 +64,8 @@ def layout(dim, coords, elems, lattice=None):
     return st, out
 
 
-def footprint(dim, coords, elems, flags=_lib.PM_FP64):
-    m = _MeshArgs(dim, coords, elems)
+def footprint(dim, coords, elems, flags=_lib.PM_FP64, period=None):
+    m = _MeshArgs(dim, coords, elems, period=period)
     b = ctypes.c_uint64(0)
     check(load().pressure_footprint(m.ref(), flags, ctypes.byref(b)), "pressure_footprint")
     return b.value
@@ -100,8 +103,8 @@ class PressureSystem:
     include/pressure_cg.h for the exact definition)."""
 
     def __init__(self, dim, coords, elems, coef, mass_coef, dt=1.0, dirichlet=None, lattice=None,
-                 flags=_lib.PM_FP64):
-        m = _MeshArgs(dim, coords, elems, dirichlet, lattice)
+                 flags=_lib.PM_FP64, period=None):
+        m = _MeshArgs(dim, coords, elems, dirichlet, lattice, period)
         c = _np(coef, np.float64)
         if c.shape != (m.elems.shape[0],):
             raise ValueError("coef must have one entry per element")
@@ -117,7 +120,7 @@ class PressureSystem:
     def from_problem(cls, prob, flags=_lib.PM_FP64):
         m = prob.mesh
         return cls(m.dim, m.coords, m.elems, prob.coef, prob.alpha, float(np.sqrt(prob.beta)),
-                   m.dirichlet, m.lattice, flags)
+                   m.dirichlet, m.lattice, flags, getattr(m, "period", None))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

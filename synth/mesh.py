@@ -42,6 +42,9 @@ class Mesh:
     elems: np.ndarray         # int32  [n_elems, dim+1]
     dirichlet: np.ndarray     # uint8  [n_nodes]
     lattice: np.ndarray       # int32  [n_nodes, dim]
+    period: object = None     # float64 [dim] (0 = open axis) for a periodic mesh, else None
+    unmerged: object = None   # periodic mesh: the same mesh before its images were merged
+    rep: object = None        # periodic mesh: merged node of each unmerged node
 
     @property
     def n_nodes(self):
@@ -153,3 +156,67 @@ def fan_mesh(k=80):
     dirichlet = np.zeros(coords.shape[0], dtype=np.uint8)
     dirichlet[1 + k:] = 1
     return Mesh(2, 0, coords, elems, dirichlet, None)
+
+
+def periodic_mesh(dim, n, periodic_axes, jitter=0.0, seed=0):
+    """The unit square/cube with n cells per axis, periodic along
+    ``periodic_axes`` (Sec. 3.6: the mesh is periodic and the matching
+    boundary vertices are merged, so there are fewer pressure unknowns).
+
+    Merged nodes have lattice indices i_ax in [0, n) on a periodic axis and
+    [0, n] on an open one, numbered i0 + m0 (i1 + m1 i2) with m_ax the count
+    per axis.  Node coordinates are (i + jitter (2u - 1)) / n with
+    u = uniform(seed, 1, 3 id + axis); nodes on an open boundary stay on the
+    lattice, every other node (also those on a periodic boundary, which may
+    then leave [0, 1)) is jittered.  Elements are those of
+    structured_mesh(dim, n) with each vertex replaced by its merged node.
+    The nodes on the open boundaries are Dirichlet nodes.
+
+    The returned mesh carries ``period`` (1 on the periodic axes, 0 on the
+    open ones), ``unmerged`` (the structured mesh of (n+1)^dim nodes in which
+    every image has its own coordinates: those of its merged node plus one
+    period per wrapped axis) and ``rep`` (the merged node of each unmerged
+    node)."""
+    axes = sorted(set(int(a) for a in periodic_axes))
+    if dim not in (2, 3) or not axes or any(a < 0 or a >= dim for a in axes):
+        raise ValueError("bad dim or periodic axes")
+    if n < 3:
+        raise ValueError("a periodic axis needs at least 3 cells")
+    per = np.zeros(dim)
+    per[axes] = 1.0
+    cnt = [n if per[ax] > 0 else n + 1 for ax in range(dim)]
+    nm = int(np.prod(cnt))
+    ids = np.arange(nm, dtype=np.int64)
+    lat = np.empty((nm, dim), dtype=np.int32)
+    rem = ids
+    for ax in range(dim):
+        lat[:, ax] = rem % cnt[ax]
+        rem = rem // cnt[ax]
+    on_open = np.zeros(nm, dtype=bool)
+    for ax in range(dim):
+        if per[ax] == 0:
+            on_open |= (lat[:, ax] == 0) | (lat[:, ax] == n)
+    coords = lat.astype(np.float64)
+    if jitter != 0.0:
+        moved = np.nonzero(~on_open)[0].astype(np.uint64)
+        for ax in range(dim):
+            u = uniform(seed, STREAM_JITTER, np.uint64(3) * moved + np.uint64(ax))
+            coords[moved.astype(np.int64), ax] = lat[moved.astype(np.int64), ax] + jitter * (2.0 * u - 1.0)
+    coords = coords / float(n)
+    # unmerged lattice and the merge map
+    ulat = _lattice(dim, n)
+    rep = np.zeros(ulat.shape[0], dtype=np.int64)
+    stride = 1
+    for ax in range(dim):
+        q = ulat[:, ax] % n if per[ax] > 0 else ulat[:, ax]
+        rep += stride * q
+        stride *= cnt[ax]
+    ucoords = coords[rep] + (ulat // n) * per[None, :]
+    uel = _elements_2d(n) if dim == 2 else _elements_3d(n)
+    udir = np.zeros(ulat.shape[0], dtype=np.uint8)
+    udir[:] = on_open[rep]
+    unmerged = Mesh(dim=dim, n=n, coords=np.ascontiguousarray(ucoords), elems=uel, dirichlet=udir, lattice=ulat)
+    elems = rep[uel].astype(np.int32)
+    return Mesh(dim=dim, n=n, coords=np.ascontiguousarray(coords), elems=elems,
+                dirichlet=on_open.astype(np.uint8), lattice=lat, period=per, unmerged=unmerged,
+                rep=rep.astype(np.int32))

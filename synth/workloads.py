@@ -15,7 +15,14 @@
   serve10k   10,000 requests over the batch256 meshes, exponential
              inter-arrival times, uniform mesh choice, 1 % right-hand-side
              perturbation per request.
-All meshes carry Dirichlet pressure nodes on the whole boundary.
+  periodic   meshes periodic along some axes with merged images (Sec. 3.6):
+             the fully periodic square (sin 2 pi x sin 2 pi y, w = 1e-2),
+             the channel periodic in x with Dirichlet walls in y
+             (sin 2 pi x sin pi y), the fully periodic cube (lognormal rho),
+             its alpha = 0 form (solved in V_0), and cube160p, the 160^3
+             fully periodic cube of the cube160 recipe.
+The non-periodic meshes carry Dirichlet pressure nodes on the whole
+boundary, and the periodic ones on their open boundaries.
 """
 
 from dataclasses import dataclass, field
@@ -23,7 +30,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import fields
-from .mesh import structured_mesh
+from .mesh import periodic_mesh, structured_mesh
 from .rng import MASTER_SEED, STREAM_ARRIVAL, STREAM_BATCH, STREAM_CHOICE, uniform
 
 
@@ -121,3 +128,39 @@ def neumann_cube(n=10, seed=MASTER_SEED, jitter=0.2, rho="lognormal"):
     xs = np.prod(np.cos(np.pi * m.coords), axis=1)
     return Problem("neumann_cube_%d" % n, m, 1.0 / r, 0.0, 1.0, 1e-12, seed, extra={"xstar": xs})
 
+
+def _sin2pi(coords):
+    return np.prod(np.sin(2.0 * np.pi * coords), axis=1)
+
+
+def periodic_square(n=32, seed=MASTER_SEED, w=1e-2, jitter=0.2):
+    """Fully periodic unit square, c = 1, alpha = w: the source of
+    p = sin(2 pi x) sin(2 pi y) for w p - Laplace p = f is f = (w + 8 pi^2) p.
+    rtol 1e-12."""
+    m = periodic_mesh(2, n, (0, 1), jitter=jitter, seed=seed)
+    p = _sin2pi(m.coords)
+    return Problem("periodic_square_%d" % n, m, np.ones(m.n_elems), w, 1.0, 1e-12, seed,
+                   extra={"source": (w + 8.0 * np.pi ** 2) * p, "exact": p})
+
+
+def periodic_channel(n=24, seed=MASTER_SEED, w=1e-2, jitter=0.2):
+    """Unit square periodic in x, Dirichlet walls at y = 0 and y = 1, c = 1,
+    alpha = w: p = sin(2 pi x) sin(pi y), f = (w + 5 pi^2) p.  rtol 1e-12."""
+    m = periodic_mesh(2, n, (0,), jitter=jitter, seed=seed)
+    p = np.sin(2.0 * np.pi * m.coords[:, 0]) * np.sin(np.pi * m.coords[:, 1])
+    return Problem("periodic_channel_%d" % n, m, np.ones(m.n_elems), w, 1.0, 1e-12, seed,
+                   extra={"source": (w + 5.0 * np.pi ** 2) * p, "exact": p})
+
+
+def periodic_cube(n=12, seed=MASTER_SEED, w=1e-3, jitter=0.2, rho="lognormal", rtol=1e-10):
+    """Fully periodic unit cube, c = 1/rho, alpha = w (w = 0: the solve is
+    posed in V_0); b = A x* with x* = prod sin(2 pi x_i)."""
+    m = periodic_mesh(3, n, (0, 1, 2), jitter=jitter, seed=seed)
+    r = fields.rho_lognormal(seed, m.n_elems, 0.5) if rho == "lognormal" else fields.rho_uniform(seed, m.n_elems)
+    return Problem("periodic_cube_%d" % n, m, 1.0 / r, w, 1.0, rtol, seed, extra={"xstar": _sin2pi(m.coords)})
+
+
+def cube160p(seed=MASTER_SEED):
+    """The cube160 recipe (jitter 0.2 h, lognormal rho, w = 1e-4) on the fully
+    periodic 160^3 mesh: 4,096,000 merged nodes, 24,576,000 tetrahedra."""
+    return periodic_cube(160, seed, 1e-4, 0.2, "lognormal", 1e-10)

@@ -106,3 +106,37 @@ def test_layout_errors():
     c = m.coords.copy()
     c[3, 1] = np.nan
     assert pm.layout(3, c, m.elems)[0] == pm.PM_EINVAL
+
+
+@pytest.mark.parametrize("dim,n,axes", [(2, 7, (0, 1)), (2, 6, (1,)), (3, 5, (0, 1, 2)), (3, 4, (2,))])
+def test_periodic_layout_matches_oracle(dim, n, axes):
+    """Periodic meshes with merged images, every third element given with the
+    opposite orientation: the library decides each sign from the
+    minimum-image edge vectors; the oracle decides it on the unmerged mesh,
+    where the images have their own coordinates, and then merges."""
+    m = smesh.periodic_mesh(dim, n, axes, jitter=0.2, seed=8)
+    flip = np.arange(m.n_elems) % 3 == 1
+    el = m.elems.copy()
+    el[flip, 1], el[flip, 2] = m.elems[flip, 2], m.elems[flip, 1]
+    uel = m.unmerged.elems.copy()
+    uel[flip, 1], uel[flip, 2] = m.unmerged.elems[flip, 2], m.unmerged.elems[flip, 1]
+    for lat in (m.lattice, None):
+        st, lay = pm.layout(dim, m.coords, el, lat, m.period)
+        assert st == 0
+        ost, uo = oracle.orient(dim, m.unmerged.coords, uel)
+        assert ost == 0
+        ol = oracle.layout(dim, m.coords, m.rep[uo].astype(np.int32), lat)
+        for k in ("node_new2old", "elem_new2old", "elems_new", "n2e_off", "n2e_ent"):
+            assert np.array_equal(lay[k].ravel(), ol[k].ravel()), k
+
+
+def test_periodic_layout_errors():
+    m = smesh.periodic_mesh(2, 4, (0, 1), jitter=0.2, seed=8)
+    for bad in ([1.0, -1.0], [np.nan, 1.0], [np.inf, 0.0]):
+        assert pm.layout(2, m.coords, m.elems, m.lattice, bad)[0] == pm.PM_EINVAL
+    with pytest.raises(ValueError):
+        pm.layout(2, m.coords, m.elems, m.lattice, [1.0, 1.0, 1.0])
+    # an element whose two vertices are images of one node has no volume
+    bad = m.elems.copy()
+    bad[5, 2] = bad[5, 0]
+    assert pm.layout(2, m.coords, bad, m.lattice, m.period)[0] == pm.PM_EDEGENERATE

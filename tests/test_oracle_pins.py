@@ -406,3 +406,98 @@ def test_v0_solution_pins():
         errs.append(np.sqrt(e @ M.matvec(e)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 1.85) and np.all(rates < 2.15), rates
+
+
+# ---------------------------------------------------------------- periodic
+def test_periodic_merge_fourier_eigenpairs():
+    """Uniform fully periodic meshes (no jitter): the merged operator is
+    circulant, so cos(2 pi (k.i)/n) over the lattice is an exact eigenvector.
+    Closed-form symbols with theta = 2 pi k / n: the two-triangle stiffness
+    is the 5-point stencil, 4 sin^2(theta_x/2) + 4 sin^2(theta_y/2), and its
+    consistent mass h^2/12 (6 + 2 cos theta_x + 2 cos theta_y +
+    2 cos(theta_x + theta_y)) (neighbours +-x, +-y, +-(1,1)); the Kuhn
+    stiffness is h times the 7-point stencil.  A wrong merge or a missed
+    image breaks the circulant structure at the seam."""
+    n, alpha = 6, 0.7
+    m = smesh.periodic_mesh(2, n, (0, 1))
+    A = oracle.assemble_periodic(m, np.ones(m.n_elems), alpha, 1.0)
+    h = 1.0 / n
+    for k in ((1, 0), (1, 2), (3, 3), (2, 5)):
+        th = 2.0 * np.pi * np.array(k) / n
+        v = np.cos(m.lattice @ th)
+        lam = (4 * np.sin(th[0] / 2) ** 2 + 4 * np.sin(th[1] / 2) ** 2
+               + alpha * h * h / 12 * (6 + 2 * np.cos(th[0]) + 2 * np.cos(th[1]) + 2 * np.cos(th[0] + th[1])))
+        assert np.max(np.abs(A.matvec(v) - lam * v)) < 1e-13, k
+    n = 5
+    m = smesh.periodic_mesh(3, n, (0, 1, 2))
+    A = oracle.assemble_periodic(m, np.ones(m.n_elems), 0.0, 1.0)
+    for k in ((1, 0, 0), (1, 2, 3), (4, 4, 1)):
+        th = 2.0 * np.pi * np.array(k) / n
+        v = np.cos(m.lattice @ th)
+        lam = (1.0 / n) * np.sum(4 * np.sin(th / 2) ** 2)
+        assert np.max(np.abs(A.matvec(v) - lam * v)) < 1e-13, k
+
+
+def test_periodic_merge_counts_and_invariants():
+    """Merging removes one node per image: n^d nodes when fully periodic,
+    n (n+1) for the 2D channel; the elements are unchanged.  The stiffness
+    part annihilates constants, the merged mass sums to |Omega| = 1 and the
+    merged lumped weights equal the mass row sums."""
+    for dim, n, axes, nodes in ((2, 5, (0, 1), 25), (2, 5, (0,), 30), (3, 4, (0, 1, 2), 64), (3, 4, (2,), 100)):
+        m = smesh.periodic_mesh(dim, n, axes, jitter=0.2, seed=3)
+        assert m.n_nodes == nodes and m.n_elems == (2 * n * n if dim == 2 else 6 * n ** 3)
+        c = 1.0 / fields.rho_uniform(3, m.n_elems)
+        K = oracle.assemble_periodic(m, c, 0.0, 1.0)
+        free = m.dirichlet == 0
+        one = free.astype(np.float64)
+        if not m.dirichlet.any():
+            assert np.max(np.abs(K.matvec(one))) < 1e-12
+        M = oracle.assemble_periodic(m, np.ones(m.n_elems), 1.0, 0.0)
+        if not m.dirichlet.any():
+            assert abs(M.to_scipy().sum() - 1.0) < 1e-13
+            mw = oracle.lumped_mass_mesh(m)
+            assert np.max(np.abs(M.matvec(np.ones(m.n_nodes)) - mw)) < 1e-15
+        S = K.to_scipy()
+        assert abs(S - S.T).max() < 1e-15
+
+
+def test_periodic_second_order_convergence():
+    """Fully periodic square (w p - Laplace p = f) and the channel periodic in
+    x with Dirichlet walls: second-order L2 convergence (from 16 cells per
+    axis, 8 per wavelength; w = 1, since with a small w the fully periodic
+    operator's constant mode, eigenvalue w, amplifies the O(h^4) discrete
+    mean of the jittered source into the error) to
+    sin(2 pi x) sin(2 pi y) and sin(2 pi x) sin(pi y) on jittered meshes."""
+    for make in (workloads.periodic_square, workloads.periodic_channel):
+        errs = []
+        for n in (16, 32, 64):
+            prob = make(n, w=1.0)
+            m = prob.mesh
+            A = oracle.assemble_problem(prob)
+            b = oracle.mass_rhs(prob, prob.extra["source"])
+            x = oracle.cg(A, b, rtol=1e-13, max_iter=20000, dirichlet=m.dirichlet)[0]
+            M = oracle.assemble_periodic(m, np.ones(m.n_elems), 1.0, 0.0)
+            e = x - prob.extra["exact"]
+            errs.append(np.sqrt(e @ M.matvec(e)))
+        rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all(rates > 1.8) and np.all(rates < 2.2), (make.__name__, rates)
+
+
+def test_periodic_v0_poisson():
+    """alpha = 0 on the fully periodic square: the V_0 solution of
+    -Laplace p = 8 pi^2 sin(2 pi x) sin(2 pi y) has zero mean and converges
+    at second order to sin(2 pi x) sin(2 pi y)."""
+    errs = []
+    for n in (12, 24, 48):
+        prob = workloads.periodic_square(n, w=0.0)
+        m = prob.mesh
+        A = oracle.assemble_problem(prob)
+        mw = oracle.lumped_mass_mesh(m)
+        b = oracle.mass_rhs(prob, prob.extra["source"])
+        p = oracle.solve_v0(A, b, mw)
+        assert abs(mw @ p) < 1e-14
+        M = oracle.assemble_periodic(m, np.ones(m.n_elems), 1.0, 0.0)
+        e = p - prob.extra["exact"]
+        errs.append(np.sqrt(e @ M.matvec(e)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8) and np.all(rates < 2.2), rates
