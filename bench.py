@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
     ap.add_argument("--serve-mixed", action="store_true", help="serving: mixed-precision solves")
+    ap.add_argument("--lumped", action="store_true", help="cube160/cube160p: lumped (diagonal) mass matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -198,6 +199,8 @@ def bench_cube160(args):
     from synth import workloads
     periodic = args.workload == "cube160p"
     prob = workloads.cube160p() if periodic else workloads.cube160()
+    if args.lumped:
+        prob = workloads.lumped(prob)
     tile_flag = {0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
     s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER | tile_flag)
     info = s.info()
@@ -226,8 +229,8 @@ def bench_cube160(args):
     else:
         what = "cube160: unit cube 160^3 x 6 tets (24,576,000 tets, 4,173,281 nodes)"
     _common(args, round(value, 4), "GDOF*iter/s", round(el / args.steps * 1e3, 3),
-            {"workload": what + ", jitter 0.2h, rho~lognormal(0,0.5), w=1e-4, FP64 CG to rtol %g; "
-                                "one step = one solve" % args.rtol,
+            {"workload": what + ", jitter 0.2h, rho~lognormal(0,0.5), w=1e-4, %s mass, FP64 CG to rtol %g; "
+                                "one step = one solve" % ("lumped" if args.lumped else "consistent", args.rtol),
              "n_free": info["n_free"], "iterations": its[0]},
             {"solves_per_s": round(args.steps / el, 3), "rel_error_vs_manufactured": err,
              "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -93,6 +93,15 @@ extern "C" {
 #define PM_TILE_256 0x10
 #define PM_TILE_512 0x20
 #define PM_TILE_128 0x30
+/* Lumped (diagonal) mass matrix instead of the consistent one: M_L =
+ * diag(m_i), m_i = int phi_i = sum over node i's elements of |T|/(d+1)
+ * (the row sums of the consistent mass).  The paper solves with the
+ * consistent mass (Sec. 3.4) and names mass lumping as what makes the
+ * general-EOS pressure system amenable to nested Newton methods (Sec. 3);
+ * with it the operator is P_I (alpha M_L + beta K_c) P_I + P_B (lumped first,
+ * then the Dirichlet rows eliminated).  Applies to every call of the handle,
+ * including the mixed, batched and V_0 solves. */
+#define PM_MASS_LUMPED 0x100
 
 /* Apply-kernel variants (pressure_set_variant). */
 #define PM_VARIANT_AUTO 0     /* tiled when the mesh has tiles, else node           */
@@ -141,7 +150,8 @@ typedef struct {
  *   elem_coef  host, n_elems doubles, each finite and > 0 (c_e = H_e)
  *   mass_coef  alpha >= 0 (1/(gamma-1) in the paper)
  *   dt         > 0; the stiffness scale is beta = dt*dt
- *   flags      PM_FP64, optionally | PM_FP32_INNER, optionally one PM_TILE_*
+ *   flags      PM_FP64, optionally | PM_FP32_INNER, optionally one PM_TILE_*,
+ *              optionally | PM_MASS_LUMPED; other bits give PM_EINVAL
  *   out        receives the handle (NULL on failure)
  * Validation: dim in {2,3}, n_nodes in [1, 2^31-1), n_elems in
  * [1, 2^29), indices in range, finite coordinates, nonzero element volume

@@ -25,6 +25,10 @@ What each function follows in the paper:
                   boundary vertices are merged (Sec. 3.6): P^T A P with A
                   assembled on the unmerged mesh and P the 0/1 merge matrix,
                   then Dirichlet elimination.
+  assemble_lumped the operator with the lumped (row-sum, diagonal) mass
+                  that the paper names for general equations of state
+                  (Sec. 3): alpha diag(m) + beta K_c, lumped before the
+                  Dirichlet elimination.
   solve_v0        the weak problem posed in V_0 = {z : int z = 0}
                   (Sec. 3.4) when the operator is singular (no mass term,
                   no Dirichlet node): the bordered system
@@ -201,27 +205,49 @@ def merge_matrix(rep, n_merged):
     return sp.csr_matrix((np.ones(rep.shape[0]), (np.arange(rep.shape[0]), rep)), shape=(rep.shape[0], n_merged))
 
 
-def assemble_periodic(mesh, coef, alpha, beta):
+def assemble_periodic(mesh, coef, alpha, beta, eliminate=True):
     """The operator of a periodic mesh with merged vertices (Sec. 3.6): the
     Galerkin matrix of the merged P1 space, P^T A P, where A is the matrix
     of the same weak problem (Sec. 3.4) on the unmerged mesh, whose images
     carry their own coordinates; then the Dirichlet nodes of the merged mesh
     are eliminated symmetrically as in ``assemble``."""
-    import scipy.sparse as sp
     u = mesh.unmerged
     full = assemble(u.dim, u.coords, u.elems, coef, alpha, beta, None).to_scipy()
     P = merge_matrix(mesh.rep, mesh.n_nodes)
     S = (P.T @ full @ P).tocsr()
-    d = np.asarray(mesh.dirichlet, dtype=bool)
+    return CSR.from_scipy(_eliminate(S, mesh.dirichlet if eliminate else None))
+
+
+def _eliminate(S, dirichlet):
+    """P_I S P_I + P_B for the 0/1 Dirichlet flags (SciPy)."""
+    import scipy.sparse as sp
+    d = np.zeros(S.shape[0], dtype=bool) if dirichlet is None else np.asarray(dirichlet, dtype=bool)
     if d.any():
         keep = sp.diags((~d).astype(np.float64))
-        S = (keep @ S @ keep + sp.diags(d.astype(np.float64))).tocsr()
+        S = keep @ S @ keep + sp.diags(d.astype(np.float64))
+    S = S.tocsr()
     S.eliminate_zeros()
-    return CSR.from_scipy(S)
+    return S
+
+
+def assemble_lumped(mesh, coef, alpha, beta):
+    """The operator with the lumped mass: alpha diag(m) + beta K_c, m the
+    lumped weights (row sums of the consistent mass, ``lumped_mass_mesh``),
+    K_c from ``assemble`` (or ``assemble_periodic``) with alpha = 0; the
+    Dirichlet nodes are eliminated after lumping."""
+    import scipy.sparse as sp
+    if getattr(mesh, "period", None) is not None:
+        K = assemble_periodic(mesh, coef, 0.0, beta, eliminate=False).to_scipy()
+    else:
+        K = assemble(mesh.dim, mesh.coords, mesh.elems, coef, 0.0, beta, None).to_scipy()
+    S = K + sp.diags(alpha * lumped_mass_mesh(mesh))
+    return CSR.from_scipy(_eliminate(S, mesh.dirichlet))
 
 
 def assemble_problem(prob):
     m = prob.mesh
+    if prob.extra.get("lumped"):
+        return assemble_lumped(m, prob.coef, prob.alpha, prob.beta)
     if getattr(m, "period", None) is not None:
         return assemble_periodic(m, prob.coef, prob.alpha, prob.beta)
     return assemble(m.dim, m.coords, m.elems, prob.coef, prob.alpha, prob.beta, m.dirichlet)

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libpressure.so")
 PM_OK, PM_NOT_CONVERGED, PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EBREAKDOWN, PM_EHIP = 0, 1, -1, -2, -3, -4, -5
 PM_FP64, PM_FP32_INNER = 1, 2
 PM_TILE_256, PM_TILE_512, PM_TILE_128 = 0x10, 0x20, 0x30
+PM_MASS_LUMPED = 0x100
 PM_VARIANT_AUTO, PM_VARIANT_NODE, PM_VARIANT_TILED = 0, 1, 2
 PM_MIXED_KEEP_DIRECTION, PM_MIXED_RESTART = 0, 1
 

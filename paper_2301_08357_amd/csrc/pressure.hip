@@ -124,7 +124,7 @@ struct MeshT {
     const R *X, *Y, *Z;
     const R *w;           // beta * c_e / (d! det_e), per element
     const uint8_t *dir;   // Dirichlet flag per node
-    R mscale;             // alpha / (d! (d+1) (d+2))
+    R mdiag, mfull;       // mass coefficients of x_a and of S = sum_b x_b, per unit det (elem_contrib)
     R per[3], iper[3];    // period and 1/period per axis; 0 = open axis
 };
 using Mesh = MeshT<double>;
@@ -152,10 +152,13 @@ __device__ __forceinline__ void elem_edges(const R *X, const R *Y, const R *Z, c
 
 
 // (alpha M_e + beta K_e) x_e for one simplex: out[a] for the local vertices.
-// xv are the nodal values (zero for Dirichlet vertices), w the element factor,
-// mscale = alpha / (d! (d+1) (d+2)).
+// xv are the nodal values (zero for Dirichlet vertices), w the element factor.
+// The mass part is det (mdiag x_a + mfull S), S = sum_b x_b: the consistent
+// mass has mdiag = mfull = alpha / (d! (d+1) (d+2)) (|T| (1 + delta_ab) /
+// ((d+1)(d+2))); the lumped mass (diagonal, |T| / (d+1) per vertex) has
+// mdiag = alpha / (d! (d+1)) and mfull = 0.
 template <int DIM, class R>
-__device__ __forceinline__ void elem_contrib(const R e[3][3], const R *xv, R w, R mscale, R out[4])
+__device__ __forceinline__ void elem_contrib(const R e[3][3], const R *xv, R w, R mdiag, R mfull, R out[4])
 {
     if (DIM == 2) {
         const R e1x = e[0][0], e1y = e[0][1];
@@ -168,7 +171,7 @@ __device__ __forceinline__ void elem_contrib(const R e[3][3], const R *xv, R w, 
         const R r2 = n2x * Gx + n2y * Gy;
         const R r0 = -(r1 + r2);
         const R S = xv[0] + xv[1] + xv[2];
-        const R m = mscale * det, mS = m * S;
+        const R m = mdiag * det, mS = (mfull * det) * S;
         out[0] = fma(w, r0, fma(m, xv[0], mS));
         out[1] = fma(w, r1, fma(m, xv[1], mS));
         out[2] = fma(w, r2, fma(m, xv[2], mS));
@@ -190,7 +193,7 @@ __device__ __forceinline__ void elem_contrib(const R e[3][3], const R *xv, R w, 
         const R r3 = n3x * Gx + n3y * Gy + n3z * Gz;
         const R r0 = -(r1 + r2 + r3);
         const R S = xv[0] + xv[1] + xv[2] + xv[3];
-        const R m = mscale * det, mS = m * S;
+        const R m = mdiag * det, mS = (mfull * det) * S;
         out[0] = fma(w, r0, fma(m, xv[0], mS));
         out[1] = fma(w, r1, fma(m, xv[1], mS));
         out[2] = fma(w, r2, fma(m, xv[2], mS));
@@ -365,7 +368,7 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
                 if (DIM == 2) xv[3] = 0.0;
                 double ed[3][3];
                 elem_edges<DIM, PER>(X, Y, Z, g, ed);
-                elem_contrib<DIM, double>(ed, xv, g.w[en >> 2], g.mscale, o);
+                elem_contrib<DIM, double>(ed, xv, g.w[en >> 2], g.mdiag, g.mfull, o);
                 const int a = en & 3;
                 yi += (a == 0) ? o[0] : (a == 1) ? o[1] : (a == 2) ? o[2] : o[3];
             }
@@ -584,7 +587,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
                 if (DIM == 2) xv[3] = R(0);
                 R ed[3][3];
                 elem_edges<DIM, PER>(X, Y, Z, g, ed);
-                elem_contrib<DIM, R>(ed, xv, iw[k], g.mscale, o);
+                elem_contrib<DIM, R>(ed, xv, iw[k], g.mdiag, g.mfull, o);
 #pragma unroll
                 for (int a = 0; a <= DIM; ++a)
                     sS[int(u[a] >> G::LVB) * RS + int(u[a] & unsigned(T - 1))] = o[a];
@@ -1102,6 +1105,7 @@ struct pm_handle {
     } mx;
     // CG vectors (device, internal order)
     double *b = nullptr, *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr;
+    bool lumped = false;        // PM_MASS_LUMPED: diagonal (row-sum) mass matrix
     // periodic mesh (merged images): period per axis, 0 = open
     bool periodic = false;
     double period[3] = {0.0, 0.0, 0.0};
@@ -1168,6 +1172,19 @@ int dupload(pm_handle *h, T **p, const std::vector<T> &v)
 
 inline unsigned grid_of(int64_t n) { return unsigned((n + BLK - 1) / BLK); }
 
+// Mass coefficients of elem_contrib: consistent, alpha / (d! (d+1) (d+2))
+// for both; lumped, alpha / (d! (d+1)) for x_a and 0 for S.
+void mass_coefs(const pm_handle *h, double *mdiag, double *mfull)
+{
+    const double dfact = (h->dim == 2) ? 2.0 : 6.0;
+    if (h->lumped) {
+        *mdiag = h->alpha / (dfact * (h->dim + 1));
+        *mfull = 0.0;
+    } else {
+        *mdiag = *mfull = h->alpha / (dfact * (h->dim + 1) * (h->dim + 2));
+    }
+}
+
 template <class R>
 MeshT<R> make_mesh(const pm_handle *h);
 
@@ -1183,8 +1200,7 @@ MeshT<double> make_mesh<double>(const pm_handle *h)
     g.Z = (h->dim == 3) ? h->coords + 2 * h->N : h->coords;
     g.w = h->w;
     g.dir = h->dir;
-    const double denom = (h->dim == 2) ? 24.0 : 120.0;   // d! (d+1) (d+2)
-    g.mscale = h->alpha / denom;
+    mass_coefs(h, &g.mdiag, &g.mfull);
     for (int ax = 0; ax < 3; ++ax) {
         g.per[ax] = h->period[ax];
         g.iper[ax] = h->period[ax] > 0.0 ? 1.0 / h->period[ax] : 0.0;
@@ -1204,8 +1220,10 @@ MeshT<float> make_mesh<float>(const pm_handle *h)
     g.Z = (h->dim == 3) ? h->coords32 + 2 * h->N : h->coords32;
     g.w = h->w32;
     g.dir = h->dir;
-    const double denom = (h->dim == 2) ? 24.0 : 120.0;
-    g.mscale = float(h->alpha / denom);
+    double md, mf;
+    mass_coefs(h, &md, &mf);
+    g.mdiag = float(md);
+    g.mfull = float(mf);
     for (int ax = 0; ax < 3; ++ax) {
         g.per[ax] = float(h->period[ax]);
         g.iper[ax] = h->period[ax] > 0.0 ? float(1.0 / h->period[ax]) : 0.0f;
@@ -1628,6 +1646,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
 {
     if (!elem_coef || !(mass_coef >= 0.0) || !std::isfinite(mass_coef) || !(dt > 0.0) || !std::isfinite(dt))
         return PM_EINVAL;
+    if (flags & ~(PM_FP64 | PM_FP32_INNER | PM_TILE_MASK | PM_MASS_LUMPED)) return PM_EINVAL;
     if (!mesh || !valid_coef(elem_coef, mesh->n_elems)) return PM_EINVAL;
     pm::Layout L;
     TRY(pm::build_layout(mesh, &L));
@@ -1648,6 +1667,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     h->alpha = mass_coef;
     h->dt = dt;
     h->flags = flags;
+    h->lumped = (flags & PM_MASS_LUMPED) != 0;
     const int64_t N = h->N, E = h->E;
     // vector kernels: about 4 nodes per lane (fewer blocks also means fewer
     // partials for the next kernel's prologue to sum)

@@ -119,6 +119,8 @@ class PressureSystem:
     @classmethod
     def from_problem(cls, prob, flags=_lib.PM_FP64):
         m = prob.mesh
+        if prob.extra.get("lumped"):
+            flags |= _lib.PM_MASS_LUMPED
         return cls(m.dim, m.coords, m.elems, prob.coef, prob.alpha, float(np.sqrt(prob.beta)),
                    m.dirichlet, m.lattice, flags, getattr(m, "period", None))
 

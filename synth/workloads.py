@@ -25,7 +25,7 @@ The non-periodic meshes carry Dirichlet pressure nodes on the whole
 boundary, and the periodic ones on their open boundaries.
 """
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -164,3 +164,9 @@ def cube160p(seed=MASTER_SEED):
     """The cube160 recipe (jitter 0.2 h, lognormal rho, w = 1e-4) on the fully
     periodic 160^3 mesh: 4,096,000 merged nodes, 24,576,000 tetrahedra."""
     return periodic_cube(160, seed, 1e-4, 0.2, "lognormal", 1e-10)
+
+
+def lumped(prob):
+    """The same problem with the lumped (diagonal, row-sum) mass matrix in
+    the operator; the right-hand side is unchanged."""
+    return replace(prob, name=prob.name + "_lumped", extra=dict(prob.extra, lumped=True))

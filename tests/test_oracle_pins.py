@@ -501,3 +501,54 @@ def test_periodic_v0_poisson():
         errs.append(np.sqrt(e @ M.matvec(e)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 1.8) and np.all(rates < 2.2), rates
+
+
+# ------------------------------------------------------------- lumped mass
+def test_lumped_operator_fourier_and_row_sums():
+    """The lumped operator alpha diag(m) + K: on uniform fully periodic
+    meshes every node carries m_i = h^d (six triangles of h^2/2 over 3 nodes;
+    24 Kuhn tetrahedra of h^3/6 over 4), so cos 2 pi (k.i)/n is an eigenvector
+    with eigenvalue (5-point or h times 7-point symbol) + alpha h^d; the
+    lumped matrix is diagonal with the consistent mass row sums."""
+    alpha = 0.9
+    for dim, n in ((2, 6), (3, 5)):
+        m = smesh.periodic_mesh(dim, n, tuple(range(dim)))
+        A = oracle.assemble_lumped(m, np.ones(m.n_elems), alpha, 1.0)
+        h = 1.0 / n
+        for k in ((1, 0, 2), (2, 3, 1), (3, 3, 3)):
+            th = 2.0 * np.pi * np.array(k[:dim]) / n
+            v = np.cos(m.lattice @ th)
+            lam = h ** (dim - 2) * np.sum(4 * np.sin(th / 2) ** 2) + alpha * h ** dim
+            assert np.max(np.abs(A.matvec(v) - lam * v)) < 1e-13, (dim, k)
+    m = smesh.structured_mesh(3, 4, jitter=0.2, seed=9)
+    ML = oracle.assemble_lumped(m, np.ones(m.n_elems), 1.0, 0.0).to_scipy()
+    M = oracle.assemble(3, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, m.dirichlet).to_scipy()
+    free = m.dirichlet == 0
+    assert abs(ML - __import__("scipy.sparse").sparse.diags(ML.diagonal())).max() == 0.0
+    full = oracle.assemble(3, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, None).to_scipy()
+    np.testing.assert_allclose(ML.diagonal()[free], np.asarray(full.sum(axis=1)).ravel()[free], rtol=1e-14)
+    assert np.all(ML.diagonal()[~free] == 1.0) and np.all(M.diagonal()[~free] == 1.0)
+
+
+def test_lumped_second_order_convergence():
+    """Mass lumping keeps P1 second order: w p - Laplace p = f on the
+    jittered square with Dirichlet boundary (w = 1) and on the periodic
+    square, to sin(pi x) sin(pi y) and sin(2 pi x) sin(2 pi y)."""
+    cases = ((lambda n: workloads.tgv2d(n, w=1.0), (16, 32, 64), "exact_tgv"),
+             (lambda n: workloads.periodic_square(n, w=1.0), (16, 32, 64), "exact"))
+    for make, ns, key in cases:
+        errs = []
+        for n in ns:
+            prob = workloads.lumped(make(n))
+            m = prob.mesh
+            A = oracle.assemble_problem(prob)
+            b = oracle.mass_rhs(prob, prob.extra["source"])
+            x = oracle.cg(A, b, rtol=1e-13, max_iter=20000, dirichlet=m.dirichlet)[0]
+            exact = (prob.extra["exact"] if key == "exact"
+                     else np.sin(np.pi * m.coords[:, 0]) * np.sin(np.pi * m.coords[:, 1]))
+            M = (oracle.assemble_periodic(m, np.ones(m.n_elems), 1.0, 0.0) if m.period is not None
+                 else oracle.assemble(2, m.coords, m.elems, np.ones(m.n_elems), 1.0, 0.0, None))
+            e = x - exact
+            errs.append(np.sqrt(e @ M.matvec(e)))
+        rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all(rates > 1.8) and np.all(rates < 2.2), (key, rates)
