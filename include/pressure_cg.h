@@ -370,6 +370,83 @@ int pressure_batch_tune(pm_handle *const *handles, int32_t n, int32_t iters, con
 int pressure_tune_tile(const pm_mesh *mesh, const double *elem_coef, double mass_coef, double dt, int32_t flags,
                        int32_t iters, const char *cache_path, int32_t *flags_out, double *ms_per_iter);
 
+/* ------------------------------------------------------------------------
+ * The projection stage around the solve (Sec. 3.3 pre-projection, Sec. 3.4
+ * projection with its Picard loop, and the momentum update of eq.
+ * momentum_dt_p).
+ *
+ * Dual mesh (Sec. 2, face-type dual cells): one dual cell C_f per face
+ * (3D) or edge (2D) f of the primal mesh, made of the sub-elements T_kf
+ * that join f to the barycenters of the one or two primal elements T_k that
+ * share it; |T_kf| = |T_k|/(d+1).  Dual cells are numbered by the sorted
+ * vertex tuples of their faces (caller node ids) in lexicographic order.
+ * With merged periodic vertices the two images of a seam face are one
+ * interior face, as Sec. 3.6 combines matching dual boundary cells.
+ */
+
+/* Number of dual cells and of boundary faces (faces of one element).
+ * Built on the host at the first call and kept by the handle. */
+int pressure_dual_count(pm_handle *h, int64_t *n_faces, int64_t *n_boundary);
+
+/* The dual cells: face_vertices (host, n_faces * dim: ascending caller node
+ * ids of face f) and face_elems (host, n_faces * 2: the caller element ids
+ * sharing f, ascending, -1 for none).  Either may be NULL. */
+int pressure_dual_faces(pm_handle *h, int32_t *face_vertices, int32_t *face_elems);
+
+/* One projection stage (all device arrays in caller numbering, FP64; node
+ * vectors n_nodes, element vectors n_elems, dual-cell vectors n_faces, and
+ * vector fields n_faces * dim, row-major per cell):
+ *   rho_dev    rho^{n+1} on the dual cells (from the transport stage), > 0
+ *   we_dev     the intermediate total energy density tilde W_E on the dual cells
+ *   wu_dev     the intermediate momentum double-tilde W_u on the dual cells
+ *   p_dev      P^n at the primal vertices, > 0
+ *   pb_dev     P^{n+1} prescribed at the Dirichlet vertices (read there only),
+ *              or NULL for P^{n+1}_B = P^n_B
+ *   bflux_dev  H W^{n+1} . eta (outward normal momentum times enthalpy) on
+ *              the boundary faces (read there only), or NULL for 0 (walls)
+ *   dp0_dev    initial guess of the first pressure correction (the paper
+ *              starts from the previous solution), or NULL for 0
+ *   gamma > 1, dt > 0, n_picard >= 1 (N_Pic; the paper suggests 2),
+ *   rtol, max_iter as pressure_solve, for every Picard iteration.
+ * Steps:
+ *  1. Pre-projection (Sec. 3.3): W_k = sum_f W_f |T_kf|/|T_k|, i.e. the mean
+ *     over the d+1 faces of T_k, for rho, tilde W_E and double-tilde W_u;
+ *     (rho K)_k = |W_u,k|^2 / (2 rho_k) with the first momentum guess
+ *     W_u^{n+1,1} = double-tilde W_u; H_f = gamma/(gamma-1) P_f / rho_f on
+ *     the dual cells, P_f the mean of the face's vertex pressures, and
+ *     H_k = the mean of H_f over the faces of T_k.
+ *  2. For k = 1 .. n_picard: the operator takes c_e = H_k, alpha =
+ *     1/(gamma-1), beta = dt^2 (the handle's mass matrix, consistent or
+ *     lumped); the right-hand side of the weak problem (Sec. 3.4) is, for a
+ *     free vertex i,
+ *       b_i = sum_{T_k ni i} [ (W_E,k - (rho K)_k) |T_k|/(d+1)
+ *                              + dt H_k W_u,k . grad(phi_i)|_k |T_k| ]
+ *             - alpha (M P^n)_i - (A g)_i
+ *             - dt sum_{boundary faces f ni i} bflux_f |f| / d,
+ *     g = P^{n+1}_B - P^n_B on the Dirichlet vertices (zero elsewhere, and
+ *     the lift A g uses the operator before elimination); b_i = g_i on a
+ *     Dirichlet vertex.  CG solves for dP (warm start: dp0, then the
+ *     previous Picard iterate); P^{n+1,k+1} = P^n + dP; the per-element
+ *     momentum W_u,k - dt grad(dP)|_k gives (rho K)_k, and P^{n+1,k+1}
+ *     gives H_f and H_k as in step 1.
+ *  3. Momentum update on the dual cells: W_u,f^{n+1} = double-tilde W_u,f
+ *     - dt grad(dP)_f, grad(dP)_f = sum_k |T_kf| grad(dP)|_k / |C_f| over
+ *     the elements of f.
+ * Outputs: p_out (n_nodes) P^{n+1}; wu_out (n_faces * dim) W_u^{n+1};
+ * h_out (n_elems, may be NULL) H^{n+1} per element; iters (host, n_picard
+ * entries, may be NULL) the CG iterations of each Picard iteration.
+ * The handle's operator is left with the coefficients of H^{n+1}.
+ * Returns PM_OK, or the first non-OK status of a CG solve (PM_NOT_CONVERGED,
+ * PM_EBREAKDOWN: a non-positive enthalpy makes the system indefinite),
+ * PM_EINVAL or PM_EHIP.  The first call allocates the handle's projection
+ * buffers (about 12 doubles per element and 4 per node); synchronises the
+ * stream before returning. */
+int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_dev, const double *wu_dev,
+                        const double *p_dev, const double *pb_dev, const double *bflux_dev,
+                        const double *dp0_dev, double gamma, double dt, int32_t n_picard, double rtol,
+                        int32_t max_iter, double *p_out, double *wu_out, double *h_out, int32_t *iters,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,10 @@ SIGNATURES = {
     "pressure_batch_tune": (ctypes.c_int, [_P, _i32, _i32, ctypes.c_char_p, _P, ctypes.POINTER(_dbl)]),
     "pressure_tune_tile": (ctypes.c_int, [_PMESH, _P, _dbl, _dbl, _i32, _i32, ctypes.c_char_p,
                                           ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]),
+    "pressure_dual_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "pressure_dual_faces": (ctypes.c_int, [_P, _P, _P]),
+    "pressure_projection": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _dbl, _dbl, _i32, _dbl, _i32,
+                                           _P, _P, _P, _P, _P]),
 }
 
 _lib = None

@@ -295,4 +295,63 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
     return PM_OK;
 }
 
+int build_faces(const pm_mesh *m, Faces *F)
+{
+    if (!m || !F || !m->elems) return PM_EINVAL;
+    const int dim = m->dim;
+    if (dim != 2 && dim != 3) return PM_EINVAL;
+    const int64_t N = m->n_nodes, E = m->n_elems;
+    const int nv = dim + 1;
+    if (N < 1 || E < 1 || E >= (int64_t(1) << 29)) return PM_EINVAL;
+    // one record per (element, local vertex): the sorted tuple of the other
+    // vertices, then the element, then the local vertex
+    struct Rec {
+        int32_t v[3];
+        int32_t e, a;
+    };
+    std::vector<Rec> rec(size_t(E) * nv);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *ev = m->elems + e * nv;
+        for (int a = 0; a < nv; ++a) {
+            Rec &r = rec[size_t(e) * nv + a];
+            int k = 0;
+            for (int b = 0; b < nv; ++b) {
+                if (b == a) continue;
+                if (ev[b] < 0 || ev[b] >= N) return PM_EINVAL;
+                r.v[k++] = ev[b];
+            }
+            if (dim == 2) r.v[2] = -1;
+            std::sort(r.v, r.v + dim);
+            r.e = int32_t(e);
+            r.a = a;
+        }
+    }
+    std::sort(rec.begin(), rec.end(), [](const Rec &x, const Rec &y) {
+        if (x.v[0] != y.v[0]) return x.v[0] < y.v[0];
+        if (x.v[1] != y.v[1]) return x.v[1] < y.v[1];
+        if (x.v[2] != y.v[2]) return x.v[2] < y.v[2];
+        return x.e != y.e ? x.e < y.e : x.a < y.a;
+    });
+    F->dim = dim;
+    F->vertices.clear();
+    F->elems.clear();
+    F->elem_face.assign(size_t(E) * nv, -1);
+    int64_t nb = 0;
+    for (size_t i = 0; i < rec.size();) {
+        size_t j = i + 1;
+        while (j < rec.size() && std::equal(rec[j].v, rec[j].v + dim, rec[i].v)) ++j;
+        if (j - i > 2) return PM_EINVAL;
+        const int32_t f = int32_t(F->vertices.size() / dim);
+        F->vertices.insert(F->vertices.end(), rec[i].v, rec[i].v + dim);
+        F->elems.push_back(rec[i].e);
+        F->elems.push_back(j - i == 2 ? rec[i + 1].e : -1);
+        nb += (j - i == 1);
+        for (size_t k = i; k < j; ++k) F->elem_face[size_t(rec[k].e) * nv + rec[k].a] = f;
+        i = j;
+    }
+    F->n_faces = int64_t(F->vertices.size() / dim);
+    F->n_boundary = nb;
+    return PM_OK;
+}
+
 }  // namespace pm

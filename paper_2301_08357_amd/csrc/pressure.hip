@@ -881,6 +881,272 @@ __global__ void __launch_bounds__(BLK) k_sub_mean(int N, double *__restrict__ v,
     }
 }
 
+// -------------------------------------------------------- projection stage
+// Sec. 3.3 - 3.5 around the solve.  Element data are in internal element
+// order, dual-cell (face) data in the caller's face numbering.
+
+struct ProjArgs {
+    const int *efc;       // 4 per element: face opposite internal-local vertex a
+    const int2 *fel;      // per face: internal elements (y = -1 on the boundary)
+    const double *rho_f, *we_f, *wu_f, *bflux;
+    double *erho, *ewe, *ewu, *erk, *evol, *egrad;   // per element (ewu, egrad: 3 each)
+    double g1;            // gamma / (gamma - 1)
+    double dt;
+};
+
+// Corner ids and (minimum-image) edge vectors of element k.
+template <int DIM, bool PER>
+__device__ __forceinline__ void elem_corners(const Mesh &g, int k, int v[4], double ed[3][3])
+{
+    const int4 c = g.conn[k];
+    v[0] = c.x & 0x7fffffff;
+    v[1] = c.y & 0x7fffffff;
+    v[2] = c.z & 0x7fffffff;
+    v[3] = c.w & 0x7fffffff;
+    double X[4], Y[4], Z[4];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        X[a] = g.X[v[a]];
+        Y[a] = g.Y[v[a]];
+        Z[a] = (DIM == 3) ? g.Z[v[a]] : 0.0;
+    }
+    elem_edges<DIM, PER>(X, Y, Z, g, ed);
+}
+
+// Adjugate normals n_a (grad phi_a = n_a / det; |n_a| = (d-1)! |face a|) and det.
+template <int DIM>
+__device__ __forceinline__ double elem_normals(const double ed[3][3], double n[4][3])
+{
+    if (DIM == 2) {
+        n[1][0] = ed[1][1];
+        n[1][1] = -ed[1][0];
+        n[2][0] = -ed[0][1];
+        n[2][1] = ed[0][0];
+        n[1][2] = n[2][2] = 0.0;
+    } else {
+        const double(*e)[3] = ed;
+        n[1][0] = e[1][1] * e[2][2] - e[1][2] * e[2][1];
+        n[1][1] = e[1][2] * e[2][0] - e[1][0] * e[2][2];
+        n[1][2] = e[1][0] * e[2][1] - e[1][1] * e[2][0];
+        n[2][0] = e[2][1] * e[0][2] - e[2][2] * e[0][1];
+        n[2][1] = e[2][2] * e[0][0] - e[2][0] * e[0][2];
+        n[2][2] = e[2][0] * e[0][1] - e[2][1] * e[0][0];
+        n[3][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];
+        n[3][1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+        n[3][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 1; a <= DIM; ++a) t += n[a][c];
+        n[0][c] = -t;
+    }
+    return ed[0][0] * n[1][0] + ed[0][1] * n[1][1] + ed[0][2] * n[1][2];
+}
+
+// H_k = mean over the faces f of T_k of g1 P_f / rho_f, with P_f the mean of
+// the face's vertex pressures pv (the face opposite vertex a has the others).
+template <int DIM>
+__device__ __forceinline__ double elem_enthalpy(const ProjArgs &pa, int k, const double pv[4])
+{
+    double h = 0.0;
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        double pf = 0.0;
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b)
+            if (b != a) pf += pv[b];
+        pf /= double(DIM);
+        h += pa.g1 * pf / pa.rho_f[pa.efc[4 * k + a]];
+    }
+    return h / double(DIM + 1);
+}
+
+// Pre-projection: element means of the dual-cell fields, (rho K)_k with
+// W_u^{n+1,1} = double-tilde W_u, element volume, and c_k = H_k from P^n.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_proj_init(Mesh g, ProjArgs pa, const double *__restrict__ pn,
+                                                   double *__restrict__ coef)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    int v[4];
+    double ed[3][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_det<DIM, double>(ed);
+    double rho = 0.0, we = 0.0, wu[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        const int f = pa.efc[4 * k + a];
+        rho += pa.rho_f[f];
+        we += pa.we_f[f];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) wu[c] += pa.wu_f[DIM * f + c];
+    }
+    constexpr double inv = 1.0 / double(DIM + 1);
+    rho *= inv;
+    we *= inv;
+    double ww = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        wu[c] *= inv;
+        ww += wu[c] * wu[c];
+        pa.ewu[3 * k + c] = wu[c];
+    }
+    double pv[4];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) pv[a] = pn[v[a]];
+    pa.erho[k] = rho;
+    pa.ewe[k] = we;
+    pa.erk[k] = ww / (2.0 * rho);
+    pa.evol[k] = det / ((DIM == 2) ? 2.0 : 6.0);
+    coef[k] = elem_enthalpy<DIM>(pa, k, pv);
+}
+
+// Right-hand side of the weak problem for one Picard iteration, node by
+// node over its elements in ascending order; written in caller order.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_proj_rhs(Mesh g, ProjArgs pa, const int *__restrict__ off,
+                                                  const int *__restrict__ ent, const double *__restrict__ coef,
+                                                  const double *__restrict__ pn, const double *__restrict__ gd,
+                                                  const int *__restrict__ new2old, double *__restrict__ b)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= g.N) return;
+    double bi = 0.0;
+    if (g.dir[i]) {
+        bi = gd[i];
+    } else {
+        constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+        for (int q = off[i]; q < off[i + 1]; ++q) {
+            const int en = ent[q], k = en >> 2, a = en & 3;
+            int v[4];
+            double ed[3][3], n[4][3];
+            elem_corners<DIM, PER>(g, k, v, ed);
+            const double det = elem_normals<DIM>(ed, n);
+            const double vol = det / dfact;
+            // sources: (W_E - rho K) |T|/(d+1) + dt H W_u . n_a / d!
+            double t = (pa.ewe[k] - pa.erk[k]) * (vol / double(DIM + 1));
+            double un = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) un += pa.ewu[3 * k + c] * n[a][c];
+            t += pa.dt * coef[k] * un / dfact;
+            // - alpha (M_e P^n)_a and - (A_e g)_a over the Dirichlet vertices
+            const int4 c4 = g.conn[k];
+            const int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+            double pv[4], gv[4], o[4];
+            double sp = 0.0;
+            bool lift = false;
+#pragma unroll
+            for (int b2 = 0; b2 <= DIM; ++b2) {
+                pv[b2] = pn[v[b2]];
+                sp += pv[b2];
+                gv[b2] = (cv[b2] < 0) ? gd[v[b2]] : 0.0;
+                lift = lift || (cv[b2] < 0);
+            }
+            if (DIM == 2) gv[3] = 0.0;
+            t -= det * (g.mdiag * pv[a] + g.mfull * sp);
+            if (lift) {
+                elem_contrib<DIM, double>(ed, gv, g.w[k], g.mdiag, g.mfull, o);
+                t -= o[a];
+            }
+            // boundary faces through vertex a: - dt bflux_f |f| / d
+            if (pa.bflux) {
+#pragma unroll
+                for (int b2 = 0; b2 <= DIM; ++b2) {
+                    if (b2 == a) continue;
+                    const int f = pa.efc[4 * k + b2];
+                    if (pa.fel[f].y >= 0) continue;
+                    const double nn = sqrt(n[b2][0] * n[b2][0] + n[b2][1] * n[b2][1] + n[b2][2] * n[b2][2]);
+                    const double area = (DIM == 2) ? nn : 0.5 * nn;
+                    t -= pa.dt * pa.bflux[f] * area / double(DIM);
+                }
+            }
+            bi += t;
+        }
+    }
+    b[new2old[i]] = bi;
+}
+
+// After a solve: grad(dP) per element, the element momentum W_u - dt grad
+// and its (rho K), and c_k = H_k from P^n + dP.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_proj_picard(Mesh g, ProjArgs pa, const double *__restrict__ pn,
+                                                     const double *__restrict__ dpi, double *__restrict__ coef)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    double d[4], pv[4];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        d[a] = dpi[v[a]];
+        pv[a] = pn[v[a]] + d[a];
+    }
+    double ww = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double gc = 0.0;
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) gc += d[a] * n[a][c];
+        gc /= det;
+        pa.egrad[3 * k + c] = gc;
+        const double wc = pa.ewu[3 * k + c] - pa.dt * gc;
+        ww += wc * wc;
+    }
+    pa.erk[k] = ww / (2.0 * pa.erho[k]);
+    coef[k] = elem_enthalpy<DIM>(pa, k, pv);
+}
+
+// Momentum update on the dual cells: W_u,f - dt (sum_k |T_k| grad_k) / (sum_k |T_k|).
+template <int DIM>
+__global__ void __launch_bounds__(BLK) k_proj_faces(int F, ProjArgs pa, double *__restrict__ wu_out)
+{
+    const int f = blockIdx.x * BLK + threadIdx.x;
+    if (f >= F) return;
+    const int2 ke = pa.fel[f];
+    double vs = pa.evol[ke.x], gs[3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) gs[c] = pa.evol[ke.x] * pa.egrad[3 * ke.x + c];
+    if (ke.y >= 0) {
+        vs += pa.evol[ke.y];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) gs[c] += pa.evol[ke.y] * pa.egrad[3 * ke.y + c];
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) wu_out[DIM * f + c] = pa.wu_f[DIM * f + c] - pa.dt * (gs[c] / vs);
+}
+
+// gd_i = P^{n+1}_B - P^n_B on Dirichlet nodes (pb null: 0), 0 elsewhere.
+__global__ void __launch_bounds__(BLK) k_proj_lift(int N, const int *__restrict__ new2old,
+                                                   const uint8_t *__restrict__ dir, const double *__restrict__ pb,
+                                                   const double *__restrict__ pn, double *__restrict__ gd)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i >= N) return;
+    gd[i] = (dir[i] && pb) ? pb[new2old[i]] - pn[i] : 0.0;
+}
+
+// out = a + b (caller order)
+__global__ void __launch_bounds__(BLK) k_add(int N, const double *__restrict__ a, const double *__restrict__ b,
+                                             double *__restrict__ out)
+{
+    const int i = blockIdx.x * BLK + threadIdx.x;
+    if (i < N) out[i] = a[i] + b[i];
+}
+
+// out[perm[k]] = v[k]
+__global__ void __launch_bounds__(BLK) k_scatter_elem(int E, const int *__restrict__ perm,
+                                                      const double *__restrict__ v, double *__restrict__ out)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k < E) out[perm[k]] = v[k];
+}
+
 // ----------------------------------------------------------- batched solve
 // Many meshes advance their CG iterations together: one launch runs the
 // apply of iteration k for every (mesh, slot) pair, the next the update.  The
@@ -1122,6 +1388,16 @@ struct pm_handle {
     CGState *hst = nullptr;     // pinned host mirror
     size_t dev_bytes = 0;
     std::vector<int32_t> elem_new2old;   // host copy, for coefficient updates
+    // projection stage: dual cells (built at the first use) and buffers
+    struct Proj {
+        bool built = false;
+        pm::Faces F;                // host, caller numbering
+        int *efc = nullptr;         // 4 per internal element: face opposite internal-local vertex a
+        int2 *fel = nullptr;        // per face: internal elements
+        int *enew2old = nullptr;    // caller element of each internal element
+        double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
+        double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
+    } pj;
     // timing (sampled: every TIMING_STRIDE-th apply launch of a solve)
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -1257,32 +1533,39 @@ bool valid_coef(const double *c, int64_t E)
 }
 
 template <class R>
-int compute_factors_t(pm_handle *h, R *w, R *inst_w)
+int compute_factors_t(pm_handle *h, R *w, R *inst_w, hipStream_t s)
 {
     MeshT<R> g = make_mesh<R>(h);
     const double beta = h->dt * h->dt;
     const dim3 grid(grid_of(h->E));
     if (h->dim == 2 && h->periodic)
-        hipLaunchKernelGGL((k_factors<2, R, true>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
+        hipLaunchKernelGGL((k_factors<2, R, true>), grid, dim3(BLK), 0, s, g, h->coef, beta, w);
     else if (h->dim == 2)
-        hipLaunchKernelGGL((k_factors<2, R, false>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
+        hipLaunchKernelGGL((k_factors<2, R, false>), grid, dim3(BLK), 0, s, g, h->coef, beta, w);
     else if (h->periodic)
-        hipLaunchKernelGGL((k_factors<3, R, true>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
+        hipLaunchKernelGGL((k_factors<3, R, true>), grid, dim3(BLK), 0, s, g, h->coef, beta, w);
     else
-        hipLaunchKernelGGL((k_factors<3, R, false>), grid, dim3(BLK), 0, 0, g, h->coef, beta, w);
+        hipLaunchKernelGGL((k_factors<3, R, false>), grid, dim3(BLK), 0, s, g, h->coef, beta, w);
     HIPCK(hipGetLastError());
     if (h->n_inst > 0) {
-        hipLaunchKernelGGL(k_inst_factors<R>, dim3(grid_of(h->n_inst)), dim3(BLK), 0, 0, int(h->n_inst),
+        hipLaunchKernelGGL(k_inst_factors<R>, dim3(grid_of(h->n_inst)), dim3(BLK), 0, s, int(h->n_inst),
                            h->t_inst_elem, w, inst_w);
         HIPCK(hipGetLastError());
     }
     return PM_OK;
 }
 
+// Element factors from the current c_e, alpha and dt, in stream order.
+int compute_factors_on(pm_handle *h, hipStream_t s)
+{
+    TRY(compute_factors_t<double>(h, h->w, h->t_inst_w, s));
+    if (h->w32) TRY(compute_factors_t<float>(h, h->w32, h->t_inst_w32, s));
+    return PM_OK;
+}
+
 int compute_factors(pm_handle *h)
 {
-    TRY(compute_factors_t<double>(h, h->w, h->t_inst_w));
-    if (h->w32) TRY(compute_factors_t<float>(h, h->w32, h->t_inst_w32));
+    TRY(compute_factors_on(h, nullptr));
     HIPCK(hipDeviceSynchronize());
     return PM_OK;
 }
@@ -1594,7 +1877,8 @@ void pressure_destroy(pm_handle *h)
                     h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst, h->t_inst_w,
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
-                    h->d32, h->p32[0], h->p32[1], h->st_in, h->mw};
+                    h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -2737,3 +3021,157 @@ int pressure_batch_next_index(pm_batch *b, int32_t *k)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- projection stage
+
+namespace {
+
+// Dual cells of the handle's mesh, numbered from the caller's elements
+// (recovered from the oriented internal connectivity: a face is a vertex
+// set, so orientation does not change it).
+int ensure_faces(pm_handle *h)
+{
+    if (h->pj.built) return PM_OK;
+    const int nv = h->dim + 1;
+    const int64_t N = h->N, E = h->E;
+    std::vector<int4> conn(E);
+    std::vector<int32_t> n2o(N);
+    HIPCK(hipMemcpy(conn.data(), h->conn, sizeof(int4) * E, hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(n2o.data(), h->new2old, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+    std::vector<int32_t> el(E * nv);
+    for (int64_t r = 0; r < E; ++r) {
+        const int64_t o = h->elem_new2old[r];
+        const int32_t cv[4] = {conn[r].x, conn[r].y, conn[r].z, conn[r].w};
+        for (int a = 0; a < nv; ++a) el[o * nv + a] = n2o[cv[a] & 0x7fffffff];
+    }
+    pm_mesh m{};
+    m.dim = h->dim;
+    m.n_nodes = N;
+    m.n_elems = E;
+    m.elems = el.data();
+    pm::Faces &F = h->pj.F;
+    TRY(pm::build_faces(&m, &F));
+    std::vector<int32_t> efc(E * 4, -1), o2n(E);
+    for (int64_t r = 0; r < E; ++r) {
+        const int64_t o = h->elem_new2old[r];
+        o2n[o] = int32_t(r);
+        for (int a = 0; a < nv; ++a) efc[r * 4 + a] = F.elem_face[o * nv + a];
+    }
+    std::vector<int2> fel(F.n_faces);
+    for (int64_t f = 0; f < F.n_faces; ++f) {
+        const int32_t x = F.elems[2 * f], y = F.elems[2 * f + 1];
+        fel[f] = make_int2(o2n[x], y < 0 ? -1 : o2n[y]);
+    }
+    TRY(dupload(h, &h->pj.efc, efc));
+    TRY(dupload(h, &h->pj.fel, fel));
+    TRY(dupload(h, &h->pj.enew2old, h->elem_new2old));
+    TRY(dalloc(h, &h->pj.e, size_t(10 * E)));
+    for (double **v : {&h->pj.pn, &h->pj.gd, &h->pj.b, &h->pj.dp, &h->pj.dpi}) TRY(dalloc(h, v, size_t(N)));
+    h->pj.built = true;
+    return PM_OK;
+}
+
+template <int DIM, bool PER>
+int projection_t(pm_handle *h, const ProjArgs &pa, const double *p_dev, const double *pb_dev, const double *dp0,
+                 int32_t n_picard, double rtol, int32_t max_iter, double *p_out, double *wu_out, double *h_out,
+                 int32_t *iters, hipStream_t s)
+{
+    const int N = int(h->N), E = int(h->E), F = int(h->pj.F.n_faces);
+    Mesh g = make_mesh<double>(h);
+    hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
+    hipLaunchKernelGGL(k_proj_lift, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->dir, pb_dev, h->pj.pn,
+                       h->pj.gd);
+    hipLaunchKernelGGL((k_proj_init<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->coef);
+    HIPCK(hipGetLastError());
+    TRY(compute_factors_on(h, s));
+    int worst = PM_OK;
+    const double *x0 = dp0;
+    for (int it = 0; it < n_picard; ++it) {
+        hipLaunchKernelGGL((k_proj_rhs<DIM, PER>), dim3(grid_of(N)), dim3(BLK), 0, s, g, pa, h->n2e_off,
+                           h->n2e_ent, h->coef, h->pj.pn, h->pj.gd, h->new2old, h->pj.b);
+        HIPCK(hipGetLastError());
+        int32_t k = 0;
+        const int st = pressure_solve(h, h->pj.b, x0, rtol, max_iter, h->pj.dp, &k, nullptr, nullptr, s);
+        if (iters) iters[it] = k;
+        if (st < 0) return st;
+        if (st == PM_NOT_CONVERGED) worst = st;
+        x0 = h->pj.dp;
+        hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->pj.dp, h->pj.dpi);
+        hipLaunchKernelGGL((k_proj_picard<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->pj.dpi,
+                           h->coef);
+        HIPCK(hipGetLastError());
+        TRY(compute_factors_on(h, s));
+    }
+    hipLaunchKernelGGL(k_proj_faces<DIM>, dim3(grid_of(F)), dim3(BLK), 0, s, F, pa, wu_out);
+    hipLaunchKernelGGL(k_add, dim3(grid_of(N)), dim3(BLK), 0, s, N, p_dev, h->pj.dp, p_out);
+    if (h_out)
+        hipLaunchKernelGGL(k_scatter_elem, dim3(grid_of(E)), dim3(BLK), 0, s, E, h->pj.enew2old, h->coef, h_out);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(s));
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pressure_dual_count(pm_handle *h, int64_t *n_faces, int64_t *n_boundary)
+{
+    if (!h) return PM_EINVAL;
+    TRY(ensure_faces(h));
+    if (n_faces) *n_faces = h->pj.F.n_faces;
+    if (n_boundary) *n_boundary = h->pj.F.n_boundary;
+    return PM_OK;
+}
+
+int pressure_dual_faces(pm_handle *h, int32_t *face_vertices, int32_t *face_elems)
+{
+    if (!h) return PM_EINVAL;
+    TRY(ensure_faces(h));
+    const pm::Faces &F = h->pj.F;
+    if (face_vertices) std::copy(F.vertices.begin(), F.vertices.end(), face_vertices);
+    if (face_elems) std::copy(F.elems.begin(), F.elems.end(), face_elems);
+    return PM_OK;
+}
+
+int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_dev, const double *wu_dev,
+                        const double *p_dev, const double *pb_dev, const double *bflux_dev,
+                        const double *dp0_dev, double gamma, double dt, int32_t n_picard, double rtol,
+                        int32_t max_iter, double *p_out, double *wu_out, double *h_out, int32_t *iters,
+                        void *stream)
+{
+    if (!h || !rho_dev || !we_dev || !wu_dev || !p_dev || !p_out || !wu_out) return PM_EINVAL;
+    if (!(gamma > 1.0) || !std::isfinite(gamma) || !(dt > 0.0) || !std::isfinite(dt) || n_picard < 1 ||
+        !(rtol > 0.0) || !std::isfinite(rtol) || max_iter < 0)
+        return PM_EINVAL;
+    TRY(ensure_faces(h));
+    hipStream_t s = (hipStream_t)stream;
+    h->alpha = 1.0 / (gamma - 1.0);
+    h->dt = dt;
+    TRY(update_v0(h));
+    const int64_t E = h->E;
+    ProjArgs pa;
+    pa.efc = h->pj.efc;
+    pa.fel = h->pj.fel;
+    pa.rho_f = rho_dev;
+    pa.we_f = we_dev;
+    pa.wu_f = wu_dev;
+    pa.bflux = bflux_dev;
+    pa.erho = h->pj.e;
+    pa.ewe = h->pj.e + E;
+    pa.erk = h->pj.e + 2 * E;
+    pa.evol = h->pj.e + 3 * E;
+    pa.ewu = h->pj.e + 4 * E;
+    pa.egrad = h->pj.e + 7 * E;
+    pa.g1 = gamma / (gamma - 1.0);
+    pa.dt = dt;
+    auto run = [&]<int DIM, bool PER>() {
+        return projection_t<DIM, PER>(h, pa, p_dev, pb_dev, dp0_dev, n_picard, rtol, max_iter, p_out, wu_out, h_out,
+                                      iters, s);
+    };
+    if (h->dim == 2) return h->periodic ? run.template operator()<2, true>() : run.template operator()<2, false>();
+    return h->periodic ? run.template operator()<3, true>() : run.template operator()<3, false>();
+}
+
+}  // extern "C"
+

@@ -193,6 +193,49 @@ class PressureSystem:
         check(load().pressure_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)), "pressure_timing_read")
         return n.value, ms.value
 
+    def dual_faces(self):
+        """The dual cells (faces of the primal mesh in the library's
+        numbering): (face_vertices [F, dim], face_elems [F, 2], n_boundary)."""
+        nf = ctypes.c_int64(0)
+        nb = ctypes.c_int64(0)
+        check(load().pressure_dual_count(self._h, ctypes.byref(nf), ctypes.byref(nb)), "pressure_dual_count")
+        fv = np.zeros((nf.value, self.dim), dtype=np.int32)
+        fe = np.zeros((nf.value, 2), dtype=np.int32)
+        check(load().pressure_dual_faces(self._h, _ptr(fv), _ptr(fe)), "pressure_dual_faces")
+        return fv, fe, nb.value
+
+    def projection(self, rho, we, wu, p, gamma, dt, pb=None, bflux=None, dp0=None, n_picard=2, rtol=1e-10,
+                   max_iter=20000, p_out=None, wu_out=None, h_out=None, stream=None):
+        """One projection stage (see pressure_projection in
+        include/pressure_cg.h).  Dual-cell fields are float64 CUDA tensors
+        in the face numbering of dual_faces(); returns
+        (P^{n+1}, W_u^{n+1}, H^{n+1} per element, CG iterations per Picard
+        iteration)."""
+        import torch
+        nf = ctypes.c_int64(0)
+        check(load().pressure_dual_count(self._h, ctypes.byref(nf), None), "pressure_dual_count")
+        F = nf.value
+        args = [_dev_ptr(rho, F, "rho"), _dev_ptr(we, F, "we"), _dev_ptr(wu, F * self.dim, "wu"),
+                _dev_ptr(p, self.n_nodes, "p"),
+                None if pb is None else _dev_ptr(pb, self.n_nodes, "pb"),
+                None if bflux is None else _dev_ptr(bflux, F, "bflux"),
+                None if dp0 is None else _dev_ptr(dp0, self.n_nodes, "dp0")]
+        if p_out is None:
+            p_out = torch.empty_like(p)
+        if wu_out is None:
+            wu_out = torch.empty_like(wu)
+        if h_out is None:
+            h_out = torch.empty(self.n_elems, dtype=torch.float64, device=p.device)
+        its = np.zeros(max(int(n_picard), 1), dtype=np.int32)
+        st = load().pressure_projection(self._h, *args, float(gamma), float(dt), int(n_picard), float(rtol),
+                                        int(max_iter), _dev_ptr(p_out, self.n_nodes, "p_out"),
+                                        _dev_ptr(wu_out, F * self.dim, "wu_out"),
+                                        _dev_ptr(h_out, self.n_elems, "h_out"), _ptr(its),
+                                        _stream_handle(stream))
+        if st < 0:
+            check(st, "pressure_projection")
+        return p_out, wu_out, h_out, its, st
+
     def info(self):
         v = (ctypes.c_int64 * 8)()
         check(load().pressure_info(self._h, v, 8), "pressure_info")
