@@ -888,6 +888,7 @@ __global__ void __launch_bounds__(BLK) k_sub_mean(int N, double *__restrict__ v,
 struct ProjArgs {
     const int *efc;       // 4 per element: face opposite internal-local vertex a
     const int2 *fel;      // per face: internal elements (y = -1 on the boundary)
+    const uint8_t *ebnd;  // per element: bit a set when the face opposite a is a boundary face
     const double *rho_f, *we_f, *wu_f, *bflux;
     double *erho, *ewe, *ewu, *erk, *evol, *egrad;   // per element (ewu, egrad: 3 each)
     double g1;            // gamma / (gamma - 1)
@@ -1004,67 +1005,97 @@ __global__ void __launch_bounds__(BLK) k_proj_init(Mesh g, ProjArgs pa, const do
     coef[k] = elem_enthalpy<DIM>(pa, k, pv);
 }
 
-// Right-hand side of the weak problem for one Picard iteration, node by
-// node over its elements in ascending order; written in caller order.
+// Right-hand side of the weak problem for one Picard iteration, element
+// pass: contrib[4k + a] = the contribution of element k to its vertex a.
 template <int DIM, bool PER>
-__global__ void __launch_bounds__(BLK) k_proj_rhs(Mesh g, ProjArgs pa, const int *__restrict__ off,
-                                                  const int *__restrict__ ent, const double *__restrict__ coef,
-                                                  const double *__restrict__ pn, const double *__restrict__ gd,
-                                                  const int *__restrict__ new2old, double *__restrict__ b)
+__global__ void __launch_bounds__(BLK) k_proj_rhs_elem(Mesh g, ProjArgs pa, const double *__restrict__ coef,
+                                                       const double *__restrict__ pn, const double *__restrict__ gd,
+                                                       double *__restrict__ contrib)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    const double vol = det / dfact;
+    // sources (W_E - rho K) |T|/(d+1) and advection dt H W_u . n_a / d!
+    const double src = (pa.ewe[k] - pa.erk[k]) * (vol / double(DIM + 1));
+    const double hdt = pa.dt * coef[k] / dfact;
+    double u[3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) u[c] = pa.ewu[3 * k + c];
+    // - alpha (M_e P^n)_a, and - (A_e g)_a over the Dirichlet vertices
+    const int4 c4 = g.conn[k];
+    const int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+    double pv[4], gv[4], o[4], t[4];
+    double sp = 0.0;
+    bool lift = false;
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        pv[a] = pn[v[a]];
+        sp += pv[a];
+        gv[a] = (cv[a] < 0) ? gd[v[a]] : 0.0;
+        lift = lift || (cv[a] < 0);
+    }
+    if (DIM == 2) gv[3] = 0.0;
+    if (lift) elem_contrib<DIM, double>(ed, gv, g.w[k], g.mdiag, g.mfull, o);
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        double un = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) un += u[c] * n[a][c];
+        t[a] = src + hdt * un;
+        t[a] -= det * (g.mdiag * pv[a] + g.mfull * sp);
+        if (lift) t[a] -= o[a];
+    }
+    // boundary faces (bit b: the face opposite vertex b): - dt bflux_f |f| / d
+    // to each of the face's vertices
+    const unsigned bits = pa.ebnd[k];
+    if (bits && pa.bflux) {
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b) {
+            if (!(bits & (1u << b))) continue;
+            const double nn = sqrt(n[b][0] * n[b][0] + n[b][1] * n[b][1] + n[b][2] * n[b][2]);
+            const double area = (DIM == 2) ? nn : 0.5 * nn;
+            const double val = pa.dt * pa.bflux[pa.efc[4 * k + b]] * area / double(DIM);
+#pragma unroll
+            for (int a = 0; a <= DIM; ++a)
+                if (a != b) t[a] -= val;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) contrib[4 * k + a] = t[a];
+}
+
+// Node pass: b_i = the sum of its element contributions, gd_i on a
+// Dirichlet node; written in caller order.  Four accumulators take the
+// incidences q = 4j + l (fixed pattern, so the sum is reproducible) and keep
+// four loads in flight per lane.
+__global__ void __launch_bounds__(BLK) k_proj_rhs_node(int N, const int *__restrict__ off, const int *__restrict__ ent,
+                                                       const uint8_t *__restrict__ dir, const double *__restrict__ gd,
+                                                       const double *__restrict__ contrib,
+                                                       const int *__restrict__ new2old, double *__restrict__ b)
 {
     const int i = blockIdx.x * BLK + threadIdx.x;
-    if (i >= g.N) return;
+    if (i >= N) return;
     double bi = 0.0;
-    if (g.dir[i]) {
+    if (dir[i]) {
         bi = gd[i];
     } else {
-        constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
-        for (int q = off[i]; q < off[i + 1]; ++q) {
-            const int en = ent[q], k = en >> 2, a = en & 3;
-            int v[4];
-            double ed[3][3], n[4][3];
-            elem_corners<DIM, PER>(g, k, v, ed);
-            const double det = elem_normals<DIM>(ed, n);
-            const double vol = det / dfact;
-            // sources: (W_E - rho K) |T|/(d+1) + dt H W_u . n_a / d!
-            double t = (pa.ewe[k] - pa.erk[k]) * (vol / double(DIM + 1));
-            double un = 0.0;
+        const int q0 = off[i], q1 = off[i + 1];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = q0;
+        for (; q + 4 <= q1; q += 4) {
+            int e[4];
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) un += pa.ewu[3 * k + c] * n[a][c];
-            t += pa.dt * coef[k] * un / dfact;
-            // - alpha (M_e P^n)_a and - (A_e g)_a over the Dirichlet vertices
-            const int4 c4 = g.conn[k];
-            const int cv[4] = {c4.x, c4.y, c4.z, c4.w};
-            double pv[4], gv[4], o[4];
-            double sp = 0.0;
-            bool lift = false;
+            for (int l = 0; l < 4; ++l) e[l] = ent[q + l];
 #pragma unroll
-            for (int b2 = 0; b2 <= DIM; ++b2) {
-                pv[b2] = pn[v[b2]];
-                sp += pv[b2];
-                gv[b2] = (cv[b2] < 0) ? gd[v[b2]] : 0.0;
-                lift = lift || (cv[b2] < 0);
-            }
-            if (DIM == 2) gv[3] = 0.0;
-            t -= det * (g.mdiag * pv[a] + g.mfull * sp);
-            if (lift) {
-                elem_contrib<DIM, double>(ed, gv, g.w[k], g.mdiag, g.mfull, o);
-                t -= o[a];
-            }
-            // boundary faces through vertex a: - dt bflux_f |f| / d
-            if (pa.bflux) {
-#pragma unroll
-                for (int b2 = 0; b2 <= DIM; ++b2) {
-                    if (b2 == a) continue;
-                    const int f = pa.efc[4 * k + b2];
-                    if (pa.fel[f].y >= 0) continue;
-                    const double nn = sqrt(n[b2][0] * n[b2][0] + n[b2][1] * n[b2][1] + n[b2][2] * n[b2][2]);
-                    const double area = (DIM == 2) ? nn : 0.5 * nn;
-                    t -= pa.dt * pa.bflux[f] * area / double(DIM);
-                }
-            }
-            bi += t;
+            for (int l = 0; l < 4; ++l) acc[l] += contrib[e[l]];
         }
+        for (int l = 0; q < q1; ++q, ++l) acc[l] += contrib[ent[q]];
+        bi = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
     b[new2old[i]] = bi;
 }
@@ -1395,6 +1426,8 @@ struct pm_handle {
         int *efc = nullptr;         // 4 per internal element: face opposite internal-local vertex a
         int2 *fel = nullptr;        // per face: internal elements
         int *enew2old = nullptr;    // caller element of each internal element
+        uint8_t *ebnd = nullptr;    // boundary-face bits per internal element
+        double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
     } pj;
@@ -1878,7 +1911,7 @@ void pressure_destroy(pm_handle *h)
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
-                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi};
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -3052,10 +3085,15 @@ int ensure_faces(pm_handle *h)
     pm::Faces &F = h->pj.F;
     TRY(pm::build_faces(&m, &F));
     std::vector<int32_t> efc(E * 4, -1), o2n(E);
+    std::vector<uint8_t> ebnd(E, 0);
     for (int64_t r = 0; r < E; ++r) {
         const int64_t o = h->elem_new2old[r];
         o2n[o] = int32_t(r);
-        for (int a = 0; a < nv; ++a) efc[r * 4 + a] = F.elem_face[o * nv + a];
+        for (int a = 0; a < nv; ++a) {
+            const int32_t f = F.elem_face[o * nv + a];
+            efc[r * 4 + a] = f;
+            if (F.elems[2 * int64_t(f) + 1] < 0) ebnd[r] |= uint8_t(1u << a);
+        }
     }
     std::vector<int2> fel(F.n_faces);
     for (int64_t f = 0; f < F.n_faces; ++f) {
@@ -3065,7 +3103,9 @@ int ensure_faces(pm_handle *h)
     TRY(dupload(h, &h->pj.efc, efc));
     TRY(dupload(h, &h->pj.fel, fel));
     TRY(dupload(h, &h->pj.enew2old, h->elem_new2old));
+    TRY(dupload(h, &h->pj.ebnd, ebnd));
     TRY(dalloc(h, &h->pj.e, size_t(10 * E)));
+    TRY(dalloc(h, &h->pj.contrib, size_t(4 * E)));
     for (double **v : {&h->pj.pn, &h->pj.gd, &h->pj.b, &h->pj.dp, &h->pj.dpi}) TRY(dalloc(h, v, size_t(N)));
     h->pj.built = true;
     return PM_OK;
@@ -3087,8 +3127,10 @@ int projection_t(pm_handle *h, const ProjArgs &pa, const double *p_dev, const do
     int worst = PM_OK;
     const double *x0 = dp0;
     for (int it = 0; it < n_picard; ++it) {
-        hipLaunchKernelGGL((k_proj_rhs<DIM, PER>), dim3(grid_of(N)), dim3(BLK), 0, s, g, pa, h->n2e_off,
-                           h->n2e_ent, h->coef, h->pj.pn, h->pj.gd, h->new2old, h->pj.b);
+        hipLaunchKernelGGL((k_proj_rhs_elem<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->coef,
+                           h->pj.pn, h->pj.gd, h->pj.contrib);
+        hipLaunchKernelGGL(k_proj_rhs_node, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->n2e_off, h->n2e_ent, h->dir,
+                           h->pj.gd, h->pj.contrib, h->new2old, h->pj.b);
         HIPCK(hipGetLastError());
         int32_t k = 0;
         const int st = pressure_solve(h, h->pj.b, x0, rtol, max_iter, h->pj.dp, &k, nullptr, nullptr, s);
@@ -3153,6 +3195,7 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
     ProjArgs pa;
     pa.efc = h->pj.efc;
     pa.fel = h->pj.fel;
+    pa.ebnd = h->pj.ebnd;
     pa.rho_f = rho_dev;
     pa.we_f = we_dev;
     pa.wu_f = wu_dev;
