@@ -447,6 +447,35 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
                         int32_t max_iter, double *p_out, double *wu_out, double *h_out, int32_t *iters,
                         void *stream);
 
+/* One explicit transport step on the dual cells, first order (Sec. 3.2,
+ * eq. discrf_mass, discrf_momentum and discrf_energy without the viscous and
+ * heat-flux terms):
+ *   rho_f^{n+1}  = rho_f - dt/|C_f| sum_j phi_rho(f, j)
+ *   W_u,f        = W_u,f - dt/|C_f| ( sum_j phi_u(f, j) + int_{C_f} grad P^n )
+ *                  + dt rho_f g
+ *   W_E,f        = W_E,f - dt/|C_f| sum_j phi_E(f, j) + dt g . W_u,f
+ * over the dual faces Gamma_fj inside the one or two primal elements of f
+ * (in element k the cells of faces a and b meet on the simplex that joins
+ * the barycenter of T_k to the primal vertices the two faces share; its
+ * area vector from a to b is eta_ab = |T_k| d/(d+1) (grad phi_a - grad
+ * phi_b)).  phi is the modified Rusanov flux of eq. flux:
+ *   phi = (Z(W_f, eta) + Z(W_j, eta))/2 - alpha_RS (Wr_j - Wr_f)/2,
+ *   Z(W, eta) = (W_u . eta, W_u (U . eta), rho K (U . eta)), U = W_u/rho,
+ *   Wr = (rho, W_u, rho K), rho K = |W_u|^2 / (2 rho),
+ *   alpha_RS = max(|U_f . eta|, |U_j . eta|) + c_alpha |eta|
+ * (the sound speed does not enter: the pressure is implicit).  The pressure
+ * force int_{C_f} grad P^n = sum_k |T_k|/(d+1) grad P^n|_k is exact for the
+ * P1 pressure.  Boundary faces of the primal mesh carry no convective flux
+ * (impermeable walls).  Arrays are device, caller face numbering as in
+ * pressure_dual_faces: rho_dev, we_dev, rho_out, we_out n_faces; wu_dev,
+ * wu_out n_faces * dim; p_dev n_nodes (P^n at the vertices).  gravity is
+ * host, dim doubles, or NULL for none; c_alpha >= 0; dt > 0.  Outputs must
+ * not alias inputs.  The first call allocates 20 doubles per element.
+ * Synchronises the stream before returning. */
+int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
+                       const double *p_dev, const double *gravity, double c_alpha, double dt, double *rho_out,
+                       double *wu_out, double *we_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

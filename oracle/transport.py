@@ -1,0 +1,135 @@
+"""CPU oracle of the first-order transport step on the dual cells -- TEST
+INFRASTRUCTURE (imported only by tests/, __graft_entry__.smoke() and the
+CPU-baseline leg of bench.py).
+
+Follows Sec. 3.2 of the paper (eq. discrf_mass, discrf_momentum,
+discrf_energy with the modified Rusanov flux of eq. flux), without the
+viscous and heat-flux terms and without the LADER reconstruction:
+
+  dual_geometry   the dual faces from their definition (Sec. 2): inside
+                  element k the cells of primal faces a and b meet on the
+                  simplex joining the barycenter B_k to the primal vertices
+                  the two faces share; its area vector comes from that
+                  simplex (segment normal in 2D, half cross product in 3D),
+                  oriented from cell a (which holds vertex b) to cell b
+                  (which holds vertex a); cell volumes are the volumes of
+                  the sub-simplices (B_k, face).
+  rusanov_flux    phi = (Z_i + Z_j)/2 - alpha_RS (Wr_j - Wr_i)/2 with
+                  Z = (W_u.eta, W_u (U.eta), rho K (U.eta)),
+                  Wr = (rho, W_u, rho K), alpha_RS = max|U.eta| + c_alpha|eta|.
+  transport_step  the update; the pressure force is eq. pressterm, the sum
+                  over the dual faces of the face-mean pressure times the
+                  area vector, plus the primal boundary faces of boundary
+                  cells (so that it is the integral of grad P over the cell);
+                  boundary faces carry no convective flux; gravity sources.
+"""
+
+import numpy as np
+
+from oracle import projection as op
+
+
+def _geometry_coords(mesh):
+    g = mesh.unmerged if getattr(mesh, "period", None) is not None else mesh
+    return np.asarray(g.coords, dtype=np.float64)[np.asarray(g.elems, dtype=np.int64)]   # [E, d+1, d]
+
+
+def _area_vector(pts, toward):
+    """Area vector of the segment / triangle pts [.., d, d], oriented so that
+    its dot with `toward` is positive."""
+    if pts.shape[-1] == 2:
+        t = pts[..., 1, :] - pts[..., 0, :]
+        eta = np.stack([t[..., 1], -t[..., 0]], axis=-1)
+    else:
+        eta = 0.5 * np.cross(pts[..., 1, :] - pts[..., 0, :], pts[..., 2, :] - pts[..., 0, :])
+    sgn = np.sign((eta * toward).sum(axis=-1))
+    return eta * sgn[..., None]
+
+
+def _simplex_volume(pts):
+    d = pts.shape[-1]
+    J = pts[..., 1:, :] - pts[..., :1, :]
+    return np.abs(np.linalg.det(J)) / (2.0 if d == 2 else 6.0)
+
+
+def dual_geometry(mesh):
+    """pairs [P, 2] local (a, b); eta [E, P, d] from cell a to cell b;
+    subvol [E, d+1] |(B, face a)|; bnd_eta [E, d+1] outward area vectors of
+    the primal faces."""
+    x = _geometry_coords(mesh)
+    E, nv, d = x.shape
+    B = x.mean(axis=1)
+    pairs = [(a, b) for a in range(nv) for b in range(a + 1, nv)]
+    eta = np.zeros((E, len(pairs), d))
+    for p, (a, b) in enumerate(pairs):
+        shared = [c for c in range(nv) if c not in (a, b)]
+        pts = np.concatenate([B[:, None, :], x[:, shared, :]], axis=1)
+        eta[:, p, :] = _area_vector(pts, x[:, a, :] - B)
+    subvol = np.zeros((E, nv))
+    bnd_eta = np.zeros((E, nv, d))
+    for a in range(nv):
+        others = [c for c in range(nv) if c != a]
+        subvol[:, a] = _simplex_volume(np.concatenate([B[:, None, :], x[:, others, :]], axis=1))
+        # outward: away from vertex a
+        bnd_eta[:, a, :] = _area_vector(x[:, others, :], x[:, others, :].mean(axis=1) - x[:, a, :])
+    return pairs, eta, subvol, bnd_eta
+
+
+def rusanov_flux(rho_i, wu_i, rho_j, wu_j, eta, c_alpha):
+    """phi [.., 2 + d]: (mass, momentum, energy)."""
+    un_i = (wu_i * eta).sum(axis=-1)
+    un_j = (wu_j * eta).sum(axis=-1)
+    v_i, v_j = un_i / rho_i, un_j / rho_j
+    rk_i = (wu_i * wu_i).sum(axis=-1) / (2.0 * rho_i)
+    rk_j = (wu_j * wu_j).sum(axis=-1) / (2.0 * rho_j)
+    a = np.maximum(np.abs(v_i), np.abs(v_j)) + c_alpha * np.sqrt((eta * eta).sum(axis=-1))
+    mass = 0.5 * (un_i + un_j) - 0.5 * a * (rho_j - rho_i)
+    mom = 0.5 * (wu_i * v_i[..., None] + wu_j * v_j[..., None]) - 0.5 * a[..., None] * (wu_j - wu_i)
+    en = 0.5 * (rk_i * v_i + rk_j * v_j) - 0.5 * a * (rk_j - rk_i)
+    return np.concatenate([mass[..., None], mom, en[..., None]], axis=-1)
+
+
+def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0):
+    """Returns dict(rho, wu, we, vol, flux_sum, pforce)."""
+    dim = mesh.dim
+    fv, fe, ef = op.dual_faces(dim, mesh.elems)
+    F = fv.shape[0]
+    pairs, eta, subvol, bnd_eta = dual_geometry(mesh)
+    rho = np.asarray(rho, dtype=np.float64)
+    wu = np.asarray(wu, dtype=np.float64).reshape(F, dim)
+    we = np.asarray(we, dtype=np.float64)
+    el = np.asarray(mesh.elems, dtype=np.int64)
+    acc = np.zeros((F, 2 + dim))
+    vol = np.zeros(F)
+    np.add.at(vol, ef, subvol)
+    for q, (a, b) in enumerate(pairs):
+        fa, fb = ef[:, a], ef[:, b]
+        phi = rusanov_flux(rho[fa], wu[fa], rho[fb], wu[fb], eta[:, q, :], c_alpha)
+        np.add.at(acc, fa, phi)
+        np.add.at(acc, fb, -phi)
+    # pressure force: face-mean pressure times area vector over the cell's
+    # boundary (dual faces, then the primal boundary faces)
+    P = np.asarray(p, dtype=np.float64)[el]                   # [E, d+1]
+    PB = P.mean(axis=1)
+    pforce = np.zeros((F, dim))
+    nv = dim + 1
+    for q, (a, b) in enumerate(pairs):
+        shared = [c for c in range(nv) if c not in (a, b)]
+        pm = (PB + P[:, shared].sum(axis=1)) / (len(shared) + 1)
+        np.add.at(pforce, ef[:, a], pm[:, None] * eta[:, q, :])
+        np.add.at(pforce, ef[:, b], -pm[:, None] * eta[:, q, :])
+    bnd = fe[:, 1] < 0
+    for a in range(nv):
+        f = ef[:, a]
+        on = bnd[f]
+        others = [c for c in range(nv) if c != a]
+        pm = P[:, others].mean(axis=1)
+        np.add.at(pforce, f[on], pm[on, None] * bnd_eta[on, a, :])
+    acc[:, 1:1 + dim] += pforce
+    g = np.zeros(dim) if gravity is None else np.asarray(gravity, dtype=np.float64)
+    q = dt / vol
+    out_rho = rho - q * acc[:, 0]
+    out_wu = wu - q[:, None] * acc[:, 1:1 + dim] + dt * rho[:, None] * g[None, :]
+    out_we = we - q * acc[:, 1 + dim] + dt * (wu @ g)
+    return {"rho": out_rho, "wu": out_wu, "we": out_we, "vol": vol, "flux_sum": acc, "pforce": pforce,
+            "faces": (fv, fe, ef)}

@@ -1178,6 +1178,136 @@ __global__ void __launch_bounds__(BLK) k_scatter_elem(int E, const int *__restri
     if (k < E) out[perm[k]] = v[k];
 }
 
+// -------------------------------------------------------- transport stage
+// First-order explicit finite volumes on the dual cells (Sec. 3.2, eq.
+// discrf_mass / discrf_momentum / discrf_energy) with the modified Rusanov
+// flux of eq. flux.  Inside element k the dual cells of faces a and b meet
+// on the triangle (3D) or segment (2D) that joins the barycenter to the
+// primal edge (vertex) they share; its area vector from cell a to cell b is
+// eta_ab = |T| d/(d+1) (grad phi_a - grad phi_b) = d/((d+1) d!) (n_a - n_b).
+
+constexpr int TR_NC = 5;   // rho, W_u (3), W_E per face slot
+
+struct TransArgs {
+    const int *efc;               // 4 per element: face opposite internal-local vertex a
+    const int2 *fsl;              // per face: element slots 4k + a of its one or two elements (-1)
+    const double *rho, *wu, *we;  // per face (caller numbering); wu: dim per face
+    double *flux;                 // TR_NC per element slot: flux sums and pressure force
+    double *evol;                 // per element: |T_k|
+    double calpha;                // artificial viscosity coefficient c_alpha
+    double dt;
+    double g[3];                  // gravity
+};
+
+// Element pass: for every face pair (a, b), a < b, the Rusanov flux from a
+// to b is added to slot a and subtracted from slot b (pairs in fixed
+// order); every slot also takes |T|/(d+1) grad(P^n) on its momentum.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_tr_elem(Mesh g, TransArgs ta, const double *__restrict__ pn)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    constexpr double ceta = double(DIM) / (double(DIM + 1) * dfact);
+    double rho[4], u[4][3], rk[4], out[4][TR_NC];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        const int f = ta.efc[4 * k + a];
+        rho[a] = ta.rho[f];
+        double w2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            u[a][c] = (c < DIM) ? ta.wu[DIM * f + c] : 0.0;
+            w2 += u[a][c] * u[a][c];
+        }
+        rk[a] = w2 / (2.0 * rho[a]);
+#pragma unroll
+        for (int c = 0; c < TR_NC; ++c) out[a][c] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+#pragma unroll
+        for (int b = a + 1; b <= DIM; ++b) {
+            double eta[3], ua = 0.0, ub = 0.0, en = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                eta[c] = ceta * (n[a][c] - n[b][c]);
+                ua += u[a][c] * eta[c];   // W_u . eta
+                ub += u[b][c] * eta[c];
+                en += eta[c] * eta[c];
+            }
+            const double va = ua / rho[a], vb = ub / rho[b];   // U . eta
+            const double ars = fmax(fabs(va), fabs(vb)) + ta.calpha * sqrt(en);
+            double phi[TR_NC];
+            phi[0] = 0.5 * (ua + ub) - 0.5 * ars * (rho[b] - rho[a]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) phi[1 + c] = 0.5 * (u[a][c] * va + u[b][c] * vb) - 0.5 * ars * (u[b][c] - u[a][c]);
+            phi[4] = 0.5 * (rk[a] * va + rk[b] * vb) - 0.5 * ars * (rk[b] - rk[a]);
+#pragma unroll
+            for (int c = 0; c < TR_NC; ++c) {
+                out[a][c] += phi[c];
+                out[b][c] -= phi[c];
+            }
+        }
+    }
+    // |T|/(d+1) grad(P^n), grad(P^n) = sum_a P_a n_a / det
+    constexpr double share = 1.0 / (dfact * double(DIM + 1));   // |T|/(d+1) = det * share
+    double gp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a <= DIM; ++a) t += pn[v[a]] * n[a][c];
+        gp[c] = t * share;   // det * share * (t / det)
+    }
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[a][1 + c] += gp[c];
+        double *dst = ta.flux + size_t(TR_NC) * (4 * size_t(k) + a);
+#pragma unroll
+        for (int c = 0; c < TR_NC; ++c) dst[c] = out[a][c];
+    }
+    ta.evol[k] = det / dfact;
+}
+
+// Face pass: W^{n+1}_f = W^n_f - dt / |C_f| (sum of its slots) + the gravity
+// source dt (rho g, g . W_u); |C_f| = sum over its elements of |T_k|/(d+1).
+template <int DIM>
+__global__ void __launch_bounds__(BLK) k_tr_face(int F, TransArgs ta, double *__restrict__ rho_out,
+                                                 double *__restrict__ wu_out, double *__restrict__ we_out)
+{
+    const int f = blockIdx.x * BLK + threadIdx.x;
+    if (f >= F) return;
+    const int2 sl = ta.fsl[f];
+    double acc[TR_NC];
+    const double *s0 = ta.flux + size_t(TR_NC) * size_t(sl.x);
+#pragma unroll
+    for (int c = 0; c < TR_NC; ++c) acc[c] = s0[c];
+    double vol = ta.evol[sl.x >> 2];
+    if (sl.y >= 0) {
+        const double *s1 = ta.flux + size_t(TR_NC) * size_t(sl.y);
+#pragma unroll
+        for (int c = 0; c < TR_NC; ++c) acc[c] += s1[c];
+        vol += ta.evol[sl.y >> 2];
+    }
+    const double q = ta.dt * double(DIM + 1) / vol;   // dt / |C_f|
+    const double r0 = ta.rho[f];
+    rho_out[f] = r0 - q * acc[0];
+    double gw = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double w0 = ta.wu[DIM * f + c];
+        gw += ta.g[c] * w0;
+        wu_out[DIM * f + c] = w0 - q * acc[1 + c] + ta.dt * r0 * ta.g[c];
+    }
+    we_out[f] = ta.we[f] - q * acc[4] + ta.dt * gw;
+}
+
 // ----------------------------------------------------------- batched solve
 // Many meshes advance their CG iterations together: one launch runs the
 // apply of iteration k for every (mesh, slot) pair, the next the update.  The
@@ -1427,6 +1557,8 @@ struct pm_handle {
         int2 *fel = nullptr;        // per face: internal elements
         int *enew2old = nullptr;    // caller element of each internal element
         uint8_t *ebnd = nullptr;    // boundary-face bits per internal element
+        int2 *fsl = nullptr;        // per face: element slots 4k + a (-1)
+        double *flux = nullptr;     // transport: 5 per element slot (allocated on first use)
         double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
@@ -1911,7 +2043,7 @@ void pressure_destroy(pm_handle *h)
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
-                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib};
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.flux};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -3095,13 +3227,21 @@ int ensure_faces(pm_handle *h)
             if (F.elems[2 * int64_t(f) + 1] < 0) ebnd[r] |= uint8_t(1u << a);
         }
     }
-    std::vector<int2> fel(F.n_faces);
+    std::vector<int2> fel(F.n_faces), fsl(F.n_faces);
     for (int64_t f = 0; f < F.n_faces; ++f) {
         const int32_t x = F.elems[2 * f], y = F.elems[2 * f + 1];
         fel[f] = make_int2(o2n[x], y < 0 ? -1 : o2n[y]);
+        auto slot = [&](int32_t o) {
+            const int64_t r = o2n[o];
+            for (int a = 0; a < nv; ++a)
+                if (efc[r * 4 + a] == f) return int32_t(4 * r + a);
+            return int32_t(-1);
+        };
+        fsl[f] = make_int2(slot(x), y < 0 ? -1 : slot(y));
     }
     TRY(dupload(h, &h->pj.efc, efc));
     TRY(dupload(h, &h->pj.fel, fel));
+    TRY(dupload(h, &h->pj.fsl, fsl));
     TRY(dupload(h, &h->pj.enew2old, h->elem_new2old));
     TRY(dupload(h, &h->pj.ebnd, ebnd));
     TRY(dalloc(h, &h->pj.e, size_t(10 * E)));
@@ -3214,6 +3354,54 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
     };
     if (h->dim == 2) return h->periodic ? run.template operator()<2, true>() : run.template operator()<2, false>();
     return h->periodic ? run.template operator()<3, true>() : run.template operator()<3, false>();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
+                       const double *p_dev, const double *gravity, double c_alpha, double dt, double *rho_out,
+                       double *wu_out, double *we_out, void *stream)
+{
+    if (!h || !rho_dev || !wu_dev || !we_dev || !p_dev || !rho_out || !wu_out || !we_out) return PM_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(c_alpha >= 0.0) || !std::isfinite(c_alpha)) return PM_EINVAL;
+    if (rho_out == rho_dev || wu_out == wu_dev || we_out == we_dev) return PM_EINVAL;
+    TRY(ensure_faces(h));
+    if (!h->pj.flux) TRY(dalloc(h, &h->pj.flux, size_t(TR_NC) * 4 * size_t(h->E)));
+    hipStream_t s = (hipStream_t)stream;
+    const int N = int(h->N), E = int(h->E), F = int(h->pj.F.n_faces);
+    TransArgs ta;
+    ta.efc = h->pj.efc;
+    ta.fsl = h->pj.fsl;
+    ta.rho = rho_dev;
+    ta.wu = wu_dev;
+    ta.we = we_dev;
+    ta.flux = h->pj.flux;
+    ta.evol = h->pj.e + 3 * int64_t(E);
+    ta.calpha = c_alpha;
+    ta.dt = dt;
+    for (int c = 0; c < 3; ++c) ta.g[c] = (gravity && c < h->dim) ? gravity[c] : 0.0;
+    for (int c = 0; c < h->dim; ++c)
+        if (!std::isfinite(ta.g[c])) return PM_EINVAL;
+    Mesh g = make_mesh<double>(h);
+    hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
+    if (h->dim == 2) {
+        if (h->periodic)
+            hipLaunchKernelGGL((k_tr_elem<2, true>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
+        else
+            hipLaunchKernelGGL((k_tr_elem<2, false>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
+        hipLaunchKernelGGL(k_tr_face<2>, dim3(grid_of(F)), dim3(BLK), 0, s, F, ta, rho_out, wu_out, we_out);
+    } else {
+        if (h->periodic)
+            hipLaunchKernelGGL((k_tr_elem<3, true>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
+        else
+            hipLaunchKernelGGL((k_tr_elem<3, false>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
+        hipLaunchKernelGGL(k_tr_face<3>, dim3(grid_of(F)), dim3(BLK), 0, s, F, ta, rho_out, wu_out, we_out);
+    }
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(s));
+    return PM_OK;
 }
 
 }  // extern "C"

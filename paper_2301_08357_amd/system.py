@@ -236,6 +236,28 @@ class PressureSystem:
             check(st, "pressure_projection")
         return p_out, wu_out, h_out, its, st
 
+    def transport(self, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, rho_out=None, wu_out=None, we_out=None,
+                  stream=None):
+        """One first-order transport step on the dual cells (see
+        pressure_transport in include/pressure_cg.h); returns (rho^{n+1},
+        double-tilde W_u, tilde W_E)."""
+        import torch
+        nf = ctypes.c_int64(0)
+        check(load().pressure_dual_count(self._h, ctypes.byref(nf), None), "pressure_dual_count")
+        F = nf.value
+        rho_out = torch.empty_like(rho) if rho_out is None else rho_out
+        wu_out = torch.empty_like(wu) if wu_out is None else wu_out
+        we_out = torch.empty_like(we) if we_out is None else we_out
+        g = None if gravity is None else _np(gravity, np.float64)
+        if g is not None and g.shape != (self.dim,):
+            raise ValueError("gravity must have dim entries")
+        check(load().pressure_transport(self._h, _dev_ptr(rho, F, "rho"), _dev_ptr(wu, F * self.dim, "wu"),
+                                        _dev_ptr(we, F, "we"), _dev_ptr(p, self.n_nodes, "p"), _ptr(g),
+                                        float(c_alpha), float(dt), _dev_ptr(rho_out, F, "rho_out"),
+                                        _dev_ptr(wu_out, F * self.dim, "wu_out"), _dev_ptr(we_out, F, "we_out"),
+                                        _stream_handle(stream)), "pressure_transport")
+        return rho_out, wu_out, we_out
+
     def info(self):
         v = (ctypes.c_int64 * 8)()
         check(load().pressure_info(self._h, v, 8), "pressure_info")

@@ -1,0 +1,111 @@
+"""Pins of the transport oracle (oracle/transport.py) against what the
+mathematics fixes:
+  * the dual cells are closed: the area vectors of a cell's dual faces plus
+    its primal boundary faces sum to zero; the sub-cell (B_k, face) has
+    volume |T_k|/(d+1) and the cells tile the domain;
+  * a uniform state is preserved (free stream), on periodic and walled
+    meshes with zero velocity;
+  * mass, momentum and energy are conserved on a periodic mesh (the
+    pressure force of a periodic P^n integrates to zero); gravity adds
+    dt g sum |C| rho to the momentum;
+  * with a uniform velocity the Rusanov mass flux is the upwind flux, so
+    under the CFL condition the density keeps its bounds;
+  * the pressure force of a linear pressure G.x is |C_i| G on every cell
+    (the face-mean rule of eq. pressterm is exact for P1 pressures).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import projection as op
+from oracle import transport as ot
+from synth import mesh as smesh
+from synth import projection as sproj
+
+
+def _state(m, seed=3):
+    fv, fe, ef = op.dual_faces(m.dim, m.elems)
+    inp = sproj.fields(m, fv, fe, seed=seed)
+    return inp, fv, fe, ef
+
+
+@pytest.mark.parametrize("dim,periodic", [(2, False), (2, True), (3, False), (3, True)])
+def test_dual_cells_are_closed_and_tile_the_domain(dim, periodic):
+    m = (smesh.periodic_mesh(dim, 5, tuple(range(dim)), jitter=0.2, seed=2) if periodic
+         else smesh.structured_mesh(dim, 4, jitter=0.2, seed=2))
+    fv, fe, ef = op.dual_faces(dim, m.elems)
+    pairs, eta, subvol, bnd_eta = ot.dual_geometry(m)
+    F = fv.shape[0]
+    clo = np.zeros((F, dim))
+    for q, (a, b) in enumerate(pairs):
+        np.add.at(clo, ef[:, a], eta[:, q])
+        np.add.at(clo, ef[:, b], -eta[:, q])
+    bnd = fe[:, 1] < 0
+    for a in range(dim + 1):
+        on = bnd[ef[:, a]]
+        np.add.at(clo, ef[on, a], bnd_eta[on, a])
+    assert np.abs(clo).max() < 1e-15
+    vol, _ = op.element_geometry(m)
+    assert np.abs(subvol - vol[:, None] / (dim + 1)).max() < 1e-16
+    assert abs(subvol.sum() - 1.0) < 1e-13
+
+
+def test_free_stream_and_rest():
+    for m in (smesh.periodic_mesh(3, 5, (0, 1, 2), jitter=0.2, seed=4), smesh.periodic_mesh(2, 7, (0, 1), jitter=0.2, seed=4)):
+        fv, fe, ef = op.dual_faces(m.dim, m.elems)
+        F = fv.shape[0]
+        w0 = np.array([0.3, -0.2, 0.1])[: m.dim]
+        out = ot.transport_step(m, np.full(F, 1.2), np.tile(w0, (F, 1)), np.full(F, 2.5), np.full(m.n_nodes, 0.7),
+                                dt=0.01, c_alpha=0.5)
+        assert np.abs(out["rho"] - 1.2).max() < 1e-14
+        assert np.abs(out["wu"] - w0).max() < 1e-14
+        assert np.abs(out["we"] - 2.5).max() < 1e-14
+    m = smesh.structured_mesh(3, 4, jitter=0.2, seed=4)
+    fv, fe, ef = op.dual_faces(3, m.elems)
+    F = fv.shape[0]
+    out = ot.transport_step(m, np.full(F, 1.2), np.zeros((F, 3)), np.full(F, 2.5), np.full(m.n_nodes, 0.7), dt=0.01)
+    assert np.abs(out["wu"]).max() < 1e-14 and np.abs(out["rho"] - 1.2).max() < 1e-15
+
+
+def test_conservation_on_a_periodic_mesh():
+    m = smesh.periodic_mesh(3, 6, (0, 1, 2), jitter=0.2, seed=5)
+    inp, fv, fe, ef = _state(m)
+    g = np.array([0.0, 0.0, -0.5])
+    out = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt=0.01, gravity=g, c_alpha=0.3)
+    vol = out["vol"]
+    assert abs(vol @ out["rho"] - vol @ inp["rho_f"]) < 1e-14 * (vol @ inp["rho_f"])
+    dmom = vol @ out["wu"] - vol @ inp["wu_f"]
+    assert np.abs(dmom - 0.01 * g * (vol @ inp["rho_f"])).max() < 1e-14
+    dE = vol @ out["we"] - vol @ inp["we_f"]
+    assert abs(dE - 0.01 * (vol @ (inp["wu_f"] @ g))) < 1e-14 * (vol @ inp["we_f"])
+
+
+def test_upwind_flux_keeps_density_bounds():
+    m = smesh.periodic_mesh(2, 16, (0, 1), jitter=0.2, seed=6)
+    fv, fe, ef = op.dual_faces(2, m.elems)
+    F = fv.shape[0]
+    c = m.coords[fv].mean(axis=1)
+    rho = 1.0 + 0.5 * (np.sin(2 * np.pi * c[:, 0]) > 0)                 # a density jump
+    u0 = np.array([0.7, 0.4])
+    h = 1.0 / 16
+    dt = 0.1 * h / np.abs(u0).sum()
+    out = ot.transport_step(m, rho, rho[:, None] * u0, np.ones(F), np.full(m.n_nodes, 0.7), dt=dt)
+    assert out["rho"].min() >= 1.0 - 1e-14 and out["rho"].max() <= 1.5 + 1e-14
+    # the flux is the upwind one: phi = (u.eta) rho_upwind
+    pairs, eta, _, _ = ot.dual_geometry(m)
+    e = eta[:, 0, :]
+    fa, fb = ef[:, 0], ef[:, 1]
+    phi = ot.rusanov_flux(rho[fa], rho[fa, None] * u0, rho[fb], rho[fb, None] * u0, e, 0.0)
+    un = e @ u0
+    up = np.where(un > 0, rho[fa], rho[fb])
+    assert np.abs(phi[:, 0] - un * up).max() < 1e-15
+
+
+def test_pressure_force_is_exact_for_linear_pressure():
+    G = np.array([0.3, -1.1, 0.7])
+    for dim in (2, 3):
+        m = smesh.structured_mesh(dim, 5, jitter=0.2, seed=7)
+        fv, fe, ef = op.dual_faces(dim, m.elems)
+        F = fv.shape[0]
+        out = ot.transport_step(m, np.ones(F), np.zeros((F, dim)), np.ones(F), m.coords @ G[:dim], dt=0.01)
+        assert np.abs(out["pforce"] - out["vol"][:, None] * G[:dim]).max() < 1e-14
