@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-2,
                     help="residual drop of the FP32 inner CG between FP64 corrections (mixed solve)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
-    ap.add_argument("--workload", default="cube64", choices=["cube64", "cube160", "cube160p", "projection160", "batch256", "serve", "copy"],
+    ap.add_argument("--workload", default="cube64", choices=["cube64", "cube160", "cube160p", "projection160", "transport160", "batch256", "serve", "copy"],
                     help="cube64 (default line) or one of the other synthetic workloads")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
@@ -74,6 +74,8 @@ def main():
         return bench_cube160(args)
     if args.workload == "projection160":
         return bench_projection(args)
+    if args.workload == "transport160":
+        return bench_transport(args)
     if args.workload == "batch256":
         return bench_batch(args)
     if args.workload == "serve":
@@ -300,6 +302,56 @@ def bench_projection(args):
                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                           "kernel": "operator apply (fused CG iteration)",
                           "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg * 1e3, 3)}})
+    s.close()
+
+
+def bench_transport(args):
+    """One first-order transport step per step (Rusanov flux on the dual
+    cells, P1 pressure force, gravity) on the jittered cube160 mesh with the
+    projection-stage input recipe.  Algorithmic bytes of a step: the dual-cell
+    state read and written (2 x 40 B per cell), the element-to-face and
+    face-to-slot maps (16 + 8 B), connectivity (16 B per element), vertex
+    coordinates and P^n (32 B per node)."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from synth import mesh as smesh
+    from synth import projection as sproj
+    from synth.rng import MASTER_SEED
+    n = 160
+    m = smesh.structured_mesh(3, n, jitter=0.2, seed=MASTER_SEED)
+    gamma, mach = 1.4, 0.1
+    dt = 0.5 * (1.0 / n) / mach
+    s = pm.PressureSystem(3, m.coords, m.elems, np.ones(m.n_elems), 1.0 / (gamma - 1.0), dt, m.dirichlet, m.lattice)
+    fv, fe, nb = s.dual_faces()
+    inp = sproj.fields(m, fv, fe, gamma=gamma, mach=mach)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    rho, wu, we, p = dev(inp["rho_f"]), dev(inp["wu_f"]), dev(inp["we_f"]), dev(inp["p"])
+    outs = (torch.empty_like(rho), torch.empty_like(wu), torch.empty_like(we))
+    g = np.array([0.0, 0.0, -1.0])
+
+    def step():
+        s.transport(rho, wu, we, p, dt, gravity=g, c_alpha=0.0, rho_out=outs[0], wu_out=outs[1], we_out=outs[2])
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    F, E, N = int(fv.shape[0]), int(m.n_elems), int(m.n_nodes)
+    alg = F * (80 + 8) + E * (16 + 16) + N * 32
+    ach = alg / el / 1e9
+    _common(args, round(F / el / 1e9, 4), "Gcell/s", round(el * 1e3, 3),
+            {"workload": "transport160: cube 160^3 x 6 tets (24,576,000 tets, %d dual cells), jitter 0.2h; one step = "
+                         "one first-order Rusanov transport step (Mach 0.1, dt = 0.5h/Mach, gravity)" % F,
+             "n_faces": F},
+            {"steps_per_s": round(1.0 / el, 3),
+             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                          "kernel": "transport step (element pass + face pass), wall time per step",
+                          "bytes_per_step": alg}})
     s.close()
 
 

@@ -379,7 +379,11 @@ int pressure_tune_tile(const pm_mesh *mesh, const double *elem_coef, double mass
  * (3D) or edge (2D) f of the primal mesh, made of the sub-elements T_kf
  * that join f to the barycenters of the one or two primal elements T_k that
  * share it; |T_kf| = |T_k|/(d+1).  Dual cells are numbered by the sorted
- * vertex tuples of their faces (caller node ids) in lexicographic order.
+ * tuples of their vertices' internal node indices (the Morton order that
+ * pressure_layout reports as node_new2old) in lexicographic order, so that
+ * dual-cell arrays are laid out in the order the kernels visit elements;
+ * pressure_dual_faces lists each cell's vertices and elements in the
+ * caller's numbering.
  * With merged periodic vertices the two images of a seam face are one
  * interior face, as Sec. 3.6 combines matching dual boundary cells.
  */
@@ -470,7 +474,9 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
  * pressure_dual_faces: rho_dev, we_dev, rho_out, we_out n_faces; wu_dev,
  * wu_out n_faces * dim; p_dev n_nodes (P^n at the vertices).  gravity is
  * host, dim doubles, or NULL for none; c_alpha >= 0; dt > 0.  Outputs must
- * not alias inputs.  The first call allocates 20 doubles per element.
+ * not alias inputs.  One pass per dual cell: each cell evaluates the fluxes
+ * across its 2d (2D: 4, 3D: 6) dual faces itself; the two cells of a dual
+ * face obtain exactly opposite fluxes, so the scheme stays conservative.
  * Synchronises the stream before returning. */
 int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
                        const double *p_dev, const double *gravity, double c_alpha, double dt, double *rho_out,

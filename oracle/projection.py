@@ -7,9 +7,11 @@ and its Picard iteration) and eq. momentum_dt_p, in plain NumPy/SciPy with
 the operator from ``oracle.assemble`` and the solve from ``oracle.cg``:
 
   dual_faces        the face-type dual cells (Sec. 2): one per face (3D) or
-                    edge (2D) of the primal mesh, numbered by sorted vertex
-                    tuples in lexicographic order; the one or two elements
-                    of each face; the face opposite each element vertex.
+                    edge (2D) of the primal mesh, numbered by the sorted
+                    tuples of their vertices' ranks (morton_rank: the
+                    library's node order) in lexicographic order; the one or
+                    two elements of each face; the face opposite each
+                    element vertex.
   element_geometry  volumes |T_k| and basis gradients grad(phi_a) from the
                     inverse Jacobian (on the unmerged mesh for a periodic
                     one).
@@ -33,17 +35,33 @@ import scipy.sparse as sp
 import oracle
 
 
-def dual_faces(dim, elems):
-    """(face_vertices [F, dim] sorted, face_elems [F, 2] ascending with -1,
-    elem_face [E, dim+1] face opposite local vertex a)."""
+def morton_rank(mesh):
+    """Rank of each node in the library's internal node order (the Morton
+    order of ``oracle.layout``, from the mesh's lattice if it has one)."""
+    lay = oracle.layout(mesh.dim, mesh.coords, mesh.elems, getattr(mesh, "lattice", None))
+    rank = np.empty(mesh.n_nodes, dtype=np.int64)
+    rank[lay["node_new2old"].astype(np.int64)] = np.arange(mesh.n_nodes)
+    return rank
+
+
+def dual_faces(dim, elems, rank=None):
+    """(face_vertices [F, dim] ascending node ids, face_elems [F, 2]
+    ascending with -1, elem_face [E, dim+1] face opposite local vertex a).
+    Faces are numbered by the sorted tuples of their vertices' ranks
+    (``rank``, default the node ids themselves) in lexicographic order."""
     elems = np.asarray(elems, dtype=np.int64)
     E, nv = elems.shape
+    r = elems if rank is None else np.asarray(rank, dtype=np.int64)[elems]
     recs = []
     for a in range(nv):
-        others = np.delete(elems, a, axis=1)
+        others = np.delete(r, a, axis=1)
         recs.append(np.sort(others, axis=1))
     tup = np.stack(recs, axis=1).reshape(E * nv, dim)          # record e*nv + a
     uniq, inv = np.unique(tup, axis=0, return_inverse=True)
+    if rank is not None:
+        old = np.empty(len(rank), dtype=np.int64)
+        old[np.asarray(rank, dtype=np.int64)] = np.arange(len(rank))
+        uniq = np.sort(old[uniq], axis=1)
     inv = inv.ravel()
     F = uniq.shape[0]
     count = np.bincount(inv, minlength=F)
@@ -125,12 +143,12 @@ def _enthalpy(g1, p_nodes, rho_f, face_vertices, elem_face, dim):
 
 
 def projection_stage(mesh, rho_f, we_f, wu_f, p, gamma, dt, pb=None, bflux=None, dp0=None, n_picard=2,
-                     rtol=1e-10, max_iter=20000, lumped=False):
+                     rtol=1e-10, max_iter=20000, lumped=False, faces=None):
     """Returns a dict: p_new, wu_new [F, d], H (per element, after the last
     update), iters, and per Picard iteration the H, (rho K), b, dP and
     element momenta it used or produced (for the identity checks)."""
     dim = mesh.dim
-    fv, fe, ef = dual_faces(dim, mesh.elems)
+    fv, fe, ef = dual_faces(dim, mesh.elems) if faces is None else faces
     vol, grad = element_geometry(mesh)
     el = np.asarray(mesh.elems, dtype=np.int64)
     N = mesh.n_nodes

@@ -89,10 +89,11 @@ def rusanov_flux(rho_i, wu_i, rho_j, wu_j, eta, c_alpha):
     return np.concatenate([mass[..., None], mom, en[..., None]], axis=-1)
 
 
-def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0):
-    """Returns dict(rho, wu, we, vol, flux_sum, pforce)."""
+def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None):
+    """Returns dict(rho, wu, we, vol, flux_sum, pforce); faces as
+    ``projection.dual_faces`` returns them (default: by node ids)."""
     dim = mesh.dim
-    fv, fe, ef = op.dual_faces(dim, mesh.elems)
+    fv, fe, ef = op.dual_faces(dim, mesh.elems) if faces is None else faces
     F = fv.shape[0]
     pairs, eta, subvol, bnd_eta = dual_geometry(mesh)
     rho = np.asarray(rho, dtype=np.float64)

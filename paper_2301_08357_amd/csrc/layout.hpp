@@ -60,16 +60,16 @@ constexpr int TILES_TOO_WIDE = 100;
 int build_tiles(const Layout &L, int tile_nodes, Tiles *T);
 
 // Dual cells of the face-type staggered mesh: one per face (3D) or edge
-// (2D) of the primal mesh.  Faces are numbered by their sorted vertex
-// tuples (caller node ids) in lexicographic order.  A face belongs to one
-// element (boundary) or two (interior; with merged periodic vertices the
-// two images of a seam face are one interior face).
+// (2D) of the primal mesh.  Faces are numbered by the sorted tuples of the
+// node ids of the mesh passed in, in lexicographic order.  A face belongs to
+// one element (boundary) or two (interior; with merged periodic vertices
+// the two images of a seam face are one interior face).
 struct Faces {
     int dim = 0;
     int64_t n_faces = 0, n_boundary = 0;
-    std::vector<int32_t> vertices;    // n_faces * dim, ascending caller node ids
-    std::vector<int32_t> elems;       // n_faces * 2 caller element ids, ascending; -1 = none
-    std::vector<int32_t> elem_face;   // n_elems * (dim+1): face opposite caller-local vertex a
+    std::vector<int32_t> vertices;    // n_faces * dim, ascending node ids
+    std::vector<int32_t> elems;       // n_faces * 2 element ids, ascending; -1 = none
+    std::vector<int32_t> elem_face;   // n_elems * (dim+1): face opposite local vertex a
 };
 
 // Returns PM_EINVAL for a face shared by more than two elements.

@@ -1186,124 +1186,106 @@ __global__ void __launch_bounds__(BLK) k_scatter_elem(int E, const int *__restri
 // primal edge (vertex) they share; its area vector from cell a to cell b is
 // eta_ab = |T| d/(d+1) (grad phi_a - grad phi_b) = d/((d+1) d!) (n_a - n_b).
 
-constexpr int TR_NC = 5;   // rho, W_u (3), W_E per face slot
-
 struct TransArgs {
     const int *efc;               // 4 per element: face opposite internal-local vertex a
     const int2 *fsl;              // per face: element slots 4k + a of its one or two elements (-1)
-    const double *rho, *wu, *we;  // per face (caller numbering); wu: dim per face
-    double *flux;                 // TR_NC per element slot: flux sums and pressure force
-    double *evol;                 // per element: |T_k|
+    const double *rho, *wu, *we;  // per face; wu: dim per face
     double calpha;                // artificial viscosity coefficient c_alpha
     double dt;
     double g[3];                  // gravity
 };
 
-// Element pass: for every face pair (a, b), a < b, the Rusanov flux from a
-// to b is added to slot a and subtracted from slot b (pairs in fixed
-// order); every slot also takes |T|/(d+1) grad(P^n) on its momentum.
-template <int DIM, bool PER>
-__global__ void __launch_bounds__(BLK) k_tr_elem(Mesh g, TransArgs ta, const double *__restrict__ pn)
+// Rusanov flux from the cell with state (ri, ui) to the cell with (rj, uj)
+// across eta: acc += phi.  Swapping the cells and negating eta gives -phi
+// bit for bit (each step is symmetric or changes sign exactly), so the two
+// cells of a dual face see opposite fluxes.
+__device__ __forceinline__ void rusanov_add(double ri, const double ui[3], double rj, const double uj[3],
+                                            const double eta[3], double calpha, double acc[5])
 {
-    const int k = blockIdx.x * BLK + threadIdx.x;
-    if (k >= g.E) return;
-    int v[4];
-    double ed[3][3], n[4][3];
-    elem_corners<DIM, PER>(g, k, v, ed);
-    const double det = elem_normals<DIM>(ed, n);
-    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
-    constexpr double ceta = double(DIM) / (double(DIM + 1) * dfact);
-    double rho[4], u[4][3], rk[4], out[4][TR_NC];
-#pragma unroll
-    for (int a = 0; a <= DIM; ++a) {
-        const int f = ta.efc[4 * k + a];
-        rho[a] = ta.rho[f];
-        double w2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            u[a][c] = (c < DIM) ? ta.wu[DIM * f + c] : 0.0;
-            w2 += u[a][c] * u[a][c];
-        }
-        rk[a] = w2 / (2.0 * rho[a]);
-#pragma unroll
-        for (int c = 0; c < TR_NC; ++c) out[a][c] = 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a <= DIM; ++a) {
-#pragma unroll
-        for (int b = a + 1; b <= DIM; ++b) {
-            double eta[3], ua = 0.0, ub = 0.0, en = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                eta[c] = ceta * (n[a][c] - n[b][c]);
-                ua += u[a][c] * eta[c];   // W_u . eta
-                ub += u[b][c] * eta[c];
-                en += eta[c] * eta[c];
-            }
-            const double va = ua / rho[a], vb = ub / rho[b];   // U . eta
-            const double ars = fmax(fabs(va), fabs(vb)) + ta.calpha * sqrt(en);
-            double phi[TR_NC];
-            phi[0] = 0.5 * (ua + ub) - 0.5 * ars * (rho[b] - rho[a]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) phi[1 + c] = 0.5 * (u[a][c] * va + u[b][c] * vb) - 0.5 * ars * (u[b][c] - u[a][c]);
-            phi[4] = 0.5 * (rk[a] * va + rk[b] * vb) - 0.5 * ars * (rk[b] - rk[a]);
-#pragma unroll
-            for (int c = 0; c < TR_NC; ++c) {
-                out[a][c] += phi[c];
-                out[b][c] -= phi[c];
-            }
-        }
-    }
-    // |T|/(d+1) grad(P^n), grad(P^n) = sum_a P_a n_a / det
-    constexpr double share = 1.0 / (dfact * double(DIM + 1));   // |T|/(d+1) = det * share
-    double gp[3];
+    double a = 0.0, b = 0.0, en = 0.0, wi = 0.0, wj = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double t = 0.0;
-#pragma unroll
-        for (int a = 0; a <= DIM; ++a) t += pn[v[a]] * n[a][c];
-        gp[c] = t * share;   // det * share * (t / det)
+        a += ui[c] * eta[c];
+        b += uj[c] * eta[c];
+        en += eta[c] * eta[c];
+        wi += ui[c] * ui[c];
+        wj += uj[c] * uj[c];
     }
+    const double vi = a / ri, vj = b / rj;           // U . eta
+    const double ki = wi / (2.0 * ri), kj = wj / (2.0 * rj);   // rho K
+    const double ars = fmax(fabs(vi), fabs(vj)) + calpha * sqrt(en);
+    acc[0] += 0.5 * (a + b) - 0.5 * ars * (rj - ri);
 #pragma unroll
-    for (int a = 0; a <= DIM; ++a) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[a][1 + c] += gp[c];
-        double *dst = ta.flux + size_t(TR_NC) * (4 * size_t(k) + a);
-#pragma unroll
-        for (int c = 0; c < TR_NC; ++c) dst[c] = out[a][c];
-    }
-    ta.evol[k] = det / dfact;
+    for (int c = 0; c < 3; ++c) acc[1 + c] += 0.5 * (ui[c] * vi + uj[c] * vj) - 0.5 * ars * (uj[c] - ui[c]);
+    acc[4] += 0.5 * (ki * vi + kj * vj) - 0.5 * ars * (kj - ki);
 }
 
-// Face pass: W^{n+1}_f = W^n_f - dt / |C_f| (sum of its slots) + the gravity
-// source dt (rho g, g . W_u); |C_f| = sum over its elements of |T_k|/(d+1).
-template <int DIM>
-__global__ void __launch_bounds__(BLK) k_tr_face(int F, TransArgs ta, double *__restrict__ rho_out,
-                                                 double *__restrict__ wu_out, double *__restrict__ we_out)
+// One pass per dual cell f, two lanes per cell (adjacent lanes 2f and
+// 2f+1 of a wave): lane `side` takes the cell's element in that slot, the
+// fluxes to the element's other d faces (ascending local index) and its
+// share |T|/(d+1) grad(P^n) of the pressure force; the even lane adds the
+// odd lane's sums to its own (side 0 + side 1) and writes the update with
+// the gravity sources.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const double *__restrict__ pn, int F,
+                                                 double *__restrict__ rho_out, double *__restrict__ wu_out,
+                                                 double *__restrict__ we_out)
 {
-    const int f = blockIdx.x * BLK + threadIdx.x;
-    if (f >= F) return;
-    const int2 sl = ta.fsl[f];
-    double acc[TR_NC];
-    const double *s0 = ta.flux + size_t(TR_NC) * size_t(sl.x);
+    const int t = blockIdx.x * BLK + threadIdx.x;
+    const int f = t >> 1, side = t & 1;
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    constexpr double ceta = double(DIM) / (double(DIM + 1) * dfact);
+    constexpr double share = 1.0 / (dfact * double(DIM + 1));
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double vol = 0.0, r0 = 1.0, u0[3] = {0.0, 0.0, 0.0};
+    const bool live = f < F;
+    if (live) {
+        r0 = ta.rho[f];
 #pragma unroll
-    for (int c = 0; c < TR_NC; ++c) acc[c] = s0[c];
-    double vol = ta.evol[sl.x >> 2];
-    if (sl.y >= 0) {
-        const double *s1 = ta.flux + size_t(TR_NC) * size_t(sl.y);
+        for (int c = 0; c < DIM; ++c) u0[c] = ta.wu[DIM * f + c];
+        const int2 sl = ta.fsl[f];
+        const int slot = side ? sl.y : sl.x;
+        if (slot >= 0) {
+            const int k = slot >> 2, a = slot & 3;
+            int v[4];
+            double ed[3][3], n[4][3];
+            elem_corners<DIM, PER>(g, k, v, ed);
+            const double det = elem_normals<DIM>(ed, n);
+            vol = det * share;
 #pragma unroll
-        for (int c = 0; c < TR_NC; ++c) acc[c] += s1[c];
-        vol += ta.evol[sl.y >> 2];
+            for (int b = 0; b <= DIM; ++b) {
+                if (b == a) continue;
+                const int fb = ta.efc[4 * k + b];
+                const double rb = ta.rho[fb];
+                double ub[3], eta[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ub[c] = (c < DIM) ? ta.wu[DIM * fb + c] : 0.0;
+                    eta[c] = ceta * (n[a][c] - n[b][c]);
+                }
+                rusanov_add(r0, u0, rb, ub, eta, ta.calpha, acc);
+            }
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                double tp = 0.0;
+#pragma unroll
+                for (int b = 0; b <= DIM; ++b) tp += pn[v[b]] * n[b][c];
+                acc[1 + c] += tp * share;
+            }
+        }
     }
-    const double q = ta.dt * double(DIM + 1) / vol;   // dt / |C_f|
-    const double r0 = ta.rho[f];
+    // the pair's lanes are 2f and 2f+1 of the same wave (BLK is a multiple of 64)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] += __shfl_xor(acc[c], 1);
+    vol += __shfl_xor(vol, 1);
+    if (!live || side) return;
+    const double q = ta.dt / vol;   // dt / |C_f|
     rho_out[f] = r0 - q * acc[0];
     double gw = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        const double w0 = ta.wu[DIM * f + c];
-        gw += ta.g[c] * w0;
-        wu_out[DIM * f + c] = w0 - q * acc[1 + c] + ta.dt * r0 * ta.g[c];
+        gw += ta.g[c] * u0[c];
+        wu_out[DIM * f + c] = u0[c] - q * acc[1 + c] + ta.dt * r0 * ta.g[c];
     }
     we_out[f] = ta.we[f] - q * acc[4] + ta.dt * gw;
 }
@@ -1552,13 +1534,13 @@ struct pm_handle {
     // projection stage: dual cells (built at the first use) and buffers
     struct Proj {
         bool built = false;
-        pm::Faces F;                // host, caller numbering
+        pm::Faces F;                // counts (the lists are dropped after the upload)
+        std::vector<int32_t> fv_caller, fe_caller;   // per face: caller node ids, caller elements
         int *efc = nullptr;         // 4 per internal element: face opposite internal-local vertex a
         int2 *fel = nullptr;        // per face: internal elements
         int *enew2old = nullptr;    // caller element of each internal element
         uint8_t *ebnd = nullptr;    // boundary-face bits per internal element
         int2 *fsl = nullptr;        // per face: element slots 4k + a (-1)
-        double *flux = nullptr;     // transport: 5 per element slot (allocated on first use)
         double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
@@ -2043,7 +2025,7 @@ void pressure_destroy(pm_handle *h)
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
-                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.flux};
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -3191,13 +3173,14 @@ int pressure_batch_next_index(pm_batch *b, int32_t *k)
 
 namespace {
 
-// Dual cells of the handle's mesh, numbered from the caller's elements
-// (recovered from the oriented internal connectivity: a face is a vertex
-// set, so orientation does not change it).
+// Dual cells of the handle's mesh, numbered by the sorted tuples of their
+// internal (Morton) vertex ids, so that dual-cell arrays follow the order
+// in which the kernels visit elements; the caller-facing lists give node
+// and element ids in the caller's numbering.
 int ensure_faces(pm_handle *h)
 {
     if (h->pj.built) return PM_OK;
-    const int nv = h->dim + 1;
+    const int nv = h->dim + 1, dim = h->dim;
     const int64_t N = h->N, E = h->E;
     std::vector<int4> conn(E);
     std::vector<int32_t> n2o(N);
@@ -3205,9 +3188,8 @@ int ensure_faces(pm_handle *h)
     HIPCK(hipMemcpy(n2o.data(), h->new2old, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
     std::vector<int32_t> el(E * nv);
     for (int64_t r = 0; r < E; ++r) {
-        const int64_t o = h->elem_new2old[r];
         const int32_t cv[4] = {conn[r].x, conn[r].y, conn[r].z, conn[r].w};
-        for (int a = 0; a < nv; ++a) el[o * nv + a] = n2o[cv[a] & 0x7fffffff];
+        for (int a = 0; a < nv; ++a) el[r * nv + a] = cv[a] & 0x7fffffff;
     }
     pm_mesh m{};
     m.dim = h->dim;
@@ -3215,29 +3197,35 @@ int ensure_faces(pm_handle *h)
     m.n_elems = E;
     m.elems = el.data();
     pm::Faces &F = h->pj.F;
-    TRY(pm::build_faces(&m, &F));
-    std::vector<int32_t> efc(E * 4, -1), o2n(E);
+    TRY(pm::build_faces(&m, &F));   // internal vertex and element ids
+    const int64_t nf = F.n_faces;
+    std::vector<int32_t> efc(E * 4, -1);
     std::vector<uint8_t> ebnd(E, 0);
-    for (int64_t r = 0; r < E; ++r) {
-        const int64_t o = h->elem_new2old[r];
-        o2n[o] = int32_t(r);
+    for (int64_t r = 0; r < E; ++r)
         for (int a = 0; a < nv; ++a) {
-            const int32_t f = F.elem_face[o * nv + a];
+            const int32_t f = F.elem_face[r * nv + a];
             efc[r * 4 + a] = f;
             if (F.elems[2 * int64_t(f) + 1] < 0) ebnd[r] |= uint8_t(1u << a);
         }
-    }
-    std::vector<int2> fel(F.n_faces), fsl(F.n_faces);
-    for (int64_t f = 0; f < F.n_faces; ++f) {
+    std::vector<int2> fel(nf), fsl(nf);
+    h->pj.fv_caller.assign(nf * dim, 0);
+    h->pj.fe_caller.assign(nf * 2, -1);
+    for (int64_t f = 0; f < nf; ++f) {
         const int32_t x = F.elems[2 * f], y = F.elems[2 * f + 1];
-        fel[f] = make_int2(o2n[x], y < 0 ? -1 : o2n[y]);
-        auto slot = [&](int32_t o) {
-            const int64_t r = o2n[o];
+        fel[f] = make_int2(x, y);
+        auto slot = [&](int32_t r) {
             for (int a = 0; a < nv; ++a)
-                if (efc[r * 4 + a] == f) return int32_t(4 * r + a);
+                if (efc[int64_t(r) * 4 + a] == f) return int32_t(4 * r + a);
             return int32_t(-1);
         };
         fsl[f] = make_int2(slot(x), y < 0 ? -1 : slot(y));
+        int32_t *vc = h->pj.fv_caller.data() + f * dim;
+        for (int c = 0; c < dim; ++c) vc[c] = n2o[F.vertices[f * dim + c]];
+        std::sort(vc, vc + dim);
+        int32_t ex = h->elem_new2old[x], ey = y < 0 ? -1 : h->elem_new2old[y];
+        if (ey >= 0 && ey < ex) std::swap(ex, ey);
+        h->pj.fe_caller[2 * f] = ex;
+        h->pj.fe_caller[2 * f + 1] = ey;
     }
     TRY(dupload(h, &h->pj.efc, efc));
     TRY(dupload(h, &h->pj.fel, fel));
@@ -3247,6 +3235,10 @@ int ensure_faces(pm_handle *h)
     TRY(dalloc(h, &h->pj.e, size_t(10 * E)));
     TRY(dalloc(h, &h->pj.contrib, size_t(4 * E)));
     for (double **v : {&h->pj.pn, &h->pj.gd, &h->pj.b, &h->pj.dp, &h->pj.dpi}) TRY(dalloc(h, v, size_t(N)));
+    // the host face lists in internal ids are not needed any more
+    std::vector<int32_t>().swap(F.vertices);
+    std::vector<int32_t>().swap(F.elems);
+    std::vector<int32_t>().swap(F.elem_face);
     h->pj.built = true;
     return PM_OK;
 }
@@ -3310,9 +3302,8 @@ int pressure_dual_faces(pm_handle *h, int32_t *face_vertices, int32_t *face_elem
 {
     if (!h) return PM_EINVAL;
     TRY(ensure_faces(h));
-    const pm::Faces &F = h->pj.F;
-    if (face_vertices) std::copy(F.vertices.begin(), F.vertices.end(), face_vertices);
-    if (face_elems) std::copy(F.elems.begin(), F.elems.end(), face_elems);
+    if (face_vertices) std::copy(h->pj.fv_caller.begin(), h->pj.fv_caller.end(), face_vertices);
+    if (face_elems) std::copy(h->pj.fe_caller.begin(), h->pj.fe_caller.end(), face_elems);
     return PM_OK;
 }
 
@@ -3368,17 +3359,14 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     if (!(dt > 0.0) || !std::isfinite(dt) || !(c_alpha >= 0.0) || !std::isfinite(c_alpha)) return PM_EINVAL;
     if (rho_out == rho_dev || wu_out == wu_dev || we_out == we_dev) return PM_EINVAL;
     TRY(ensure_faces(h));
-    if (!h->pj.flux) TRY(dalloc(h, &h->pj.flux, size_t(TR_NC) * 4 * size_t(h->E)));
     hipStream_t s = (hipStream_t)stream;
-    const int N = int(h->N), E = int(h->E), F = int(h->pj.F.n_faces);
+    const int N = int(h->N), F = int(h->pj.F.n_faces);
     TransArgs ta;
     ta.efc = h->pj.efc;
     ta.fsl = h->pj.fsl;
     ta.rho = rho_dev;
     ta.wu = wu_dev;
     ta.we = we_dev;
-    ta.flux = h->pj.flux;
-    ta.evol = h->pj.e + 3 * int64_t(E);
     ta.calpha = c_alpha;
     ta.dt = dt;
     for (int c = 0; c < 3; ++c) ta.g[c] = (gravity && c < h->dim) ? gravity[c] : 0.0;
@@ -3386,19 +3374,15 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
         if (!std::isfinite(ta.g[c])) return PM_EINVAL;
     Mesh g = make_mesh<double>(h);
     hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
-    if (h->dim == 2) {
-        if (h->periodic)
-            hipLaunchKernelGGL((k_tr_elem<2, true>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
-        else
-            hipLaunchKernelGGL((k_tr_elem<2, false>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
-        hipLaunchKernelGGL(k_tr_face<2>, dim3(grid_of(F)), dim3(BLK), 0, s, F, ta, rho_out, wu_out, we_out);
-    } else {
-        if (h->periodic)
-            hipLaunchKernelGGL((k_tr_elem<3, true>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
-        else
-            hipLaunchKernelGGL((k_tr_elem<3, false>), dim3(grid_of(E)), dim3(BLK), 0, s, g, ta, h->pj.pn);
-        hipLaunchKernelGGL(k_tr_face<3>, dim3(grid_of(F)), dim3(BLK), 0, s, F, ta, rho_out, wu_out, we_out);
-    }
+    const dim3 grid(grid_of(2 * int64_t(F)));
+    if (h->dim == 2 && h->periodic)
+        hipLaunchKernelGGL((k_tr_cell<2, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
+    else if (h->dim == 2)
+        hipLaunchKernelGGL((k_tr_cell<2, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
+    else if (h->periodic)
+        hipLaunchKernelGGL((k_tr_cell<3, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
+    else
+        hipLaunchKernelGGL((k_tr_cell<3, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(s));
     return PM_OK;

@@ -62,7 +62,7 @@ def test_dual_faces_match_oracle(case):
     m, lumped = _mesh(case)
     s = _system(m, lumped)
     fv, fe, nb = s.dual_faces()
-    ofv, ofe, oef = op.dual_faces(m.dim, m.elems)
+    ofv, ofe, oef = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
     assert np.array_equal(fv, ofv) and np.array_equal(fe, ofe)
     assert nb == int((ofe[:, 1] < 0).sum())
     s.close()
@@ -73,12 +73,12 @@ def test_projection_stage_matches_oracle(case):
     m, lumped = _mesh(case)
     print("case", case, m.n_nodes, flush=True)
     gamma, dt = 1.4, 0.03
-    fv, fe, ef = op.dual_faces(m.dim, m.elems)
+    fv, fe, ef = faces = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
     inp = sproj.fields(m, fv, fe, seed=11)
     pb = inp["pb"] if m.dirichlet.any() else None
     bflux = inp["bflux"] if (fe[:, 1] < 0).any() else None
     ref = op.projection_stage(m, inp["rho_f"], inp["we_f"], inp["wu_f"], inp["p"], gamma, dt, pb=pb, bflux=bflux,
-                              n_picard=2, rtol=1e-12, lumped=lumped)
+                              n_picard=2, rtol=1e-12, lumped=lumped, faces=faces)
     s = _system(m, lumped, gamma, dt)
     p_new, wu_new, h_new, its, st = s.projection(
         _dev(inp["rho_f"]), _dev(inp["we_f"]), _dev(inp["wu_f"]), _dev(inp["p"]), gamma, dt,

@@ -63,11 +63,12 @@ def _close(a, b, a0):
 def test_transport_matches_oracle(case):
     m = _mesh(case)
     print("case", case, flush=True)
-    fv, fe, ef = op.dual_faces(m.dim, m.elems)
+    fv, fe, ef = faces = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
     inp = sproj.fields(m, fv, fe, seed=13)
     g = np.array([0.1, -0.8, 0.3])[: m.dim]
     dt = 0.2 / (m.n ** 1)
-    ref = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, gravity=g, c_alpha=0.4)
+    ref = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, gravity=g, c_alpha=0.4,
+                           faces=faces)
     s = _system(m)
     rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
                               gravity=g, c_alpha=0.4)
@@ -84,11 +85,11 @@ def test_transport_matches_oracle(case):
 def test_one_time_step_transport_then_projection():
     m = smesh.periodic_mesh(2, 16, (0,), jitter=0.2, seed=9)
     gamma, dt = 1.4, 0.01
-    fv, fe, ef = op.dual_faces(2, m.elems)
+    fv, fe, ef = faces = op.dual_faces(2, m.elems, op.morton_rank(m))
     inp = sproj.fields(m, fv, fe, seed=21)
-    tr = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt)
+    tr = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, faces=faces)
     ref = op.projection_stage(m, tr["rho"], tr["we"], tr["wu"], inp["p"], gamma, dt, pb=inp["pb"],
-                              n_picard=2, rtol=1e-12)
+                              n_picard=2, rtol=1e-12, faces=faces)
     s = _system(m, gamma, dt)
     rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt)
     p_new, wu_new, h_new, its, st = s.projection(rho, we, wu, _dev(inp["p"]), gamma, dt, pb=_dev(inp["pb"]),
