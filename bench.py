@@ -54,7 +54,8 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-2,
                     help="residual drop of the FP32 inner CG between FP64 corrections (mixed solve)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
-    ap.add_argument("--workload", default="cube64", choices=["cube64", "cube160", "cube160p", "projection160", "transport160", "batch256", "serve", "copy"],
+    ap.add_argument("--workload", default="cube64", choices=["cube64", "cube160", "cube160p", "projection160", "transport160", "timestep160", "batch256",
+                             "serve", "copy"],
                     help="cube64 (default line) or one of the other synthetic workloads")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
@@ -76,6 +77,8 @@ def main():
         return bench_projection(args)
     if args.workload == "transport160":
         return bench_transport(args)
+    if args.workload == "timestep160":
+        return bench_timestep(args)
     if args.workload == "batch256":
         return bench_batch(args)
     if args.workload == "serve":
@@ -352,6 +355,73 @@ def bench_transport(args):
                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                           "kernel": "transport step (element pass + face pass), wall time per step",
                           "bytes_per_step": alg}})
+    s.close()
+
+
+def bench_timestep(args):
+    """Whole time steps on the jittered cube160 mesh: first-order transport
+    (Sec. 3.2), the projection stage with N_Pic = 2 (Sec. 3.3-3.4) and the
+    post-projection energy update (Sec. 3.5); each step starts from the
+    previous step's state (P, W_u, W_E, rho), Mach 0.1, dt = 0.5h/Mach,
+    Dirichlet boundary pressure held at P^n, walls.  The time step follows
+    the paper's rule dt = CFL r_min / |U|_max with CFL = 1/d, |U|_max from
+    the initial state and r_min = 0.17 h, the smallest incircle-diameter
+    estimate 2 d |C| / |dC| of the jittered Kuhn dual cells (measured on a
+    10^3 mesh: 0.177 h)."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from synth import mesh as smesh
+    from synth import projection as sproj
+    from synth.rng import MASTER_SEED
+    n = 160
+    m = smesh.structured_mesh(3, n, jitter=0.2, seed=MASTER_SEED)
+    gamma, mach = 1.4, 0.1
+    s = pm.PressureSystem(3, m.coords, m.elems, np.ones(m.n_elems), 1.0 / (gamma - 1.0), 1.0, m.dirichlet, m.lattice)
+    fv, fe, nb = s.dual_faces()
+    inp = sproj.fields(m, fv, fe, gamma=gamma, mach=mach)
+    umax = float(np.max(np.linalg.norm(inp["wu_f"], axis=1) / inp["rho_f"]))
+    dt = (1.0 / 3.0) * 0.17 * (1.0 / n) / umax
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    st = {"rho": dev(inp["rho_f"]), "wu": dev(inp["wu_f"]), "we": dev(inp["we_f"]), "p": dev(inp["p"])}
+    its_all = []
+
+    def step(st):
+        # the first Picard solve starts from the previous step's correction
+        rho, wu, we = s.transport(st["rho"], st["wu"], st["we"], st["p"], dt)
+        p_new, wu_new, _, its, code = s.projection(rho, we, wu, st["p"], gamma, dt, dp0=st.get("dp"), n_picard=2,
+                                                   rtol=args.rtol)
+        if code != 0:
+            raise RuntimeError("projection status %d" % code)
+        its_all.append([int(i) for i in its])
+        we_new = s.post_projection(rho, we, wu_new, p_new, gamma, dt)
+        return {"rho": rho, "wu": wu_new, "we": we_new, "p": p_new, "dp": p_new - st["p"]}
+
+    for _ in range(args.warmup):
+        st = step(st)
+    s.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step(st)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    nl, ms = s.timing_read()
+    info = s.info()
+    avg = ms / max(nl, 1)
+    achieved = info["apply_bytes"] / (avg * 1e-3) / 1e9
+    timed = its_all[args.warmup:]
+    total_it = sum(sum(x) for x in timed)
+    _common(args, round(info["n_free"] * total_it / (el * args.steps) / 1e9, 4), "GDOF*iter/s", round(el * 1e3, 3),
+            {"workload": "timestep160: cube 160^3 x 6 tets (24,576,000 tets, 4,173,281 nodes, %d dual cells), jitter "
+                         "0.2h; one step = transport + projection (N_Pic = 2, FP64 CG to rtol %g, warm start from "
+                         "the previous step's correction) + post-projection, Mach 0.1, dt = (1/d) 0.17h / |U|_max"
+                         % (fv.shape[0], args.rtol),
+             "dt": dt, "cg_iterations": timed},
+            {"time_steps_per_s": round(1.0 / el, 3),
+             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                          "kernel": "operator apply (fused CG iteration)",
+                          "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg * 1e3, 3)}})
     s.close()
 
 

@@ -451,6 +451,22 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
                         int32_t max_iter, double *p_out, double *wu_out, double *h_out, int32_t *iters,
                         void *stream);
 
+/* Post-projection (Sec. 3.5, eq. WEupdatek and the weighted average back to
+ * the dual cells): the total energy per primal element
+ *   W_E,k = W_E,k~ - dt/|T_k| sum_{faces l of T_k} H_l W_u,l^{n+1} . A_kl,
+ * W_E,k~ the mean of tilde W_E over the faces of T_k (as in the
+ * pre-projection), A_kl the outward area vector of face l, W_u,l^{n+1} the
+ * momentum of the dual cell of l and H_l = gamma/(gamma-1) P_l / rho_l with
+ * P_l the mean of the face's vertex pressures P^{n+1}; then
+ * W_E,f^{n+1} = sum_k |T_kf| W_E,k / |C_f|.  Interior faces cancel between
+ * their two elements, so the total energy changes only through the primal
+ * boundary.  Arrays as in pressure_projection (caller face numbering):
+ * rho_dev rho^{n+1}, we_dev tilde W_E, wu_dev W_u^{n+1} (n_faces * dim), p_dev
+ * P^{n+1} at the vertices; we_out (n_faces) W_E^{n+1}, not aliasing we_dev.
+ * Synchronises the stream before returning. */
+int pressure_post_projection(pm_handle *h, const double *rho_dev, const double *we_dev, const double *wu_dev,
+                             const double *p_dev, double gamma, double dt, double *we_out, void *stream);
+
 /* One explicit transport step on the dual cells, first order (Sec. 3.2,
  * eq. discrf_mass, discrf_momentum and discrf_energy without the viscous and
  * heat-flux terms):

@@ -218,3 +218,44 @@ def projection_stage(mesh, rho_f, we_f, wu_f, p, gamma, dt, pb=None, bflux=None,
     out["we_k"] = we_k
     out["rho_k"] = rho_k
     return out
+
+
+def post_projection(mesh, rho_f, we_f, wu_new, p_new, gamma, dt, faces=None):
+    """Sec. 3.5: W_E per primal element from the intermediate energy (mean
+    over the element's faces) minus dt/|T_k| times the enthalpy flux through
+    its faces, each face l carrying the momentum of its dual cell and
+    H_l = gamma/(gamma-1) P_l / rho_l (P_l the mean of the face's vertex
+    pressures); the outward area vectors come from the face vertices (on the
+    unmerged mesh for a periodic one); then the |T_kf|-weighted mean back to
+    the dual cells.  Returns (we_new [F], we_elem [E], vol [E])."""
+    dim = mesh.dim
+    fv, fe, ef = dual_faces(dim, mesh.elems) if faces is None else faces
+    g = _geometry_mesh(mesh)
+    x = np.asarray(g.coords, dtype=np.float64)[np.asarray(g.elems, dtype=np.int64)]
+    vol, _ = element_geometry(mesh)
+    g1 = gamma / (gamma - 1.0)
+    rho_f = np.asarray(rho_f, dtype=np.float64)
+    wu = np.asarray(wu_new, dtype=np.float64).reshape(-1, dim)
+    pf = np.asarray(p_new, dtype=np.float64)[fv].mean(axis=1)
+    hf = g1 * pf / rho_f
+    we_k = np.asarray(we_f, dtype=np.float64)[ef].mean(axis=1)
+    flux = np.zeros(mesh.n_elems)
+    nv = dim + 1
+    for l in range(nv):
+        others = [c for c in range(nv) if c != l]
+        pts = x[:, others, :]
+        if dim == 2:
+            t = pts[:, 1] - pts[:, 0]
+            A = np.stack([t[:, 1], -t[:, 0]], axis=1)
+        else:
+            A = 0.5 * np.cross(pts[:, 1] - pts[:, 0], pts[:, 2] - pts[:, 0])
+        out = pts.mean(axis=1) - x[:, l, :]
+        A = A * np.sign((A * out).sum(axis=1))[:, None]
+        f = ef[:, l]
+        flux += hf[f] * (wu[f] * A).sum(axis=1)
+    we_el = we_k - dt * flux / vol
+    num = np.zeros(fv.shape[0])
+    den = np.zeros(fv.shape[0])
+    np.add.at(num, ef, (vol * we_el)[:, None] * np.ones((1, nv)))
+    np.add.at(den, ef, vol[:, None] * np.ones((1, nv)))
+    return num / den, we_el, vol

@@ -893,6 +893,7 @@ struct ProjArgs {
     double *erho, *ewe, *ewu, *erk, *evol, *egrad;   // per element (ewu, egrad: 3 each)
     double g1;            // gamma / (gamma - 1)
     double dt;
+    double *w;            // element factors beta c_k / (d! det), written with c_k = H_k
 };
 
 // Corner ids and (minimum-image) edge vectors of element k.
@@ -1001,8 +1002,11 @@ __global__ void __launch_bounds__(BLK) k_proj_init(Mesh g, ProjArgs pa, const do
     pa.erho[k] = rho;
     pa.ewe[k] = we;
     pa.erk[k] = ww / (2.0 * rho);
-    pa.evol[k] = det / ((DIM == 2) ? 2.0 : 6.0);
-    coef[k] = elem_enthalpy<DIM>(pa, k, pv);
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    pa.evol[k] = det / dfact;
+    const double hk = elem_enthalpy<DIM>(pa, k, pv);
+    coef[k] = hk;
+    pa.w[k] = (pa.dt * pa.dt * hk) / (dfact * det);
 }
 
 // Right-hand side of the weak problem for one Picard iteration, element
@@ -1130,7 +1134,10 @@ __global__ void __launch_bounds__(BLK) k_proj_picard(Mesh g, ProjArgs pa, const 
         ww += wc * wc;
     }
     pa.erk[k] = ww / (2.0 * pa.erho[k]);
-    coef[k] = elem_enthalpy<DIM>(pa, k, pv);
+    const double hk = elem_enthalpy<DIM>(pa, k, pv);
+    coef[k] = hk;
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    pa.w[k] = (pa.dt * pa.dt * hk) / (dfact * det);
 }
 
 // Momentum update on the dual cells: W_u,f - dt (sum_k |T_k| grad_k) / (sum_k |T_k|).
@@ -1176,6 +1183,62 @@ __global__ void __launch_bounds__(BLK) k_scatter_elem(int E, const int *__restri
 {
     const int k = blockIdx.x * BLK + threadIdx.x;
     if (k < E) out[perm[k]] = v[k];
+}
+
+// Post-projection (Sec. 3.5, eq. WEupdatek): the total energy per primal
+// element from the intermediate energy and the enthalpy flux through its
+// faces, then back to the dual cells.  On primal face l of T_k the momentum
+// is W_u^{n+1} of the dual cell of l and the enthalpy H_l = g1 P_l / rho_l,
+// P_l the mean of the face's vertex pressures P^{n+1}; the outward area
+// vector of face l is -n_l / (d-1)!.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_post_elem(Mesh g, ProjArgs pa, const double *__restrict__ pnew,
+                                                   double *__restrict__ ewe_new)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    constexpr double ffact = (DIM == 2) ? 1.0 : 2.0;   // (d-1)!
+    double pv[4];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) pv[a] = pnew[v[a]];
+    double we = 0.0, flux = 0.0;
+#pragma unroll
+    for (int l = 0; l <= DIM; ++l) {
+        const int f = pa.efc[4 * k + l];
+        we += pa.we_f[f];
+        double pf = 0.0;
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b)
+            if (b != l) pf += pv[b];
+        const double hl = pa.g1 * (pf / double(DIM)) / pa.rho_f[f];
+        double wn = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) wn += pa.wu_f[DIM * f + c] * n[l][c];
+        flux -= hl * wn / ffact;
+    }
+    const double vol = det / dfact;
+    pa.evol[k] = vol;
+    ewe_new[k] = we / double(DIM + 1) - pa.dt * flux / vol;
+}
+
+// W_E,f = sum_k |T_kf| W_E,k / |C_f| over the one or two elements of f.
+__global__ void __launch_bounds__(BLK) k_post_faces(int F, ProjArgs pa, const double *__restrict__ ewe_new,
+                                                    double *__restrict__ we_out)
+{
+    const int f = blockIdx.x * BLK + threadIdx.x;
+    if (f >= F) return;
+    const int2 ke = pa.fel[f];
+    double vs = pa.evol[ke.x], es = pa.evol[ke.x] * ewe_new[ke.x];
+    if (ke.y >= 0) {
+        vs += pa.evol[ke.y];
+        es += pa.evol[ke.y] * ewe_new[ke.y];
+    }
+    we_out[f] = es / vs;
 }
 
 // -------------------------------------------------------- transport stage
@@ -1699,6 +1762,19 @@ int compute_factors_t(pm_handle *h, R *w, R *inst_w, hipStream_t s)
                            h->t_inst_elem, w, inst_w);
         HIPCK(hipGetLastError());
     }
+    return PM_OK;
+}
+
+// Per-instance copies of the FP64 element factors (after a kernel wrote w
+// itself), and the FP32 factors if the handle has them, in stream order.
+int refresh_factors_after_w(pm_handle *h, hipStream_t s)
+{
+    if (h->n_inst > 0) {
+        hipLaunchKernelGGL(k_inst_factors<double>, dim3(grid_of(h->n_inst)), dim3(BLK), 0, s, int(h->n_inst),
+                           h->t_inst_elem, h->w, h->t_inst_w);
+        HIPCK(hipGetLastError());
+    }
+    if (h->w32) TRY(compute_factors_t<float>(h, h->w32, h->t_inst_w32, s));
     return PM_OK;
 }
 
@@ -3255,7 +3331,7 @@ int projection_t(pm_handle *h, const ProjArgs &pa, const double *p_dev, const do
                        h->pj.gd);
     hipLaunchKernelGGL((k_proj_init<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->coef);
     HIPCK(hipGetLastError());
-    TRY(compute_factors_on(h, s));
+    TRY(refresh_factors_after_w(h, s));
     int worst = PM_OK;
     const double *x0 = dp0;
     for (int it = 0; it < n_picard; ++it) {
@@ -3274,7 +3350,7 @@ int projection_t(pm_handle *h, const ProjArgs &pa, const double *p_dev, const do
         hipLaunchKernelGGL((k_proj_picard<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->pj.dpi,
                            h->coef);
         HIPCK(hipGetLastError());
-        TRY(compute_factors_on(h, s));
+        TRY(refresh_factors_after_w(h, s));
     }
     hipLaunchKernelGGL(k_proj_faces<DIM>, dim3(grid_of(F)), dim3(BLK), 0, s, F, pa, wu_out);
     hipLaunchKernelGGL(k_add, dim3(grid_of(N)), dim3(BLK), 0, s, N, p_dev, h->pj.dp, p_out);
@@ -3339,6 +3415,7 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
     pa.egrad = h->pj.e + 7 * E;
     pa.g1 = gamma / (gamma - 1.0);
     pa.dt = dt;
+    pa.w = h->w;
     auto run = [&]<int DIM, bool PER>() {
         return projection_t<DIM, PER>(h, pa, p_dev, pb_dev, dp0_dev, n_picard, rtol, max_iter, p_out, wu_out, h_out,
                                       iters, s);
@@ -3383,6 +3460,46 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
         hipLaunchKernelGGL((k_tr_cell<3, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
     else
         hipLaunchKernelGGL((k_tr_cell<3, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(s));
+    return PM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int pressure_post_projection(pm_handle *h, const double *rho_dev, const double *we_dev, const double *wu_dev,
+                             const double *p_dev, double gamma, double dt, double *we_out, void *stream)
+{
+    if (!h || !rho_dev || !we_dev || !wu_dev || !p_dev || !we_out || we_out == we_dev) return PM_EINVAL;
+    if (!(gamma > 1.0) || !std::isfinite(gamma) || !(dt > 0.0) || !std::isfinite(dt)) return PM_EINVAL;
+    TRY(ensure_faces(h));
+    hipStream_t s = (hipStream_t)stream;
+    const int N = int(h->N), E = int(h->E), F = int(h->pj.F.n_faces);
+    ProjArgs pa{};
+    pa.efc = h->pj.efc;
+    pa.fel = h->pj.fel;
+    pa.ebnd = h->pj.ebnd;
+    pa.rho_f = rho_dev;
+    pa.we_f = we_dev;
+    pa.wu_f = wu_dev;
+    pa.evol = h->pj.e + 3 * int64_t(E);
+    pa.g1 = gamma / (gamma - 1.0);
+    pa.dt = dt;
+    double *ewe_new = h->pj.e + 2 * int64_t(E);   // the (rho K) slot, free outside a projection
+    Mesh g = make_mesh<double>(h);
+    hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
+    const dim3 ge(grid_of(E));
+    if (h->dim == 2 && h->periodic)
+        hipLaunchKernelGGL((k_post_elem<2, true>), ge, dim3(BLK), 0, s, g, pa, h->pj.pn, ewe_new);
+    else if (h->dim == 2)
+        hipLaunchKernelGGL((k_post_elem<2, false>), ge, dim3(BLK), 0, s, g, pa, h->pj.pn, ewe_new);
+    else if (h->periodic)
+        hipLaunchKernelGGL((k_post_elem<3, true>), ge, dim3(BLK), 0, s, g, pa, h->pj.pn, ewe_new);
+    else
+        hipLaunchKernelGGL((k_post_elem<3, false>), ge, dim3(BLK), 0, s, g, pa, h->pj.pn, ewe_new);
+    hipLaunchKernelGGL(k_post_faces, dim3(grid_of(F)), dim3(BLK), 0, s, F, pa, ewe_new, we_out);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(s));
     return PM_OK;

@@ -236,6 +236,20 @@ class PressureSystem:
             check(st, "pressure_projection")
         return p_out, wu_out, h_out, its, st
 
+    def post_projection(self, rho, we, wu, p, gamma, dt, we_out=None, stream=None):
+        """The total energy W_E^{n+1} on the dual cells (see
+        pressure_post_projection in include/pressure_cg.h)."""
+        import torch
+        nf = ctypes.c_int64(0)
+        check(load().pressure_dual_count(self._h, ctypes.byref(nf), None), "pressure_dual_count")
+        F = nf.value
+        we_out = torch.empty_like(we) if we_out is None else we_out
+        check(load().pressure_post_projection(self._h, _dev_ptr(rho, F, "rho"), _dev_ptr(we, F, "we"),
+                                              _dev_ptr(wu, F * self.dim, "wu"), _dev_ptr(p, self.n_nodes, "p"),
+                                              float(gamma), float(dt), _dev_ptr(we_out, F, "we_out"),
+                                              _stream_handle(stream)), "pressure_post_projection")
+        return we_out
+
     def transport(self, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, rho_out=None, wu_out=None, we_out=None,
                   stream=None):
         """One first-order transport step on the dual cells (see

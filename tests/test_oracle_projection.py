@@ -161,3 +161,43 @@ def test_discrete_energy_equation_holds(case):
         assert np.max(np.abs(res)) < 1e-9 * scale, (case, it, np.max(np.abs(res)) / scale)
         # the Dirichlet values are imposed exactly
         assert np.max(np.abs((inp["p"] + dp - inp["pb"])[~free])) < 1e-15 if (~free).any() else True
+
+
+def test_post_projection_conserves_and_keeps_uniform_states():
+    """Sec. 3.5: on a periodic mesh every face's enthalpy flux cancels
+    between its two elements, so sum |C_f| W_E^{n+1} = sum |C_f| tilde W_E;
+    on a walled mesh the change is -dt times the flux through the primal
+    boundary; a uniform state (uniform W_u, P and rho) is unchanged."""
+    gamma, dt = 1.4, 0.02
+    mp = smesh.periodic_mesh(3, 5, (0, 1, 2), jitter=0.2, seed=3)
+    fv, fe, ef = faces = op.dual_faces(3, mp.elems)
+    inp = sproj.fields(mp, fv, fe, seed=4)
+    we_new, we_el, vol = op.post_projection(mp, inp["rho_f"], inp["we_f"], inp["wu_f"], inp["p"], gamma, dt, faces)
+    cvol = np.zeros(fv.shape[0])
+    np.add.at(cvol, ef, vol[:, None] * np.ones((1, 4)) / 4)
+    assert abs(cvol @ we_new - cvol @ inp["we_f"]) < 1e-13 * (cvol @ inp["we_f"])
+    assert abs(vol @ we_el - cvol @ inp["we_f"]) < 1e-13 * (cvol @ inp["we_f"])
+    F = fv.shape[0]
+    w0 = np.array([0.2, -0.1, 0.4])
+    we_u, _, _ = op.post_projection(mp, np.full(F, 1.1), np.full(F, 3.0), np.tile(w0, (F, 1)),
+                                    np.full(mp.n_nodes, 0.8), gamma, dt, faces)
+    assert np.abs(we_u - 3.0).max() < 1e-13
+    # walled square: the total changes by the boundary flux only
+    m = smesh.structured_mesh(2, 6, jitter=0.2, seed=5)
+    fv, fe, ef = faces = op.dual_faces(2, m.elems)
+    inp = sproj.fields(m, fv, fe, seed=6)
+    we_new, we_el, vol = op.post_projection(m, inp["rho_f"], inp["we_f"], inp["wu_f"], inp["p"], gamma, dt, faces)
+    bnd = fe[:, 1] < 0
+    area = op.face_areas(m, fe, ef)
+    # outward unit normals of the boundary edges of the unit square
+    c = m.coords[fv].mean(axis=1)
+    nrm = np.zeros((fv.shape[0], 2))
+    nrm[np.isclose(c[:, 0], 0.0), 0] = -1.0
+    nrm[np.isclose(c[:, 0], 1.0), 0] = 1.0
+    nrm[np.isclose(c[:, 1], 0.0), 1] = -1.0
+    nrm[np.isclose(c[:, 1], 1.0), 1] = 1.0
+    hf = gamma / (gamma - 1.0) * inp["p"][fv].mean(axis=1) / inp["rho_f"]
+    bflux = (hf * (inp["wu_f"] * nrm).sum(axis=1) * area)[bnd].sum()
+    cvol = np.zeros(fv.shape[0])
+    np.add.at(cvol, ef, vol[:, None] * np.ones((1, 3)) / 3)
+    assert abs((cvol @ we_new - cvol @ inp["we_f"]) + dt * bflux) < 1e-13 * (cvol @ inp["we_f"])
