@@ -156,3 +156,32 @@ def test_three_time_steps_match_oracle_and_conserve():
     assert np.abs(cvol @ got["wu"] - tot0[1]).max() < 1e-13 * np.abs(cvol @ np.abs(inp["wu_f"])).max()
     assert abs(cvol @ got["we"] - tot0[2]) < 1e-13 * tot0[2]
     s.close()
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_full_size_uniform_states_are_kept(periodic):
+    """160^3 (the bench meshes, 49M dual cells): a uniform flow on the fully
+    periodic mesh, and a state at rest on the walled one, pass unchanged
+    through transport, projection (N_Pic = 2) and post-projection: every
+    flux difference, pressure gradient and enthalpy flux then vanishes."""
+    n = 160
+    if periodic:
+        m = smesh.periodic_mesh(3, n, (0, 1, 2), jitter=0.2, seed=31)
+        w0 = np.array([0.05, -0.03, 0.02])
+    else:
+        m = smesh.structured_mesh(3, n, jitter=0.2, seed=31)
+        w0 = np.zeros(3)
+    print("case full size uniform, periodic=%s" % periodic, flush=True)
+    gamma, dt = 1.4, 2e-3
+    s = _system(m, gamma, dt)
+    F = s.dual_faces()[0].shape[0]
+    rho0, p0 = 1.2, 0.7
+    we0 = p0 / (gamma - 1.0) + (w0 @ w0) / (2.0 * rho0)
+    st = {"rho": _dev(np.full(F, rho0)), "wu": _dev(np.tile(w0, F)), "we": _dev(np.full(F, we0)),
+          "p": _dev(np.full(m.n_nodes, p0))}
+    out = _gpu_step(s, st, gamma, dt)
+    assert float((out["rho"] - rho0).abs().max()) < 1e-14
+    assert float((out["wu"] - _dev(np.tile(w0, F))).abs().max()) < 1e-13
+    assert float((out["we"] - we0).abs().max()) < 1e-12
+    assert float((out["p"] - p0).abs().max()) < 1e-12
+    s.close()
