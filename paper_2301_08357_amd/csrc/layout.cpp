@@ -199,14 +199,18 @@ int build_layout(const pm_mesh *m, Layout *L)
     return PM_OK;
 }
 
-int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
+int build_tiles(const Layout &L, int tile_nodes, Tiles *T, int64_t n_tiles)
 {
     const int64_t N = L.n_nodes, E = L.n_elems;
     const int nv = L.dim + 1;
     if (tile_nodes < 64 || tile_nodes > 4096) return PM_EINVAL;
+    if (n_tiles < 0 || n_tiles > N || (n_tiles > 0 && (N + n_tiles - 1) / n_tiles > tile_nodes)) return PM_EINVAL;
     T->tile_nodes = tile_nodes;
-    T->n_tiles = (N + tile_nodes - 1) / tile_nodes;
+    T->n_tiles = n_tiles > 0 ? n_tiles : (N + tile_nodes - 1) / tile_nodes;
     const int64_t nt = T->n_tiles;
+    T->node_off.assign(nt + 1, 0);
+    for (int64_t t = 0; t <= nt; ++t)
+        T->node_off[t] = int32_t(n_tiles > 0 ? (t * N) / nt : std::min<int64_t>(N, t * tile_nodes));
     T->halo_off.assign(nt + 1, 0);
     T->inst_off.assign(nt + 1, 0);
     T->halo.clear();
@@ -233,7 +237,7 @@ int build_tiles(const Layout &L, int tile_nodes, Tiles *T)
 
     std::vector<int32_t> halo_el, halo_nd;
     for (int64_t t = 0; t < nt; ++t) {
-        const int64_t s = t * tile_nodes, f = std::min<int64_t>(N, s + tile_nodes);
+        const int64_t s = T->node_off[t], f = T->node_off[t + 1];
         const int32_t own0 = ebeg[s], own1 = ebeg[f];
         halo_el.clear();
         for (int64_t i = s; i < f; ++i)

@@ -40,7 +40,8 @@ int build_layout(const pm_mesh *m, Layout *L);
 // Node i's k-th element in ascending order is the instance whose vertex i
 // has row k.  lvb = 10 for tiles of up to 256 nodes, 11 for larger ones.
 struct Tiles {
-    int tile_nodes = 0;
+    int tile_nodes = 0;                   // largest tile
+    std::vector<int32_t> node_off;        // n_tiles + 1: tile t owns nodes [node_off[t], node_off[t+1])
     int lvb = 0;
     int64_t n_tiles = 0;
     int max_inst = 0;                     // largest instance count of a tile
@@ -57,7 +58,11 @@ struct Tiles {
 // own and halo nodes, than a record can name at this tile size.
 constexpr int TILES_TOO_WIDE = 100;
 
-int build_tiles(const Layout &L, int tile_nodes, Tiles *T);
+// n_tiles = 0: runs of tile_nodes nodes (the last one shorter); n_tiles > 0:
+// that many runs of equal length (floor(t N / n_tiles) boundaries), each at
+// most tile_nodes long, so that a grid of B resident blocks gets exactly
+// n_tiles / B tiles per block.
+int build_tiles(const Layout &L, int tile_nodes, Tiles *T, int64_t n_tiles = 0);
 
 // Dual cells of the face-type staggered mesh: one per face (3D) or edge
 // (2D) of the primal mesh.  Faces are numbered by the sorted tuples of the

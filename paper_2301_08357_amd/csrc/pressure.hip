@@ -325,13 +325,13 @@ __device__ __forceinline__ int tile_at(int b, int k, int n_blocks, int n_tiles)
 // Reference kernel: each element is recomputed for each of its vertices.
 // With CG set, x is p_k = r + beta p_{k-1}, formed on the fly.
 // Nodes are visited in the tiled kernel's order (tile t by block t mod grid,
-// node t*T + j*BLK + lane), so the block partials of p.Ap, and hence whole
-// solves, agree bit for bit between the two kernels.
+// node node_off[t] + j*BLK + lane), so the block partials of p.Ap, and hence
+// whole solves, agree bit for bit between the two kernels.
 template <int DIM, bool CG, bool PER>
 __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restrict__ off,
-                                                    const int *__restrict__ ent, int T,
-                                                    const double *__restrict__ x, double *__restrict__ y,
-                                                    Iter it)
+                                                    const int *__restrict__ ent, const int *__restrict__ node_off,
+                                                    int n_tiles, const double *__restrict__ x,
+                                                    double *__restrict__ y, Iter it)
 {
     __shared__ double red[BLK / 64];
     double beta = 0.0;
@@ -341,13 +341,12 @@ __global__ void __launch_bounds__(BLK) k_apply_node(Mesh g, const int *__restric
         return it.first ? it.r[v] : it.r[v] + beta * it.p_old[v];
     };
     double part = 0.0;
-    const int n_tiles = (g.N + T - 1) / T;
     for (int kt = 0;; ++kt) {
     const int t = tile_at(blockIdx.x, kt, gridDim.x, n_tiles);
     if (t < 0) break;
-    for (int jj = threadIdx.x; jj < T; jj += BLK) {
-        const int i = t * T + jj;
-        if (i >= g.N) break;
+    const int ts = node_off[t], te = node_off[t + 1];
+    for (int jj = threadIdx.x; ts + jj < te; jj += BLK) {
+        const int i = ts + jj;
         const double xi = val(i);
         double yi = 0.0;
         if (g.dir[i]) {
@@ -422,6 +421,7 @@ template <class R>
 struct TileArgsT {
     int n_tiles;
     int max_deg;                  // rows of the LDS sums table
+    const int *node_off;          // tile t owns nodes [node_off[t], node_off[t+1])
     const int *halo_off, *halo;
     const int *inst_off;
     const uint2 *inst;            // packed instance records
@@ -475,8 +475,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     R iw[IPT];
     R vX[SPT], vY[SPT], vZ[SPT], vP[SPT], vQ[SPT];
     uint8_t vF[SPT];
-    auto load_ids = [&](int t, int h0, int nh, int *gi) {
-        const int s = t * T, nt = min(T, g.N - s);
+    auto load_ids = [&](int s, int nt, int h0, int nh, int *gi) {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int l = threadIdx.x + q * NTH;
@@ -512,22 +511,25 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     };
 
     double part = 0.0;
-    // offsets of tile tt as vector loads (lanes 0-3 of each wave), read out
-    // with readlane when needed: unlike scalar loads they do not hold up the
-    // waits on LDS operations
+    // offsets of tile tt as vector loads (lanes 0-5 of each wave: halo,
+    // instance and node ranges), read out with readlane when needed: unlike
+    // scalar loads they do not hold up the waits on LDS operations
     const int lane = threadIdx.x & 63;
     auto load_offsets = [&](int tt) -> int {
         int v = 0;
-        if (tt >= 0 && lane < 4) v = (lane < 2) ? ta.halo_off[tt + lane] : ta.inst_off[tt + lane - 2];
+        if (tt >= 0 && lane < 6)
+            v = (lane < 2) ? ta.halo_off[tt + lane] : (lane < 4) ? ta.inst_off[tt + lane - 2] : ta.node_off[tt + lane - 4];
         return v;
     };
     int t = tile_at(vb, 0, nvb, ta.n_tiles);
-    int ni = 0;
+    int ni = 0, cs = 0, cn = 0;   // instances, first node and node count of tile t
     if (t >= 0) {
         const int h0 = ta.halo_off[t], nh = ta.halo_off[t + 1] - h0;
         const int i0 = ta.inst_off[t];
         ni = ta.inst_off[t + 1] - i0;
-        load_ids(t, h0, nh, gidx);
+        cs = ta.node_off[t];
+        cn = ta.node_off[t + 1] - cs;
+        load_ids(cs, cn, h0, nh, gidx);
 #pragma unroll
         for (int k = 0; k < IPT; ++k) load_inst(k, i0, ni);
         load_nodes(gidx);
@@ -539,7 +541,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
     if (CG && !iter_decide<R, NTH>(it, red, beta, vb)) return;
     const R rbeta = R(beta);
     for (int kt = 0; t >= 0; ++kt) {
-        const int s = t * T, nt = min(T, g.N - s);
+        const int s = cs, nt = cn;
         // 1. node table; own values kept for the row sums
         R ownP[NPT];
         uint8_t ownF[NPT];
@@ -563,8 +565,9 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         // offsets and halo ids of the next tile
         const int h0n = __builtin_amdgcn_readlane(vo, 0), nhn = __builtin_amdgcn_readlane(vo, 1) - h0n;
         const int i0n = __builtin_amdgcn_readlane(vo, 2), nin = __builtin_amdgcn_readlane(vo, 3) - i0n;
+        const int sn = __builtin_amdgcn_readlane(vo, 4), cnn = __builtin_amdgcn_readlane(vo, 5) - sn;
         int gidn[SPT];
-        if (tn >= 0) load_ids(tn, h0n, nhn, gidn);
+        if (tn >= 0) load_ids(sn, cnn, h0n, nhn, gidn);
         __syncthreads();
         // 2. element contributions into the sums table.  The next tile's
         // loads go into the registers as this tile frees them: its instances
@@ -629,6 +632,8 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         }
         t = tn;
         ni = nin;
+        cs = sn;
+        cn = cnn;
         tn = tn2;
     }
     if (CG) {
@@ -1559,6 +1564,7 @@ struct pm_handle {
     size_t lds_limit = 65536;
     int64_t n_inst = 0;
     int *t_halo_off = nullptr, *t_halo = nullptr, *t_inst_off = nullptr, *t_inst_elem = nullptr;
+    int *t_node_off = nullptr;  // tile t owns internal nodes [t_node_off[t], t_node_off[t+1])
     uint2 *t_inst = nullptr;
     double *t_inst_w = nullptr;
     uint8_t *t_nflag = nullptr;
@@ -1723,6 +1729,7 @@ TileArgsT<R> make_tiles(const pm_handle *h)
     TileArgsT<R> ta;
     ta.n_tiles = h->n_tiles;
     ta.max_deg = h->max_deg;
+    ta.node_off = h->t_node_off;
     ta.halo_off = h->t_halo_off;
     ta.halo = h->t_halo;
     ta.inst_off = h->t_inst_off;
@@ -1910,10 +1917,10 @@ int launch_node_t(pm_handle *h, const double *x, double *y, const Iter &it, hipS
     Mesh g = make_mesh<double>(h);
     if (h->periodic)
         hipLaunchKernelGGL((k_apply_node<DIM, CG, true>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off,
-                           h->n2e_ent, h->tile_nodes, x, y, it);
+                           h->n2e_ent, h->t_node_off, h->n_tiles, x, y, it);
     else
         hipLaunchKernelGGL((k_apply_node<DIM, CG, false>), dim3(h->n_ablocks), dim3(BLK), 0, s, g, h->n2e_off,
-                           h->n2e_ent, h->tile_nodes, x, y, it);
+                           h->n2e_ent, h->t_node_off, h->n_tiles, x, y, it);
     HIPCK(hipGetLastError());
     return PM_OK;
 }
@@ -1970,24 +1977,33 @@ int event_pair(pm_handle *h, size_t k, hipEvent_t *a, hipEvent_t *b)
 // not fit the tiled kernel at this tile size (a node with more elements, or
 // a tile with more own and halo nodes, than a record names; no size class
 // or not enough LDS for the largest tile).
-int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
+// Smallest size class of this tile size that covers the tiles' instances
+// and node tables, or -1.
+int pick_class(int tile_nodes, int max_inst, int max_local)
 {
-    pm::Tiles T;
-    TRY(pm::build_tiles(L, tile_nodes, &T));
+    for (int c = 0; c < N_TILE_CLASSES; ++c)
+        if (TILE_CLASSES[c].t == tile_nodes && TILE_CLASSES[c].ipt * TILE_CLASSES[c].nth >= max_inst &&
+            TILE_CLASSES[c].lm >= max_local)
+            return c;
+    return -1;
+}
+
+void adopt_tiles(pm_handle *h, const pm::Tiles &T, int tile_nodes)
+{
     h->tile_nodes = tile_nodes;
     h->n_tiles = int(T.n_tiles);
     h->max_local = tile_nodes + T.max_halo;
     h->max_deg = T.max_deg;
     h->max_inst = T.max_inst;
     h->n_inst = int64_t(T.inst_elem.size());
-    // smallest size class covering the tile, its instances and node table
-    h->tile_class = -1;
-    for (int c = 0; c < N_TILE_CLASSES; ++c)
-        if (TILE_CLASSES[c].t == tile_nodes && TILE_CLASSES[c].ipt * TILE_CLASSES[c].nth >= T.max_inst &&
-            TILE_CLASSES[c].lm >= h->max_local) {
-            h->tile_class = c;
-            break;
-        }
+    h->tile_class = pick_class(tile_nodes, T.max_inst, h->max_local);
+}
+
+int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
+{
+    pm::Tiles T;
+    TRY(pm::build_tiles(L, tile_nodes, &T));
+    adopt_tiles(h, T, tile_nodes);
     if (h->tile_class < 0 || tiled_lds_bytes<double>(h) > h->lds_limit) {
         h->tile_class = -1;
         return pm::TILES_TOO_WIDE;
@@ -1995,6 +2011,7 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
     std::vector<uint8_t> nflag(L.n_nodes);
     for (int64_t i = 0; i < L.n_nodes; ++i)
         nflag[i] = uint8_t((L.n2e_off[i + 1] - L.n2e_off[i]) | (L.dirichlet[i] ? 0x80 : 0));
+    TRY(dupload(h, &h->t_node_off, T.node_off));
     TRY(dupload(h, &h->t_halo_off, T.halo_off));
     TRY(dupload(h, &h->t_halo, T.halo));
     TRY(dupload(h, &h->t_inst_off, T.inst_off));
@@ -2018,6 +2035,9 @@ int setup_node_only(pm_handle *h)
     h->n_tiles = int((h->N + 127) / 128);
     h->n_inst = 0;
     h->max_inst = 0;
+    std::vector<int32_t> off(h->n_tiles + 1);
+    for (int64_t t = 0; t <= h->n_tiles; ++t) off[t] = int32_t(std::min<int64_t>(h->N, 128 * t));
+    TRY(dupload(h, &h->t_node_off, off));
     int g = std::min(AGRID_MAX, 8 * h->n_cu);
     if (g >= N_XCD) g -= g % N_XCD;
     h->n_ablocks = std::max(1, std::min(g, h->n_tiles));
@@ -2085,6 +2105,7 @@ int pressure_footprint(const pm_mesh *mesh, int32_t flags, uint64_t *bytes)
     b += 16 * E;                            // c_e and w_e
     b += N;                                 // Dirichlet flags
     b += I * (8 + 8 + 4) + 8 * N + 8 * N;   // tiles: records, factors, element ids; halo lists, flags
+    b += 4 * (N / 64 + 2);                  // tile node ranges
     b += 7 * 8 * N;                         // b, x, r, q, t, p (x2)
     b += 8 * (AGRID_MAX + 3 * VGRID_MAX) + 1024 * 8 + 256;
     if (flags & PM_FP32_INNER)   // FP32 coordinates, factors and inner-CG vectors
@@ -2097,7 +2118,7 @@ void pressure_destroy(pm_handle *h)
 {
     if (!h) return;
     void *ptrs[] = {h->new2old, h->n2e_off, h->n2e_ent, h->conn, h->coords, h->coef, h->w, h->dir,
-                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst, h->t_inst_w,
+                    h->t_halo_off, h->t_halo, h->t_inst_off, h->t_inst_elem, h->t_inst, h->t_inst_w, h->t_node_off,
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
