@@ -169,6 +169,11 @@ def main():
             "launches": launches,
         },
     }
+    tr = out["roofline"]["traffic"]
+    if tr:
+        # the rate of the measured HBM traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy)
+        out["roofline"]["traffic_achieved"] = round(tr / (avg_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_frac"] = round(tr / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_mixed:
         out["mixed"] = mixed_comparison(systems, rhs, xstar, args, elapsed / len(lat))
     if not args.no_cpu:
