@@ -442,8 +442,11 @@ int pressure_dual_faces(pm_handle *h, int32_t *face_vertices, int32_t *face_elem
  * The handle's operator is left with the coefficients of H^{n+1}.
  * Returns PM_OK, or the first non-OK status of a CG solve (PM_NOT_CONVERGED,
  * PM_EBREAKDOWN: a non-positive enthalpy makes the system indefinite),
- * PM_EINVAL or PM_EHIP.  The first call allocates the handle's projection
- * buffers (about 12 doubles per element and 4 per node); synchronises the
+ * PM_EINVAL or PM_EHIP.  The first call on a handle (of this function,
+ * pressure_transport, pressure_post_projection or the dual-cell queries)
+ * builds the dual cells on the host and allocates their device data: about
+ * 14 doubles and 21 bytes of indices per element, 16 bytes per dual cell
+ * and 5 doubles per node, kept until pressure_destroy.  Synchronises the
  * stream before returning. */
 int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_dev, const double *wu_dev,
                         const double *p_dev, const double *pb_dev, const double *bflux_dev,
