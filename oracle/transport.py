@@ -3,8 +3,9 @@ INFRASTRUCTURE (imported only by tests/, __graft_entry__.smoke() and the
 CPU-baseline leg of bench.py).
 
 Follows Sec. 3.2 of the paper (eq. discrf_mass, discrf_momentum,
-discrf_energy with the modified Rusanov flux of eq. flux), without the
-viscous and heat-flux terms and without the LADER reconstruction:
+discrf_energy with the modified Rusanov flux of eq. flux and the viscous
+terms of eq. visc_mom / visc_toten), without the heat flux and without the
+LADER reconstruction:
 
   dual_geometry   the dual faces from their definition (Sec. 2): inside
                   element k the cells of primal faces a and b meet on the
@@ -89,9 +90,28 @@ def rusanov_flux(rho_i, wu_i, rho_j, wu_j, eta, c_alpha):
     return np.concatenate([mass[..., None], mom, en[..., None]], axis=-1)
 
 
-def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None):
-    """Returns dict(rho, wu, we, vol, flux_sum, pforce); faces as
-    ``projection.dual_faces`` returns them (default: by node ids)."""
+def cr_gradients(mesh, vel_f, ef):
+    """Galerkin (Crouzeix-Raviart) gradient of a face field on each primal
+    element: the face-based P1 basis function of face a is 1 - d phi_a, so
+    grad u = -d sum_a u_{f_a} (x) grad phi_a; returns [E, d, d] with
+    [k, c, e] = d u_c / d x_e."""
+    _, grad = op.element_geometry(mesh)
+    return -mesh.dim * np.einsum("kac,kae->kce", vel_f[ef], grad)
+
+
+def viscous_stress(mesh, vel_f, ef, mu):
+    """tau = mu (grad u + grad u^T - 2/3 div u I) per element."""
+    G = cr_gradients(mesh, vel_f, ef)
+    dv = np.trace(G, axis1=1, axis2=2)
+    return mu * (G + np.transpose(G, (0, 2, 1)) - (2.0 / 3.0) * dv[:, None, None] * np.eye(mesh.dim)[None])
+
+
+def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None, mu=0.0):
+    """Returns dict(rho, wu, we, vol, flux_sum, pforce, visc); faces as
+    ``projection.dual_faces`` returns them (default: by node ids).  With
+    mu > 0 the viscous terms of eq. discrf_momentum / discrf_energy are
+    added: the element stress integrated over each dual face (in the energy
+    term times the mean velocity of the two cells)."""
     dim = mesh.dim
     fv, fe, ef = op.dual_faces(dim, mesh.elems) if faces is None else faces
     F = fv.shape[0]
@@ -127,10 +147,21 @@ def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=No
         pm = P[:, others].mean(axis=1)
         np.add.at(pforce, f[on], pm[on, None] * bnd_eta[on, a, :])
     acc[:, 1:1 + dim] += pforce
+    visc = np.zeros((F, 1 + dim))
+    if mu > 0.0:
+        vel = wu / rho[:, None]
+        tau = viscous_stress(mesh, vel, ef, mu)
+        for q, (a, b) in enumerate(pairs):
+            fa, fb = ef[:, a], ef[:, b]
+            te = np.einsum("kce,ke->kc", tau, eta[:, q, :])             # tau eta_ab
+            en = (te * 0.5 * (vel[fa] + vel[fb])).sum(axis=1)
+            np.add.at(visc, fa, -np.concatenate([te, en[:, None]], axis=1))
+            np.add.at(visc, fb, np.concatenate([te, en[:, None]], axis=1))
+        acc[:, 1:] += visc
     g = np.zeros(dim) if gravity is None else np.asarray(gravity, dtype=np.float64)
     q = dt / vol
     out_rho = rho - q * acc[:, 0]
     out_wu = wu - q[:, None] * acc[:, 1:1 + dim] + dt * rho[:, None] * g[None, :]
     out_we = we - q * acc[:, 1 + dim] + dt * (wu @ g)
     return {"rho": out_rho, "wu": out_wu, "we": out_we, "vol": vol, "flux_sum": acc, "pforce": pforce,
-            "faces": (fv, fe, ef)}
+            "visc": visc, "faces": (fv, fe, ef)}

@@ -1259,6 +1259,7 @@ struct TransArgs {
     const int2 *fsl;              // per face: element slots 4k + a of its one or two elements (-1)
     const double *rho, *wu, *we;  // per face; wu: dim per face
     double calpha;                // artificial viscosity coefficient c_alpha
+    double mu;                    // dynamic viscosity (0: inviscid)
     double dt;
     double g[3];                  // gravity
 };
@@ -1320,18 +1321,22 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
             elem_corners<DIM, PER>(g, k, v, ed);
             const double det = elem_normals<DIM>(ed, n);
             vol = det * share;
+            // states of the element's faces (the cell's own at a)
+            double rs[4], us[4][3];
+#pragma unroll
+            for (int b = 0; b <= DIM; ++b) {
+                const int fb = (b == a) ? f : ta.efc[4 * k + b];
+                rs[b] = (b == a) ? r0 : ta.rho[fb];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) us[b][c] = (b == a) ? u0[c] : ((c < DIM) ? ta.wu[DIM * fb + c] : 0.0);
+            }
 #pragma unroll
             for (int b = 0; b <= DIM; ++b) {
                 if (b == a) continue;
-                const int fb = ta.efc[4 * k + b];
-                const double rb = ta.rho[fb];
-                double ub[3], eta[3];
+                double eta[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    ub[c] = (c < DIM) ? ta.wu[DIM * fb + c] : 0.0;
-                    eta[c] = ceta * (n[a][c] - n[b][c]);
-                }
-                rusanov_add(r0, u0, rb, ub, eta, ta.calpha, acc);
+                for (int c = 0; c < 3; ++c) eta[c] = ceta * (n[a][c] - n[b][c]);
+                rusanov_add(r0, u0, rs[b], us[b], eta, ta.calpha, acc);
             }
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
@@ -1339,6 +1344,56 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
 #pragma unroll
                 for (int b = 0; b <= DIM; ++b) tp += pn[v[b]] * n[b][c];
                 acc[1 + c] += tp * share;
+            }
+            if (ta.mu > 0.0) {
+                // Crouzeix-Raviart gradient of the face velocities on T_k,
+                // grad u = -d sum_b u_b (x) grad phi_b, and the stress
+                // tau = mu (grad u + grad u^T - 2/3 div u I), constant on T_k
+                double vel[4][3], gu[3][3], tau[3][3];
+#pragma unroll
+                for (int b = 0; b <= DIM; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) vel[b][c] = us[b][c] / rs[b];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int b = 0; b <= DIM; ++b) t += vel[b][c] * n[b][e];
+                        gu[c][e] = -double(DIM) * t / det;
+                    }
+                const double dv = gu[0][0] + gu[1][1] + gu[2][2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+                        tau[c][e] = ta.mu * (gu[c][e] + gu[e][c] - ((c == e) ? (2.0 / 3.0) * dv : 0.0));
+                // momentum: minus the integral of tau eta over the cell's dual
+                // faces in T_k, which close on n_a / (d-1)!
+                constexpr double ffact = (DIM == 2) ? 1.0 : 2.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int e = 0; e < DIM; ++e) t += tau[c][e] * n[a][e];
+                    acc[1 + c] -= t / ffact;
+                }
+                // energy: minus (tau u) . eta on each dual face, u the mean
+                // velocity of the two cells
+#pragma unroll
+                for (int b = 0; b <= DIM; ++b) {
+                    if (b == a) continue;
+                    double te = 0.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int e = 0; e < DIM; ++e) t += tau[c][e] * (ceta * (n[a][e] - n[b][e]));
+                        te += t * (0.5 * (vel[a][c] + vel[b][c]));
+                    }
+                    acc[4] -= te;
+                }
             }
         }
     }
@@ -3450,11 +3505,12 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
 extern "C" {
 
 int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
-                       const double *p_dev, const double *gravity, double c_alpha, double dt, double *rho_out,
-                       double *wu_out, double *we_out, void *stream)
+                       const double *p_dev, const double *gravity, double c_alpha, double mu, double dt,
+                       double *rho_out, double *wu_out, double *we_out, void *stream)
 {
     if (!h || !rho_dev || !wu_dev || !we_dev || !p_dev || !rho_out || !wu_out || !we_out) return PM_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || !(c_alpha >= 0.0) || !std::isfinite(c_alpha)) return PM_EINVAL;
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return PM_EINVAL;
     if (rho_out == rho_dev || wu_out == wu_dev || we_out == we_dev) return PM_EINVAL;
     TRY(ensure_faces(h));
     hipStream_t s = (hipStream_t)stream;
@@ -3466,6 +3522,7 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     ta.wu = wu_dev;
     ta.we = we_dev;
     ta.calpha = c_alpha;
+    ta.mu = mu;
     ta.dt = dt;
     for (int c = 0; c < 3; ++c) ta.g[c] = (gravity && c < h->dim) ? gravity[c] : 0.0;
     for (int c = 0; c < h->dim; ++c)

@@ -59,19 +59,22 @@ def _close(a, b, a0):
     return np.abs(a - b).max() <= 1e-10 * scale + 1e-14 * np.abs(a0).max()
 
 
+@pytest.mark.parametrize("mu", [0.0, 0.05])
 @pytest.mark.parametrize("case", CASES)
-def test_transport_matches_oracle(case):
+def test_transport_matches_oracle(case, mu):
     m = _mesh(case)
-    print("case", case, flush=True)
+    print("case", case, "mu", mu, flush=True)
     fv, fe, ef = faces = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
     inp = sproj.fields(m, fv, fe, seed=13)
     g = np.array([0.1, -0.8, 0.3])[: m.dim]
     dt = 0.2 / (m.n ** 1)
     ref = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, gravity=g, c_alpha=0.4,
-                           faces=faces)
+                           faces=faces, mu=mu)
     s = _system(m)
     rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
-                              gravity=g, c_alpha=0.4)
+                              gravity=g, c_alpha=0.4, mu=mu)
+    if mu > 0.0:
+        assert np.abs(ref["visc"]).max() > 1e-3 * np.abs(ref["flux_sum"]).max()
     rho, wu, we = _host(rho), _host(wu).reshape(-1, m.dim), _host(we)
     assert _close(rho, ref["rho"], inp["rho_f"])
     assert _close(wu, ref["wu"], inp["wu_f"])
