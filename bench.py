@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
     ap.add_argument("--serve-mixed", action="store_true", help="serving: mixed-precision solves")
     ap.add_argument("--lumped", action="store_true", help="cube160/cube160p: lumped (diagonal) mass matrix")
+    ap.add_argument("--mu", type=float, default=0.0,
+                    help="transport160/timestep160: dynamic viscosity of the transport stage (0: inviscid)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -315,8 +317,9 @@ def bench_projection(args):
 
 def bench_transport(args):
     """One first-order transport step per step (Rusanov flux on the dual
-    cells, P1 pressure force, gravity) on the jittered cube160 mesh with the
-    projection-stage input recipe.  Algorithmic bytes of a step: the dual-cell
+    cells, P1 pressure force, gravity, with --mu the viscous stress) on the
+    jittered cube160 mesh with the projection-stage input recipe.
+    Algorithmic bytes of a step: the dual-cell
     state read and written (2 x 40 B per cell), the element-to-face and
     face-to-slot maps (16 + 8 B), connectivity (16 B per element), vertex
     coordinates and P^n (32 B per node)."""
@@ -338,7 +341,8 @@ def bench_transport(args):
     g = np.array([0.0, 0.0, -1.0])
 
     def step():
-        s.transport(rho, wu, we, p, dt, gravity=g, c_alpha=0.0, rho_out=outs[0], wu_out=outs[1], we_out=outs[2])
+        s.transport(rho, wu, we, p, dt, gravity=g, c_alpha=0.0, mu=args.mu, rho_out=outs[0], wu_out=outs[1],
+                    we_out=outs[2])
 
     for _ in range(max(args.warmup, 1)):
         step()
@@ -353,12 +357,13 @@ def bench_transport(args):
     ach = alg / el / 1e9
     _common(args, round(F / el / 1e9, 4), "Gcell/s", round(el * 1e3, 3),
             {"workload": "transport160: cube 160^3 x 6 tets (24,576,000 tets, %d dual cells), jitter 0.2h; one step = "
-                         "one first-order Rusanov transport step (Mach 0.1, dt = 0.5h/Mach, gravity)" % F,
-             "n_faces": F},
+                         "one first-order Rusanov transport step (Mach 0.1, dt = 0.5h/Mach, gravity, mu = %g)"
+                         % (F, args.mu),
+             "n_faces": F, "mu": args.mu},
             {"steps_per_s": round(1.0 / el, 3),
              "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                          "kernel": "transport step (element pass + face pass), wall time per step",
+                          "kernel": "transport step (gather of P^n + one pass per dual cell), wall time per step",
                           "bytes_per_step": alg}})
     s.close()
 
@@ -369,10 +374,10 @@ def bench_timestep(args):
     post-projection energy update (Sec. 3.5); each step starts from the
     previous step's state (P, W_u, W_E, rho), Mach 0.1, dt = 0.5h/Mach,
     Dirichlet boundary pressure held at P^n, walls.  The time step follows
-    the paper's rule dt = CFL r_min / |U|_max with CFL = 1/d, |U|_max from
-    the initial state and r_min = 0.17 h, the smallest incircle-diameter
-    estimate 2 d |C| / |dC| of the jittered Kuhn dual cells (measured on a
-    10^3 mesh: 0.177 h)."""
+    the rule of Sec. 4, dt = CFL r^2 / (|U|_max r + (8/3) nu_max) with
+    CFL = 1/d, nu = mu / rho, |U|_max and min rho from the initial state and
+    r = 0.17 h, the smallest incircle-diameter estimate 2 d |C| / |dC| of
+    the jittered Kuhn dual cells (measured on a 10^3 mesh: 0.177 h)."""
     import torch
     import paper_2301_08357_amd as pm
     from synth import mesh as smesh
@@ -385,14 +390,17 @@ def bench_timestep(args):
     fv, fe, nb = s.dual_faces()
     inp = sproj.fields(m, fv, fe, gamma=gamma, mach=mach)
     umax = float(np.max(np.linalg.norm(inp["wu_f"], axis=1) / inp["rho_f"]))
-    dt = (1.0 / 3.0) * 0.17 * (1.0 / n) / umax
+    # dt = CFL r^2 / (|U|_max r + 2 (4/3) nu_max), nu = mu / rho (no heat flux)
+    r = 0.17 * (1.0 / n)
+    numax = args.mu / float(np.min(inp["rho_f"]))
+    dt = (1.0 / 3.0) * r * r / (umax * r + (8.0 / 3.0) * numax)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
     st = {"rho": dev(inp["rho_f"]), "wu": dev(inp["wu_f"]), "we": dev(inp["we_f"]), "p": dev(inp["p"])}
     its_all = []
 
     def step(st):
         # the first Picard solve starts from the previous step's correction
-        rho, wu, we = s.transport(st["rho"], st["wu"], st["we"], st["p"], dt)
+        rho, wu, we = s.transport(st["rho"], st["wu"], st["we"], st["p"], dt, mu=args.mu)
         p_new, wu_new, _, its, code = s.projection(rho, we, wu, st["p"], gamma, dt, dp0=st.get("dp"), n_picard=2,
                                                    rtol=args.rtol)
         if code != 0:
@@ -419,9 +427,9 @@ def bench_timestep(args):
     _common(args, round(info["n_free"] * total_it / (el * args.steps) / 1e9, 4), "GDOF*iter/s", round(el * 1e3, 3),
             {"workload": "timestep160: cube 160^3 x 6 tets (24,576,000 tets, 4,173,281 nodes, %d dual cells), jitter "
                          "0.2h; one step = transport + projection (N_Pic = 2, FP64 CG to rtol %g, warm start from "
-                         "the previous step's correction) + post-projection, Mach 0.1, dt = (1/d) 0.17h / |U|_max"
-                         % (fv.shape[0], args.rtol),
-             "dt": dt, "cg_iterations": timed},
+                         "the previous step's correction) + post-projection, Mach 0.1, dt = (1/d) r^2 / (|U|_max r + (8/3) nu_max), r = 0.17h, "
+                         "mu = %g" % (fv.shape[0], args.rtol, args.mu),
+             "dt": dt, "mu": args.mu, "cg_iterations": timed},
             {"time_steps_per_s": round(1.0 / el, 3),
              "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

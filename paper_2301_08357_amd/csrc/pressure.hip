@@ -1294,8 +1294,8 @@ __device__ __forceinline__ void rusanov_add(double ri, const double ui[3], doubl
 // fluxes to the element's other d faces (ascending local index) and its
 // share |T|/(d+1) grad(P^n) of the pressure force; the even lane adds the
 // odd lane's sums to its own (side 0 + side 1) and writes the update with
-// the gravity sources.
-template <int DIM, bool PER>
+// the gravity sources.  VISC adds the viscous stress (mu > 0).
+template <int DIM, bool PER, bool VISC>
 __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const double *__restrict__ pn, int F,
                                                  double *__restrict__ rho_out, double *__restrict__ wu_out,
                                                  double *__restrict__ we_out)
@@ -1321,22 +1321,36 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
             elem_corners<DIM, PER>(g, k, v, ed);
             const double det = elem_normals<DIM>(ed, n);
             vol = det * share;
-            // states of the element's faces (the cell's own at a)
+            // states of the element's faces (the cell's own at a); the
+            // viscous stress needs all of them at once
             double rs[4], us[4][3];
+            if constexpr (VISC) {
 #pragma unroll
-            for (int b = 0; b <= DIM; ++b) {
-                const int fb = (b == a) ? f : ta.efc[4 * k + b];
-                rs[b] = (b == a) ? r0 : ta.rho[fb];
+                for (int b = 0; b <= DIM; ++b) {
+                    const int fb = (b == a) ? f : ta.efc[4 * k + b];
+                    rs[b] = (b == a) ? r0 : ta.rho[fb];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) us[b][c] = (b == a) ? u0[c] : ((c < DIM) ? ta.wu[DIM * fb + c] : 0.0);
+                    for (int c = 0; c < 3; ++c)
+                        us[b][c] = (b == a) ? u0[c] : ((c < DIM) ? ta.wu[DIM * fb + c] : 0.0);
+                }
             }
 #pragma unroll
             for (int b = 0; b <= DIM; ++b) {
                 if (b == a) continue;
-                double eta[3];
+                double eta[3], rb, ub[3];
+                if constexpr (VISC) {
+                    rb = rs[b];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ub[c] = us[b][c];
+                } else {
+                    const int fb = ta.efc[4 * k + b];
+                    rb = ta.rho[fb];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ub[c] = (c < DIM) ? ta.wu[DIM * fb + c] : 0.0;
+                }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) eta[c] = ceta * (n[a][c] - n[b][c]);
-                rusanov_add(r0, u0, rs[b], us[b], eta, ta.calpha, acc);
+                rusanov_add(r0, u0, rb, ub, eta, ta.calpha, acc);
             }
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
@@ -1345,7 +1359,7 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
                 for (int b = 0; b <= DIM; ++b) tp += pn[v[b]] * n[b][c];
                 acc[1 + c] += tp * share;
             }
-            if (ta.mu > 0.0) {
+            if constexpr (VISC) {
                 // Crouzeix-Raviart gradient of the face velocities on T_k,
                 // grad u = -d sum_b u_b (x) grad phi_b, and the stress
                 // tau = mu (grad u + grad u^T - 2/3 div u I), constant on T_k
@@ -3530,14 +3544,18 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     Mesh g = make_mesh<double>(h);
     hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
     const dim3 grid(grid_of(2 * int64_t(F)));
-    if (h->dim == 2 && h->periodic)
-        hipLaunchKernelGGL((k_tr_cell<2, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
-    else if (h->dim == 2)
-        hipLaunchKernelGGL((k_tr_cell<2, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
-    else if (h->periodic)
-        hipLaunchKernelGGL((k_tr_cell<3, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
+    auto launch = [&]<int DIM, bool PER>() {
+        if (mu > 0.0)
+            hipLaunchKernelGGL((k_tr_cell<DIM, PER, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
+                               wu_out, we_out);
+        else
+            hipLaunchKernelGGL((k_tr_cell<DIM, PER, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
+                               wu_out, we_out);
+    };
+    if (h->dim == 2)
+        h->periodic ? launch.template operator()<2, true>() : launch.template operator()<2, false>();
     else
-        hipLaunchKernelGGL((k_tr_cell<3, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out, wu_out, we_out);
+        h->periodic ? launch.template operator()<3, true>() : launch.template operator()<3, false>();
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(s));
     return PM_OK;
