@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--lumped", action="store_true", help="cube160/cube160p: lumped (diagonal) mass matrix")
     ap.add_argument("--mu", type=float, default=0.0,
                     help="transport160/timestep160: dynamic viscosity of the transport stage (0: inviscid)")
+    ap.add_argument("--lam", type=float, default=0.0,
+                    help="transport160/timestep160: thermal conductivity (gas constant R = 1; 0: no heat flux)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -317,7 +319,8 @@ def bench_projection(args):
 
 def bench_transport(args):
     """One first-order transport step per step (Rusanov flux on the dual
-    cells, P1 pressure force, gravity, with --mu the viscous stress) on the
+    cells, P1 pressure force, gravity, with --mu / --lam the viscous stress
+    and the heat flux) on the
     jittered cube160 mesh with the projection-stage input recipe.
     Algorithmic bytes of a step: the dual-cell
     state read and written (2 x 40 B per cell), the element-to-face and
@@ -341,8 +344,8 @@ def bench_transport(args):
     g = np.array([0.0, 0.0, -1.0])
 
     def step():
-        s.transport(rho, wu, we, p, dt, gravity=g, c_alpha=0.0, mu=args.mu, rho_out=outs[0], wu_out=outs[1],
-                    we_out=outs[2])
+        s.transport(rho, wu, we, p, dt, gravity=g, c_alpha=0.0, mu=args.mu, lam=args.lam, r_gas=1.0,
+                    rho_out=outs[0], wu_out=outs[1], we_out=outs[2])
 
     for _ in range(max(args.warmup, 1)):
         step()
@@ -357,9 +360,9 @@ def bench_transport(args):
     ach = alg / el / 1e9
     _common(args, round(F / el / 1e9, 4), "Gcell/s", round(el * 1e3, 3),
             {"workload": "transport160: cube 160^3 x 6 tets (24,576,000 tets, %d dual cells), jitter 0.2h; one step = "
-                         "one first-order Rusanov transport step (Mach 0.1, dt = 0.5h/Mach, gravity, mu = %g)"
-                         % (F, args.mu),
-             "n_faces": F, "mu": args.mu},
+                         "one first-order Rusanov transport step (Mach 0.1, dt = 0.5h/Mach, gravity, mu = %g, "
+                         "lambda = %g, R = 1)" % (F, args.mu, args.lam),
+             "n_faces": F, "mu": args.mu, "lambda": args.lam},
             {"steps_per_s": round(1.0 / el, 3),
              "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
@@ -374,8 +377,9 @@ def bench_timestep(args):
     post-projection energy update (Sec. 3.5); each step starts from the
     previous step's state (P, W_u, W_E, rho), Mach 0.1, dt = 0.5h/Mach,
     Dirichlet boundary pressure held at P^n, walls.  The time step follows
-    the rule of Sec. 4, dt = CFL r^2 / (|U|_max r + (8/3) nu_max) with
-    CFL = 1/d, nu = mu / rho, |U|_max and min rho from the initial state and
+    the rule of Sec. 4, dt = CFL r^2 / (|U|_max r + (8/3) (nu + gamma
+    lambda / (c_p rho))_max) with CFL = 1/d, nu = mu / rho, R = 1,
+    |U|_max and min rho from the initial state and
     r = 0.17 h, the smallest incircle-diameter estimate 2 d |C| / |dC| of
     the jittered Kuhn dual cells (measured on a 10^3 mesh: 0.177 h)."""
     import torch
@@ -390,17 +394,20 @@ def bench_timestep(args):
     fv, fe, nb = s.dual_faces()
     inp = sproj.fields(m, fv, fe, gamma=gamma, mach=mach)
     umax = float(np.max(np.linalg.norm(inp["wu_f"], axis=1) / inp["rho_f"]))
-    # dt = CFL r^2 / (|U|_max r + 2 (4/3) nu_max), nu = mu / rho (no heat flux)
+    # dt = CFL r^2 / (|U|_max r + 2 (4/3) (nu_max + gamma lambda / (c_p rho_min))),
+    # nu = mu / rho, c_p = gamma R / (gamma - 1) with R = 1
     r = 0.17 * (1.0 / n)
-    numax = args.mu / float(np.min(inp["rho_f"]))
-    dt = (1.0 / 3.0) * r * r / (umax * r + (8.0 / 3.0) * numax)
+    rmin = float(np.min(inp["rho_f"]))
+    cp = gamma / (gamma - 1.0)
+    diff = args.mu / rmin + gamma * args.lam / (cp * rmin)
+    dt = (1.0 / 3.0) * r * r / (umax * r + (8.0 / 3.0) * diff)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
     st = {"rho": dev(inp["rho_f"]), "wu": dev(inp["wu_f"]), "we": dev(inp["we_f"]), "p": dev(inp["p"])}
     its_all = []
 
     def step(st):
         # the first Picard solve starts from the previous step's correction
-        rho, wu, we = s.transport(st["rho"], st["wu"], st["we"], st["p"], dt, mu=args.mu)
+        rho, wu, we = s.transport(st["rho"], st["wu"], st["we"], st["p"], dt, mu=args.mu, lam=args.lam, r_gas=1.0)
         p_new, wu_new, _, its, code = s.projection(rho, we, wu, st["p"], gamma, dt, dp0=st.get("dp"), n_picard=2,
                                                    rtol=args.rtol)
         if code != 0:
@@ -427,9 +434,9 @@ def bench_timestep(args):
     _common(args, round(info["n_free"] * total_it / (el * args.steps) / 1e9, 4), "GDOF*iter/s", round(el * 1e3, 3),
             {"workload": "timestep160: cube 160^3 x 6 tets (24,576,000 tets, 4,173,281 nodes, %d dual cells), jitter "
                          "0.2h; one step = transport + projection (N_Pic = 2, FP64 CG to rtol %g, warm start from "
-                         "the previous step's correction) + post-projection, Mach 0.1, dt = (1/d) r^2 / (|U|_max r + (8/3) nu_max), r = 0.17h, "
-                         "mu = %g" % (fv.shape[0], args.rtol, args.mu),
-             "dt": dt, "mu": args.mu, "cg_iterations": timed},
+                         "the previous step's correction) + post-projection, Mach 0.1, dt by the rule of Sec. 4 "
+                         "with r = 0.17h, mu = %g, lambda = %g, R = 1" % (fv.shape[0], args.rtol, args.mu, args.lam),
+             "dt": dt, "mu": args.mu, "lambda": args.lam, "cg_iterations": timed},
             {"time_steps_per_s": round(1.0 / el, 3),
              "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

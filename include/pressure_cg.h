@@ -471,14 +471,15 @@ int pressure_post_projection(pm_handle *h, const double *rho_dev, const double *
                              const double *p_dev, double gamma, double dt, double *we_out, void *stream);
 
 /* One explicit transport step on the dual cells, first order (Sec. 3.2,
- * eq. discrf_mass, discrf_momentum and discrf_energy, without the heat
- * flux):
+ * eq. discrf_mass, discrf_momentum and discrf_energy, with the viscous
+ * terms of eq. visc_mom and visc_toten and the heat flux):
  *   rho_f^{n+1}  = rho_f - dt/|C_f| sum_j phi_rho(f, j)
  *   W_u,f        = W_u,f - dt/|C_f| ( sum_j phi_u(f, j) + int_{C_f} grad P^n
  *                                     - sum_j int_{Gamma_fj} tau eta )
  *                  + dt rho_f g
  *   W_E,f        = W_E,f - dt/|C_f| ( sum_j phi_E(f, j)
- *                                     - sum_j int_{Gamma_fj} (tau u) . eta )
+ *                                     - sum_j int_{Gamma_fj} (tau u) . eta
+ *                                     + sum_j int_{Gamma_fj} Q . eta )
  *                  + dt g . W_u,f
  * over the dual faces Gamma_fj inside the one or two primal elements of f
  * (in element k the cells of faces a and b meet on the simplex that joins
@@ -494,21 +495,27 @@ int pressure_post_projection(pm_handle *h, const double *rho_dev, const double *
  * primal element, from the Galerkin (Crouzeix-Raviart) gradient of the face
  * velocities u_f = W_u,f / rho_f: grad u = -d sum_a u_{f_a} (x) grad phi_a;
  * in the energy term u on Gamma_fj is the mean of the two cells' velocities;
- * mu = 0 gives the Euler step.  The pressure
+ * The heat flux Q = -lambda grad Theta is constant on each primal element
+ * too: Theta_f = P_f / (rho_f R) on the cells, P_f the mean of the face's
+ * vertex pressures P^n, and the same Galerkin gradient (eq. heatflux,
+ * stateequation; Sec. 3.2, heat flux term).  mu = lambda = 0 gives the
+ * Euler step.  The pressure
  * force int_{C_f} grad P^n = sum_k |T_k|/(d+1) grad P^n|_k is exact for the
  * P1 pressure.  Boundary faces of the primal mesh carry no convective flux
  * (impermeable walls).  Arrays are device, caller face numbering as in
  * pressure_dual_faces: rho_dev, we_dev, rho_out, we_out n_faces; wu_dev,
  * wu_out n_faces * dim; p_dev n_nodes (P^n at the vertices).  gravity is
- * host, dim doubles, or NULL for none; c_alpha >= 0; mu >= 0; dt > 0.
- * Primal boundary faces carry no viscous flux either.  Outputs must
+ * host, dim doubles, or NULL for none; c_alpha >= 0; mu >= 0; lambda >= 0
+ * (thermal conductivity); r_gas > 0 (R = c_p - c_v, read only when
+ * lambda > 0); dt > 0; otherwise PM_EINVAL.  Primal boundary faces carry no
+ * viscous or heat flux either (stress-free, adiabatic walls).  Outputs must
  * not alias inputs.  One pass per dual cell: each cell evaluates the fluxes
  * across its 2d (2D: 4, 3D: 6) dual faces itself; the two cells of a dual
  * face obtain exactly opposite fluxes, so the scheme stays conservative.
  * Synchronises the stream before returning. */
 int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
-                       const double *p_dev, const double *gravity, double c_alpha, double mu, double dt,
-                       double *rho_out, double *wu_out, double *we_out, void *stream);
+                       const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
+                       double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -3,9 +3,9 @@ INFRASTRUCTURE (imported only by tests/, __graft_entry__.smoke() and the
 CPU-baseline leg of bench.py).
 
 Follows Sec. 3.2 of the paper (eq. discrf_mass, discrf_momentum,
-discrf_energy with the modified Rusanov flux of eq. flux and the viscous
-terms of eq. visc_mom / visc_toten), without the heat flux and without the
-LADER reconstruction:
+discrf_energy with the modified Rusanov flux of eq. flux, the viscous
+terms of eq. visc_mom / visc_toten and the heat flux), without the LADER
+reconstruction:
 
   dual_geometry   the dual faces from their definition (Sec. 2): inside
                   element k the cells of primal faces a and b meet on the
@@ -99,6 +99,15 @@ def cr_gradients(mesh, vel_f, ef):
     return -mesh.dim * np.einsum("kac,kae->kce", vel_f[ef], grad)
 
 
+def heat_flux(mesh, rho, p, fv, ef, lam, r_gas):
+    """Q = -lambda grad Theta per element (eq. heatflux), Theta = P / (rho R)
+    on the cells (eq. stateequation) with P the mean of the face's vertex
+    pressures, grad Theta the Galerkin gradient as for the velocity."""
+    theta = p[fv].mean(axis=1) / (rho * r_gas)
+    _, grad = op.element_geometry(mesh)
+    return lam * mesh.dim * np.einsum("ka,kae->ke", theta[ef], grad)
+
+
 def viscous_stress(mesh, vel_f, ef, mu):
     """tau = mu (grad u + grad u^T - 2/3 div u I) per element."""
     G = cr_gradients(mesh, vel_f, ef)
@@ -106,12 +115,13 @@ def viscous_stress(mesh, vel_f, ef, mu):
     return mu * (G + np.transpose(G, (0, 2, 1)) - (2.0 / 3.0) * dv[:, None, None] * np.eye(mesh.dim)[None])
 
 
-def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None, mu=0.0):
+def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None, mu=0.0, lam=0.0, r_gas=1.0):
     """Returns dict(rho, wu, we, vol, flux_sum, pforce, visc); faces as
     ``projection.dual_faces`` returns them (default: by node ids).  With
     mu > 0 the viscous terms of eq. discrf_momentum / discrf_energy are
     added: the element stress integrated over each dual face (in the energy
-    term times the mean velocity of the two cells)."""
+    term times the mean velocity of the two cells).  With lam > 0 the heat
+    flux Q . eta over each dual face enters the energy ("heat")."""
     dim = mesh.dim
     fv, fe, ef = op.dual_faces(dim, mesh.elems) if faces is None else faces
     F = fv.shape[0]
@@ -158,10 +168,18 @@ def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=No
             np.add.at(visc, fa, -np.concatenate([te, en[:, None]], axis=1))
             np.add.at(visc, fb, np.concatenate([te, en[:, None]], axis=1))
         acc[:, 1:] += visc
+    heat = np.zeros(F)
+    if lam > 0.0:
+        Q = heat_flux(mesh, rho, p, fv, ef, lam, r_gas)
+        for q, (a, b) in enumerate(pairs):
+            qe = (Q * eta[:, q, :]).sum(axis=1)                         # Q . eta_ab
+            np.add.at(heat, ef[:, a], qe)
+            np.add.at(heat, ef[:, b], -qe)
+        acc[:, 1 + dim] += heat
     g = np.zeros(dim) if gravity is None else np.asarray(gravity, dtype=np.float64)
     q = dt / vol
     out_rho = rho - q * acc[:, 0]
     out_wu = wu - q[:, None] * acc[:, 1:1 + dim] + dt * rho[:, None] * g[None, :]
     out_we = we - q * acc[:, 1 + dim] + dt * (wu @ g)
     return {"rho": out_rho, "wu": out_wu, "we": out_we, "vol": vol, "flux_sum": acc, "pforce": pforce,
-            "visc": visc, "faces": (fv, fe, ef)}
+            "visc": visc, "heat": heat, "faces": (fv, fe, ef)}

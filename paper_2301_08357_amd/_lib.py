@@ -62,7 +62,7 @@ SIGNATURES = {
     "pressure_dual_faces": (ctypes.c_int, [_P, _P, _P]),
     "pressure_projection": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _dbl, _dbl, _i32, _dbl, _i32,
                                            _P, _P, _P, _P, _P]),
-    "pressure_transport": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _dbl, _dbl, _dbl, _P, _P, _P, _P]),
+    "pressure_transport": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _dbl, _dbl, _dbl, _dbl, _dbl, _P, _P, _P, _P]),
     "pressure_post_projection": (ctypes.c_int, [_P, _P, _P, _P, _P, _dbl, _dbl, _P, _P]),
 }
 

@@ -1260,6 +1260,7 @@ struct TransArgs {
     const double *rho, *wu, *we;  // per face; wu: dim per face
     double calpha;                // artificial viscosity coefficient c_alpha
     double mu;                    // dynamic viscosity (0: inviscid)
+    double lam_r;                 // thermal conductivity over the gas constant, lambda / R
     double dt;
     double g[3];                  // gravity
 };
@@ -1294,7 +1295,8 @@ __device__ __forceinline__ void rusanov_add(double ri, const double ui[3], doubl
 // fluxes to the element's other d faces (ascending local index) and its
 // share |T|/(d+1) grad(P^n) of the pressure force; the even lane adds the
 // odd lane's sums to its own (side 0 + side 1) and writes the update with
-// the gravity sources.  VISC adds the viscous stress (mu > 0).
+// the gravity sources.  VISC adds the diffusive terms: the viscous stress
+// and the heat flux.
 template <int DIM, bool PER, bool VISC>
 __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const double *__restrict__ pn, int F,
                                                  double *__restrict__ rho_out, double *__restrict__ wu_out,
@@ -1363,25 +1365,29 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
                 // Crouzeix-Raviart gradient of the face velocities on T_k,
                 // grad u = -d sum_b u_b (x) grad phi_b, and the stress
                 // tau = mu (grad u + grad u^T - 2/3 div u I), constant on T_k
-                double vel[4][3], gu[3][3], tau[3][3];
+                double vel[4][DIM], gu[DIM][DIM], tau[DIM][DIM], ir[4];
 #pragma unroll
-                for (int b = 0; b <= DIM; ++b)
+                for (int b = 0; b <= DIM; ++b) {
+                    ir[b] = 1.0 / rs[b];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) vel[b][c] = us[b][c] / rs[b];
+                    for (int c = 0; c < DIM; ++c) vel[b][c] = us[b][c] * ir[b];
+                }
+                const double gs = -double(DIM) / det;
+                double dv = 0.0;
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < DIM; ++c)
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) {
+                    for (int e = 0; e < DIM; ++e) {
                         double t = 0.0;
 #pragma unroll
                         for (int b = 0; b <= DIM; ++b) t += vel[b][c] * n[b][e];
-                        gu[c][e] = -double(DIM) * t / det;
+                        gu[c][e] = t * gs;
+                        if (c == e) dv += gu[c][e];
                     }
-                const double dv = gu[0][0] + gu[1][1] + gu[2][2];
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < DIM; ++c)
 #pragma unroll
-                    for (int e = 0; e < 3; ++e)
+                    for (int e = 0; e < DIM; ++e)
                         tau[c][e] = ta.mu * (gu[c][e] + gu[e][c] - ((c == e) ? (2.0 / 3.0) * dv : 0.0));
                 // momentum: minus the integral of tau eta over the cell's dual
                 // faces in T_k, which close on n_a / (d-1)!
@@ -1408,6 +1414,26 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
                     }
                     acc[4] -= te;
                 }
+                // heat flux Q = -lambda grad Theta with Theta = P / (rho R) on
+                // each cell, P the mean of its face's vertex pressures, and
+                // the same Galerkin gradient; Q . eta over the cell's dual
+                // faces in T_k closes on Q . n_a / (d-1)!
+                double pv[4], ps = 0.0;
+#pragma unroll
+                for (int b = 0; b <= DIM; ++b) {
+                    pv[b] = pn[v[b]];
+                    ps += pv[b];
+                }
+                double qn = 0.0;
+#pragma unroll
+                for (int b = 0; b <= DIM; ++b) {
+                    const double th = (ps - pv[b]) * (1.0 / double(DIM)) * ir[b];
+                    double nn = 0.0;
+#pragma unroll
+                    for (int e = 0; e < DIM; ++e) nn += n[b][e] * n[a][e];
+                    qn += th * nn;
+                }
+                acc[4] -= ta.lam_r * gs * qn / ffact;
             }
         }
     }
@@ -3519,12 +3545,13 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
 extern "C" {
 
 int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
-                       const double *p_dev, const double *gravity, double c_alpha, double mu, double dt,
-                       double *rho_out, double *wu_out, double *we_out, void *stream)
+                       const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
+                       double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream)
 {
     if (!h || !rho_dev || !wu_dev || !we_dev || !p_dev || !rho_out || !wu_out || !we_out) return PM_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || !(c_alpha >= 0.0) || !std::isfinite(c_alpha)) return PM_EINVAL;
-    if (!(mu >= 0.0) || !std::isfinite(mu)) return PM_EINVAL;
+    if (!(mu >= 0.0) || !std::isfinite(mu) || !(lambda >= 0.0) || !std::isfinite(lambda)) return PM_EINVAL;
+    if (lambda > 0.0 && (!(r_gas > 0.0) || !std::isfinite(r_gas))) return PM_EINVAL;
     if (rho_out == rho_dev || wu_out == wu_dev || we_out == we_dev) return PM_EINVAL;
     TRY(ensure_faces(h));
     hipStream_t s = (hipStream_t)stream;
@@ -3537,6 +3564,7 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     ta.we = we_dev;
     ta.calpha = c_alpha;
     ta.mu = mu;
+    ta.lam_r = (lambda > 0.0) ? lambda / r_gas : 0.0;
     ta.dt = dt;
     for (int c = 0; c < 3; ++c) ta.g[c] = (gravity && c < h->dim) ? gravity[c] : 0.0;
     for (int c = 0; c < h->dim; ++c)
@@ -3545,7 +3573,7 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
     const dim3 grid(grid_of(2 * int64_t(F)));
     auto launch = [&]<int DIM, bool PER>() {
-        if (mu > 0.0)
+        if (mu > 0.0 || lambda > 0.0)
             hipLaunchKernelGGL((k_tr_cell<DIM, PER, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
                                wu_out, we_out);
         else

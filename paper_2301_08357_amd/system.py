@@ -250,8 +250,8 @@ class PressureSystem:
                                               _stream_handle(stream)), "pressure_post_projection")
         return we_out
 
-    def transport(self, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, mu=0.0, rho_out=None, wu_out=None,
-                  we_out=None, stream=None):
+    def transport(self, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, mu=0.0, lam=0.0, r_gas=1.0, rho_out=None,
+                  wu_out=None, we_out=None, stream=None):
         """One first-order transport step on the dual cells (see
         pressure_transport in include/pressure_cg.h); returns (rho^{n+1},
         double-tilde W_u, tilde W_E)."""
@@ -267,7 +267,8 @@ class PressureSystem:
             raise ValueError("gravity must have dim entries")
         check(load().pressure_transport(self._h, _dev_ptr(rho, F, "rho"), _dev_ptr(wu, F * self.dim, "wu"),
                                         _dev_ptr(we, F, "we"), _dev_ptr(p, self.n_nodes, "p"), _ptr(g),
-                                        float(c_alpha), float(mu), float(dt), _dev_ptr(rho_out, F, "rho_out"),
+                                        float(c_alpha), float(mu), float(lam), float(r_gas), float(dt),
+                                        _dev_ptr(rho_out, F, "rho_out"),
                                         _dev_ptr(wu_out, F * self.dim, "wu_out"), _dev_ptr(we_out, F, "we_out"),
                                         _stream_handle(stream)), "pressure_transport")
         return rho_out, wu_out, we_out

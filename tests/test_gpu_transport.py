@@ -59,22 +59,24 @@ def _close(a, b, a0):
     return np.abs(a - b).max() <= 1e-10 * scale + 1e-14 * np.abs(a0).max()
 
 
-@pytest.mark.parametrize("mu", [0.0, 0.05])
+@pytest.mark.parametrize("mu,lam", [(0.0, 0.0), (0.05, 0.0), (0.0, 0.08), (0.05, 0.08)])
 @pytest.mark.parametrize("case", CASES)
-def test_transport_matches_oracle(case, mu):
+def test_transport_matches_oracle(case, mu, lam):
     m = _mesh(case)
-    print("case", case, "mu", mu, flush=True)
+    print("case", case, "mu", mu, "lambda", lam, flush=True)
     fv, fe, ef = faces = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
     inp = sproj.fields(m, fv, fe, seed=13)
     g = np.array([0.1, -0.8, 0.3])[: m.dim]
     dt = 0.2 / (m.n ** 1)
     ref = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, gravity=g, c_alpha=0.4,
-                           faces=faces, mu=mu)
+                           faces=faces, mu=mu, lam=lam, r_gas=0.4)
     s = _system(m)
     rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
-                              gravity=g, c_alpha=0.4, mu=mu)
+                              gravity=g, c_alpha=0.4, mu=mu, lam=lam, r_gas=0.4)
     if mu > 0.0:
         assert np.abs(ref["visc"]).max() > 1e-3 * np.abs(ref["flux_sum"]).max()
+    if lam > 0.0:
+        assert np.abs(ref["heat"]).max() > 1e-3 * np.abs(ref["flux_sum"]).max()
     rho, wu, we = _host(rho), _host(wu).reshape(-1, m.dim), _host(we)
     assert _close(rho, ref["rho"], inp["rho_f"])
     assert _close(wu, ref["wu"], inp["wu_f"])
@@ -189,4 +191,19 @@ def test_full_size_uniform_states_are_kept(periodic):
     assert float((out["wu"] - _dev(np.tile(w0, F))).abs().max()) < 1e-13
     assert float((out["we"] - we0).abs().max()) < 1e-12
     assert float((out["p"] - p0).abs().max()) < 1e-12
+    s.close()
+
+
+def test_transport_rejects_invalid_diffusion_parameters():
+    """mu < 0, lambda < 0, or lambda > 0 without a positive gas constant are
+    refused before any launch."""
+    m = _mesh("square_walls")
+    fv, fe, ef = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
+    inp = sproj.fields(m, fv, fe, seed=13)
+    s = _system(m)
+    args = (_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), 0.01)
+    for kw in ({"mu": -1.0}, {"lam": -0.1}, {"lam": 0.1, "r_gas": 0.0}, {"mu": float("nan")}):
+        with pytest.raises(pm.PressureError):
+            s.transport(*args, **kw)
+    s.transport(*args, lam=0.0, r_gas=0.0)          # R is read only when lambda > 0
     s.close()

@@ -182,3 +182,54 @@ def test_viscous_terms():
         err = np.abs(np.array(rs) - 1.0)
         r = np.log2(err[:-1] / err[1:])
         assert err[-1] < 1e-2 and np.all(r > 1.7), (rs, r)
+
+
+def test_heat_flux():
+    """Heat flux (eq. heatflux with Theta = P / (rho R), Sec. 3.2 heat flux
+    term):
+      * a linear temperature gives the constant Q = -lambda grad Theta: no
+        exchange for interior cells, and a boundary cell's term is
+        -Q . (its primal boundary area vector), by closure;
+      * on a periodic mesh the exchanges sum to zero;
+      * Theta = 2 + sin 2 pi x (rho = R = 1): the term tends weakly to
+        |C| div Q = lambda (2 pi)^2 sin 2 pi x |C| at second order, with
+        the sign that takes energy from hot cells to cold ones;
+      * mass and momentum are untouched."""
+    m = smesh.structured_mesh(3, 4, jitter=0.2, seed=9)
+    fv, fe, ef = op.dual_faces(3, m.elems)
+    F = fv.shape[0]
+    G = np.array([0.4, -0.3, 0.9])
+    rho, R, lam = 2.0, 0.7, 0.3
+    P = 3.0 + m.coords @ G
+    out = ot.transport_step(m, np.full(F, rho), np.zeros((F, 3)), np.ones(F), P, 0.01, lam=lam, r_gas=R)
+    Q = -lam * G / (rho * R)
+    assert np.abs(ot.heat_flux(m, np.full(F, rho), P, fv, ef, lam, R) - Q).max() < 1e-13
+    inner = fe[:, 1] >= 0
+    assert np.abs(out["heat"][inner]).max() < 1e-14
+    _, _, _, bnd_eta = ot.dual_geometry(m)
+    want = np.zeros(F)
+    bnd = ~inner
+    for a in range(4):
+        on = bnd[ef[:, a]]
+        np.add.at(want, ef[on, a], -(bnd_eta[on, a] @ Q))
+    assert np.abs(out["heat"] - want).max() < 1e-14
+    mp = smesh.periodic_mesh(3, 5, (0, 1, 2), jitter=0.2, seed=4)
+    inp, fv, fe, ef = _state(mp, seed=8)
+    base = ot.transport_step(mp, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], 0.01)
+    out = ot.transport_step(mp, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], 0.01, lam=0.05, r_gas=1.0)
+    assert abs(out["heat"].sum()) < 1e-15 * np.abs(out["heat"]).sum() + 1e-17
+    assert np.abs(out["heat"]).max() > 1e-6
+    assert np.array_equal(out["rho"], base["rho"]) and np.array_equal(out["wu"], base["wu"])
+    ratios = []
+    for n in (16, 32, 64):
+        m = smesh.periodic_mesh(2, n, (0, 1), jitter=0.2, seed=5)
+        fv, fe, ef = op.dual_faces(2, m.elems)
+        F = fv.shape[0]
+        c = _face_centroids(m, fe, ef)
+        P = 2.0 + np.sin(2 * np.pi * m.coords[:, 0])
+        out = ot.transport_step(m, np.ones(F), np.zeros((F, 2)), np.ones(F), P, 0.01, lam=0.7, r_gas=1.0)
+        g = np.sin(2 * np.pi * c[:, 0])
+        ratios.append((out["heat"] @ g) / (0.7 * (2 * np.pi) ** 2 * (out["vol"] * g) @ g))
+    err = np.abs(np.array(ratios) - 1.0)
+    r = np.log2(err[:-1] / err[1:])
+    assert err[-1] < 1e-2 and np.all(r > 1.7), (ratios, r)
