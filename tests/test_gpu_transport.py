@@ -207,3 +207,65 @@ def test_transport_rejects_invalid_diffusion_parameters():
             s.transport(*args, **kw)
     s.transport(*args, lam=0.0, r_gas=0.0)          # R is read only when lambda > 0
     s.close()
+
+
+def _sub_faces(elems, fv, fe, cells):
+    """The elements of `cells` (face ids of the full mesh) as a sub-mesh for
+    the oracle: (sub element ids, sub faces (fv, fe, ef) in a local
+    numbering, full face id of each local face).  A cell's update depends
+    only on its one or two elements, their faces' states and their vertex
+    pressures, so on this sub-mesh the oracle gives the full mesh's update
+    for every cell in `cells`."""
+    E = elems.shape[0]
+    sub = np.unique(fe[cells].ravel())
+    sub = sub[sub >= 0]
+    pos = np.full(E + 1, -1, dtype=np.int64)           # pos[-1] stays -1 for "no element"
+    pos[sub] = np.arange(sub.size)
+    fe64 = fe.astype(np.int64)
+    touch = (pos[fe64[:, 0]] >= 0) | (pos[fe64[:, 1]] >= 0)
+    rows = np.nonzero(touch)[0]
+    fe_sub = pos[fe64[rows]]
+    ef_sub = np.full((sub.size, elems.shape[1]), -1, dtype=np.int64)
+    for slot in (0, 1):
+        r = np.nonzero(fe_sub[:, slot] >= 0)[0]
+        kl = fe_sub[r, slot]
+        verts = elems[sub[kl]]
+        on = (verts[:, :, None] == fv[rows[r]][:, None, :]).any(axis=2)
+        a = np.argmin(on, axis=1)                       # the vertex opposite the face
+        ef_sub[kl, a] = r
+    assert (ef_sub >= 0).all()
+    return sub, (fv[rows], fe_sub, ef_sub), rows
+
+
+def test_transport_full_size_sampled_cells():
+    """160^3 walled cube with the projection-stage input recipe (49M dual
+    cells), one transport step with every term (Rusanov with c_alpha,
+    pressure force, gravity, viscous stress, heat flux): 4000 seeded
+    random cells match the oracle, evaluated on the sub-mesh of their
+    elements."""
+    import types
+    from synth.rng import MASTER_SEED
+    n = 160
+    m = smesh.structured_mesh(3, n, jitter=0.2, seed=MASTER_SEED)
+    print("case full size sampled transport", flush=True)
+    s = _system(m)
+    fv, fe, _ = s.dual_faces()
+    inp = sproj.fields(m, fv, fe, gamma=1.4, mach=0.1)
+    g = np.array([0.0, 0.0, -1.0])
+    dt, mu, lam, R = 2e-4, 1e-3, 5e-3, 1.0
+    rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
+                              gravity=g, c_alpha=0.4, mu=mu, lam=lam, r_gas=R)
+    rho, wu, we = _host(rho), _host(wu).reshape(-1, 3), _host(we)
+    s.close()
+    F = fv.shape[0]
+    cells = np.sort(np.random.default_rng(MASTER_SEED).choice(F, 4000, replace=False))
+    sub, faces, rows = _sub_faces(m.elems, fv, fe, cells)
+    sm = types.SimpleNamespace(dim=3, coords=m.coords, elems=m.elems[sub], n_nodes=m.n_nodes, n_elems=sub.size,
+                               period=None)
+    ref = ot.transport_step(sm, inp["rho_f"][rows], inp["wu_f"][rows], inp["we_f"][rows], inp["p"], dt, gravity=g,
+                            c_alpha=0.4, faces=faces, mu=mu, lam=lam, r_gas=R)
+    loc = np.searchsorted(rows, cells)
+    assert np.array_equal(rows[loc], cells)
+    assert np.abs(ref["visc"][loc]).max() > 0 and np.abs(ref["heat"][loc]).max() > 0
+    for got, want, a0 in ((rho, ref["rho"], inp["rho_f"]), (wu, ref["wu"], inp["wu_f"]), (we, ref["we"], inp["we_f"])):
+        assert _close(got[cells], want[loc], a0[cells])
