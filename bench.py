@@ -30,16 +30,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_cube64_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2301_08357_amd", "csrc", "pressure.hip")
 
 
-def measured_traffic():
+def measured_traffic(n_tiles, tiled):
     """HBM bytes per apply launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE measurement, if it was taken on the current kernel source."""
+    WRITE_SIZE measurement, if it was taken on the current kernel source and
+    the same launch: the tiled kernel over the same number of tiles."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    return rec.get("traffic_bytes_per_launch") if rec.get("source_sha256") == sha else None
+    if rec.get("source_sha256") != sha or not tiled or rec.get("n_tiles") != n_tiles:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def main():
@@ -167,7 +170,8 @@ def main():
         "rel_error_vs_manufactured": err,
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(info["n_tiles"], args.variant != pm.PM_VARIANT_NODE),
             "kernel": "operator apply (fused CG iteration)",
             "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg_ms * 1e3, 3),
             "launches": launches,

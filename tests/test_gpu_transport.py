@@ -237,10 +237,11 @@ def _sub_faces(elems, fv, fe, cells):
     return sub, (fv[rows], fe_sub, ef_sub), rows
 
 
-def test_transport_full_size_sampled_cells():
+def test_transport_and_post_projection_full_size_sampled_cells():
     """160^3 walled cube with the projection-stage input recipe (49M dual
-    cells), one transport step with every term (Rusanov with c_alpha,
-    pressure force, gravity, viscous stress, heat flux): 4000 seeded
+    cells): one transport step with every term (Rusanov with c_alpha,
+    pressure force, gravity, viscous stress, heat flux), then the
+    post-projection of its output with a perturbed P^{n+1}; 4000 seeded
     random cells match the oracle, evaluated on the sub-mesh of their
     elements."""
     import types
@@ -255,6 +256,8 @@ def test_transport_full_size_sampled_cells():
     dt, mu, lam, R = 2e-4, 1e-3, 5e-3, 1.0
     rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
                               gravity=g, c_alpha=0.4, mu=mu, lam=lam, r_gas=R)
+    p_new = inp["p"] * (1.0 + 1e-3 * np.cos(2.0 * np.pi * m.coords[:, 0]))
+    we_post = _host(s.post_projection(rho, we, wu, _dev(p_new), 1.4, dt))
     rho, wu, we = _host(rho), _host(wu).reshape(-1, 3), _host(we)
     s.close()
     F = fv.shape[0]
@@ -269,3 +272,6 @@ def test_transport_full_size_sampled_cells():
     assert np.abs(ref["visc"][loc]).max() > 0 and np.abs(ref["heat"][loc]).max() > 0
     for got, want, a0 in ((rho, ref["rho"], inp["rho_f"]), (wu, ref["wu"], inp["wu_f"]), (we, ref["we"], inp["we_f"])):
         assert _close(got[cells], want[loc], a0[cells])
+    # the post-projection of the GPU transport output on the same sub-mesh
+    post, _, _ = op.post_projection(sm, rho[rows], we[rows], wu[rows], p_new, 1.4, dt, faces)
+    assert _close(we_post[cells], post[loc], we[cells])
