@@ -318,6 +318,17 @@ __device__ __forceinline__ int tile_at(int b, int k, int n_blocks, int n_tiles)
     return t < end ? t : -1;
 }
 
+// The block index a one-item-per-lane kernel works on, chosen so that XCD
+// x = b mod 8 runs a contiguous chunk of the index range (blocks x, x + 8,
+// ... take chunk x in order): items that share gathered data then share
+// one L2.  A bijection on [0, nb) for any nb.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int x = b % N_XCD, j = b / N_XCD;
+    const int q = nb / N_XCD, r = nb % N_XCD;
+    return x * q + min(x, r) + j;
+}
+
 // ------------------------------------------------------------ apply kernels
 
 // One lane per node: y_i = sum over the node's elements (ascending) of the
@@ -1081,13 +1092,14 @@ __global__ void __launch_bounds__(BLK) k_proj_rhs_elem(Mesh g, ProjArgs pa, cons
 // Node pass: b_i = the sum of its element contributions, gd_i on a
 // Dirichlet node; written in caller order.  Four accumulators take the
 // incidences q = 4j + l (fixed pattern, so the sum is reproducible) and keep
-// four loads in flight per lane.
+// four loads in flight per lane.  Nodes go to XCDs in contiguous chunks, so
+// the contributions of shared elements are read through one L2.
 __global__ void __launch_bounds__(BLK) k_proj_rhs_node(int N, const int *__restrict__ off, const int *__restrict__ ent,
                                                        const uint8_t *__restrict__ dir, const double *__restrict__ gd,
                                                        const double *__restrict__ contrib,
                                                        const int *__restrict__ new2old, double *__restrict__ b)
 {
-    const int i = blockIdx.x * BLK + threadIdx.x;
+    const int i = xcd_block(int(blockIdx.x), int(gridDim.x)) * BLK + threadIdx.x;
     if (i >= N) return;
     double bi = 0.0;
     if (dir[i]) {
@@ -1296,13 +1308,15 @@ __device__ __forceinline__ void rusanov_add(double ri, const double ui[3], doubl
 // share |T|/(d+1) grad(P^n) of the pressure force; the even lane adds the
 // odd lane's sums to its own (side 0 + side 1) and writes the update with
 // the gravity sources.  VISC adds the diffusive terms: the viscous stress
-// and the heat flux.
+// and the heat flux.  Cells go to XCDs in contiguous chunks (xcd_block): the
+// element and neighbour data of nearby cells then share one L2, which more
+// than halves the kernel's HBM reads.
 template <int DIM, bool PER, bool VISC>
 __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const double *__restrict__ pn, int F,
                                                  double *__restrict__ rho_out, double *__restrict__ wu_out,
                                                  double *__restrict__ we_out)
 {
-    const int t = blockIdx.x * BLK + threadIdx.x;
+    const int t = xcd_block(int(blockIdx.x), int(gridDim.x)) * BLK + threadIdx.x;
     const int f = t >> 1, side = t & 1;
     constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
     constexpr double ceta = double(DIM) / (double(DIM + 1) * dfact);
