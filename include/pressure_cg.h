@@ -512,6 +512,8 @@ int pressure_post_projection(pm_handle *h, const double *rho_dev, const double *
  * not alias inputs.  One pass per dual cell: each cell evaluates the fluxes
  * across its 2d (2D: 4, 3D: 6) dual faces itself; the two cells of a dual
  * face obtain exactly opposite fluxes, so the scheme stays conservative.
+ * The first call on a handle also allocates 64 bytes per dual cell (the
+ * element records of both sides of each cell), kept until pressure_destroy.
  * Synchronises the stream before returning. */
 int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
                        const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,

@@ -931,6 +931,20 @@ __device__ __forceinline__ void elem_corners(const Mesh &g, int k, int v[4], dou
     elem_edges<DIM, PER>(X, Y, Z, g, ed);
 }
 
+// The same for vertex ids that are already known.
+template <int DIM, bool PER>
+__device__ __forceinline__ void elem_corners_of(const Mesh &g, const int v[4], double ed[3][3])
+{
+    double X[4], Y[4], Z[4];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        X[a] = g.X[v[a]];
+        Y[a] = g.Y[v[a]];
+        Z[a] = (DIM == 3) ? g.Z[v[a]] : 0.0;
+    }
+    elem_edges<DIM, PER>(X, Y, Z, g, ed);
+}
+
 // Adjugate normals n_a (grad phi_a = n_a / det; |n_a| = (d-1)! |face a|) and det.
 template <int DIM>
 __device__ __forceinline__ double elem_normals(const double ed[3][3], double n[4][3])
@@ -981,86 +995,38 @@ __device__ __forceinline__ double elem_enthalpy(const ProjArgs &pa, int k, const
     return h / double(DIM + 1);
 }
 
-// Pre-projection: element means of the dual-cell fields, (rho K)_k with
-// W_u^{n+1,1} = double-tilde W_u, element volume, and c_k = H_k from P^n.
-template <int DIM, bool PER>
-__global__ void __launch_bounds__(BLK) k_proj_init(Mesh g, ProjArgs pa, const double *__restrict__ pn,
-                                                   double *__restrict__ coef)
+// Right-hand side of the weak problem for one Picard iteration, the element
+// part: contrib[4k + a] = the contribution of element k to its vertex a,
+//   (W_E,k - (rho K)_k) |T_k|/(d+1) + dt H_k W_u,k . n_a / d!
+//   - alpha (M_e P^n)_a - (A_e g)_a over the Dirichlet vertices
+//   - dt bflux_f |f| / d for each boundary face f of T_k that holds vertex a.
+// The node pass (k_proj_rhs_node) sums the contributions of each vertex.  It
+// runs inside the kernel that has just formed H_k, w_k and (rho K)_k, so
+// that the element's geometry and fields are read once.
+template <int DIM>
+__device__ __forceinline__ void rhs_elem_write(const Mesh &g, const ProjArgs &pa, int k, const int v[4],
+                                               const double ed[3][3], const double n[4][3], double det,
+                                               double wek, double rkk, const double u[3], double hk, double wk,
+                                               const double pv[4], const double *__restrict__ gd,
+                                               double *__restrict__ contrib)
 {
-    const int k = blockIdx.x * BLK + threadIdx.x;
-    if (k >= g.E) return;
-    int v[4];
-    double ed[3][3];
-    elem_corners<DIM, PER>(g, k, v, ed);
-    const double det = elem_det<DIM, double>(ed);
-    double rho = 0.0, we = 0.0, wu[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a <= DIM; ++a) {
-        const int f = pa.efc[4 * k + a];
-        rho += pa.rho_f[f];
-        we += pa.we_f[f];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) wu[c] += pa.wu_f[DIM * f + c];
-    }
-    constexpr double inv = 1.0 / double(DIM + 1);
-    rho *= inv;
-    we *= inv;
-    double ww = 0.0;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        wu[c] *= inv;
-        ww += wu[c] * wu[c];
-        pa.ewu[3 * k + c] = wu[c];
-    }
-    double pv[4];
-#pragma unroll
-    for (int a = 0; a <= DIM; ++a) pv[a] = pn[v[a]];
-    pa.erho[k] = rho;
-    pa.ewe[k] = we;
-    pa.erk[k] = ww / (2.0 * rho);
     constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
-    pa.evol[k] = det / dfact;
-    const double hk = elem_enthalpy<DIM>(pa, k, pv);
-    coef[k] = hk;
-    pa.w[k] = (pa.dt * pa.dt * hk) / (dfact * det);
-}
-
-// Right-hand side of the weak problem for one Picard iteration, element
-// pass: contrib[4k + a] = the contribution of element k to its vertex a.
-template <int DIM, bool PER>
-__global__ void __launch_bounds__(BLK) k_proj_rhs_elem(Mesh g, ProjArgs pa, const double *__restrict__ coef,
-                                                       const double *__restrict__ pn, const double *__restrict__ gd,
-                                                       double *__restrict__ contrib)
-{
-    const int k = blockIdx.x * BLK + threadIdx.x;
-    if (k >= g.E) return;
-    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
-    int v[4];
-    double ed[3][3], n[4][3];
-    elem_corners<DIM, PER>(g, k, v, ed);
-    const double det = elem_normals<DIM>(ed, n);
     const double vol = det / dfact;
-    // sources (W_E - rho K) |T|/(d+1) and advection dt H W_u . n_a / d!
-    const double src = (pa.ewe[k] - pa.erk[k]) * (vol / double(DIM + 1));
-    const double hdt = pa.dt * coef[k] / dfact;
-    double u[3];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) u[c] = pa.ewu[3 * k + c];
-    // - alpha (M_e P^n)_a, and - (A_e g)_a over the Dirichlet vertices
+    const double src = (wek - rkk) * (vol / double(DIM + 1));
+    const double hdt = pa.dt * hk / dfact;
     const int4 c4 = g.conn[k];
     const int cv[4] = {c4.x, c4.y, c4.z, c4.w};
-    double pv[4], gv[4], o[4], t[4];
+    double gv[4], o[4], t[4];
     double sp = 0.0;
     bool lift = false;
 #pragma unroll
     for (int a = 0; a <= DIM; ++a) {
-        pv[a] = pn[v[a]];
         sp += pv[a];
         gv[a] = (cv[a] < 0) ? gd[v[a]] : 0.0;
         lift = lift || (cv[a] < 0);
     }
     if (DIM == 2) gv[3] = 0.0;
-    if (lift) elem_contrib<DIM, double>(ed, gv, g.w[k], g.mdiag, g.mfull, o);
+    if (lift) elem_contrib<DIM, double>(ed, gv, wk, g.mdiag, g.mfull, o);
 #pragma unroll
     for (int a = 0; a <= DIM; ++a) {
         double un = 0.0;
@@ -1087,6 +1053,55 @@ __global__ void __launch_bounds__(BLK) k_proj_rhs_elem(Mesh g, ProjArgs pa, cons
     }
 #pragma unroll
     for (int a = 0; a <= DIM; ++a) contrib[4 * k + a] = t[a];
+}
+
+// Pre-projection: element means of the dual-cell fields, (rho K)_k with
+// W_u^{n+1,1} = double-tilde W_u, element volume, and c_k = H_k from P^n;
+// then the element part of the first Picard iteration's right-hand side.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_proj_init(Mesh g, ProjArgs pa, const double *__restrict__ pn,
+                                                   double *__restrict__ coef, const double *__restrict__ gd,
+                                                   double *__restrict__ contrib)
+{
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    double rho = 0.0, we = 0.0, wu[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        const int f = pa.efc[4 * k + a];
+        rho += pa.rho_f[f];
+        we += pa.we_f[f];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) wu[c] += pa.wu_f[DIM * f + c];
+    }
+    constexpr double inv = 1.0 / double(DIM + 1);
+    rho *= inv;
+    we *= inv;
+    double ww = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        wu[c] *= inv;
+        ww += wu[c] * wu[c];
+        pa.ewu[3 * k + c] = wu[c];
+    }
+    double pv[4];
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) pv[a] = pn[v[a]];
+    const double rk = ww / (2.0 * rho);
+    pa.erho[k] = rho;
+    pa.ewe[k] = we;
+    pa.erk[k] = rk;
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    pa.evol[k] = det / dfact;
+    const double hk = elem_enthalpy<DIM>(pa, k, pv);
+    const double wk = (pa.dt * pa.dt * hk) / (dfact * det);
+    coef[k] = hk;
+    pa.w[k] = wk;
+    rhs_elem_write<DIM>(g, pa, k, v, ed, n, det, we, rk, wu, hk, wk, pv, gd, contrib);
 }
 
 // Node pass: b_i = the sum of its element contributions, gd_i on a
@@ -1122,10 +1137,12 @@ __global__ void __launch_bounds__(BLK) k_proj_rhs_node(int N, const int *__restr
 }
 
 // After a solve: grad(dP) per element, the element momentum W_u - dt grad
-// and its (rho K), and c_k = H_k from P^n + dP.
-template <int DIM, bool PER>
+// and its (rho K), and c_k = H_k from P^n + dP; with RHS, then the element
+// part of the next Picard iteration's right-hand side.
+template <int DIM, bool PER, bool RHS>
 __global__ void __launch_bounds__(BLK) k_proj_picard(Mesh g, ProjArgs pa, const double *__restrict__ pn,
-                                                     const double *__restrict__ dpi, double *__restrict__ coef)
+                                                     const double *__restrict__ dpi, double *__restrict__ coef,
+                                                     const double *__restrict__ gd, double *__restrict__ contrib)
 {
     const int k = blockIdx.x * BLK + threadIdx.x;
     if (k >= g.E) return;
@@ -1133,13 +1150,14 @@ __global__ void __launch_bounds__(BLK) k_proj_picard(Mesh g, ProjArgs pa, const 
     double ed[3][3], n[4][3];
     elem_corners<DIM, PER>(g, k, v, ed);
     const double det = elem_normals<DIM>(ed, n);
-    double d[4], pv[4];
+    double d[4], p0[4], pv[4];
 #pragma unroll
     for (int a = 0; a <= DIM; ++a) {
         d[a] = dpi[v[a]];
-        pv[a] = pn[v[a]] + d[a];
+        p0[a] = pn[v[a]];
+        pv[a] = p0[a] + d[a];
     }
-    double ww = 0.0;
+    double ww = 0.0, u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         double gc = 0.0;
@@ -1147,14 +1165,18 @@ __global__ void __launch_bounds__(BLK) k_proj_picard(Mesh g, ProjArgs pa, const 
         for (int a = 0; a <= DIM; ++a) gc += d[a] * n[a][c];
         gc /= det;
         pa.egrad[3 * k + c] = gc;
-        const double wc = pa.ewu[3 * k + c] - pa.dt * gc;
+        u[c] = pa.ewu[3 * k + c];
+        const double wc = u[c] - pa.dt * gc;
         ww += wc * wc;
     }
-    pa.erk[k] = ww / (2.0 * pa.erho[k]);
+    const double rk = ww / (2.0 * pa.erho[k]);
+    pa.erk[k] = rk;
     const double hk = elem_enthalpy<DIM>(pa, k, pv);
-    coef[k] = hk;
     constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
-    pa.w[k] = (pa.dt * pa.dt * hk) / (dfact * det);
+    const double wk = (pa.dt * pa.dt * hk) / (dfact * det);
+    coef[k] = hk;
+    pa.w[k] = wk;
+    if constexpr (RHS) rhs_elem_write<DIM>(g, pa, k, v, ed, n, det, pa.ewe[k], rk, u, hk, wk, p0, gd, contrib);
 }
 
 // Momentum update on the dual cells: W_u,f - dt (sum_k |T_k| grad_k) / (sum_k |T_k|).
@@ -1267,8 +1289,7 @@ __global__ void __launch_bounds__(BLK) k_post_faces(int F, ProjArgs pa, const do
 // eta_ab = |T| d/(d+1) (grad phi_a - grad phi_b) = d/((d+1) d!) (n_a - n_b).
 
 struct TransArgs {
-    const int *efc;               // 4 per element: face opposite internal-local vertex a
-    const int2 *fsl;              // per face: element slots 4k + a of its one or two elements (-1)
+    const int4 *trec;             // 2 per (face, side): vertex ids, then faces opposite them (-1: no element)
     const double *rho, *wu, *we;  // per face; wu: dim per face
     double calpha;                // artificial viscosity coefficient c_alpha
     double mu;                    // dynamic viscosity (0: inviscid)
@@ -1277,29 +1298,66 @@ struct TransArgs {
     double g[3];                  // gravity
 };
 
-// Rusanov flux from the cell with state (ri, ui) to the cell with (rj, uj)
-// across eta: acc += phi.  Swapping the cells and negating eta gives -phi
-// bit for bit (each step is symmetric or changes sign exactly), so the two
-// cells of a dual face see opposite fluxes.
-__device__ __forceinline__ void rusanov_add(double ri, const double ui[3], double rj, const double uj[3],
-                                            const double eta[3], double calpha, double acc[5])
+// One cell's state for the flux: rho, 1/rho, W_u and rho K = |W_u|^2 / (2 rho),
+// formed once per state by the same expressions in every lane.
+struct CellState {
+    double r, ir, k;
+};
+
+__device__ __forceinline__ CellState cell_state(double r, const double u[3])
 {
-    double a = 0.0, b = 0.0, en = 0.0, wi = 0.0, wj = 0.0;
+    const double ir = 1.0 / r;
+    const double w = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return {r, ir, 0.5 * w * ir};
+}
+
+// Rusanov flux from the cell with state (si, ui) to the cell with (sj, uj)
+// across eta: acc += phi.  Swapping the cells and negating eta gives -phi
+// bit for bit (each step is symmetric or changes sign exactly, and a state's
+// 1/rho and rho K do not depend on the side it is on), so the two cells of
+// a dual face see opposite fluxes.
+__device__ __forceinline__ void rusanov_add(const CellState &si, const double ui[3], const CellState &sj,
+                                            const double uj[3], const double eta[3], double calpha, double acc[5])
+{
+    const double ri = si.r, rj = sj.r, ki = si.k, kj = sj.k;
+    double a = 0.0, b = 0.0, en = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         a += ui[c] * eta[c];
         b += uj[c] * eta[c];
         en += eta[c] * eta[c];
-        wi += ui[c] * ui[c];
-        wj += uj[c] * uj[c];
     }
-    const double vi = a / ri, vj = b / rj;           // U . eta
-    const double ki = wi / (2.0 * ri), kj = wj / (2.0 * rj);   // rho K
-    const double ars = fmax(fabs(vi), fabs(vj)) + calpha * sqrt(en);
+    const double vi = a * si.ir, vj = b * sj.ir;     // U . eta
+    const double ars = fmax(fabs(vi), fabs(vj)) + ((calpha > 0.0) ? calpha * sqrt(en) : 0.0);
     acc[0] += 0.5 * (a + b) - 0.5 * ars * (rj - ri);
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[1 + c] += 0.5 * (ui[c] * vi + uj[c] * vj) - 0.5 * ars * (uj[c] - ui[c]);
     acc[4] += 0.5 * (ki * vi + kj * vj) - 0.5 * ars * (kj - ki);
+}
+
+// Per (face f, side s) the element of f on that side as two records: its
+// vertex ids (internal order, Dirichlet bit cleared) and the faces opposite
+// them, f itself at its local index; -1 in the second record when f has no
+// element on that side.  Lane 2f + s of the transport kernel reads its two
+// records with one coalesced load each, in place of a slot, connectivity
+// and face lookup that depend on one another.
+__global__ void __launch_bounds__(BLK) k_tr_records(int F, const int2 *__restrict__ fsl,
+                                                    const int4 *__restrict__ conn, const int *__restrict__ efc,
+                                                    int4 *__restrict__ trec)
+{
+    const int t = blockIdx.x * BLK + threadIdx.x;
+    if (t >= 2 * F) return;
+    const int2 sl = fsl[t >> 1];
+    const int slot = (t & 1) ? sl.y : sl.x;
+    int4 va = make_int4(0, 0, 0, 0), fa = make_int4(-1, -1, -1, -1);
+    if (slot >= 0) {
+        const int k = slot >> 2;
+        const int4 c = conn[k];
+        va = make_int4(c.x & 0x7fffffff, c.y & 0x7fffffff, c.z & 0x7fffffff, c.w & 0x7fffffff);
+        fa = make_int4(efc[4 * k], efc[4 * k + 1], efc[4 * k + 2], efc[4 * k + 3]);
+    }
+    trec[2 * t] = va;
+    trec[2 * t + 1] = fa;
 }
 
 // One pass per dual cell f, two lanes per cell (adjacent lanes 2f and
@@ -1328,22 +1386,23 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
         r0 = ta.rho[f];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) u0[c] = ta.wu[DIM * f + c];
-        const int2 sl = ta.fsl[f];
-        const int slot = side ? sl.y : sl.x;
-        if (slot >= 0) {
-            const int k = slot >> 2, a = slot & 3;
-            int v[4];
+        const int4 ra = ta.trec[2 * t], rb = ta.trec[2 * t + 1];
+        if (rb.x >= 0) {
+            const int v[4] = {ra.x, ra.y, ra.z, ra.w};
+            const int fe4[4] = {rb.x, rb.y, rb.z, rb.w};    // fe4[a] == f
+            const int a = (rb.y == f) ? 1 : (rb.z == f) ? 2 : (DIM == 3 && rb.w == f) ? 3 : 0;
             double ed[3][3], n[4][3];
-            elem_corners<DIM, PER>(g, k, v, ed);
+            elem_corners_of<DIM, PER>(g, v, ed);
             const double det = elem_normals<DIM>(ed, n);
             vol = det * share;
             // states of the element's faces (the cell's own at a); the
             // viscous stress needs all of them at once
             double rs[4], us[4][3];
+            const CellState s0 = cell_state(r0, u0);
             if constexpr (VISC) {
 #pragma unroll
                 for (int b = 0; b <= DIM; ++b) {
-                    const int fb = (b == a) ? f : ta.efc[4 * k + b];
+                    const int fb = fe4[b];
                     rs[b] = (b == a) ? r0 : ta.rho[fb];
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
@@ -1359,14 +1418,14 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
 #pragma unroll
                     for (int c = 0; c < 3; ++c) ub[c] = us[b][c];
                 } else {
-                    const int fb = ta.efc[4 * k + b];
+                    const int fb = fe4[b];
                     rb = ta.rho[fb];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) ub[c] = (c < DIM) ? ta.wu[DIM * fb + c] : 0.0;
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) eta[c] = ceta * (n[a][c] - n[b][c]);
-                rusanov_add(r0, u0, rb, ub, eta, ta.calpha, acc);
+                rusanov_add(s0, u0, cell_state(rb, ub), ub, eta, ta.calpha, acc);
             }
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
@@ -1719,6 +1778,7 @@ struct pm_handle {
         int *enew2old = nullptr;    // caller element of each internal element
         uint8_t *ebnd = nullptr;    // boundary-face bits per internal element
         int2 *fsl = nullptr;        // per face: element slots 4k + a (-1)
+        int4 *trec = nullptr;       // transport records, 2 per (face, side); built on the first transport
         double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
@@ -3459,14 +3519,14 @@ int projection_t(pm_handle *h, const ProjArgs &pa, const double *p_dev, const do
     hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
     hipLaunchKernelGGL(k_proj_lift, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->dir, pb_dev, h->pj.pn,
                        h->pj.gd);
-    hipLaunchKernelGGL((k_proj_init<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->coef);
+    // the element passes also write the element part of the next right-hand side
+    hipLaunchKernelGGL((k_proj_init<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->coef,
+                       h->pj.gd, h->pj.contrib);
     HIPCK(hipGetLastError());
     TRY(refresh_factors_after_w(h, s));
     int worst = PM_OK;
     const double *x0 = dp0;
     for (int it = 0; it < n_picard; ++it) {
-        hipLaunchKernelGGL((k_proj_rhs_elem<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->coef,
-                           h->pj.pn, h->pj.gd, h->pj.contrib);
         hipLaunchKernelGGL(k_proj_rhs_node, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->n2e_off, h->n2e_ent, h->dir,
                            h->pj.gd, h->pj.contrib, h->new2old, h->pj.b);
         HIPCK(hipGetLastError());
@@ -3477,8 +3537,12 @@ int projection_t(pm_handle *h, const ProjArgs &pa, const double *p_dev, const do
         if (st == PM_NOT_CONVERGED) worst = st;
         x0 = h->pj.dp;
         hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->pj.dp, h->pj.dpi);
-        hipLaunchKernelGGL((k_proj_picard<DIM, PER>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn, h->pj.dpi,
-                           h->coef);
+        if (it + 1 < n_picard)
+            hipLaunchKernelGGL((k_proj_picard<DIM, PER, true>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn,
+                               h->pj.dpi, h->coef, h->pj.gd, h->pj.contrib);
+        else
+            hipLaunchKernelGGL((k_proj_picard<DIM, PER, false>), dim3(grid_of(E)), dim3(BLK), 0, s, g, pa, h->pj.pn,
+                               h->pj.dpi, h->coef, h->pj.gd, h->pj.contrib);
         HIPCK(hipGetLastError());
         TRY(refresh_factors_after_w(h, s));
     }
@@ -3570,9 +3634,14 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     TRY(ensure_faces(h));
     hipStream_t s = (hipStream_t)stream;
     const int N = int(h->N), F = int(h->pj.F.n_faces);
+    if (!h->pj.trec) {
+        TRY(dalloc(h, &h->pj.trec, size_t(4) * size_t(F)));
+        hipLaunchKernelGGL(k_tr_records, dim3(grid_of(2 * int64_t(F))), dim3(BLK), 0, s, F, h->pj.fsl, h->conn,
+                           h->pj.efc, h->pj.trec);
+        HIPCK(hipGetLastError());
+    }
     TransArgs ta;
-    ta.efc = h->pj.efc;
-    ta.fsl = h->pj.fsl;
+    ta.trec = h->pj.trec;
     ta.rho = rho_dev;
     ta.wu = wu_dev;
     ta.we = we_dev;
