@@ -119,3 +119,29 @@ def test_state_at_rest_stays_at_rest():
     assert st == 0
     assert np.max(np.abs(_host(p_new) - 0.7)) < 1e-12 and np.max(np.abs(_host(wu_new))) < 1e-12
     s.close()
+
+
+def test_projection_with_every_node_dirichlet():
+    """The unit cube as 6 tets: every vertex is a Dirichlet vertex, so each
+    Picard solve takes no CG iteration and P^{n+1} = P_B exactly; the
+    momentum update (from grad dP with dP = P_B - P^n) and H match the
+    oracle."""
+    m = smesh.structured_mesh(3, 1, jitter=0.0, seed=1)
+    assert m.dirichlet.all()
+    gamma, dt = 1.4, 0.03
+    fv, fe, ef = faces = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
+    inp = sproj.fields(m, fv, fe, seed=11)
+    ref = op.projection_stage(m, inp["rho_f"], inp["we_f"], inp["wu_f"], inp["p"], gamma, dt, pb=inp["pb"],
+                              bflux=inp["bflux"], n_picard=2, rtol=1e-12, faces=faces)
+    s = _system(m, False, gamma, dt)
+    p_new, wu_new, h_new, its, st = s.projection(
+        _dev(inp["rho_f"]), _dev(inp["we_f"]), _dev(inp["wu_f"]), _dev(inp["p"]), gamma, dt,
+        pb=_dev(inp["pb"]), bflux=_dev(inp["bflux"]), n_picard=2, rtol=1e-12)
+    assert st == 0 and list(its) == [0, 0] == list(ref["iters"])
+    p_new, wu_new, h_new = _host(p_new), _host(wu_new).reshape(-1, 3), _host(h_new)
+    assert np.array_equal(p_new, inp["pb"])
+    dw = ref["wu_new"] - inp["wu_f"]
+    assert np.abs(dw).max() > 0
+    assert np.linalg.norm(wu_new - ref["wu_new"]) <= 1e-12 * np.linalg.norm(dw) + 1e-15 * np.linalg.norm(inp["wu_f"])
+    assert np.max(np.abs(h_new - ref["H"]) / np.abs(ref["H"])) <= 1e-13
+    s.close()

@@ -43,10 +43,14 @@ def _mesh(case):
         return smesh.structured_mesh(3, 7, jitter=0.2, seed=3)
     if case == "channel":
         return smesh.periodic_mesh(2, 15, (0,), jitter=0.2, seed=5)
+    if case == "one_square":                      # 2 triangles: every cell on the boundary but one
+        return smesh.structured_mesh(2, 1, jitter=0.0, seed=1)
+    if case == "one_cube":                        # 6 tets, every node a Dirichlet node
+        return smesh.structured_mesh(3, 1, jitter=0.0, seed=1)
     return smesh.periodic_mesh(3, 7, (0, 1, 2), jitter=0.2, seed=6)
 
 
-CASES = ["square_walls", "cube_walls", "channel", "periodic_cube"]
+CASES = ["square_walls", "cube_walls", "channel", "periodic_cube", "one_square", "one_cube"]
 
 
 def _system(m, gamma=1.4, dt=0.02):
@@ -107,7 +111,7 @@ def test_one_time_step_transport_then_projection():
     s.close()
 
 
-@pytest.mark.parametrize("case", ["square_walls", "periodic_cube"])
+@pytest.mark.parametrize("case", ["square_walls", "periodic_cube", "one_cube"])
 def test_post_projection_matches_oracle(case):
     m = _mesh(case)
     gamma, dt = 1.4, 0.02
