@@ -2551,6 +2551,22 @@ static int shift_mean(pm_handle *h, hipStream_t s)
     return PM_OK;
 }
 
+// Iterations to launch before the host looks at the state again: the
+// number still needed at the residual's mean rate since the last look
+// (plus 10 % and 2), within [4, 64]; doubling while no rate is known or the
+// residual did not fall (the CG residual is not monotone).  Launches past
+// convergence exit at once, so an overestimate costs little and an
+// underestimate one more look.
+static int next_chunk(const CGState &st, int chunk, double rr_seen, int it_seen)
+{
+    const int doubled = std::min(chunk * 2, 64);
+    if (!(rr_seen > 0.0) || !(st.rr > 0.0) || !(st.rr < rr_seen) || st.iter <= it_seen) return doubled;
+    const double rate = 0.5 * std::log(st.rr / rr_seen) / double(st.iter - it_seen);   // log of the factor per iteration
+    const double need = std::log(st.tol / std::sqrt(st.rr)) / rate;
+    if (!std::isfinite(need) || !(need > 0.0)) return doubled;
+    return int(std::clamp(std::ceil(1.1 * need) + 2.0, 4.0, 64.0));
+}
+
 static int read_state(pm_handle *h, hipStream_t s)
 {
     HIPCK(hipMemcpyAsync(h->hst, h->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
@@ -2584,14 +2600,18 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
     size_t timed = 0;
     for (;;) {
         int chunk = 4;
+        double rr_seen = -1.0;
+        int it_seen = 0;
         for (;;) {
             const size_t t0 = timed;
             TRY(launch_iterations(h, k, chunk, first, &timed, s));
             const int kfirst = k;
             k += chunk;
             first = false;
-            chunk = std::min(chunk * 2, 64);
             TRY(read_state(h, s));
+            chunk = next_chunk(*h->hst, chunk, rr_seen, it_seen);
+            rr_seen = h->hst->rr;
+            it_seen = h->hst->iter;
             if (h->timing) {
                 // sampled launches that ran a full iteration (k <= final count)
                 size_t idx = t0;
