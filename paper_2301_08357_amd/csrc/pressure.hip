@@ -2750,14 +2750,18 @@ int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_d
         const int iter0 = resume ? h->hst_in->iter : 0;
         int chunk = 4;
         bool first = !resume;
+        double rr_seen = -1.0;
+        int it_seen = 0;
         for (;;) {
             TRY(launch_iterations32(h, k, chunk, first, s));
             k += chunk;
             first = false;
-            chunk = std::min(chunk * 2, 64);
             HIPCK(hipMemcpyAsync(h->hst_in, h->st_in, sizeof(CGState), hipMemcpyDeviceToHost, s));
             HIPCK(hipStreamSynchronize(s));
             if (h->hst_in->done) break;
+            chunk = next_chunk(*h->hst_in, chunk, rr_seen, it_seen);
+            rr_seen = h->hst_in->rr;
+            it_seen = h->hst_in->iter;
         }
         const int done_iter = h->hst_in->iter;   // last completed inner iteration
         k = done_iter + 1;
