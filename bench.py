@@ -70,7 +70,7 @@ def main():
                     help="transport160/timestep160: thermal conductivity (gas constant R = 1; 0: no heat flux)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
