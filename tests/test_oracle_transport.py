@@ -11,7 +11,13 @@ mathematics fixes:
   * with a uniform velocity the Rusanov mass flux is the upwind flux, so
     under the CFL condition the density keeps its bounds;
   * the pressure force of a linear pressure G.x is |C_i| G on every cell
-    (the face-mean rule of eq. pressterm is exact for P1 pressures).
+    (the face-mean rule of eq. pressterm is exact for P1 pressures);
+  * viscous terms: Crouzeix-Raviart gradients exact for linear velocities,
+    the Galerkin form of the momentum term, conservation, and second-order
+    weak convergence of the momentum and energy terms on a shear wave;
+  * heat flux: the constant flux of a linear temperature and its closure
+    on boundary cells, conservation, and second-order weak convergence on
+    a sine temperature.
 """
 
 import numpy as np
