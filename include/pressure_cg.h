@@ -243,10 +243,11 @@ int pressure_layout(const pm_mesh *mesh, int32_t *node_new2old, int32_t *elem_ne
 int pressure_set_variant(pm_handle *h, int32_t variant);
 
 /* Kernel timing with HIP events on the solve stream.  enable != 0 starts
- * recording the duration of every operator-apply launch inside
- * pressure_solve (and resets the totals); pressure_timing_read returns the
+ * recording the duration of a sample of the operator-apply launches inside
+ * pressure_solve, iterations 1, 33, 65, ... of each solve that ran a full
+ * iteration (and resets the totals); pressure_timing_read returns the
  * number of recorded launches and their summed duration in milliseconds.
- * Recording adds two event records per launch. */
+ * Each sampled launch gets two event records. */
 int pressure_timing_enable(pm_handle *h, int32_t enable);
 int pressure_timing_read(pm_handle *h, int64_t *launches, double *total_ms);
 

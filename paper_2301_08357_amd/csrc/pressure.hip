@@ -1796,7 +1796,7 @@ struct pm_handle {
 
 namespace {
 
-constexpr int TIMING_STRIDE = 8;
+constexpr int TIMING_STRIDE = 32;
 
 #define HIPCK(x)                               \
     do {                                       \
