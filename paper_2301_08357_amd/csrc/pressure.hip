@@ -2291,7 +2291,7 @@ void pressure_destroy(pm_handle *h)
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
-                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl};
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.trec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);

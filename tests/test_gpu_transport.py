@@ -279,3 +279,33 @@ def test_transport_and_post_projection_full_size_sampled_cells():
     # the post-projection of the GPU transport output on the same sub-mesh
     post, _, _ = op.post_projection(sm, rho[rows], we[rows], wu[rows], p_new, 1.4, dt, faces)
     assert _close(we_post[cells], post[loc], we[cells])
+
+
+def test_handle_returns_its_device_memory():
+    """Setup, the dual cells, a projection stage and a transport step (whose
+    element records take 64 B per dual cell) and destroy, three times over:
+    the device's free memory comes back each time."""
+    m = smesh.structured_mesh(3, 40, jitter=0.2, seed=3)
+    print("case handle memory, 40^3", flush=True)
+    s = _system(m)
+    fv, fe, _ = s.dual_faces()
+    inp = sproj.fields(m, fv, fe, seed=13)
+    args = [_dev(inp[k]) for k in ("rho_f", "wu_f", "we_f", "p")]
+    outs = [torch.empty_like(args[0]), torch.empty_like(args[1]), torch.empty_like(args[2])]
+    proj = [torch.empty_like(args[3]), torch.empty_like(args[1]), torch.empty(m.n_elems, dtype=torch.float64,
+                                                                                device=DEV)]
+
+    def cycle(system):
+        system.transport(*args, 0.01, mu=1e-3, lam=1e-3, rho_out=outs[0], wu_out=outs[1], we_out=outs[2])
+        system.projection(args[0], args[2], args[1], args[3], 1.4, 0.01, n_picard=1, rtol=1e-8, p_out=proj[0],
+                          wu_out=proj[1], h_out=proj[2])
+        torch.cuda.synchronize()
+        system.close()
+
+    cycle(s)
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(3):
+        cycle(_system(m))
+    free1 = torch.cuda.mem_get_info()[0]
+    F = fv.shape[0]
+    assert free0 - free1 < 16 * F, (free0 - free1, 64 * F)
