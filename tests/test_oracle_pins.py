@@ -195,6 +195,78 @@ def test_mass_integrates_domain_and_patch_test():
         assert np.abs(Kc @ np.ones(m.n_nodes)).max() < 1e-12
 
 
+def _numpy_element_sum(dim, coords, elems, coef, alpha, beta, dirichlet, x):
+    """Brute force: y = A_D x from element matrices written out with NumPy
+    (gradients of the barycentric coordinates from numpy.linalg.inv of the
+    edge matrix, |T| from numpy.linalg.det), scattered with numpy.add.at,
+    then the Dirichlet rows and columns eliminated.  No oracle code."""
+    X = coords[elems]                                    # [E, d+1, d]
+    J = np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))   # columns e_k
+    vol = np.abs(np.linalg.det(J)) / math.factorial(dim)
+    Gi = np.linalg.inv(J)                                # rows: grad(phi_k), k = 1..d
+    G = np.concatenate([-Gi.sum(axis=1, keepdims=True), Gi], axis=1)   # [E, d+1, d]
+    K = np.einsum("eak,ebk->eab", G, G) * (beta * coef * vol)[:, None, None]
+    Mm = (np.ones((dim + 1, dim + 1)) + np.eye(dim + 1)) / ((dim + 1) * (dim + 2))
+    Ae = K + alpha * vol[:, None, None] * Mm[None]
+    free = dirichlet == 0
+    xf = np.where(free, x, 0.0)
+    contrib = np.einsum("eab,eb->ea", Ae, xf[elems])
+    y = np.zeros(coords.shape[0])
+    np.add.at(y, elems.ravel(), contrib.ravel())
+    return np.where(free, y, x)
+
+
+@pytest.mark.parametrize("dim,n,seed", [(2, 11, 3), (3, 5, 4)])
+def test_apply_elements_pinned(dim, n, seed):
+    """oracle.apply_elements, both the whole-vector and the rows= branch,
+    against (1) the oracle's assembled operator and (2) a NumPy element sum
+    written out here: jittered mesh, lognormal coefficient, alpha and beta
+    both nonzero, Dirichlet nodes on the boundary and inside, elements in a
+    shuffled order with some of them negatively oriented, and a random x
+    (so a wrong local index, a kept Dirichlet column or a dropped mass or
+    stiffness term changes the result)."""
+    m = smesh.structured_mesh(dim, n, jitter=0.2, seed=seed)
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(m.n_elems)
+    elems = m.elems[perm].copy()
+    flip = rng.random(m.n_elems) < 0.3
+    elems[flip, 1], elems[flip, 2] = m.elems[perm][flip, 2], m.elems[perm][flip, 1]
+    coef = 1.0 / fields.rho_lognormal(seed, m.n_elems)
+    alpha, beta = 0.37, 1.9
+    dirichlet = m.dirichlet.copy()
+    inner = np.nonzero(dirichlet == 0)[0]
+    dirichlet[rng.choice(inner, 3, replace=False)] = 1
+    x = rng.normal(size=m.n_nodes)
+    y = oracle.apply_elements(dim, m.coords, elems, coef, alpha, beta, dirichlet, x)
+    A = oracle.assemble(dim, m.coords, m.elems[perm], coef, alpha, beta, dirichlet)
+    bound = np.abs(A.to_scipy()) @ np.abs(x)
+    assert np.all(np.abs(y - A.matvec(x)) <= 1e-14 * bound)
+    yn = _numpy_element_sum(dim, m.coords, elems, coef, alpha, beta, dirichlet, x)
+    assert np.all(np.abs(y - yn) <= 1e-13 * bound)
+    # Dirichlet rows are the identity; free rows see no Dirichlet column
+    d = dirichlet == 1
+    assert np.array_equal(y[d], x[d])
+    x2 = x.copy()
+    x2[d] += 5.0
+    y2 = oracle.apply_elements(dim, m.coords, elems, coef, alpha, beta, dirichlet, x2)
+    assert np.array_equal(y2[~d], y[~d])
+    # the rows= branch: random free and Dirichlet rows, repeats and the ends
+    rows = np.concatenate([rng.choice(m.n_nodes, 40), np.nonzero(d)[0][:4], [0, m.n_nodes - 1, 5, 5]])
+    yr = oracle.apply_elements(dim, m.coords, elems, coef, alpha, beta, dirichlet, x, rows=rows)
+    assert np.all(np.abs(yr - yn[rows]) <= 1e-13 * bound[rows])
+    yall = oracle.apply_elements(dim, m.coords, elems, coef, alpha, beta, dirichlet, x,
+                                 rows=np.arange(m.n_nodes))
+    assert np.all(np.abs(yall - y) <= 1e-14 * bound)
+    # without Dirichlet nodes (the unmerged periodic use): the plain A x
+    yo = oracle.apply_elements(dim, m.coords, elems, coef, alpha, beta, None, x)
+    zero = np.zeros(m.n_nodes, dtype=np.uint8)
+    yno = _numpy_element_sum(dim, m.coords, elems, coef, alpha, beta, zero, x)
+    b0 = np.abs(oracle.assemble(dim, m.coords, m.elems[perm], coef, alpha, beta).to_scipy()) @ np.abs(x)
+    assert np.all(np.abs(yo - yno) <= 1e-13 * b0)
+    yor = oracle.apply_elements(dim, m.coords, elems, coef, alpha, beta, None, x, rows=rows)
+    assert np.all(np.abs(yor - yno[rows]) <= 1e-13 * b0[rows])
+
+
 @pytest.mark.parametrize("dim,n", [(2, 5), (3, 3)])
 def test_spd_and_symmetric(dim, n):
     m = smesh.structured_mesh(dim, n, jitter=0.2, seed=9)
