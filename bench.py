@@ -1,15 +1,22 @@
 """Benchmark of the matrix-free P1 pressure solve on one MI355X.
 
-Workload (one step): the 3D unit cube, 64^3 cells x 6 tetrahedra
-(1,572,864 tets, 274,625 nodes, Morton order), c = 1/rho with
-rho ~ U[0.5, 2] per element, and one FP64 CG solve to rtol 1e-10 from
-x0 = 0 for each mass weight w in {1e-6, 1e-3, 1}.  The right-hand side is
-b = A_D x* with x* = prod sin(pi x_i), computed once before timing.
+Default workload (one step): the 3D unit cube, 160^3 cells x 6 tetrahedra
+(24,576,000 tets, 4,173,281 nodes, Morton order), interior nodes jittered
+by up to 0.2h, c = 1/rho with rho lognormal(0, 0.5) per element, w = 1e-4,
+and one FP64 CG solve to rtol 1e-10 from x0 = 0.  The right-hand side is
+b = A_D x* with x* = prod sin(pi x_i), computed once before timing.  The
+same system is then solved by FP32-inner defect correction (FP64
+corrections), timed after the FP64 region.
 
 Prints one JSON line: GDOF*iter/s (free nodes x CG iterations per second,
 whole job), solves/s, p50/p99 solve latency, the roofline of the operator
 apply kernel (algorithmic bytes / measured average kernel duration against
-the 8 TB/s HBM peak) and the CPU oracle timed on a bounded sample.
+the 8 TB/s HBM peak, with the rocprofv3-measured HBM bytes when the
+committed record matches the kernel source), the mixed-precision speedup,
+two extra legs (the 64^3 cube over w in {1e-6, 1e-3, 1}, and the latency of
+the 2D 32 x 32 square at rtol 1e-12) and the CPU oracle timed on the host
+(one thread on a bounded sample, and all host cores on the whole solve,
+whose solution the GPU's are compared with).
 """
 
 import argparse
@@ -26,23 +33,36 @@ if ROOT not in sys.path:
 
 METRIC = "pressure-solve GDOF·iter/s + % HBM peak; solves/s & p50/p99 latency at rtol 1e-10"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_cube64_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2301_08357_amd", "csrc", "pressure.hip")
 
 
-def measured_traffic(n_tiles, tiled):
+def measured_traffic(workload, n_tiles, tiled):
     """HBM bytes per apply launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE measurement, if it was taken on the current kernel source and
-    the same launch: the tiled kernel over the same number of tiles."""
+    WRITE_SIZE measurement of this workload (profiles/apply_<workload>_traffic.json),
+    if it was taken on the current kernel source and the same launch: the
+    tiled kernel over the same number of tiles."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", "apply_%s_traffic.json" % workload)
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(path))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != sha or not tiled or rec.get("n_tiles") != n_tiles:
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_info():
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cpu
 
 
 def main():
@@ -57,9 +77,13 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-2,
                     help="residual drop of the FP32 inner CG between FP64 corrections (mixed solve)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
-    ap.add_argument("--workload", default="cube64", choices=["cube64", "cube160", "cube160p", "projection160", "transport160", "timestep160", "batch256",
-                             "serve", "copy"],
-                    help="cube64 (default line) or one of the other synthetic workloads")
+    ap.add_argument("--workload", default="cube160",
+                    choices=["cube160", "cube64", "cube160p", "projection160", "transport160", "timestep160",
+                             "batch256", "serve", "copy"],
+                    help="cube160 (default line) or one of the other synthetic workloads")
+    ap.add_argument("--no-extras", action="store_true", help="cube160: skip the cube64 and tgv2d_32 legs")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="single-thread oracle sample length (seconds of CG iterations)")
     ap.add_argument("--requests", type=int, default=10000, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving: HBM budget (0 = 80%% of free)")
     ap.add_argument("--serve-mixed", action="store_true", help="serving: mixed-precision solves")
@@ -74,10 +98,8 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import paper_2301_08357_amd as pm
-    from synth import workloads
-
+    if args.workload == "cube64":
+        return bench_cube64(args)
     if args.workload in ("cube160", "cube160p"):
         return bench_cube160(args)
     if args.workload == "projection160":
@@ -92,6 +114,15 @@ def main():
         return bench_serve(args)
     if args.workload == "copy":
         return bench_copy(args)
+
+
+def bench_cube64(args):
+    """The 64^3 cube (1,572,864 tets, 274,625 nodes, no jitter), c = 1/rho
+    with rho ~ U[0.5, 2] per element, one FP64 CG solve to rtol 1e-10 from
+    x0 = 0 for each w in {1e-6, 1e-3, 1} per step."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from synth import workloads
     dev = torch.device("cuda:0")
     ws = workloads.CUBE64_W
     probs = [workloads.cube64(w) for w in ws]
@@ -171,7 +202,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(info["n_tiles"], args.variant != pm.PM_VARIANT_NODE),
+            "traffic": measured_traffic("cube64", info["n_tiles"], args.variant != pm.PM_VARIANT_NODE),
             "kernel": "operator apply (fused CG iteration)",
             "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg_ms * 1e3, 3),
             "launches": launches,
@@ -185,7 +216,7 @@ def main():
     if not args.no_mixed:
         out["mixed"] = mixed_comparison(systems, rhs, xstar, args, elapsed / len(lat))
     if not args.no_cpu:
-        out["cpu_baseline"], x_oracle, b_oracle = cpu_baseline(probs)
+        out["cpu_baseline"], x_oracle, b_oracle = cpu_baseline_cube64(probs)
         # error of each GPU solve against the oracle's FP64 solution of the
         # same system (the oracle's right-hand side), per w
         def vs_oracle(xg, xo):
@@ -212,8 +243,10 @@ def _common(args, metric_value, unit, ms_per_step, config, extra):
 
 def bench_cube160(args):
     """160^3 x 6 tets, jitter 0.2h, rho lognormal(0, 0.5), w = 1e-4: FP64 CG
-    and FP32-inner defect correction, both to rtol 1e-10.  cube160p: the same
-    recipe on the fully periodic mesh with merged images."""
+    and FP32-inner defect correction, both to rtol 1e-10 (the default line,
+    with the cube64 and tgv2d_32 legs and the CPU oracle).  cube160p: the
+    same recipe on the fully periodic mesh with merged images; --lumped: the
+    lumped mass matrix (these two print the solve and roofline only)."""
     import torch
     import paper_2301_08357_amd as pm
     from synth import workloads
@@ -221,8 +254,12 @@ def bench_cube160(args):
     prob = workloads.cube160p() if periodic else workloads.cube160()
     if args.lumped:
         prob = workloads.lumped(prob)
+    main_line = not periodic and not args.lumped
     tile_flag = {0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
+    t_setup = time.perf_counter()
     s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER | tile_flag)
+    t_setup = time.perf_counter() - t_setup
+    s.set_variant(args.variant)
     info = s.info()
     xs = torch.tensor(prob.extra["xstar"], device="cuda")
     b = s.apply(xs)
@@ -230,34 +267,197 @@ def bench_cube160(args):
         s.solve(b, rtol=args.rtol)
     s.timing_enable(True)
     torch.cuda.synchronize()
+    lat, its = [], []
     t0 = time.perf_counter()
-    its = []
     for _ in range(args.steps):
+        ta = time.perf_counter()
         r = s.solve(b, rtol=args.rtol)
+        lat.append(time.perf_counter() - ta)
         its.append(r.iters)
+        if r.status != 0:
+            raise RuntimeError("solve status %d" % r.status)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     n, ms = s.timing_read()
+    s.timing_enable(False)
     avg = ms / max(n, 1)
     achieved = info["apply_bytes"] / (avg * 1e-3) / 1e9
     value = info["n_free"] * sum(its) / el / 1e9
-    mixed = None if args.no_mixed else mixed_comparison([s], [b], xs, args, el / args.steps)
     err = float(torch.linalg.norm(r.p - xs) / torch.linalg.norm(xs))
     if periodic:
         what = ("cube160p: unit cube 160^3 x 6 tets, periodic along x, y and z with merged images "
                 "(24,576,000 tets, 4,096,000 nodes)")
     else:
         what = "cube160: unit cube 160^3 x 6 tets (24,576,000 tets, 4,173,281 nodes)"
-    _common(args, round(value, 4), "GDOF*iter/s", round(el / args.steps * 1e3, 3),
-            {"workload": what + ", jitter 0.2h, rho~lognormal(0,0.5), w=1e-4, %s mass, FP64 CG to rtol %g; "
-                                "one step = one solve" % ("lumped" if args.lumped else "consistent", args.rtol),
-             "n_free": info["n_free"], "iterations": its[0]},
-            {"solves_per_s": round(args.steps / el, 3), "rel_error_vs_manufactured": err,
-             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                          "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg * 1e3, 3)},
-             "mixed": mixed})
+    tiled = args.variant != pm.PM_VARIANT_NODE
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.workload, info["n_tiles"], tiled) if main_line else None,
+            "kernel": "operator apply (fused CG iteration)",
+            "bytes_per_launch": info["apply_bytes"], "avg_launch_us": round(avg * 1e3, 3), "launches": n}
+    if roof["traffic"]:
+        # the rate of the measured HBM traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy)
+        roof["traffic_achieved"] = round(roof["traffic"] / (avg * 1e-3) / 1e9, 1)
+        roof["traffic_frac"] = round(roof["traffic_achieved"] / HBM_PEAK_GBS, 4)
+    out = {"metric": METRIC, "value": round(value, 4), "unit": "GDOF*iter/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered 160^3 Kuhn mesh, rho lognormal)",
+           "config": {"workload": what + ", jitter 0.2h, rho~lognormal(0,0.5), w=1e-4, %s mass, FP64 matrix-free CG "
+                                         "to rtol %g from x0=0, b = A x* with x* = prod sin(pi x_i), Morton order; one "
+                                         "step = one solve" % ("lumped" if args.lumped else "consistent", args.rtol),
+                      "n_nodes": info["n_nodes"], "n_free": info["n_free"], "n_elems": info["n_elems"],
+                      "rtol": args.rtol, "iterations": its[0]},
+           "solves_per_s": round(args.steps / el, 3),
+           "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+           "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+           "setup_s": round(t_setup, 2),
+           "rel_error_vs_manufactured": err, "roofline": roof}
+    if not args.no_mixed:
+        out["mixed"] = mixed_comparison([s], [b], xs, args, el / args.steps)
+    if main_line and not args.no_extras:
+        out["cube64"] = extra_cube64(args)
+        out["tgv2d_32"] = extra_tgv2d32(args)
+    if main_line and not args.no_cpu:
+        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline_cube160(prob, s, args)
+    print(json.dumps(out), flush=True)
     s.close()
+
+
+def extra_cube64(args, reps=3):
+    """The 64^3 cube (no jitter, rho ~ U[0.5, 2]) over w in {1e-6, 1e-3, 1}:
+    reps FP64 solves per w to rtol 1e-10, with the apply's roofline."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from synth import workloads
+    probs = [workloads.cube64(w) for w in workloads.CUBE64_W]
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    info = systems[0].info()
+    xs = torch.tensor(probs[0].extra["xstar"], device="cuda")
+    rhs = [q.apply(xs) for q in systems]
+    for q, b in zip(systems, rhs):
+        q.solve(b, rtol=args.rtol)
+        q.timing_enable(True)
+    torch.cuda.synchronize()
+    lat, its = [], []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for q, b in zip(systems, rhs):
+            ta = time.perf_counter()
+            r = q.solve(b, rtol=args.rtol)
+            lat.append(time.perf_counter() - ta)
+            its.append(r.iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nl, ms = 0, 0.0
+    for q in systems:
+        a, t = q.timing_read()
+        nl, ms = nl + a, ms + t
+        q.close()
+    avg = ms / max(nl, 1)
+    ach = info["apply_bytes"] / (avg * 1e-3) / 1e9
+    return {"workload": "cube64: 64^3 x 6 tets (1,572,864 tets, 274,625 nodes), no jitter, rho~U[0.5,2], "
+                        "w in {1e-6,1e-3,1}, FP64 CG to rtol %g, %d solves per w" % (args.rtol, reps),
+            "value": round(info["n_free"] * sum(its) / el / 1e9, 4), "unit": "GDOF*iter/s",
+            "iterations": its[:3], "solves_per_s": round(len(lat) / el, 2),
+            "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "avg_launch_us": round(avg * 1e3, 3), "bytes_per_launch": info["apply_bytes"],
+                         "traffic": measured_traffic("cube64", info["n_tiles"], True)}}
+
+
+def extra_tgv2d32(args, solves=300):
+    """The 2D unit square, 32 x 32 cells x 2 triangles (2048 tris, 1089
+    nodes), jitter 0.2h, c = 1, w = 1e-2, Dirichlet boundary, FP64 CG to
+    rtol 1e-12 from x0 = 0: latency of single solves (a latency-bound size).
+    The right-hand side is b = A_D p* with p* = sin(pi x) sin(pi y) at the
+    nodes (computed by the library, so that the timed path calls nothing
+    else)."""
+    import torch
+    import paper_2301_08357_amd as pm
+    from synth import fields, workloads
+    prob = workloads.tgv2d(32)
+    q = pm.PressureSystem.from_problem(prob)
+    b = q.apply(torch.tensor(fields.sine_product(prob.mesh.coords), device="cuda"))
+    for _ in range(10):
+        q.solve(b, rtol=1e-12)
+    torch.cuda.synchronize()
+    lat, its = [], []
+    t0 = time.perf_counter()
+    for _ in range(solves):
+        ta = time.perf_counter()
+        r = q.solve(b, rtol=1e-12)
+        lat.append(time.perf_counter() - ta)
+        its.append(r.iters)
+    el = time.perf_counter() - t0
+    nfree = q.info()["n_free"]
+    q.close()
+    return {"workload": "tgv2d_32: unit square 32x32 x 2 tris (2048 tris, 1089 nodes), jitter 0.2h, c=1, w=1e-2, "
+                        "FP64 CG to rtol 1e-12, b = A_D p*, %d single solves" % solves,
+            "solves_per_s": round(solves / el, 1), "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4), "iterations": its[0],
+            "GDOF_iter_per_s": round(nfree * sum(its) / el / 1e9, 4)}
+
+
+def cpu_baseline_cube160(prob, s, args):
+    """The CPU oracle (assembled CSR, textbook CG) on the cube160 system:
+    one thread on a bounded sample of CG iterations (about --cpu-seconds),
+    and all host cores (OpenMP SpMV rows, fixed-order chunked dots) on the
+    whole solve to rtol, bounded at about 60 s.  Assembly is not timed.
+    Then the GPU solves (FP64 and mixed) of the oracle's right-hand side
+    b = A x*, each accepted by the oracle's operator and compared with the
+    oracle's solution and with x*."""
+    import torch
+    import oracle
+    m = prob.mesh
+    t0 = time.perf_counter()
+    A = oracle.assemble_problem(prob)
+    t_asm = time.perf_counter() - t0
+    xs = prob.extra["xstar"]
+    b = A.matvec(xs)
+    nfree = int((m.dirichlet == 0).sum())
+    cores = len(os.sched_getaffinity(0))
+
+    def timed_cg(k, rtol=1e-300):
+        ta = time.perf_counter()
+        x, st, it, _, tr = oracle.cg(A, b, rtol=rtol, max_iter=k, dirichlet=m.dirichlet)
+        return time.perf_counter() - ta, x, st, it, tr
+
+    oracle.set_threads(1)
+    t8 = timed_cg(8)[0]
+    k1 = max(8, int(8 * args.cpu_seconds / max(t8, 1e-3)))
+    t1, _, _, it1, _ = timed_cg(k1)
+    single = nfree * it1 / t1 / 1e9
+    oracle.set_threads(cores)
+    t8 = timed_cg(8)[0]
+    cap = max(8, int(8 * 60.0 / max(t8, 1e-3)))
+    ta, x_o, st_o, it_o, tr_o = timed_cg(min(20000, cap), rtol=args.rtol)
+    oracle.set_threads(1)
+    allc = nfree * it_o / ta / 1e9
+    base = {"value": round(allc, 5), "unit": "GDOF*iter/s", "cores": cores, "kind": "oracle",
+            "sample": "cube160 FP64 CG (assembled CSR, assembly %.1f s not timed) on all %d host cores: %d iterations "
+                      "in %.1f s (%s); one thread: %d iterations in %.1f s = %.5f GDOF*iter/s; %s"
+                      % (t_asm, cores, it_o, ta, "converged" if st_o == 0 else "bounded sample", k1, t1, single,
+                         cpu_info()),
+            "single_thread": {"value": round(single, 5), "iterations": it1, "seconds": round(t1, 2)},
+            "all_cores": {"value": round(allc, 5), "iterations": it_o, "seconds": round(ta, 2), "status": st_o}}
+    bd = torch.tensor(b, device="cuda")
+    checks = {"rhs": "the oracle's b = A x*"}
+    for name, res in (("fp64", s.solve(bd, rtol=args.rtol)),
+                      ("mixed", None if args.no_mixed else s.solve_mixed(bd, rtol=args.rtol,
+                                                                          inner_rtol=args.inner_rtol))):
+        if res is None:
+            continue
+        x = res.p.cpu().numpy()
+        rec = {"status": res.status, "iterations": res.iters,
+               "oracle_relres": float(np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)),
+               "rel_error_vs_xstar": float(np.linalg.norm(x - xs) / np.linalg.norm(xs))}
+        if st_o == 0:
+            rec["rel_diff_vs_oracle_solution"] = float(np.linalg.norm(x - x_o) / np.linalg.norm(x_o))
+        checks[name] = rec
+    checks["oracle_iterations"] = it_o
+    return base, checks
 
 
 def bench_projection(args):
@@ -657,7 +857,7 @@ def mixed_comparison(systems, rhs, xstar, args, fp64_solve_s):
             "max_rel_diff_vs_fp64_solution": worst_diff}
 
 
-def cpu_baseline(probs, min_seconds=10.0):
+def cpu_baseline_cube64(probs, min_seconds=10.0):
     """The CPU oracle (assembled CSR + textbook CG, one thread) on the same
     three systems, one solve each, the round of three repeated until at
     least min_seconds of solve time; assembly is not timed.  Returns the

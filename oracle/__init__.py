@@ -55,7 +55,7 @@ def build():
     """Compile the oracle with gcc (no FMA contraction)."""
     os.makedirs(_LIBDIR, exist_ok=True)
     tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-shared", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
                            _SRC, "-o", tmp, "-lm"])
     os.replace(tmp, _LIB)
 
@@ -93,6 +93,8 @@ def lib():
     L.orc_cg_mixed.argtypes = [P, P, P, P, dbl, dbl, i32, i32, P, P, P]
     L.orc_apply_elements.restype = ctypes.c_int
     L.orc_apply_elements.argtypes = [ctypes.c_int, i64, i64, P, P, P, dbl, dbl, P, P, P, P, i64, P]
+    L.orc_set_threads.restype = None
+    L.orc_set_threads.argtypes = [ctypes.c_int]
     L.orc_layout.restype = ctypes.c_int
     L.orc_layout.argtypes = [ctypes.c_int, i64, i64, P, P, P, P, P, P, P, P]
     _lib = L
@@ -277,6 +279,13 @@ def cg_mixed(A, b, x0=None, rtol=1e-10, inner_rtol=1e-5, max_outer=50, max_inner
                             int(max_outer), int(max_inner), ctypes.byref(o), ctypes.byref(i),
                             ctypes.byref(tr))
     return x, st, o.value, i.value, tr.value
+
+
+def set_threads(n):
+    """Host threads of cg (1 = the plain sequential oracle).  More threads
+    split the SpMV rows (same bits) and sum each dot product over n
+    contiguous chunks in chunk order (a fixed order for a given n)."""
+    lib().orc_set_threads(int(n))
 
 
 def apply_elements(dim, coords, elems, coef, alpha, beta, dirichlet, x, rows=None):

@@ -324,9 +324,20 @@ void orc_csr_free(void *h)
     free(A);
 }
 
+/* Host threads of the CG loops (the CPU baseline's all-core leg; default
+ * 1).  With T > 1 the SpMV rows and the vector updates are split over T
+ * OpenMP threads (each row still sums in CSR order, so the SpMV gives the
+ * same bits), and a dot product is the sum, in chunk order, of T sequential
+ * sums over contiguous chunks: a fixed order for a given T. */
+static int orc_nthreads = 1;
+
+void orc_set_threads(int t) { orc_nthreads = t < 1 ? 1 : t; }
+
 void orc_spmv(const void *h, const double *x, double *y)
 {
     const orc_csr *A = h;
+    const int T = orc_nthreads;
+#pragma omp parallel for schedule(static) num_threads(T) if (T > 1)
     for (int64_t i = 0; i < A->n; ++i) {
         double s = 0.0;
         for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) s += A->val[k] * x[A->col[k]];
@@ -336,8 +347,23 @@ void orc_spmv(const void *h, const double *x, double *y)
 
 static double orc_dot(int64_t n, const double *a, const double *b)
 {
+    const int T = orc_nthreads;
+    if (T == 1) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+        return s;
+    }
+    double part[256];
+    const int nc = T < 256 ? T : 256;
+#pragma omp parallel for schedule(static, 1) num_threads(T)
+    for (int c = 0; c < nc; ++c) {
+        const int64_t lo = n * c / nc, hi = n * (c + 1) / nc;
+        double s = 0.0;
+        for (int64_t i = lo; i < hi; ++i) s += a[i] * b[i];
+        part[c] = s;
+    }
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int c = 0; c < nc; ++c) s += part[c];
     return s;
 }
 
@@ -387,10 +413,13 @@ int orc_cg(const void *h, const uint8_t *dirichlet, const double *b, double *x,
             double pq = orc_dot(n, p, q);
             if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_EBREAKDOWN; goto done; }
             double a = rr / pq;
+            const int T = orc_nthreads;
+#pragma omp parallel for schedule(static) num_threads(T) if (T > 1)
             for (int64_t i = 0; i < n; ++i) { x[i] += a * p[i]; r[i] -= a * q[i]; }
             double rr1 = orc_dot(n, r, r);
             double bt = rr1 / rr;
             rr = rr1;
+#pragma omp parallel for schedule(static) num_threads(T) if (T > 1)
             for (int64_t i = 0; i < n; ++i) p[i] = r[i] + bt * p[i];
             ++k;
             if (hist) hist[k] = sqrt(rr) / bnorm;

@@ -69,7 +69,7 @@ class PressureServer:
 
     def __init__(self, problems, budget_bytes, max_in_flight=64, rtol=1e-10, max_iter=20000,
                  graph_iters=16, tiles_per_slot=4, nodes_per_lane=8, keep_x0=False, mixed=False,
-                 inner_rtol=1e-2):
+                 inner_rtol=1e-2, on_result=None, retain=False):
         self.problems = problems
         self.budget = int(budget_bytes)
         self.max_in_flight = int(max_in_flight)
@@ -79,6 +79,14 @@ class PressureServer:
         self.tps = tiles_per_slot
         self.npl = nodes_per_lane
         self.keep_x0 = keep_x0
+        # A finished request's device tensors (rhs, warm start, result) are
+        # handed to on_result(req, p) and then released, so the resident
+        # meshes and their last solutions are all the server holds.  With
+        # retain set they stay on the request (for callers that inspect
+        # them afterwards) and count against the budget.
+        self.on_result = on_result
+        self.retain = bool(retain)
+        self.retained = 0                             # bytes held by finished requests
         self.mixed = bool(mixed)
         self.inner_rtol = inner_rtol
         self.flags = _lib.PM_FP64 | (_lib.PM_FP32_INNER if self.mixed else 0)
@@ -96,12 +104,13 @@ class PressureServer:
 
     # -- residency ---------------------------------------------------------
     def _used(self):
-        return sum(self.cost[m] for m in self.resident)
+        return sum(self.cost[m] for m in self.resident) + self.retained
 
     def _make_room(self, m, busy):
         """Evict idle meshes (least recently used first) until mesh m fits."""
-        if self.cost[m] > self.budget:
-            raise ValueError("mesh %d needs %d bytes, more than the budget" % (m, self.cost[m]))
+        if self.cost[m] + self.retained > self.budget:
+            raise ValueError("mesh %d needs %d bytes, more than the budget left by %d bytes of retained "
+                             "results" % (m, self.cost[m], self.retained))
         while self._used() + self.cost[m] > self.budget:
             victim = next((v for v in self.resident if v not in busy), None)
             if victim is None:
@@ -193,8 +202,15 @@ class PressureServer:
                     r = in_flight.pop(m)
                     res = self.batch.finish(self.slot[m], r.rhs, self.rtol)
                     r.done = clock() - t0
-                    r.iters, r.status, r.true_relres, r.result = res.iters, res.status, res.true_relres, res.p
+                    r.iters, r.status, r.true_relres = res.iters, res.status, res.true_relres
                     self.last[m] = res.p
+                    if self.on_result is not None:
+                        self.on_result(r, res.p)
+                    if self.retain:
+                        r.result = res.p
+                        self.retained += sum(8 * t.numel() for t in (r.rhs, r.x0, r.result) if t is not None)
+                    else:
+                        r.rhs = r.x0 = None
                     finished.append(r)
                 self.stats.t_finish += clock() - t_d
             elif pending:

@@ -152,3 +152,58 @@ def test_mixed_batch_matches_single_mixed():
     batch.close()
     for s in systems:
         s.close()
+
+
+def _real_mix_sample(k=16):
+    """k meshes of the 256-mesh batched workload itself: its largest 2D and
+    3D meshes, its smallest one and its extreme mass weights, the rest
+    spread evenly over the list (seeded, same meshes every run)."""
+    params = workloads.batch_params()
+    size = [(n + 1) ** d for d, n, w in params]
+    idx = set()
+    for d in (2, 3):
+        same = [i for i in range(len(params)) if params[i][0] == d]
+        idx.add(max(same, key=lambda i: size[i]))
+    idx.add(min(range(len(params)), key=lambda i: size[i]))
+    idx.add(min(range(len(params)), key=lambda i: params[i][2]))
+    idx.add(max(range(len(params)), key=lambda i: params[i][2]))
+    for i in np.linspace(0, len(params) - 1, 2 * k).astype(int):
+        if len(idx) >= k:
+            break
+        idx.add(int(i))
+    return [workloads.batch_problem(i, params) for i in sorted(idx)]
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batch_real_mix_at_tuned_shape(mixed):
+    """16 meshes of the real 256-mesh mix (up to 2e5 nodes, both its
+    largest 2D and 3D meshes) in the launch shape the autotuner picks for
+    that mix on the MI355X (8 Morton tiles per apply slot, 4 nodes per lane
+    of an update slot): every result accepted by the oracle's operator at
+    1.05 x rtol, and equal to the single solve on the same grids."""
+    probs = _real_mix_sample()
+    assert max(p.mesh.n_nodes for p in probs if p.mesh.dim == 2) > 1.5e5
+    assert max(p.mesh.n_nodes for p in probs if p.mesh.dim == 3) > 1.5e5
+    print("case real mix mixed=%s" % mixed, [(p.mesh.dim, p.mesh.n_nodes) for p in probs], flush=True)
+    As = [oracle.assemble_problem(p) for p in probs]
+    bs = [A.matvec(p.extra["xstar"]) for p, A in zip(probs, As)]
+    flags = pm.PM_FP64 | (pm.PM_FP32_INNER if mixed else 0)
+    systems = [pm.PressureSystem.from_problem(p, flags=flags) for p in probs]
+    batch = pm.PressureBatch(systems, tiles_per_slot=8, nodes_per_lane=4, mixed=mixed, inner_rtol=1e-2)
+    rhs = [_dev(b) for b in bs]
+    code, res = batch.solve(rhs, rtol=1e-10)
+    assert code == 0
+    xb = [_host(r.p).copy() for r in res]
+    batch.close()
+    for p, A, b, r, x in zip(probs, As, bs, res, xb):
+        assert r.status == 0 and r.true_relres <= 1e-10
+        accept = np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)
+        assert accept <= 1.05e-10, (p.name, accept)
+        err = np.linalg.norm(x - p.extra["xstar"]) / np.linalg.norm(p.extra["xstar"])
+        print(p.name, p.mesh.dim, p.mesh.n_nodes, "iters", r.iters, "accept %.2e err %.2e" % (accept, err),
+              flush=True)
+    for s, b, r, x in zip(systems, rhs, res, xb):
+        single = s.solve_mixed(b, rtol=1e-10, inner_rtol=1e-2) if mixed else s.solve(b, rtol=1e-10)
+        assert single.iters == r.iters
+        assert np.array_equal(_host(single.p).view(np.uint64), x.view(np.uint64))
+        s.close()

@@ -4,12 +4,14 @@ Requests for several meshes arrive over time; the server admits them by HBM
 budget (evicting idle meshes), overlaps their solves in one batch and warm
 starts each mesh from its previous solution.  Every result must equal the
 same solve (same right-hand side, same initial guess, same launch grids) run
-alone, bit for bit, and reach the requested tolerance.
+alone, bit for bit, and the CPU oracle's assembled operator must accept it
+at the requested tolerance (||rhs - A x|| <= 1.05 rtol ||rhs||).
 """
 
 import numpy as np
 import pytest
 
+import oracle
 import paper_2301_08357_amd as pm
 from paper_2301_08357_amd.serve import PressureServer, Request
 from synth import fields, workloads
@@ -52,26 +54,62 @@ def test_serving_results_equal_alone_and_in_the_mix(mixed):
     reqs = [Request(rid=i, mesh=int(m), arrival=float(t)) for i, (t, m) in enumerate(zip(arrivals, meshes))]
     costs = [pm.footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems, flags) + 8 * p.mesh.n_nodes for p in probs]
     budget = sum(sorted(costs)[-3:])           # at most ~3 meshes resident: forces evictions
+    # results leave the device as they finish (the server then releases
+    # the request's tensors)
+    kept = {}
+
+    def on_result(r, p):
+        kept[r.rid] = (r.rhs.cpu().numpy(), None if r.x0 is None else r.x0.cpu().numpy(), p.cpu().numpy())
+
     srv = PressureServer(probs, budget, max_in_flight=3, rtol=1e-10, graph_iters=4, tiles_per_slot=2,
-                         nodes_per_lane=4, keep_x0=True, mixed=mixed, inner_rtol=1e-2)
+                         nodes_per_lane=4, keep_x0=True, mixed=mixed, inner_rtol=1e-2, on_result=on_result)
     done = srv.run(reqs, rhs_fn)
     st = srv.stats
     print("stats", st, flush=True)
     assert st.n == 30 and st.evictions > 0 and st.max_in_flight_seen >= 2
     assert all(r.status == 0 and r.true_relres <= 1e-10 for r in done)
     assert any(not r.cold for r in done)
-    # replay every request alone on a fresh handle with the same grids
+    assert all(r.rhs is None and r.x0 is None and r.result is None for r in done) and srv.retained == 0
     srv.close()
+    # the oracle accepts every served result
+    ops = [oracle.assemble_problem(p) for p in probs]
+    for r in done:
+        b, _, x = kept[r.rid]
+        acc = np.linalg.norm(b - ops[r.mesh].matvec(x)) / np.linalg.norm(b)
+        assert acc <= 1.05e-10, (r.rid, acc)
+    # replay every request alone on a fresh handle with the same grids
     for m, p in enumerate(probs):
         s = pm.PressureSystem.from_problem(p, flags=flags)
         pm.PressureBatch([s], tiles_per_slot=2, nodes_per_lane=4).close()   # same launch grids
         for r in [r for r in done if r.mesh == m]:
+            b, x0, x = kept[r.rid]
+            b_d = torch.tensor(b, device="cuda")
+            x0_d = None if x0 is None else torch.tensor(x0, device="cuda")
             if mixed:
-                alone = s.solve_mixed(r.rhs, x0=r.x0, rtol=1e-10, inner_rtol=1e-2)
+                alone = s.solve_mixed(b_d, x0=x0_d, rtol=1e-10, inner_rtol=1e-2)
             else:
-                alone = s.solve(r.rhs, x0=r.x0, rtol=1e-10)
+                alone = s.solve(b_d, x0=x0_d, rtol=1e-10)
             assert alone.iters == r.iters, (r.rid, alone.iters, r.iters)
             a = alone.p.cpu().numpy()
-            b = r.result.cpu().numpy()
-            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), r.rid
+            assert np.array_equal(a.view(np.uint64), x.view(np.uint64)), r.rid
         s.close()
+
+
+def test_serving_retain_counts_against_the_budget():
+    """With retain set the finished requests keep their tensors, and their
+    bytes count against the HBM budget."""
+    probs = _pool()[:2]
+    base = []
+    for p in probs:
+        s = pm.PressureSystem.from_problem(p)
+        base.append(s.apply(torch.tensor(fields.sine_product(p.mesh.coords), device="cuda")).clone())
+        s.close()
+    costs = [pm.footprint(p.mesh.dim, p.mesh.coords, p.mesh.elems, pm.PM_FP64) + 8 * p.mesh.n_nodes for p in probs]
+    srv = PressureServer(probs, 4 * sum(costs), max_in_flight=2, rtol=1e-10, graph_iters=4, tiles_per_slot=2,
+                         nodes_per_lane=4, retain=True)
+    reqs = [Request(rid=i, mesh=i % 2, arrival=0.0) for i in range(4)]
+    done = srv.run(reqs, lambda r: base[r.mesh].clone())
+    assert all(r.status == 0 and r.result is not None for r in done)
+    want = sum(8 * (r.rhs.numel() + r.result.numel() + (0 if r.x0 is None else r.x0.numel())) for r in done)
+    assert srv.retained == want and srv._used() == sum(costs) + want
+    srv.close()

@@ -255,6 +255,11 @@ def test_transport_and_post_projection_full_size_sampled_cells():
     print("case full size sampled transport", flush=True)
     s = _system(m)
     fv, fe, _ = s.dual_faces()
+    # the library's dual cells against the oracle's definition (every face
+    # once, in the order of the sorted Morton-rank tuples, with its
+    # elements), so the sampled cells below are the oracle's cells too
+    from dualcheck import check_dual_faces
+    check_dual_faces(m.elems, fv, fe, op.morton_rank(m), 12 * n ** 3 + 6 * n ** 2)
     inp = sproj.fields(m, fv, fe, gamma=1.4, mach=0.1)
     g = np.array([0.0, 0.0, -1.0])
     dt, mu, lam, R = 2e-4, 1e-3, 5e-3, 1.0

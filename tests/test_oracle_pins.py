@@ -624,3 +624,23 @@ def test_lumped_second_order_convergence():
             errs.append(np.sqrt(e @ M.matvec(e)))
         rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
         assert np.all(rates > 1.8) and np.all(rates < 2.2), (key, rates)
+
+
+def test_threaded_cg_matches_sequential():
+    """The all-core leg of the CPU baseline: the SpMV gives the same bits on
+    4 threads, and the CG solution agrees with the sequential oracle's."""
+    prob = workloads.cube(10, w=1e-3, jitter=0.2, rho="lognormal")
+    m = prob.mesh
+    A = oracle.assemble_problem(prob)
+    b = A.matvec(fields.sine_product(m.coords))
+    x1, st1, it1, _, tr1 = oracle.cg(A, b, rtol=1e-10, dirichlet=m.dirichlet)
+    y1 = A.matvec(b)
+    try:
+        oracle.set_threads(4)
+        y4 = A.matvec(b)
+        x4, st4, it4, _, tr4 = oracle.cg(A, b, rtol=1e-10, dirichlet=m.dirichlet)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(y1.view(np.uint64), y4.view(np.uint64))
+    assert st1 == st4 == 0 and abs(it1 - it4) <= 1 and tr4 <= 1e-10
+    assert np.linalg.norm(x4 - x1) <= 1e-10 * np.linalg.norm(x1)

@@ -201,3 +201,31 @@ def test_post_projection_conserves_and_keeps_uniform_states():
     cvol = np.zeros(fv.shape[0])
     np.add.at(cvol, ef, vol[:, None] * np.ones((1, 3)) / 3)
     assert abs((cvol @ we_new - cvol @ inp["we_f"]) + dt * bflux) < 1e-13 * (cvol @ inp["we_f"])
+
+
+@pytest.mark.parametrize("dim,n", [(2, 7), (3, 4)])
+def test_dual_face_count_and_checker(dim, n):
+    """The oracle's dual cells of the structured meshes number 3n^2 + 2n (2D,
+    Table 1's dual elements) and 12n^3 + 6n^2 (3D Kuhn cube: (4E + 12n^2)/2),
+    and the definition checker used on the full-size mesh accepts the
+    oracle's list and rejects it with two faces swapped, an element dropped
+    or a wrong count."""
+    from dualcheck import check_dual_faces
+    m = smesh.structured_mesh(dim, n, jitter=0.2, seed=3)
+    rank = op.morton_rank(m)
+    fv, fe, _ = op.dual_faces(dim, m.elems, rank)
+    want = 3 * n * n + 2 * n if dim == 2 else 12 * n ** 3 + 6 * n ** 2
+    assert fv.shape[0] == want
+    check_dual_faces(m.elems, fv, fe, rank, want)
+    with pytest.raises(AssertionError):
+        check_dual_faces(m.elems, fv, fe, rank, want + 1)
+    sw = fv.copy(), fe.copy()
+    for a in sw:
+        a[[3, 4]] = a[[4, 3]]
+    with pytest.raises(AssertionError):
+        check_dual_faces(m.elems, sw[0], sw[1], rank, want)
+    bad = fe.copy()
+    k = np.nonzero(bad[:, 1] >= 0)[0][0]
+    bad[k, 1] = -1
+    with pytest.raises(AssertionError):
+        check_dual_faces(m.elems, fv, bad, rank, want)
