@@ -20,14 +20,33 @@ HIPCC_FLAGS = [
 
 
 def build(verbose=False):
+    """Compile every source to an object file (in parallel), then link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OUTDIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["/opt/rocm/bin/hipcc"] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    tag = ".tmp%d" % os.getpid()
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(OUTDIR, src + tag + ".o")
+        objs.append(obj)
+        cmds.append(["/opt/rocm/bin/hipcc"] + compile_flags + ["-I", INCLUDE, "-I", CSRC, "-c",
+                                                               os.path.join(CSRC, src), "-o", obj])
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            list(ex.map(run, cmds))
+        tmp = LIB + tag
+        run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 
