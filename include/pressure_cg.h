@@ -79,6 +79,7 @@ extern "C" {
 #define PM_ENOMEM (-3)        /* device or host allocation failed                 */
 #define PM_EBREAKDOWN (-4)    /* CG breakdown: p.Ap <= 0 or not finite            */
 #define PM_EHIP (-5)          /* a HIP runtime call failed                         */
+#define PM_ETOOLARGE (-6)     /* beyond the static scratch of pressure_solve_noalloc */
 
 /* Precision flags for pressure_setup / pressure_footprint. */
 #define PM_FP64 1             /* FP64 operator data (always present)               */
@@ -206,6 +207,28 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
 int pressure_solve_mixed(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                          double inner_rtol, int32_t max_iter, double *p_dev, int32_t *iters,
                          int32_t *outer, double *res_hist, double *true_relres, void *stream);
+
+/* pressure_solve without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and status codes as
+ * pressure_solve, bit for bit the same results; the CG vectors, block
+ * partials, solver state and residual history live in one static device
+ * array of the library (about 26 MB: 6 vectors of PM_NOALLOC_MAX_NODES
+ * doubles, the partials and PM_NOALLOC_MAX_ITER + 1 history entries), which
+ * each GPU the library runs on holds until the process ends; its address
+ * is looked up at pressure_setup.  The call allocates no device memory, no
+ * events (handle timing is not recorded) and no host memory of its own.
+ *   n_nodes > PM_NOALLOC_MAX_NODES or max_iter > PM_NOALLOC_MAX_ITER:
+ *   PM_ETOOLARGE, nothing launched.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (from two host threads, or on two streams) race and must not be made.
+ * The array keeps the last call's contents; the call clears what must start
+ * at zero (the two direction buffers) itself. */
+#define PM_NOALLOC_MAX_NODES 524288
+#define PM_NOALLOC_MAX_ITER 65535
+int pressure_solve_noalloc(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
+                           int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
+                           double *true_relres, void *stream);
 
 /* Inner-solve mode of pressure_solve_mixed for this handle. */
 #define PM_MIXED_KEEP_DIRECTION 0

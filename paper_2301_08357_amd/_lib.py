@@ -10,6 +10,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libpressure.so")
 
 PM_OK, PM_NOT_CONVERGED, PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EBREAKDOWN, PM_EHIP = 0, 1, -1, -2, -3, -4, -5
+PM_ETOOLARGE = -6
+PM_NOALLOC_MAX_NODES, PM_NOALLOC_MAX_ITER = 524288, 65535
 PM_FP64, PM_FP32_INNER = 1, 2
 PM_TILE_256, PM_TILE_512, PM_TILE_128 = 0x10, 0x20, 0x30
 PM_MASS_LUMPED = 0x100
@@ -35,6 +37,8 @@ SIGNATURES = {
     "pressure_apply": (ctypes.c_int, [_P, _P, _P, _P]),
     "pressure_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, ctypes.POINTER(_i32), _P,
                                       ctypes.POINTER(_dbl), _P]),
+    "pressure_solve_noalloc": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, ctypes.POINTER(_i32), _P,
+                                              ctypes.POINTER(_dbl), _P]),
     "pressure_solve_mixed": (ctypes.c_int, [_P, _P, _P, _dbl, _dbl, _i32, _P, ctypes.POINTER(_i32),
                                             ctypes.POINTER(_i32), _P, ctypes.POINTER(_dbl), _P]),
     "pressure_footprint": (ctypes.c_int, [_PMESH, _i32, ctypes.POINTER(ctypes.c_uint64)]),

@@ -43,6 +43,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2216,6 +2217,95 @@ int setup_node_only(pm_handle *h)
 }  // namespace
 
 // ======================================================================
+// Static scratch of pressure_solve_noalloc: the CG vectors, block partials,
+// solver state and residual history of one FP64 solve of up to
+// PM_NOALLOC_MAX_NODES nodes and PM_NOALLOC_MAX_ITER iterations, in a
+// file-scope device array, so that the call allocates nothing.  Every GPU
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is not a device address on the host).
+// Layout (doubles): b | x | r | q | p_0 | p_1 (one PM_NOALLOC_MAX_NODES
+// stride each), block partials, history, solver state.
+
+namespace {
+constexpr size_t NA_VEC = size_t(PM_NOALLOC_MAX_NODES);
+constexpr size_t NA_PART = size_t(AGRID_MAX + 3 * VGRID_MAX);
+constexpr size_t NA_HIST = size_t(PM_NOALLOC_MAX_ITER) + 1;
+constexpr size_t NA_STATE = (sizeof(CGState) + 7) / 8;
+constexpr size_t NA_DOUBLES = 6 * NA_VEC + NA_PART + NA_HIST + NA_STATE;
+}  // namespace
+
+static __device__ __align__(256) double scratch[NA_DOUBLES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch, looked up once per device
+// (the caller has made `device` current).
+int noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= NA_MAX_DEVICES) return PM_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return PM_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return PM_EHIP;
+    }
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+    return PM_OK;
+}
+
+double *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NA_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+__global__ void k_fill2(int64_t n, double *a, double *b, double v)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        a[i] = v;
+        b[i] = v;
+    }
+}
+
+// The handle's solve buffers, swapped for the scratch for one call and put
+// back on every return path.
+struct ScratchSwap {
+    pm_handle *h;
+    double *b, *x, *r, *q, *p0, *p1, *part, *hist;
+    CGState *st;
+    int32_t hist_cap;
+    bool timing;
+    ScratchSwap(pm_handle *hh, double *base) : h(hh)
+    {
+        b = h->b, x = h->x, r = h->r, q = h->q, p0 = h->pbuf[0], p1 = h->pbuf[1];
+        part = h->part, hist = h->hist, st = h->st, hist_cap = h->hist_cap, timing = h->timing;
+        h->b = base;
+        h->x = base + NA_VEC;
+        h->r = base + 2 * NA_VEC;
+        h->q = base + 3 * NA_VEC;
+        h->pbuf[0] = base + 4 * NA_VEC;
+        h->pbuf[1] = base + 5 * NA_VEC;
+        h->part = base + 6 * NA_VEC;
+        h->hist = h->part + NA_PART;
+        h->hist_cap = int32_t(NA_HIST);
+        h->st = reinterpret_cast<CGState *>(h->hist + NA_HIST);
+        h->timing = false;   // timing events would be created on demand
+    }
+    ~ScratchSwap()
+    {
+        h->b = b, h->x = x, h->r = r, h->q = q, h->pbuf[0] = p0, h->pbuf[1] = p1;
+        h->part = part, h->hist = hist, h->st = st, h->hist_cap = hist_cap, h->timing = timing;
+    }
+};
+}  // namespace
+
+// ======================================================================
 // C ABI
 
 extern "C" {
@@ -2230,6 +2320,9 @@ const char *pressure_strerror(int status)
     case PM_ENOMEM: return "out of memory";
     case PM_EBREAKDOWN: return "CG breakdown (p.Ap <= 0 or not finite)";
     case PM_EHIP: return "HIP runtime error";
+    case PM_ETOOLARGE:
+        return "larger than the static scratch of pressure_solve_noalloc (n_nodes > PM_NOALLOC_MAX_NODES or "
+               "max_iter > PM_NOALLOC_MAX_ITER)";
     default: return "unknown status";
     }
 }
@@ -2348,6 +2441,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     pm::Layout L;
     TRY(pm::build_layout(mesh, &L));
     HIPCK(hipGetDevice(&h->device));
+    TRY(noalloc_scratch_init(h->device));
     {
         int v = 0;
         HIPCK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -2659,6 +2753,22 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
     if (true_relres) *true_relres = rel;
     if (fin.status != 0) return fin.status;
     return (rel <= rtol) ? PM_OK : PM_NOT_CONVERGED;
+}
+
+int pressure_solve_noalloc(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
+                           int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
+                           double *true_relres, void *stream)
+{
+    if (!h || max_iter < 0) return PM_EINVAL;
+    if (h->N > PM_NOALLOC_MAX_NODES || max_iter > PM_NOALLOC_MAX_ITER) return PM_ETOOLARGE;
+    double *base = noalloc_scratch(h->device);
+    if (!base) return PM_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    ScratchSwap swap(h, base);
+    // the direction buffers start at zero, as the handle's own do after setup
+    hipLaunchKernelGGL(k_fill2, dim3(grid_of(h->N)), dim3(BLK), 0, s, h->N, h->pbuf[0], h->pbuf[1], 0.0);
+    HIPCK(hipGetLastError());
+    return pressure_solve(h, rhs_dev, x0_dev, rtol, max_iter, p_dev, iters, res_hist, true_relres, stream);
 }
 
 // Launch FP32 inner-CG iterations k0 .. k0+count-1.

@@ -168,6 +168,24 @@ class PressureSystem:
         check(st, "pressure_solve")
         return SolveResult(out, st, it.value, hist[: it.value + 1].copy(), tr.value)
 
+    def solve_noalloc(self, rhs, out, x0=None, rtol=1e-10, max_iter=20000, stream=None, hist=None):
+        """pressure_solve_noalloc: solve without any device allocation (the
+        library's static scratch holds the CG state).  The caller provides
+        the output tensor `out` (and, optionally, the host array `hist` of at
+        least max_iter + 1 doubles for the residual history)."""
+        it = ctypes.c_int32(0)
+        tr = ctypes.c_double(0.0)
+        if hist is None:
+            hist = np.zeros(max_iter + 1)
+        elif hist.dtype != np.float64 or not hist.flags.c_contiguous or hist.size < max_iter + 1:
+            raise ValueError("hist must be a contiguous float64 array of at least max_iter + 1 entries")
+        st = load().pressure_solve_noalloc(self._h, _dev_ptr(rhs, self.n_nodes, "rhs"),
+                                           None if x0 is None else _dev_ptr(x0, self.n_nodes, "x0"),
+                                           float(rtol), int(max_iter), _dev_ptr(out, self.n_nodes, "p"),
+                                           ctypes.byref(it), _ptr(hist), ctypes.byref(tr), _stream_handle(stream))
+        check(st, "pressure_solve_noalloc")
+        return SolveResult(out, st, it.value, hist[: it.value + 1].copy(), tr.value)
+
     def solve_mixed(self, rhs, x0=None, rtol=1e-10, inner_rtol=1e-2, max_iter=20000, out=None, stream=None):
         import torch
         if out is None:
