@@ -434,11 +434,11 @@ struct TileArgsT {
     int n_tiles;
     int max_deg;                  // rows of the LDS sums table
     const int *node_off;          // tile t owns nodes [node_off[t], node_off[t+1])
-    const int *halo_off, *halo;
+    const int *halo_off, *halo;   // halo node ids, Dirichlet flag in bit 31
     const int *inst_off;
     const uint2 *inst;            // packed instance records
     const R *inst_w;              // element factor per instance
-    const uint8_t *nflag;         // per node: element count | Dirichlet << 7
+    const uint8_t *nflag;         // per node: element count | Dirichlet << 7 (read for own nodes)
 };
 
 // LDS bytes of the tiled kernel: node table (DIM+1 fields of LM entries)
@@ -496,18 +496,26 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
             else if (l >= T && l < T + nh) gi[q] = ta.halo[h0 + l - T];
         }
     };
+    // instance records and factors are read once per apply: non-temporal
+    // loads keep them from evicting node data that neighbouring tiles
+    // read again as halo
     auto load_inst = [&](int k, int i0, int ni) {
         const int j = threadIdx.x + k * NTH;
         if (j < ni) {
-            ic[k] = ta.inst[i0 + j];
-            iw[k] = ta.inst_w[i0 + j];
+            const unsigned long long raw =
+                __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(ta.inst) + (i0 + j));
+            ic[k] = make_uint2(unsigned(raw), unsigned(raw >> 32));
+            iw[k] = __builtin_nontemporal_load(ta.inst_w + (i0 + j));
         }
     };
+    // own slots (l < T) take the node's flag byte; halo slots take the
+    // Dirichlet flag from bit 31 of the halo id (one gather fewer per halo node)
     auto load_nodes = [&](const int *gi) {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
-            const int v = gi[q];
-            if (v >= 0) {
+            const int raw = gi[q];
+            const int v = raw & 0x7fffffff;
+            if (raw != -1) {
                 vX[q] = g.X[v];
                 vY[q] = g.Y[v];
                 if (DIM == 3) vZ[q] = g.Z[v];
@@ -517,7 +525,8 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
                 } else {
                     vP[q] = x[v];
                 }
-                vF[q] = ta.nflag[v];
+                const int l = threadIdx.x + q * NTH;
+                vF[q] = (l < T) ? ta.nflag[v] : ((raw < 0) ? uint8_t(0x80) : uint8_t(0));
             }
         }
     };
@@ -561,7 +570,7 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         for (int q = 0; q < SPT; ++q) {
             const int l = threadIdx.x + q * NTH;
             if (CG && !it.first) vP[q] = vP[q] + rbeta * vQ[q];   // p_k = r + beta p_{k-1}
-            if (gidx[q] >= 0) {
+            if (gidx[q] != -1) {
                 const bool d = (vF[q] & 0x80u) != 0;
                 sN[l] = vX[q];
                 sN[LM + l] = vY[q];
@@ -2183,7 +2192,13 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
         nflag[i] = uint8_t((L.n2e_off[i + 1] - L.n2e_off[i]) | (L.dirichlet[i] ? 0x80 : 0));
     TRY(dupload(h, &h->t_node_off, T.node_off));
     TRY(dupload(h, &h->t_halo_off, T.halo_off));
-    TRY(dupload(h, &h->t_halo, T.halo));
+    {
+        // halo ids carry the Dirichlet flag in bit 31
+        std::vector<int32_t> hal(T.halo);
+        for (auto &v : hal)
+            if (L.dirichlet[v]) v = int32_t(uint32_t(v) | DIR_BIT);
+        TRY(dupload(h, &h->t_halo, hal));
+    }
     TRY(dupload(h, &h->t_inst_off, T.inst_off));
     TRY(dupload(h, &h->t_inst_elem, T.inst_elem));
     TRY(dupload(h, &h->t_nflag, nflag));
