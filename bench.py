@@ -737,7 +737,8 @@ def bench_serve(args):
     each request warm-started from its mesh's previous solution with the rhs
     perturbed by 1 % (normal noise scaled to ||rhs|| / sqrt(N_free)).  The
     main rate is 0.8 x the saturated rate measured in a closed-loop pass;
-    0.5 x and 0.95 x are extra points on fewer requests.  The same requests
+    0.8 x, 0.5 x and 0.95 x on 2000 requests are extra points (the 0.8 x one
+    shows whether the tail grows with the run length).  The same requests
     served one at a time by single FP64 solves give the sequential rate."""
     import torch
     import paper_2301_08357_amd as pm
@@ -777,6 +778,7 @@ def bench_serve(args):
         last[m] = r.p
     torch.cuda.synchronize()
     seq_rate = n_seq / (time.perf_counter() - t0)
+    print("serve: sequential single solves %.1f/s" % seq_rate, file=sys.stderr, flush=True)
     del last
     tps, npl, _ = pm.tune_batch(pool, iters=32)
     for s in pool:
@@ -795,6 +797,7 @@ def bench_serve(args):
     srv.run([Request(rid=10 ** 6 + i, mesh=int(m), arrival=0.0) for i, m in enumerate(choice)], rhs_fn)
     sat = srv.stats.solves_per_s
     srv.close()
+    print("serve: closed-loop saturation %.1f/s" % sat, file=sys.stderr, flush=True)
 
     def point(factor, n_req, rid0):
         times, choice = workloads.arrivals(n_req, factor * sat, 256)
@@ -804,15 +807,22 @@ def bench_serve(args):
         st = srv.stats
         bad = sum(1 for r in done if r.status != 0 or r.true_relres > args.rtol)
         srv.close()
+        print("serve: %d requests at %.2f x saturation: %.1f/s, p50 %.1f ms, p99 %.1f ms"
+              % (n_req, factor, st.solves_per_s, st.latency_ms["p50"], st.latency_ms["p99"]), file=sys.stderr,
+              flush=True)
         return st, bad
+
+    def lat(d):
+        return {k: round(v, 3) for k, v in d.items()}
 
     st, bad = point(0.8, args.requests, 0)
     extra_points = []
-    for f in (0.5, 0.95):
+    for f in (0.8, 0.5, 0.95):
         e, eb = point(f, min(2000, args.requests), 3 * 10 ** 6 + int(f * 100) * 10 ** 4)
         extra_points.append({"rate_factor": f, "rate_per_s": round(f * sat, 2), "requests": e.n,
                              "solves_per_s": round(e.solves_per_s, 3), "latency_ms_p50": round(e.latency_ms["p50"], 3),
-                             "latency_ms_p99": round(e.latency_ms["p99"], 3), "failed": eb})
+                             "latency_ms_p99": round(e.latency_ms["p99"], 3), "latency_ms_warm": lat(e.latency_ms_warm),
+                             "service_ms_mean": round(e.service_ms_mean, 3), "failed": eb})
     kind = "mixed-precision (FP32 inner, FP64 corrections)" if args.serve_mixed else "FP64"
     _common(args, round(st.solves_per_s, 3), "solves/s", round(st.makespan_s * 1e3, 3),
             {"workload": "serve: %d requests, Poisson arrivals at 0.8 x saturation over the 256-mesh pool, warm "
@@ -820,6 +830,8 @@ def bench_serve(args):
              "rate_per_s": round(0.8 * sat, 2), "saturation_solves_per_s": round(sat, 2), "budget_bytes": budget,
              "tiles_per_slot": tps, "nodes_per_lane": npl},
             {"latency_ms_p50": round(st.latency_ms["p50"], 3), "latency_ms_p99": round(st.latency_ms["p99"], 3),
+             "latency_ms_warm": lat(st.latency_ms_warm), "latency_ms_cold": lat(st.latency_ms_cold),
+             "service_ms_mean": round(st.service_ms_mean, 3),
              "mean_iterations_cold": round(st.mean_iters_cold, 1), "mean_iterations_warm": round(st.mean_iters_warm, 1),
              "loads": st.loads, "evictions": st.evictions, "batch_rebuilds": st.rebuilds,
              "max_in_flight": st.max_in_flight_seen, "failed": bad,

@@ -42,6 +42,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -1808,9 +1809,19 @@ namespace {
 
 constexpr int TIMING_STRIDE = 32;
 
-#define HIPCK(x)                               \
-    do {                                       \
-        if ((x) != hipSuccess) return PM_EHIP; \
+// A failed HIP call returns PM_EHIP; with the environment variable
+// PM_DEBUG set, the call, its source line and HIP's message go to stderr.
+int hip_failed(hipError_t e, const char *what, int line)
+{
+    static const bool debug = std::getenv("PM_DEBUG") != nullptr;
+    if (debug) std::fprintf(stderr, "libpressure: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+    return PM_EHIP;
+}
+
+#define HIPCK(x)                                                        \
+    do {                                                                \
+        const hipError_t hipck_e = (x);                                 \
+        if (hipck_e != hipSuccess) return hip_failed(hipck_e, #x, __LINE__); \
     } while (0)
 
 #define TRY(x)                      \
@@ -1833,11 +1844,67 @@ int dalloc(pm_handle *h, T **p, size_t count)
     return PM_OK;
 }
 
+// Setup work (uploads, clears, setup kernels) runs on a private non-blocking
+// stream of the calling thread while a SetupStream is alive, so that a setup
+// on one host thread neither waits for nor disturbs the streams of another
+// (a graph capture there, for one: the legacy default stream would tie into
+// it); the stream is drained before the setup call returns.
+thread_local hipStream_t g_setup = nullptr;
+
+struct SetupStream {
+    bool owner = false;
+    int status = PM_OK;
+    SetupStream()
+    {
+        if (g_setup) return;   // nested: the outer call's stream
+        if (hipStreamCreateWithFlags(&g_setup, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            g_setup = nullptr;
+            status = PM_EHIP;
+            return;
+        }
+        owner = true;
+    }
+    int finish()
+    {
+        if (owner && g_setup && hipStreamSynchronize(g_setup) != hipSuccess) return PM_EHIP;
+        return PM_OK;
+    }
+    ~SetupStream()
+    {
+        if (!owner) return;
+        (void)hipStreamSynchronize(g_setup);
+        (void)hipStreamDestroy(g_setup);
+        g_setup = nullptr;
+    }
+};
+
+// host -> device (or device -> host) copy that is complete on return
+int hcopy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind)
+{
+    if (bytes == 0) return PM_OK;
+    if (!g_setup) {
+        HIPCK(hipMemcpy(dst, src, bytes, kind));
+        return PM_OK;
+    }
+    HIPCK(hipMemcpyAsync(dst, src, bytes, kind, g_setup));
+    HIPCK(hipStreamSynchronize(g_setup));
+    return PM_OK;
+}
+
+// zero device memory, in setup-stream order
+int hzero(void *p, size_t bytes)
+{
+    if (g_setup) HIPCK(hipMemsetAsync(p, 0, bytes, g_setup));
+    else HIPCK(hipMemset(p, 0, bytes));
+    return PM_OK;
+}
+
 template <class T>
 int dupload(pm_handle *h, T **p, const std::vector<T> &v)
 {
     TRY(dalloc(h, p, v.size()));
-    if (!v.empty()) HIPCK(hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    if (!v.empty()) TRY(hcopy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
     return PM_OK;
 }
 
@@ -1974,8 +2041,9 @@ int compute_factors_on(pm_handle *h, hipStream_t s)
 
 int compute_factors(pm_handle *h)
 {
-    TRY(compute_factors_on(h, nullptr));
-    HIPCK(hipDeviceSynchronize());
+    TRY(compute_factors_on(h, g_setup));
+    if (g_setup) HIPCK(hipStreamSynchronize(g_setup));
+    else HIPCK(hipDeviceSynchronize());
     return PM_OK;
 }
 
@@ -2204,7 +2272,7 @@ int build_tiles_on_device(pm_handle *h, const pm::Layout &L, int tile_nodes)
     TRY(dupload(h, &h->t_nflag, nflag));
     TRY(dalloc(h, &h->t_inst, size_t(h->n_inst)));
     if (h->n_inst > 0)
-        HIPCK(hipMemcpy(h->t_inst, T.inst.data(), sizeof(uint16_t) * T.inst.size(), hipMemcpyHostToDevice));
+        TRY(hcopy(h->t_inst, T.inst.data(), sizeof(uint16_t) * T.inst.size(), hipMemcpyHostToDevice));
     TRY(dalloc(h, &h->t_inst_w, size_t(h->n_inst)));
     TRY(apply_grid<double>(h, &h->n_ablocks));
     return PM_OK;
@@ -2419,16 +2487,16 @@ static int update_v0(pm_handle *h)
     Mesh g = make_mesh<double>(h);
     const dim3 grid(grid_of(N));
     if (h->dim == 2 && h->periodic)
-        hipLaunchKernelGGL((k_lumped_mass<2, true>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+        hipLaunchKernelGGL((k_lumped_mass<2, true>), grid, dim3(BLK), 0, g_setup, g, h->n2e_off, h->n2e_ent, h->mw);
     else if (h->dim == 2)
-        hipLaunchKernelGGL((k_lumped_mass<2, false>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+        hipLaunchKernelGGL((k_lumped_mass<2, false>), grid, dim3(BLK), 0, g_setup, g, h->n2e_off, h->n2e_ent, h->mw);
     else if (h->periodic)
-        hipLaunchKernelGGL((k_lumped_mass<3, true>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+        hipLaunchKernelGGL((k_lumped_mass<3, true>), grid, dim3(BLK), 0, g_setup, g, h->n2e_off, h->n2e_ent, h->mw);
     else
-        hipLaunchKernelGGL((k_lumped_mass<3, false>), grid, dim3(BLK), 0, 0, g, h->n2e_off, h->n2e_ent, h->mw);
+        hipLaunchKernelGGL((k_lumped_mass<3, false>), grid, dim3(BLK), 0, g_setup, g, h->n2e_off, h->n2e_ent, h->mw);
     HIPCK(hipGetLastError());
     std::vector<double> mw(N);
-    HIPCK(hipMemcpy(mw.data(), h->mw, 8 * N, hipMemcpyDeviceToHost));
+    TRY(hcopy(mw.data(), h->mw, 8 * N, hipMemcpyDeviceToHost));
     double tot = 0.0;
     for (double v : mw) tot += v;
     h->m_total = tot;
@@ -2495,7 +2563,7 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     TRY(dupload(h, &h->n2e_off, L.n2e_off));
     TRY(dupload(h, &h->n2e_ent, L.n2e_ent));
     TRY(dalloc(h, &h->conn, E));
-    HIPCK(hipMemcpy(h->conn, conn.data(), 16 * E, hipMemcpyHostToDevice));
+    TRY(hcopy(h->conn, conn.data(), 16 * E, hipMemcpyHostToDevice));
     TRY(dupload(h, &h->coords, L.coords));
     TRY(dupload(h, &h->coef, cnew));
     TRY(dalloc(h, &h->w, E));
@@ -2519,11 +2587,11 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
         TRY(dalloc(h, &h->w32, E));
         TRY(dalloc(h, &h->t_inst_w32, size_t(std::max<int64_t>(h->n_inst, 1))));
         for (float **v : {&h->r32, &h->q32, &h->d32, &h->p32[0], &h->p32[1]}) TRY(dalloc(h, v, N));
-        HIPCK(hipMemset(h->p32[0], 0, 4 * N));
-        HIPCK(hipMemset(h->p32[1], 0, 4 * N));
+        TRY(hzero(h->p32[0], 4 * N));
+        TRY(hzero(h->p32[1], 4 * N));
         TRY(dalloc(h, &h->st_in, 1));
-        HIPCK(hipMemset(h->st_in, 0, sizeof(CGState)));
-        hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, 0, h->st_in);   // idle until a mixed solve starts
+        TRY(hzero(h->st_in, sizeof(CGState)));
+        hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, g_setup, h->st_in);   // idle until a mixed solve starts
         HIPCK(hipHostMalloc((void **)&h->hst_in, sizeof(CGState), hipHostMallocDefault));
         if (tiled_lds_bytes<float>(h) > h->lds_limit) return PM_EINVAL;
         TRY(apply_grid<float>(h, &h->n_ablocks32));
@@ -2532,12 +2600,12 @@ static int setup_impl(const pm_mesh *mesh, const double *elem_coef, double mass_
     TRY(dalloc(h, &h->st, 1));
     TRY(ensure_hist(h, 1023));
     HIPCK(hipHostMalloc((void **)&h->hst, sizeof(CGState), hipHostMallocDefault));
-    HIPCK(hipMemset(h->st, 0, sizeof(CGState)));
-    hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, 0, h->st);   // idle until a solve starts
+    TRY(hzero(h->st, sizeof(CGState)));
+    hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, g_setup, h->st);   // idle until a solve starts
     HIPCK(hipGetLastError());
-    HIPCK(hipMemset(h->part, 0, sizeof(double) * (AGRID_MAX + 3 * VGRID_MAX)));
-    HIPCK(hipMemset(h->pbuf[0], 0, 8 * N));
-    HIPCK(hipMemset(h->pbuf[1], 0, 8 * N));
+    TRY(hzero(h->part, sizeof(double) * (AGRID_MAX + 3 * VGRID_MAX)));
+    TRY(hzero(h->pbuf[0], 8 * N));
+    TRY(hzero(h->pbuf[1], 8 * N));
     TRY(compute_factors(h));
     return update_v0(h);
 }
@@ -2548,9 +2616,12 @@ int pressure_setup(const pm_mesh *mesh, const double *elem_coef, double mass_coe
     if (!out) return PM_EINVAL;
     *out = nullptr;
     pm_handle *h = nullptr;
+    SetupStream ss;
+    if (ss.status != PM_OK) return ss.status;
     try {
         h = new pm_handle();
         int s = setup_impl(mesh, elem_coef, mass_coef, dt, flags, h);
+        if (s == PM_OK) s = ss.finish();
         if (s != PM_OK) {
             pressure_destroy(h);
             return s;
@@ -2570,16 +2641,19 @@ int pressure_update_coef(pm_handle *h, const double *elem_coef, double mass_coef
 {
     if (!h || !(mass_coef >= 0.0) || !std::isfinite(mass_coef) || !(dt > 0.0) || !std::isfinite(dt))
         return PM_EINVAL;
+    SetupStream ss;
+    if (ss.status != PM_OK) return ss.status;
     if (elem_coef) {
         if (!valid_coef(elem_coef, h->E)) return PM_EINVAL;
         std::vector<double> cnew(h->E);
         for (int64_t e = 0; e < h->E; ++e) cnew[e] = elem_coef[h->elem_new2old[e]];
-        HIPCK(hipMemcpy(h->coef, cnew.data(), 8 * h->E, hipMemcpyHostToDevice));
+        TRY(hcopy(h->coef, cnew.data(), 8 * h->E, hipMemcpyHostToDevice));
     }
     h->alpha = mass_coef;
     h->dt = dt;
     TRY(compute_factors(h));
-    return update_v0(h);
+    TRY(update_v0(h));
+    return ss.finish();
 }
 
 int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *stream)
@@ -2978,6 +3052,14 @@ struct pm_batch {
     void *d_meshes = nullptr;      // BatchMeshT<double> or BatchMeshT<float>
     int2 *d_aslots = nullptr, *d_uslots = nullptr;
     int n_aslots = 0, n_uslots = 0;
+    // continuous batching: the slots of the meshes in flight (begun and not
+    // yet finished), so that a step launches no blocks for idle meshes
+    std::vector<int> a_off, u_off;          // per mesh: first apply / update slot (n + 1 entries)
+    std::vector<uint8_t> in_flight;         // per mesh
+    int2 *d_aslots_act = nullptr, *d_uslots_act = nullptr;
+    int2 *h_slots_act = nullptr;            // pinned staging of both active tables
+    int n_aslots_act = 0, n_uslots_act = 0;
+    bool act_dirty = true;
     BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
     CGState *d_states = nullptr, *h_states = nullptr;
     int bclass = -1;
@@ -3027,49 +3109,81 @@ const void *batch_apply_kernel(const pm_batch *b)
 }
 
 template <int C, class R>
-void launch_batch_apply_c(pm_batch *b, hipStream_t s)
+void launch_batch_apply_c(pm_batch *b, const int2 *slots, int n_slots, hipStream_t s)
 {
     if (b->periodic)
-        hipLaunchKernelGGL((k_batch_apply<C, R, true>), dim3(b->n_aslots), dim3(BLK), b->lds, s,
-                           (const BatchMeshT<R> *)b->d_meshes, b->d_aslots, b->d_ctl);
+        hipLaunchKernelGGL((k_batch_apply<C, R, true>), dim3(n_slots), dim3(BLK), b->lds, s,
+                           (const BatchMeshT<R> *)b->d_meshes, slots, b->d_ctl);
     else
-        hipLaunchKernelGGL((k_batch_apply<C, R, false>), dim3(b->n_aslots), dim3(BLK), b->lds, s,
-                           (const BatchMeshT<R> *)b->d_meshes, b->d_aslots, b->d_ctl);
+        hipLaunchKernelGGL((k_batch_apply<C, R, false>), dim3(n_slots), dim3(BLK), b->lds, s,
+                           (const BatchMeshT<R> *)b->d_meshes, slots, b->d_ctl);
 }
 
+// count iterations over the slots of every mesh (active = false: the
+// captured graph) or of the meshes in flight only (the active tables).
 template <class R>
-int launch_batch_iterations_t(pm_batch *b, int count, hipStream_t s)
+int launch_batch_iterations_t(pm_batch *b, int count, bool active, hipStream_t s)
 {
+    const int2 *as = active ? b->d_aslots_act : b->d_aslots;
+    const int2 *us = active ? b->d_uslots_act : b->d_uslots;
+    const int na = active ? b->n_aslots_act : b->n_aslots, nu = active ? b->n_uslots_act : b->n_uslots;
     for (int i = 0; i < count; ++i) {
         switch (b->bclass) {
-        case 0: launch_batch_apply_c<0, R>(b, s); break;
-        case 1: launch_batch_apply_c<1, R>(b, s); break;
-        case 2: launch_batch_apply_c<2, R>(b, s); break;
-        case 3: launch_batch_apply_c<3, R>(b, s); break;
-        case 4: launch_batch_apply_c<4, R>(b, s); break;
-        case 5: launch_batch_apply_c<5, R>(b, s); break;
+        case 0: launch_batch_apply_c<0, R>(b, as, na, s); break;
+        case 1: launch_batch_apply_c<1, R>(b, as, na, s); break;
+        case 2: launch_batch_apply_c<2, R>(b, as, na, s); break;
+        case 3: launch_batch_apply_c<3, R>(b, as, na, s); break;
+        case 4: launch_batch_apply_c<4, R>(b, as, na, s); break;
+        case 5: launch_batch_apply_c<5, R>(b, as, na, s); break;
         default: return PM_EINVAL;
         }
-        hipLaunchKernelGGL(k_batch_update<R>, dim3(b->n_uslots), dim3(BLK), 0, s,
-                           (const BatchMeshT<R> *)b->d_meshes, b->d_uslots, b->d_ctl);
+        hipLaunchKernelGGL(k_batch_update<R>, dim3(nu), dim3(BLK), 0, s, (const BatchMeshT<R> *)b->d_meshes, us,
+                           b->d_ctl);
     }
     HIPCK(hipGetLastError());
     return PM_OK;
 }
 
-int launch_batch_iterations(pm_batch *b, int count, hipStream_t s)
+int launch_batch_iterations(pm_batch *b, int count, bool active, hipStream_t s)
 {
-    return b->mixed ? launch_batch_iterations_t<float>(b, count, s) : launch_batch_iterations_t<double>(b, count, s);
+    return b->mixed ? launch_batch_iterations_t<float>(b, count, active, s)
+                    : launch_batch_iterations_t<double>(b, count, active, s);
+}
+
+// Upload the slot tables of the meshes in flight (in mesh order, each
+// mesh's slots in order), in stream order.
+int refresh_active_slots(pm_batch *b, hipStream_t s)
+{
+    if (!b->act_dirty) return PM_OK;
+    // the staging buffer is free: every step ends with its stream synchronised
+    const int n = int(b->hs.size());
+    int na = 0, nu = 0;
+    int2 *ha = b->h_slots_act, *hu = b->h_slots_act + b->n_aslots;
+    for (int m = 0; m < n; ++m) {
+        if (!b->in_flight[m]) continue;
+        for (int j = b->a_off[m]; j < b->a_off[m + 1]; ++j) ha[na++] = make_int2(m, j - b->a_off[m]);
+        for (int j = b->u_off[m]; j < b->u_off[m + 1]; ++j) hu[nu++] = make_int2(m, j - b->u_off[m]);
+    }
+    if (na > 0) HIPCK(hipMemcpyAsync(b->d_aslots_act, ha, sizeof(int2) * na, hipMemcpyHostToDevice, s));
+    if (nu > 0) HIPCK(hipMemcpyAsync(b->d_uslots_act, hu, sizeof(int2) * nu, hipMemcpyHostToDevice, s));
+    b->n_aslots_act = na;
+    b->n_uslots_act = nu;
+    b->act_dirty = false;
+    return PM_OK;
 }
 
 void batch_free(pm_batch *b)
 {
     if (!b) return;
+    // work queued by begin / finish completes first: a batch rebuilt over
+    // the same handles reads their solver states
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (void *p : {(void *)b->d_meshes, (void *)b->d_aslots, (void *)b->d_uslots, (void *)b->d_ctl,
-                    (void *)b->d_states})
+                    (void *)b->d_states, (void *)b->d_aslots_act, (void *)b->d_uslots_act})
         if (p) (void)hipFree(p);
+    if (b->h_slots_act) (void)hipHostFree(b->h_slots_act);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     if (b->h_states) (void)hipHostFree(b->h_states);
     if (b->ev) (void)hipEventDestroy(b->ev);
@@ -3170,6 +3284,8 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
         h->n_ablocks32 = h->n_ablocks;
         h->n_vblocks = int(std::max<int64_t>(1, std::min<int64_t>(VGRID_MAX, (h->N + int64_t(BLK) * b->nodes_per_lane - 1) /
                                                                                  (int64_t(BLK) * b->nodes_per_lane))));
+        b->a_off.push_back(int(aslots.size()));
+        b->u_off.push_back(int(uslots.size()));
         for (int j = 0; j < h->n_ablocks; ++j) aslots.push_back(make_int2(m, j));
         for (int j = 0; j < h->n_vblocks; ++j) uslots.push_back(make_int2(m, j));
         b->hs.push_back(h);
@@ -3199,6 +3315,12 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     };
     TRY(up(&b->d_aslots, aslots));
     TRY(up(&b->d_uslots, uslots));
+    b->a_off.push_back(b->n_aslots);
+    b->u_off.push_back(b->n_uslots);
+    b->in_flight.assign(n, 0);
+    TRY(up(&b->d_aslots_act, aslots));
+    TRY(up(&b->d_uslots_act, uslots));
+    HIPCK(hipHostMalloc((void **)&b->h_slots_act, sizeof(int2) * (b->n_aslots + b->n_uslots), hipHostMallocDefault));
     if (hipMalloc((void **)&b->d_ctl, sizeof(BatchCtl)) != hipSuccess) return PM_ENOMEM;
     if (hipMalloc((void **)&b->d_states, sizeof(CGState) * n) != hipSuccess) return PM_ENOMEM;
     HIPCK(hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault));
@@ -3207,6 +3329,19 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     HIPCK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIPCK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
     TRY(b->mixed ? upload_meshes<float>(b) : upload_meshes<double>(b));
+    // a batch rebuilt over handles whose solves are running (begun in an
+    // earlier batch, not finished) continues them: they are in flight here
+    for (int m = 0; m < n; ++m) {
+        pm_handle *h = b->hs[m];
+        if (b->mixed) {
+            b->in_flight[m] = (h->mx.phase == MX_RESIDUAL || h->mx.phase == MX_INNER) ? 1 : 0;
+        } else {
+            CGState st{};
+            HIPCK(hipMemcpy(&st, h->st, sizeof(CGState), hipMemcpyDeviceToHost));
+            b->in_flight[m] = st.done ? 0 : 1;
+        }
+    }
+    b->act_dirty = true;
     // solves of the handles that are in flight continue at launch index k_start
     b->k_next = k_start;
     b->h_ctl->k_apply = k_start;
@@ -3230,7 +3365,7 @@ int batch_capture(pm_batch *b)
     }
     if (b->graph_iters <= 0) return PM_OK;
     HIPCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    const int st = launch_batch_iterations(b, b->graph_iters, b->stream);
+    const int st = launch_batch_iterations(b, b->graph_iters, false, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (st != PM_OK) {
@@ -3254,7 +3389,7 @@ int batch_create_common(pm_handle *const *handles, int32_t n, const int32_t *par
         b->mixed = mixed;
         b->inner_rtol = inner_rtol;
         int s = batch_create_impl(b, handles, n, params);
-        if (s == PM_OK) s = batch_capture(b);
+        // the graph is captured at the first step that replays it
         if (s != PM_OK) {
             batch_free(b);
             return s;
@@ -3287,6 +3422,10 @@ int batch_begin_impl(pm_batch *b, int m, const double *rhs_dev, const double *x0
     TRY(ensure_hist(h, max_iter));
     const int N = int(h->N);
     const unsigned vg = h->n_vblocks;
+    if (!b->in_flight[m]) {
+        b->in_flight[m] = 1;
+        b->act_dirty = true;
+    }
     hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                        h->part_misc());
     TRY(project_rhs(h, s));
@@ -3400,13 +3539,18 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
 {
     const int n = int(b->hs.size());
     if (b->mixed) TRY(batch_corrections(b, s));
+    TRY(refresh_active_slots(b, s));
     int its = 0;
-    if (b->gexec) {
+    if (b->graph_iters > 0 && b->n_aslots_act == b->n_aslots) {
+        // every mesh in flight: the captured graph over all slots (captured
+        // on the batch's stream at the first such step)
+        if (!b->gexec) TRY(batch_capture(b));
         HIPCK(hipGraphLaunch(b->gexec, s));
         its = b->graph_iters;
-    } else {
-        its = 8;
-        TRY(launch_batch_iterations(b, its, s));
+    } else if (b->n_aslots_act > 0) {
+        // some meshes idle: launches over the slots of the meshes in flight
+        its = b->graph_iters > 0 ? b->graph_iters : 8;
+        TRY(launch_batch_iterations(b, its, true, s));
     }
     b->k_next += its;
     if (b->mixed)
@@ -3437,6 +3581,10 @@ int batch_finish_impl(pm_batch *b, int m, const double *rhs_dev, double rtol, do
     pm_handle *h = b->hs[m];
     const int N = int(h->N);
     const unsigned vg = h->n_vblocks;
+    if (b->in_flight[m]) {
+        b->in_flight[m] = 0;
+        b->act_dirty = true;
+    }
     if (b->mixed) {
         pm_handle::MixedSolve &X = b->hs[m]->mx;
         TRY(shift_mean(h, s));
@@ -3499,7 +3647,16 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
     if (!b || iterations_per_replay < 0 || iterations_per_replay > 256 || (iterations_per_replay % 2) != 0)
         return PM_EINVAL;
     b->graph_iters = iterations_per_replay;
-    return batch_capture(b);
+    // the graph of the new length is captured at the next step that replays it
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return PM_OK;
 }
 
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,

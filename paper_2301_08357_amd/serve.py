@@ -9,7 +9,9 @@ Admitted requests join the running batch at the next step, so solves of
 different meshes overlap on the device; a mesh serves one request at a time
 because each request starts from that mesh's previous solution (the warm
 start of the paper's projection stage, Sec. 3.4).  A solve's result does not
-depend on when it joined or on the other solves in flight.
+depend on when it joined or on the other solves in flight.  Meshes are set
+up on worker threads, so that a burst of first requests (each needing its
+mesh's host layout and upload) does not hold up the solves in flight.
 
 The heavy lifting (setup, batched CG steps, residuals) happens in
 libpressure.so; this module only schedules calls.
@@ -17,6 +19,7 @@ libpressure.so; this module only schedules calls.
 
 import collections
 import time
+from concurrent.futures import ThreadPoolExecutor, FIRST_COMPLETED, wait
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -39,6 +42,7 @@ class Request:
     true_relres: float = 0.0
     result: object = None
     cold: bool = True
+    step0: int = 0                  # server step at admission
 
 
 @dataclass
@@ -47,6 +51,11 @@ class ServeStats:
     makespan_s: float = 0.0
     solves_per_s: float = 0.0
     latency_ms: dict = field(default_factory=dict)
+    # the first request of each mesh (cold: setup included, x0 = 0) and the
+    # others (warm), separately; service = completion - admission
+    latency_ms_warm: dict = field(default_factory=dict)
+    latency_ms_cold: dict = field(default_factory=dict)
+    service_ms_mean: float = 0.0
     mean_iters_cold: float = 0.0
     mean_iters_warm: float = 0.0
     loads: int = 0
@@ -69,7 +78,7 @@ class PressureServer:
 
     def __init__(self, problems, budget_bytes, max_in_flight=64, rtol=1e-10, max_iter=20000,
                  graph_iters=16, tiles_per_slot=4, nodes_per_lane=8, keep_x0=False, mixed=False,
-                 inner_rtol=1e-2, on_result=None, retain=False):
+                 inner_rtol=1e-2, on_result=None, retain=False, loaders=4):
         self.problems = problems
         self.budget = int(budget_bytes)
         self.max_in_flight = int(max_in_flight)
@@ -87,6 +96,13 @@ class PressureServer:
         self.on_result = on_result
         self.retain = bool(retain)
         self.retained = 0                             # bytes held by finished requests
+        # Mesh setups (host layout, upload) run on `loaders` worker threads
+        # (the C call releases the GIL), so the batch keeps stepping the
+        # solves in flight while meshes load; 0 sets meshes up inline.
+        self.loaders = int(loaders)
+        self._pool = None
+        self.loading = {}                             # mesh -> Future of its PressureSystem
+        self._device = None
         self.mixed = bool(mixed)
         self.inner_rtol = inner_rtol
         self.flags = _lib.PM_FP64 | (_lib.PM_FP32_INNER if self.mixed else 0)
@@ -104,7 +120,7 @@ class PressureServer:
 
     # -- residency ---------------------------------------------------------
     def _used(self):
-        return sum(self.cost[m] for m in self.resident) + self.retained
+        return sum(self.cost[m] for m in self.resident) + sum(self.cost[m] for m in self.loading) + self.retained
 
     def _make_room(self, m, busy):
         """Evict idle meshes (least recently used first) until mesh m fits."""
@@ -127,10 +143,38 @@ class PressureServer:
             self.dirty = True
         return True
 
+    def _setup(self, m):
+        import torch
+        torch.cuda.set_device(self._device)
+        return PressureSystem.from_problem(self.problems[m], flags=self.flags)
+
     def _load(self, m):
-        p = self.problems[m]
-        self.resident[m] = PressureSystem.from_problem(p, flags=self.flags)
-        self.stats.loads += 1
+        """Set mesh m up: at once (returns True) or on a loader thread."""
+        if self.loaders <= 0:
+            self.resident[m] = PressureSystem.from_problem(self.problems[m], flags=self.flags)
+            self.stats.loads += 1
+            return True
+        if self._pool is None:
+            import torch
+            self._device = torch.cuda.current_device()
+            self._pool = ThreadPoolExecutor(max_workers=self.loaders)
+        self.loading[m] = self._pool.submit(self._setup, m)
+        return False
+
+    def _collect_loads(self, block=False):
+        """Meshes whose setup finished become resident; with block set, wait
+        for the first one.  Returns True if the resident set changed."""
+        if not self.loading:
+            return False
+        if block:
+            wait(list(self.loading.values()), timeout=0.01, return_when=FIRST_COMPLETED)
+        ready = [m for m, f in self.loading.items() if f.done()]
+        for m in ready:
+            self.resident[m] = self.loading.pop(m).result()
+            self.stats.loads += 1
+        if ready:
+            self.dirty = True                          # the batch must take the new meshes
+        return bool(ready)
 
     def _rebuild(self):
         first = self.batch.next_index() if self.batch is not None else self.batch_next
@@ -161,17 +205,21 @@ class PressureServer:
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
                 queues[r.mesh].append(r)
+            changed = self._collect_loads()
             # admission: oldest waiting request first, one per mesh
             waiting = sorted((q[0] for m, q in queues.items() if q and m not in in_flight), key=lambda r: r.arrival)
-            admit, changed = [], False
+            admit = []
             for r in waiting:
                 if len(in_flight) + len(admit) >= self.max_in_flight:
                     break
+                if r.mesh in self.loading:
+                    continue
                 if r.mesh not in self.resident:
-                    busy = set(in_flight) | {a.mesh for a in admit}
+                    busy = set(in_flight) | {a.mesh for a in admit} | set(self.loading)
                     if not self._make_room(r.mesh, busy):
                         continue
-                    self._load(r.mesh)
+                    if not self._load(r.mesh):
+                        continue                  # loading; admitted once resident
                     changed = True
                 admit.append(r)
             t_a = clock()
@@ -189,13 +237,23 @@ class PressureServer:
                     r.x0 = r.x0.clone()
                 r.start = clock() - t0
                 self.batch.begin(self.slot[r.mesh], r.rhs, r.x0, self.rtol, self.max_iter)
+                r.step0 = self.stats.steps
                 in_flight[r.mesh] = r
             t_c = clock()
             self.stats.t_admit += t_c - t_b
             self.stats.max_in_flight_seen = max(self.stats.max_in_flight_seen, len(in_flight))
             if in_flight:
+                if self.batch is None:
+                    raise RuntimeError("requests in flight without a batch")
                 done = self.batch.step()
                 t_d = clock()
+                # every step advances each solve in flight by at least 8 CG
+                # iterations (mixed: or one correction), so a solve still in
+                # flight after this many steps has stopped making progress
+                limit = self.max_iter // 4 + 1000
+                stuck = [m for m, r in in_flight.items() if self.stats.steps - r.step0 > limit]
+                if stuck:
+                    raise RuntimeError("solves of meshes %s made no progress in %d steps" % (stuck[:8], limit))
                 self.stats.t_step += t_d - t_c
                 self.stats.steps += 1
                 for m in [m for m in in_flight if done[self.slot[m]]]:
@@ -213,16 +271,25 @@ class PressureServer:
                         r.rhs = r.x0 = None
                     finished.append(r)
                 self.stats.t_finish += clock() - t_d
+            elif self.loading:
+                self._collect_loads(block=True)
             elif pending:
                 time.sleep(max(0.0, min(1e-3, pending[0].arrival - (clock() - t0))))
         st = self.stats
         st.n = len(finished)
         st.makespan_s = max(r.done for r in finished) if finished else 0.0
         st.solves_per_s = st.n / st.makespan_s if st.makespan_s > 0 else 0.0
-        lat = np.array([r.done - r.arrival for r in finished]) * 1e3
-        if lat.size:
-            st.latency_ms = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                             "mean": float(lat.mean()), "max": float(lat.max())}
+        def pct(rs):
+            lat = np.array([r.done - r.arrival for r in rs]) * 1e3
+            if not lat.size:
+                return {}
+            return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                    "mean": float(lat.mean()), "max": float(lat.max()), "n": int(lat.size)}
+        st.latency_ms = pct(finished)
+        st.latency_ms_warm = pct([r for r in finished if not r.cold])
+        st.latency_ms_cold = pct([r for r in finished if r.cold])
+        if finished:
+            st.service_ms_mean = float(np.mean([r.done - r.start for r in finished])) * 1e3
         cold = [r.iters for r in finished if r.cold]
         warm = [r.iters for r in finished if not r.cold]
         st.mean_iters_cold = float(np.mean(cold)) if cold else 0.0
@@ -230,6 +297,12 @@ class PressureServer:
         return finished
 
     def close(self):
+        for f in self.loading.values():
+            f.result().close()
+        self.loading.clear()
+        if self._pool is not None:
+            self._pool.shutdown()
+            self._pool = None
         if self.batch is not None:
             self.batch.close()
             self.batch = None
