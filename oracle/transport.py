@@ -23,6 +23,24 @@ reconstruction:
                   area vector, plus the primal boundary faces of boundary
                   cells (so that it is the integral of grad P over the cell);
                   boundary faces carry no convective flux; gravity sources.
+  lader_states    the second-order (LADER) states of Sec. 3.2.1 at each dual
+                  face: Step 1, the ENO choice per scalar conservative
+                  variable between the Galerkin (Crouzeix-Raviart) gradient
+                  of the centred element T_ij and that of the upwind element
+                  (the other primal element of the cell; none for a boundary
+                  cell), by the smaller |grad W . (N_ij - N_i)|; Step 2, the
+                  extrapolation W_i + (N_ij - N_i) . grad W to the dual
+                  face's barycentre N_ij (N_i the barycentre of the cell's
+                  primal face); Step 3, the half-step evolution by the
+                  Cauchy-Kovalevskaya form of the mass and momentum
+                  equations written with those gradients (drho/dt =
+                  -div W_u, dW_u/dt = -div(W_u (x) U) - grad P + rho g, grad P
+                  the P1 gradient of P^n on T_ij); Step 4 is the Rusanov flux
+                  of eq. flux_lmnt_lader at the evolved states (lader=True in
+                  transport_step).  The printed Step 3 (a length L_ij that
+                  is not defined, the two sides' fluxes added across one
+                  eta_ij) is read as this predictor; the energy flux takes
+                  rho K from the evolved density and momentum.
 """
 
 import numpy as np
@@ -115,7 +133,90 @@ def viscous_stress(mesh, vel_f, ef, mu):
     return mu * (G + np.transpose(G, (0, 2, 1)) - (2.0 / 3.0) * dv[:, None, None] * np.eye(mesh.dim)[None])
 
 
-def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None, mu=0.0, lam=0.0, r_gas=1.0):
+def other_element(fe, k):
+    """The other primal element of the cell of face f (rows of fe [F, 2]
+    for the faces of elements k), -1 when the face has one element."""
+    return np.where(fe[:, 0] == k, fe[:, 1], fe[:, 0])
+
+
+def eno_extrapolate(w, g_c, g_u, delta):
+    """Step 1 and 2 for one scalar: the gradient of the upwind element g_u
+    when |g_u . delta| <= |g_c . delta| (g_c that of the centred element),
+    else g_c; returns (the chosen gradient, w + delta . gradient)."""
+    dc = (g_c * delta).sum(axis=-1)
+    du = (g_u * delta).sum(axis=-1)
+    pick_u = np.abs(du) <= np.abs(dc)
+    g = np.where(pick_u[..., None], g_u, g_c)
+    return g, w + np.where(pick_u, du, dc)
+
+
+def lader_states(mesh, rho, wu, p, dt, faces, gravity=None):
+    """Evolved states (Steps 1-3) of both sides of every dual face.
+    Returns dict with, per element and local pair (a, b) of
+    dual_geometry's order, the extrapolated ("ext_*") and the evolved
+    ("rho_a", "wu_a", "rho_b", "wu_b") density and momentum of side a (the
+    cell of face a) and side b, the barycentres N_ab and the gradients."""
+    dim = mesh.dim
+    fv, fe, ef = faces
+    F = fv.shape[0]
+    nv = dim + 1
+    rho = np.asarray(rho, dtype=np.float64)
+    wu = np.asarray(wu, dtype=np.float64).reshape(F, dim)
+    fe = np.asarray(fe, dtype=np.int64)
+    ef = np.asarray(ef, dtype=np.int64)
+    x = _geometry_coords(mesh)                                   # [E, d+1, d]
+    E = x.shape[0]
+    B = x.mean(axis=1)
+    _, gphi = op.element_geometry(mesh)                          # grad phi_a [E, d+1, d]
+    # Galerkin (Crouzeix-Raviart) gradients per element: the face-based P1
+    # basis function of face a is 1 - d phi_a
+    g_rho = -dim * np.einsum("ka,kae->ke", rho[ef], gphi)       # [E, d]
+    g_wu = -dim * np.einsum("kac,kae->kce", wu[ef], gphi)       # [E, d, d]: d W_u,c / d x_e
+    P = np.asarray(p, dtype=np.float64)[np.asarray(mesh.elems, dtype=np.int64)]
+    g_p = np.einsum("ka,kae->ke", P, gphi)                      # grad P^n on each element
+    g = np.zeros(dim) if gravity is None else np.asarray(gravity, dtype=np.float64)
+    k_ids = np.arange(E)
+    pairs = [(a, b) for a in range(nv) for b in range(a + 1, nv)]
+    out = {k: np.zeros((E, len(pairs))) for k in ("rho_a", "rho_b", "ext_rho_a", "ext_rho_b")}
+    for k in ("wu_a", "wu_b", "ext_wu_a", "ext_wu_b", "nab"):
+        out[k] = np.zeros((E, len(pairs), dim))
+
+    def side(face_loc, other_loc, q):
+        f = ef[:, face_loc]
+        ko = other_element(fe[f], k_ids)
+        ko_safe = np.where(ko >= 0, ko, k_ids)                    # no upwind element: the centred one
+        shared = [c for c in range(nv) if c not in (face_loc, other_loc)]
+        n_ab = (B + x[:, shared, :].sum(axis=1)) / dim            # barycentre of the dual face
+        n_i = x[:, [c for c in range(nv) if c != face_loc], :].mean(axis=1)   # barycentre of the cell's face
+        delta = n_ab - n_i
+        gr, r = eno_extrapolate(rho[f], g_rho, g_rho[ko_safe], delta)
+        gw = np.zeros((E, dim, dim))
+        u = np.zeros((E, dim))
+        for c in range(dim):
+            gw[:, c, :], u[:, c] = eno_extrapolate(wu[f, c], g_wu[:, c, :], g_wu[ko_safe, c, :], delta)
+        # half-step evolution (Cauchy-Kovalevskaya with the chosen gradients)
+        vel = u / r[:, None]
+        tr = np.trace(gw, axis1=1, axis2=2)
+        div_u = (tr - (vel * gr).sum(axis=1)) / r
+        dr = -tr
+        dw = -(np.einsum("kce,ke->kc", gw, vel) + u * div_u[:, None]) - g_p + r[:, None] * g[None, :]
+        return r, u, r + 0.5 * dt * dr, u + 0.5 * dt * dw, n_ab
+
+    for q, (a, b) in enumerate(pairs):
+        ra, ua, rae, uae, nab = side(a, b, q)
+        rb, ub, rbe, ube, _ = side(b, a, q)
+        out["ext_rho_a"][:, q], out["ext_wu_a"][:, q] = ra, ua
+        out["ext_rho_b"][:, q], out["ext_wu_b"][:, q] = rb, ub
+        out["rho_a"][:, q], out["wu_a"][:, q] = rae, uae
+        out["rho_b"][:, q], out["wu_b"][:, q] = rbe, ube
+        out["nab"][:, q] = nab
+    out["pairs"] = pairs
+    out["g_rho"], out["g_wu"] = g_rho, g_wu
+    return out
+
+
+def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=None, mu=0.0, lam=0.0, r_gas=1.0,
+                   lader=False):
     """Returns dict(rho, wu, we, vol, flux_sum, pforce, visc); faces as
     ``projection.dual_faces`` returns them (default: by node ids).  With
     mu > 0 the viscous terms of eq. discrf_momentum / discrf_energy are
@@ -133,9 +234,15 @@ def transport_step(mesh, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, faces=No
     acc = np.zeros((F, 2 + dim))
     vol = np.zeros(F)
     np.add.at(vol, ef, subvol)
+    ls = lader_states(mesh, rho, wu, p, dt, (fv, fe, ef), gravity) if lader else None
     for q, (a, b) in enumerate(pairs):
         fa, fb = ef[:, a], ef[:, b]
-        phi = rusanov_flux(rho[fa], wu[fa], rho[fb], wu[fb], eta[:, q, :], c_alpha)
+        if lader:
+            # Step 4: the flux at the evolved states of the two sides
+            phi = rusanov_flux(ls["rho_a"][:, q], ls["wu_a"][:, q], ls["rho_b"][:, q], ls["wu_b"][:, q],
+                               eta[:, q, :], c_alpha)
+        else:
+            phi = rusanov_flux(rho[fa], wu[fa], rho[fb], wu[fb], eta[:, q, :], c_alpha)
         np.add.at(acc, fa, phi)
         np.add.at(acc, fb, -phi)
     # pressure force: face-mean pressure times area vector over the cell's
