@@ -546,6 +546,35 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
                        const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
                        double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream);
 
+/* The same transport step at second order in space and time, by the LADER
+ * method of Sec. 3.2.1 (Steps 1-4); arguments, outputs and errors as
+ * pressure_transport.  Only the convective fluxes change:
+ *  1. on every primal element the Galerkin (Crouzeix-Raviart) gradients of
+ *     rho and of each momentum component, grad W = -d sum_a W_{f_a} grad
+ *     phi_a over the element's d+1 dual cells; for the side of cell i on the
+ *     dual face Gamma_ij (inside the centred element T_ij) and each scalar,
+ *     the gradient of the upwind element T_ijL (the other primal element of
+ *     cell i; T_ij itself for a boundary cell) when |grad W . (N_ij - N_i)|
+ *     is not larger than with T_ij's gradient (ENO), else T_ij's; N_ij the
+ *     barycentre of Gamma_ij, N_i that of cell i's primal face;
+ *  2. the extrapolated state W_i + (N_ij - N_i) . grad W;
+ *  3. its evolution by dt/2: the printed Step 3 divides by a length L_ij it
+ *     does not define and adds the two sides' fluxes across one eta_ij; it
+ *     is read as the Cauchy-Kovalevskaya form of the mass and momentum
+ *     equations written with the chosen gradients, d rho/dt = -div W_u,
+ *     d W_u/dt = -div(W_u (x) U) - grad P^n|_{T_ij} + rho g (the pressure and
+ *     gravity terms are the printed ones);
+ *  4. the Rusanov flux of eq. flux_lmnt_lader at the evolved states of the
+ *     two sides (rho K from the evolved rho and W_u).
+ * The pressure force, gravity sources and the viscous and heat-flux terms
+ * are those of pressure_transport (first order in time).  The first call on a
+ * handle also allocates (d + d^2) doubles per primal element for the
+ * gradients, kept until pressure_destroy.  Synchronises the stream before
+ * returning. */
+int pressure_transport_lader(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
+                             const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
+                             double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,8 @@ SIGNATURES = {
     "pressure_projection": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _dbl, _dbl, _i32, _dbl, _i32,
                                            _P, _P, _P, _P, _P]),
     "pressure_transport": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _dbl, _dbl, _dbl, _dbl, _dbl, _P, _P, _P, _P]),
+    "pressure_transport_lader": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _dbl, _dbl, _dbl, _dbl, _dbl, _P, _P, _P,
+                                                _P]),
     "pressure_post_projection": (ctypes.c_int, [_P, _P, _P, _P, _P, _dbl, _dbl, _P, _P]),
 }
 

@@ -1302,6 +1302,8 @@ __global__ void __launch_bounds__(BLK) k_post_faces(int F, ProjArgs pa, const do
 struct TransArgs {
     const int4 *trec;             // 2 per (face, side): vertex ids, then faces opposite them (-1: no element)
     const double *rho, *wu, *we;  // per face; wu: dim per face
+    const int2 *fsl;              // per face: element slots 4k + a of its two sides (-1: none)
+    const double *grad;           // LADER: Galerkin gradients of rho and W_u per element (DIM + DIM^2 each)
     double calpha;                // artificial viscosity coefficient c_alpha
     double mu;                    // dynamic viscosity (0: inviscid)
     double lam_r;                 // thermal conductivity over the gas constant, lambda / R
@@ -1371,16 +1373,111 @@ __global__ void __launch_bounds__(BLK) k_tr_records(int F, const int2 *__restric
     trec[2 * t + 1] = fa;
 }
 
+// LADER (Sec. 3.2.1), the gradients: on every primal element the Galerkin
+// (Crouzeix-Raviart) gradient of rho and of each momentum component from the
+// states of its d+1 dual cells, whose face-based basis functions are
+// 1 - d phi_a: grad W = -d sum_a W_a grad phi_a = -(d / det) sum_a W_a n_a.
+// Per element (internal order) DIM + DIM^2 doubles: grad rho, then
+// grad W_u,c for c = 0 .. DIM-1.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(BLK) k_tr_grad(Mesh g, const int *__restrict__ efc, const double *__restrict__ rho,
+                                                 const double *__restrict__ wu, double *__restrict__ grad)
+{
+    constexpr int NG = DIM + DIM * DIM;
+    const int k = blockIdx.x * BLK + threadIdx.x;
+    if (k >= g.E) return;
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, k, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    double gr[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) gr[j] = 0.0;
+#pragma unroll
+    for (int a = 0; a <= DIM; ++a) {
+        const int f = efc[4 * k + a];
+        const double r = rho[f];
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) gr[e] += r * n[a][e];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const double w = wu[DIM * f + c];
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) gr[DIM + c * DIM + e] += w * n[a][e];
+        }
+    }
+    const double sc = -double(DIM) / det;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) grad[int64_t(NG) * k + j] = gr[j] * sc;
+}
+
+// LADER Steps 1-3 for one side of a dual face: the cell's state (r, u), the
+// gradients of the centred element gc and of the cell's other (upwind)
+// element gu (gc again when there is none), dl = N_ij - N_i.  Per scalar
+// (rho, then each momentum component) the ENO choice takes the upwind
+// gradient when its extrapolation is not larger in magnitude; the
+// extrapolated state is evolved by half a time step (hdt = dt/2) with the
+// Cauchy-Kovalevskaya form of the mass and momentum equations written with
+// the chosen gradients: d rho/dt = -div W_u, d W_u/dt = -div(W_u (x) U)
+// - grad P + rho g, div(W_u (x) U) = (grad W_u) U + W_u div U,
+// div U = (div W_u - U . grad rho) / rho.  Both lanes that see the face
+// evaluate this with the same inputs in the same order.
+template <int DIM>
+__device__ __forceinline__ void lader_side(double r, const double u[3], const double *__restrict__ gc,
+                                           const double *__restrict__ gu, const double dl[3], const double gp[3],
+                                           const double gv[3], double hdt, double &rbar, double ubar[3])
+{
+    double G[1 + DIM][DIM], w[1 + DIM];
+#pragma unroll
+    for (int sc = 0; sc <= DIM; ++sc) {
+        const int o = (sc == 0) ? 0 : DIM + (sc - 1) * DIM;
+        double dc = 0.0, du = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+            dc += gc[o + e] * dl[e];
+            du += gu[o + e] * dl[e];
+        }
+        const bool up = fabs(du) <= fabs(dc);
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) G[sc][e] = up ? gu[o + e] : gc[o + e];
+        w[sc] = ((sc == 0) ? r : u[sc - 1]) + (up ? du : dc);
+    }
+    const double ir = 1.0 / w[0];
+    double U[DIM], tr = 0.0, ug = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        U[c] = w[1 + c] * ir;
+        tr += G[1 + c][c];
+    }
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) ug += U[e] * G[0][e];
+    const double divu = (tr - ug) * ir;
+    rbar = w[0] - hdt * tr;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (c < DIM) {
+            double t = 0.0;
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) t += G[1 + c][e] * U[e];
+            ubar[c] = w[1 + c] - hdt * (t + w[1 + c] * divu + gp[c] - w[0] * gv[c]);
+        } else {
+            ubar[c] = 0.0;
+        }
+    }
+}
+
 // One pass per dual cell f, two lanes per cell (adjacent lanes 2f and
 // 2f+1 of a wave): lane `side` takes the cell's element in that slot, the
 // fluxes to the element's other d faces (ascending local index) and its
 // share |T|/(d+1) grad(P^n) of the pressure force; the even lane adds the
 // odd lane's sums to its own (side 0 + side 1) and writes the update with
 // the gravity sources.  VISC adds the diffusive terms: the viscous stress
-// and the heat flux.  Cells go to XCDs in contiguous chunks (xcd_block): the
-// element and neighbour data of nearby cells then share one L2, which more
-// than halves the kernel's HBM reads.
-template <int DIM, bool PER, bool VISC>
+// and the heat flux.  LADER takes the convective fluxes at the evolved
+// states of the two sides of each dual face (lader_side, from the element
+// gradients of k_tr_grad) instead of the cell states.  Cells go to XCDs in
+// contiguous chunks (xcd_block): the element and neighbour data of nearby
+// cells then share one L2, which more than halves the kernel's HBM reads.
+template <int DIM, bool PER, bool VISC, bool LADER>
 __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const double *__restrict__ pn, int F,
                                                  double *__restrict__ rho_out, double *__restrict__ wu_out,
                                                  double *__restrict__ we_out)
@@ -1410,6 +1507,60 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
             // viscous stress needs all of them at once
             double rs[4], us[4][3];
             const CellState s0 = cell_state(r0, u0);
+            if constexpr (LADER) {
+                // the element k of this side, the cell's other element (the
+                // upwind one of its ENO choices), grad P^n on k, and the
+                // positions of k's vertices and barycentre relative to vertex 0
+                constexpr int NG = DIM + DIM * DIM;
+                const int2 sl = ta.fsl[f];
+                const int k = (side ? sl.y : sl.x) >> 2;
+                const int so = side ? sl.x : sl.y;
+                const double *gk = ta.grad + int64_t(NG) * k;
+                const double *ga = (so < 0) ? gk : ta.grad + int64_t(NG) * (so >> 2);
+                double X[4][3], Bc[3], gp[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    X[0][c] = 0.0;
+                    double t = 0.0, sp = 0.0;
+#pragma unroll
+                    for (int b = 1; b <= DIM; ++b) {
+                        X[b][c] = ed[b - 1][c];
+                        t += X[b][c];
+                    }
+#pragma unroll
+                    for (int b = 0; b <= DIM; ++b) sp += pn[v[b]] * n[b][c];
+                    Bc[c] = t / double(DIM + 1);
+                    gp[c] = (c < DIM) ? sp / det : 0.0;
+                }
+                const double hdt = 0.5 * ta.dt;
+#pragma unroll
+                for (int b = 0; b <= DIM; ++b) {
+                    if (b == a) continue;
+                    const int fb = fe4[b];
+                    const double rB = ta.rho[fb];
+                    double ub[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ub[c] = (c < DIM) ? ta.wu[DIM * fb + c] : 0.0;
+                    // the other element of face b (besides k): side b's upwind element
+                    const int2 sb = ta.fsl[fb];
+                    const int e0 = sb.x >> 2, e1 = (sb.y < 0) ? -1 : (sb.y >> 2);
+                    const int kb = (e0 == k) ? e1 : e0;
+                    const double *gb = (kb < 0) ? gk : ta.grad + int64_t(NG) * kb;
+                    // N_ab - N_a = (B - X_b) / d and N_ab - N_b = (B - X_a) / d
+                    double dla[3], dlb[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        dla[c] = (Bc[c] - X[b][c]) / double(DIM);
+                        dlb[c] = (Bc[c] - X[a][c]) / double(DIM);
+                    }
+                    double rEa, uEa[3], rEb, uEb[3], eta[3];
+                    lader_side<DIM>(r0, u0, gk, ga, dla, gp, ta.g, hdt, rEa, uEa);
+                    lader_side<DIM>(rB, ub, gk, gb, dlb, gp, ta.g, hdt, rEb, uEb);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) eta[c] = ceta * (n[a][c] - n[b][c]);
+                    rusanov_add(cell_state(rEa, uEa), uEa, cell_state(rEb, uEb), uEb, eta, ta.calpha, acc);
+                }
+            }
             if constexpr (VISC) {
 #pragma unroll
                 for (int b = 0; b <= DIM; ++b) {
@@ -1422,7 +1573,7 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
             }
 #pragma unroll
             for (int b = 0; b <= DIM; ++b) {
-                if (b == a) continue;
+                if (LADER || b == a) continue;
                 double eta[3], rb, ub[3];
                 if constexpr (VISC) {
                     rb = rs[b];
@@ -1790,6 +1941,7 @@ struct pm_handle {
         uint8_t *ebnd = nullptr;    // boundary-face bits per internal element
         int2 *fsl = nullptr;        // per face: element slots 4k + a (-1)
         int4 *trec = nullptr;       // transport records, 2 per (face, side); built on the first transport
+        double *grad = nullptr;     // LADER: element gradients of rho and W_u; allocated on the first LADER step
         double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
@@ -2467,7 +2619,7 @@ void pressure_destroy(pm_handle *h)
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
-                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.trec};
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.trec, h->pj.grad};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -3926,11 +4078,12 @@ int pressure_projection(pm_handle *h, const double *rho_dev, const double *we_de
 
 }  // extern "C"
 
-extern "C" {
+namespace {
 
-int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
-                       const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
-                       double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream)
+int transport_impl(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
+                   const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
+                   double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, bool lader,
+                   void *stream)
 {
     if (!h || !rho_dev || !wu_dev || !we_dev || !p_dev || !rho_out || !wu_out || !we_out) return PM_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt) || !(c_alpha >= 0.0) || !std::isfinite(c_alpha)) return PM_EINVAL;
@@ -3946,8 +4099,12 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
                            h->pj.efc, h->pj.trec);
         HIPCK(hipGetLastError());
     }
+    const int NG = h->dim + h->dim * h->dim;
+    if (lader && !h->pj.grad) TRY(dalloc(h, &h->pj.grad, size_t(NG) * size_t(h->E)));
     TransArgs ta;
     ta.trec = h->pj.trec;
+    ta.fsl = h->pj.fsl;
+    ta.grad = h->pj.grad;
     ta.rho = rho_dev;
     ta.wu = wu_dev;
     ta.we = we_dev;
@@ -3962,12 +4119,23 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     hipLaunchKernelGGL(k_gather, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, p_dev, h->pj.pn);
     const dim3 grid(grid_of(2 * int64_t(F)));
     auto launch = [&]<int DIM, bool PER>() {
-        if (mu > 0.0 || lambda > 0.0)
-            hipLaunchKernelGGL((k_tr_cell<DIM, PER, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
+        const bool visc = mu > 0.0 || lambda > 0.0;
+        if (lader) {
+            hipLaunchKernelGGL((k_tr_grad<DIM, PER>), dim3(grid_of(h->E)), dim3(BLK), 0, s, g, h->pj.efc, rho_dev,
+                               wu_dev, h->pj.grad);
+            if (visc)
+                hipLaunchKernelGGL((k_tr_cell<DIM, PER, true, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F,
+                                   rho_out, wu_out, we_out);
+            else
+                hipLaunchKernelGGL((k_tr_cell<DIM, PER, false, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F,
+                                   rho_out, wu_out, we_out);
+        } else if (visc) {
+            hipLaunchKernelGGL((k_tr_cell<DIM, PER, true, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
                                wu_out, we_out);
-        else
-            hipLaunchKernelGGL((k_tr_cell<DIM, PER, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
-                               wu_out, we_out);
+        } else {
+            hipLaunchKernelGGL((k_tr_cell<DIM, PER, false, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F,
+                               rho_out, wu_out, we_out);
+        }
     };
     if (h->dim == 2)
         h->periodic ? launch.template operator()<2, true>() : launch.template operator()<2, false>();
@@ -3976,6 +4144,26 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(s));
     return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
+                       const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
+                       double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream)
+{
+    return transport_impl(h, rho_dev, wu_dev, we_dev, p_dev, gravity, c_alpha, mu, lambda, r_gas, dt, rho_out,
+                          wu_out, we_out, false, stream);
+}
+
+int pressure_transport_lader(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
+                             const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
+                             double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream)
+{
+    return transport_impl(h, rho_dev, wu_dev, we_dev, p_dev, gravity, c_alpha, mu, lambda, r_gas, dt, rho_out,
+                          wu_out, we_out, true, stream);
 }
 
 }  // extern "C"

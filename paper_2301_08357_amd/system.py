@@ -269,10 +269,11 @@ class PressureSystem:
         return we_out
 
     def transport(self, rho, wu, we, p, dt, gravity=None, c_alpha=0.0, mu=0.0, lam=0.0, r_gas=1.0, rho_out=None,
-                  wu_out=None, we_out=None, stream=None):
-        """One first-order transport step on the dual cells (see
-        pressure_transport in include/pressure_cg.h); returns (rho^{n+1},
-        double-tilde W_u, tilde W_E)."""
+                  wu_out=None, we_out=None, stream=None, lader=False):
+        """One transport step on the dual cells, first order (see
+        pressure_transport in include/pressure_cg.h) or, with lader set, the
+        second-order LADER step (pressure_transport_lader); returns
+        (rho^{n+1}, double-tilde W_u, tilde W_E)."""
         import torch
         nf = ctypes.c_int64(0)
         check(load().pressure_dual_count(self._h, ctypes.byref(nf), None), "pressure_dual_count")
@@ -283,12 +284,13 @@ class PressureSystem:
         g = None if gravity is None else _np(gravity, np.float64)
         if g is not None and g.shape != (self.dim,):
             raise ValueError("gravity must have dim entries")
-        check(load().pressure_transport(self._h, _dev_ptr(rho, F, "rho"), _dev_ptr(wu, F * self.dim, "wu"),
-                                        _dev_ptr(we, F, "we"), _dev_ptr(p, self.n_nodes, "p"), _ptr(g),
-                                        float(c_alpha), float(mu), float(lam), float(r_gas), float(dt),
-                                        _dev_ptr(rho_out, F, "rho_out"),
-                                        _dev_ptr(wu_out, F * self.dim, "wu_out"), _dev_ptr(we_out, F, "we_out"),
-                                        _stream_handle(stream)), "pressure_transport")
+        fn = load().pressure_transport_lader if lader else load().pressure_transport
+        check(fn(self._h, _dev_ptr(rho, F, "rho"), _dev_ptr(wu, F * self.dim, "wu"),
+                 _dev_ptr(we, F, "we"), _dev_ptr(p, self.n_nodes, "p"), _ptr(g),
+                 float(c_alpha), float(mu), float(lam), float(r_gas), float(dt),
+                 _dev_ptr(rho_out, F, "rho_out"),
+                 _dev_ptr(wu_out, F * self.dim, "wu_out"), _dev_ptr(we_out, F, "we_out"),
+                 _stream_handle(stream)), "pressure_transport_lader" if lader else "pressure_transport")
         return rho_out, wu_out, we_out
 
     def info(self):

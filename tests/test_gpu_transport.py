@@ -91,6 +91,39 @@ def test_transport_matches_oracle(case, mu, lam):
     s.close()
 
 
+@pytest.mark.parametrize("visc", [False, True])
+@pytest.mark.parametrize("case", CASES)
+def test_lader_transport_matches_oracle(case, visc):
+    """The second-order (LADER, Sec. 3.2.1) step against the oracle's: ENO
+    choices, extrapolation, half-step evolution and the flux at the evolved
+    states, with gravity, pressure and artificial viscosity (and, with
+    visc, the first-order viscous and heat-flux terms)."""
+    m = _mesh(case)
+    mu, lam = (0.05, 0.08) if visc else (0.0, 0.0)
+    print("case lader", case, "mu", mu, "lambda", lam, flush=True)
+    fv, fe, ef = faces = op.dual_faces(m.dim, m.elems, op.morton_rank(m))
+    inp = sproj.fields(m, fv, fe, seed=19)
+    g = np.array([0.1, -0.8, 0.3])[: m.dim]
+    dt = 0.2 / m.n
+    ref = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, gravity=g, c_alpha=0.4,
+                           faces=faces, mu=mu, lam=lam, r_gas=0.4, lader=True)
+    first = ot.transport_step(m, inp["rho_f"], inp["wu_f"], inp["we_f"], inp["p"], dt, gravity=g, c_alpha=0.4,
+                             faces=faces, mu=mu, lam=lam, r_gas=0.4)
+    s = _system(m)
+    rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
+                              gravity=g, c_alpha=0.4, mu=mu, lam=lam, r_gas=0.4, lader=True)
+    rho, wu, we = _host(rho), _host(wu).reshape(-1, m.dim), _host(we)
+    if m.n > 1:
+        assert np.abs(ref["rho"] - first["rho"]).max() > 1e-3 * np.abs(first["rho"] - inp["rho_f"]).max()
+    assert _close(rho, ref["rho"], inp["rho_f"])
+    assert _close(wu, ref["wu"], inp["wu_f"])
+    assert _close(we, ref["we"], inp["we_f"])
+    if m.period is not None and not m.dirichlet.any():
+        vol = ref["vol"]
+        assert abs(vol @ rho - vol @ inp["rho_f"]) < 1e-13 * (vol @ inp["rho_f"])
+    s.close()
+
+
 def test_one_time_step_transport_then_projection():
     m = smesh.periodic_mesh(2, 16, (0,), jitter=0.2, seed=9)
     gamma, dt = 1.4, 0.01
@@ -213,16 +246,19 @@ def test_transport_rejects_invalid_diffusion_parameters():
     s.close()
 
 
-def _sub_faces(elems, fv, fe, cells):
-    """The elements of `cells` (face ids of the full mesh) as a sub-mesh for
-    the oracle: (sub element ids, sub faces (fv, fe, ef) in a local
-    numbering, full face id of each local face).  A cell's update depends
-    only on its one or two elements, their faces' states and their vertex
-    pressures, so on this sub-mesh the oracle gives the full mesh's update
-    for every cell in `cells`."""
+def _sub_faces(elems, fv, fe, cells, sub=None):
+    """The elements of `cells` (face ids of the full mesh), or the element
+    ids `sub`, as a sub-mesh for the oracle: (sub element ids, sub faces
+    (fv, fe, ef) in a local numbering, full face id of each local face).  A
+    first-order cell update depends only on its one or two elements, their
+    faces' states and their vertex pressures, so on this sub-mesh the oracle
+    gives the full mesh's update for every cell in `cells`; a LADER update
+    also reads the gradients of the other elements of those faces, which
+    the caller then adds to `sub`."""
     E = elems.shape[0]
-    sub = np.unique(fe[cells].ravel())
-    sub = sub[sub >= 0]
+    if sub is None:
+        sub = np.unique(fe[cells].ravel())
+        sub = sub[sub >= 0]
     pos = np.full(E + 1, -1, dtype=np.int64)           # pos[-1] stays -1 for "no element"
     pos[sub] = np.arange(sub.size)
     fe64 = fe.astype(np.int64)
@@ -314,3 +350,49 @@ def test_handle_returns_its_device_memory():
     free1 = torch.cuda.mem_get_info()[0]
     F = fv.shape[0]
     assert free0 - free1 < 16 * F, (free0 - free1, 64 * F)
+
+
+def test_lader_full_size_sampled_cells():
+    """160^3 walled cube with the projection-stage input recipe: one LADER
+    step (c_alpha, gravity, P^n) on the GPU; 3000 sampled cells against the
+    oracle on the sub-mesh of the elements that their updates read: their own
+    elements and, for each face of those, the face's other element (the
+    upwind element of the neighbour's ENO choice)."""
+    import types
+    from synth.rng import MASTER_SEED
+    n = 160
+    m = smesh.structured_mesh(3, n, jitter=0.2, seed=MASTER_SEED)
+    print("case full size sampled LADER transport", flush=True)
+    s = _system(m)
+    fv, fe, _ = s.dual_faces()
+    from dualcheck import check_dual_faces
+    check_dual_faces(m.elems, fv, fe, op.morton_rank(m), 12 * n ** 3 + 6 * n ** 2)
+    inp = sproj.fields(m, fv, fe, gamma=1.4, mach=0.1)
+    g = np.array([0.0, 0.0, -1.0])
+    dt = 2e-4
+    rho, wu, we = s.transport(_dev(inp["rho_f"]), _dev(inp["wu_f"]), _dev(inp["we_f"]), _dev(inp["p"]), dt,
+                              gravity=g, c_alpha=0.4, lader=True)
+    rho, wu, we = _host(rho), _host(wu).reshape(-1, 3), _host(we)
+    s.close()
+    F = fv.shape[0]
+    cells = np.sort(np.random.default_rng(MASTER_SEED + 1).choice(F, 3000, replace=False))
+    # elements of the sampled cells, then the other element of each of their faces
+    own = np.unique(fe[cells].ravel())
+    own = own[own >= 0]
+    E = m.n_elems
+    # faces of the own elements: those whose element list holds one of them
+    inown = np.zeros(E + 1, dtype=bool)
+    inown[own] = True
+    fe64 = fe.astype(np.int64)
+    touch = inown[fe64[:, 0]] | inown[fe64[:, 1]]
+    sub = np.unique(fe64[touch].ravel())
+    sub = sub[sub >= 0]
+    _, faces, rows = _sub_faces(m.elems, fv, fe, None, sub=sub)
+    sm = types.SimpleNamespace(dim=3, coords=m.coords, elems=m.elems[sub], n_nodes=m.n_nodes, n_elems=sub.size,
+                               period=None)
+    ref = ot.transport_step(sm, inp["rho_f"][rows], inp["wu_f"][rows], inp["we_f"][rows], inp["p"], dt, gravity=g,
+                            c_alpha=0.4, faces=faces, lader=True)
+    loc = np.searchsorted(rows, cells)
+    assert np.array_equal(rows[loc], cells)
+    for got, want, a0 in ((rho, ref["rho"], inp["rho_f"]), (wu, ref["wu"], inp["wu_f"]), (we, ref["we"], inp["we_f"])):
+        assert _close(got[cells], want[loc], a0[cells])
