@@ -92,6 +92,8 @@ def main():
                     help="transport160/timestep160: dynamic viscosity of the transport stage (0: inviscid)")
     ap.add_argument("--lam", type=float, default=0.0,
                     help="transport160/timestep160: thermal conductivity (gas constant R = 1; 0: no heat flux)")
+    ap.add_argument("--lader", action="store_true",
+                    help="transport160: the second-order LADER step (Sec. 3.2.1) instead of the first-order one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -549,7 +551,7 @@ def bench_transport(args):
 
     def step():
         s.transport(rho, wu, we, p, dt, gravity=g, c_alpha=0.0, mu=args.mu, lam=args.lam, r_gas=1.0,
-                    rho_out=outs[0], wu_out=outs[1], we_out=outs[2])
+                    rho_out=outs[0], wu_out=outs[1], we_out=outs[2], lader=args.lader)
 
     for _ in range(max(args.warmup, 1)):
         step()
@@ -561,16 +563,21 @@ def bench_transport(args):
     el = (time.perf_counter() - t0) / args.steps
     F, E, N = int(fv.shape[0]), int(m.n_elems), int(m.n_nodes)
     alg = F * (80 + 8) + E * (16 + 16) + N * 32
+    if args.lader:
+        # the element gradients of rho and W_u (12 doubles) written once and read once
+        alg += E * 2 * 8 * 12
     ach = alg / el / 1e9
     _common(args, round(F / el / 1e9, 4), "Gcell/s", round(el * 1e3, 3),
             {"workload": "transport160: cube 160^3 x 6 tets (24,576,000 tets, %d dual cells), jitter 0.2h; one step = "
-                         "one first-order Rusanov transport step (Mach 0.1, dt = 0.5h/Mach, gravity, mu = %g, "
-                         "lambda = %g, R = 1)" % (F, args.mu, args.lam),
-             "n_faces": F, "mu": args.mu, "lambda": args.lam},
+                         "one %s transport step (Mach 0.1, dt = 0.5h/Mach, gravity, mu = %g, "
+                         "lambda = %g, R = 1)" % (F, "second-order LADER" if args.lader else "first-order Rusanov",
+                                                   args.mu, args.lam),
+             "n_faces": F, "mu": args.mu, "lambda": args.lam, "lader": bool(args.lader)},
             {"steps_per_s": round(1.0 / el, 3),
              "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                          "kernel": "transport step (gather of P^n + one pass per dual cell), wall time per step",
+                          "kernel": "transport step (gather of P^n, %sone pass per dual cell), wall time per step"
+                                    % ("element gradients, " if args.lader else ""),
                           "bytes_per_step": alg}})
     s.close()
 
@@ -650,12 +657,41 @@ def bench_timestep(args):
 
 
 def bench_copy(args):
-    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the reference
-    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    """The practical HBM ceiling and the counter scale: the hand-written
+    probe kernels of libstream_probe.so (csrc/stream_probe.hip) copy 1 GiB
+    (read 1 GiB, write 1 GiB) and read 1 GiB, over a sweep of grid sizes
+    (best of the steps per grid, HIP events on the probe's stream); torch's
+    copy_ of the same buffers for comparison.  Under rocprofv3 --pmc the
+    counters of the probe kernels (k_copy, k_read) give the FETCH_SIZE /
+    WRITE_SIZE readings of a known byte count."""
+    import ctypes
     import torch
+    from paper_2301_08357_amd import build as pbuild
+    if not os.path.exists(pbuild.PROBE_LIB):
+        raise RuntimeError("libstream_probe.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(pbuild.PROBE_LIB)
+    lib.stream_probe.restype = ctypes.c_int
+    lib.stream_probe.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                 ctypes.c_void_p]
     n = 2 ** 27
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    res = {}
+    for kind, name, nbytes in ((0, "copy", 16 * n), (1, "read", 8 * n)):
+        best = {}
+        for grid in (1024, 2048, 4096, 8192):
+            ts = []
+            for _ in range(max(args.steps, 3)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                if lib.stream_probe(kind, a.data_ptr(), b.data_ptr(), n, grid, ctypes.c_void_p(st.cuda_stream)):
+                    raise RuntimeError("stream_probe failed")
+                e1.record(st)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            best[grid] = round(nbytes / min(ts) / 1e9, 1)
+        res[name] = {"bytes_per_launch": nbytes, "GB_per_s_by_grid": best, "GB_per_s_best": max(best.values())}
     for _ in range(args.warmup):
         b.copy_(a)
     torch.cuda.synchronize()
@@ -664,8 +700,8 @@ def bench_copy(args):
         b.copy_(a)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
-    print(json.dumps({"workload": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
-                      "GB_per_s": round(16 * n / el / 1e9, 1)}), flush=True)
+    res["torch_copy_GB_per_s"] = round(16 * n / el / 1e9, 1)
+    print(json.dumps({"workload": "copy (1 GiB probe kernels)", **res}), flush=True)
 
 
 def _batch_problems(n):

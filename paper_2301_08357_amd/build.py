@@ -10,6 +10,8 @@ OUTDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUTDIR, "libpressure.so")
 
 SOURCES = ["pressure.hip", "layout.cpp", "tune.cpp"]
+PROBE_SOURCE = "stream_probe.hip"          # the benchmark's bandwidth probe (libstream_probe.so)
+PROBE_LIB = os.path.join(OUTDIR, "libstream_probe.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-shared",
@@ -37,14 +39,17 @@ def build(verbose=False):
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
 
+    probe_tmp = PROBE_LIB + tag
+    cmds.append(["/opt/rocm/bin/hipcc"] + HIPCC_FLAGS + [os.path.join(CSRC, PROBE_SOURCE), "-o", probe_tmp])
     try:
         with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
             list(ex.map(run, cmds))
+        os.replace(probe_tmp, PROBE_LIB)
         tmp = LIB + tag
         run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
         os.replace(tmp, LIB)
     finally:
-        for o in objs:
+        for o in objs + [probe_tmp]:
             if os.path.exists(o):
                 os.remove(o)
     return LIB
