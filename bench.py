@@ -743,6 +743,13 @@ def bench_batch(args):
     el, dofit, res = timed(batch)
     its = np.array([r.iters for r in res])
     ref = [r.p.clone() for r in res]
+    # the same solves as one persistent cooperative launch per 16-iteration
+    # step (grid barriers between the phases): timed after, checked bit for bit
+    batch.set_persistent(True)
+    el_p, _, res_p = timed(batch)
+    same = all(bool(torch.equal(r.p, q)) and r.iters == int(k) for r, q, k in zip(res_p, ref, its))
+    persistent = {"persistent_batch_ms": round(el_p / args.steps * 1e3, 3),
+                  "persistent_speedup_vs_graph": round(el / el_p, 3), "persistent_bitwise_equal": same}
     batch.close()
     mixed = {}
     if not args.no_mixed:
@@ -763,7 +770,8 @@ def bench_batch(args):
             dict({"solves_per_s": round(256 * args.steps / el, 2), "iterations_max": int(its.max()),
                   "iterations_mean": float(its.mean()), "graph_iterations_per_replay": 16,
                   "tuned_tiles_per_slot": tps, "tuned_nodes_per_lane": npl,
-                  "tuned_ms_per_iteration": round(tuned_ms, 4), "tuning_s": round(tune_s, 2)}, **mixed))
+                  "tuned_ms_per_iteration": round(tuned_ms, 4), "tuning_s": round(tune_s, 2)}, **persistent,
+                 **mixed))
     for s in systems:
         s.close()
 

@@ -80,6 +80,7 @@ extern "C" {
 #define PM_EBREAKDOWN (-4)    /* CG breakdown: p.Ap <= 0 or not finite            */
 #define PM_EHIP (-5)          /* a HIP runtime call failed                         */
 #define PM_ETOOLARGE (-6)     /* beyond the static scratch of pressure_solve_noalloc */
+#define PM_ETIMEOUT (-7)      /* a grid barrier of a persistent batched launch timed out */
 
 /* Precision flags for pressure_setup / pressure_footprint. */
 #define PM_FP64 1             /* FP64 operator data (always present)               */
@@ -287,7 +288,9 @@ int pressure_info(pm_handle *h, int64_t *info, int32_t n_info);
  * Each CG iteration of all meshes is two kernel launches (the operator apply
  * of every (mesh, tile slot), then the vector update of every (mesh, node
  * slot)); chunks of iterations are captured once in a HIP graph and
- * replayed, and meshes that have converged skip their slots.  This is the
+ * replayed, and meshes that have converged skip their slots.  Optionally
+ * (pressure_batch_set_persistent) each chunk is one cooperative launch of a
+ * persistent kernel whose phases meet at grid barriers.  This is the
  * same classical CG as pressure_solve (paper Sec. 3.4), run for many systems
  * at once.
  */
@@ -361,6 +364,19 @@ int pressure_batch_next_index(pm_batch *b, int32_t *k);
 /* Number of CG iterations captured per graph replay (default 16, even, 2..256);
  * 0 disables graph capture (iterations are launched one by one). */
 int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay);
+
+/* Launch form of the batch's steps.  persistent = 0 (default): two
+ * launches per CG iteration, chunks replayed from the captured graph.
+ * persistent = 1: each step is ONE cooperative launch of a persistent
+ * kernel, as many blocks as can be resident on the device, that runs the
+ * step's iterations (pressure_batch_set_graph's count, 8 if 0) over the
+ * slots of the meshes in flight; inside it the phases (apply of every
+ * slot, update of every slot) are separated by grid barriers instead of
+ * kernel boundaries.  The arithmetic is the same, so results equal the
+ * two-launch form bit for bit.  Each barrier wait is bounded (2 s); if one
+ * times out the step returns PM_ETIMEOUT and the solves in flight are lost
+ * (begin them again).  Errors: PM_EINVAL. */
+int pressure_batch_set_persistent(pm_batch *b, int32_t persistent);
 
 /* Release the batch (not its handles).  NULL is ignored. */
 void pressure_batch_destroy(pm_batch *b);

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libpressure.so")
 
 PM_OK, PM_NOT_CONVERGED, PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EBREAKDOWN, PM_EHIP = 0, 1, -1, -2, -3, -4, -5
 PM_ETOOLARGE = -6
+PM_ETIMEOUT = -7
 PM_NOALLOC_MAX_NODES, PM_NOALLOC_MAX_ITER = 524288, 65535
 PM_FP64, PM_FP32_INNER = 1, 2
 PM_TILE_256, PM_TILE_512, PM_TILE_128 = 0x10, 0x20, 0x30
@@ -54,6 +55,7 @@ SIGNATURES = {
     "pressure_batch_create_mixed": (ctypes.c_int, [_P, _i32, _P, _dbl, ctypes.POINTER(_P)]),
     "pressure_batch_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, _P, _P, _P, _P]),
     "pressure_batch_set_graph": (ctypes.c_int, [_P, _i32]),
+    "pressure_batch_set_persistent": (ctypes.c_int, [_P, _i32]),
     "pressure_batch_next_index": (ctypes.c_int, [_P, ctypes.POINTER(_i32)]),
     "pressure_batch_begin": (ctypes.c_int, [_P, _i32, _P, _P, _dbl, _i32, _P]),
     "pressure_batch_step": (ctypes.c_int, [_P, _P, _P]),

@@ -1713,23 +1713,21 @@ struct BatchCtl {
     int k_apply;   // iteration the next apply launch runs
     int k_update;  // iteration the next update launch runs
     int n_done;
-    int pad;
+    int failed;    // persistent launches: a grid barrier timed out
+    unsigned bar_count, bar_gen;   // persistent launches: grid barrier
+    int pad[2];
 };
 
-// C: size class (128-node tiles) covering every mesh of the batch.  Each
-// solve numbers its iterations from its first launch (k_first) and picks
-// its p and r.r buffers by the parity of that number, as a single-mesh
-// solve does; so a solve may start, or continue, at any launch.
+// The apply of iteration k (launch index) for one (mesh, tile slot) pair
+// ms.  Each solve numbers its iterations from its first launch (k_first)
+// and picks its p and r.r buffers by the parity of that number, as a
+// single-mesh solve does; so a solve may start, or continue, at any launch.
+// C: size class (128-node tiles) covering every mesh of the batch.
 template <int C, class R, bool PER>
-__global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
-                                                     const int2 *__restrict__ slots, BatchCtl *ctl)
+__device__ __forceinline__ void batch_apply_slot(const BatchMeshT<R> *__restrict__ meshes, int2 ms, int k, R *smem,
+                                                 double *red)
 {
-    extern __shared__ double smem_d[];
-    __shared__ double red[BLK / 64];
-    const int2 ms = slots[blockIdx.x];
     const BatchMeshT<R> &M = meshes[ms.x];
-    const int k = ctl->k_apply;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_update = k;
     const int kl = k - M.st->k_first + 1;
     IterT<R> it;
     it.k = kl;
@@ -1746,7 +1744,6 @@ __global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CL
     it.n_vblocks = M.n_vb;
     constexpr TileClass tc = TILE_CLASSES[C];
     static_assert(tc.t == 128, "batched meshes use 128-node tiles");
-    R *smem = reinterpret_cast<R *>(smem_d);
     if (M.dim == 3)
         apply_tiled_body<3, true, R, 128, tc.ipt, tc.lm, BLK, PER>(M.g, M.ta, nullptr, M.q, it, smem, red, ms.y,
                                                                   M.n_ab);
@@ -1755,18 +1752,120 @@ __global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CL
                                                                   M.n_ab);
 }
 
+// The vector update of iteration k for one (mesh, node slot) pair ms.
+template <class R>
+__device__ __forceinline__ void batch_update_slot(const BatchMeshT<R> *__restrict__ meshes, int2 ms, int k,
+                                                  double *red)
+{
+    const BatchMeshT<R> &M = meshes[ms.x];
+    const int kl = k - M.st->k_first + 1;
+    update_body<R>(M.N, M.x, M.r, (kl & 1) ? M.p1 : M.p0, M.q, M.st, M.part_pq, M.n_ab,
+                   (kl & 1) ? M.rr0 : M.rr1, (kl & 1) ? M.rr1 : M.rr0, red, ms.y, M.n_vb);
+}
+
+// Two launches per iteration: the apply over the slot table, then the
+// update.  The iteration number lives in ctl (each kernel reads the field
+// the previous one wrote and writes the other), so a chunk of iterations
+// can be captured in a HIP graph and replayed.
+template <int C, class R, bool PER>
+__global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_apply(const BatchMeshT<R> *__restrict__ meshes,
+                                                     const int2 *__restrict__ slots, BatchCtl *ctl)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[BLK / 64];
+    const int k = ctl->k_apply;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_update = k;
+    batch_apply_slot<C, R, PER>(meshes, slots[blockIdx.x], k, reinterpret_cast<R *>(smem_d), red);
+}
+
 template <class R>
 __global__ void __launch_bounds__(BLK) k_batch_update(const BatchMeshT<R> *__restrict__ meshes,
                                                       const int2 *__restrict__ slots, BatchCtl *ctl)
 {
     __shared__ double red[BLK / 64];
-    const int2 ms = slots[blockIdx.x];
-    const BatchMeshT<R> &M = meshes[ms.x];
     const int k = ctl->k_update;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->k_apply = k + 1;
-    const int kl = k - M.st->k_first + 1;
-    update_body<R>(M.N, M.x, M.r, (kl & 1) ? M.p1 : M.p0, M.q, M.st, M.part_pq, M.n_ab,
-                   (kl & 1) ? M.rr0 : M.rr1, (kl & 1) ? M.rr1 : M.rr0, red, ms.y, M.n_vb);
+    batch_update_slot<R>(meshes, slots[blockIdx.x], k, red);
+}
+
+// Grid barrier of a persistent launch (every block resident: cooperative
+// launch).  Thread 0 of each block releases the block's writes at agent
+// scope (on gfx950 a write-back of its XCD's L2) and arrives on the
+// counter; the last block to arrive resets the counter and advances the
+// generation, the others poll the generation with relaxed loads (an acquire
+// per poll would invalidate the L2 under the blocks still working) and
+// acquire once it has moved.  The wait is bounded by wall-clock time (the
+// 100 MHz constant clock, `limit` ticks): a block that waits longer marks
+// the launch failed and returns false, as does every block once the mark
+// is set, so a launch ends in bounded time whatever happens to its blocks.
+__device__ bool grid_barrier(BatchCtl *ctl, unsigned nblocks, long long limit, int *ok_lds)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == nblocks) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->bar_gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long t0 = wall_clock64();
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (wall_clock64() - t0 > limit ||
+                    __hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = 0;
+                    __hip_atomic_store(&ctl->failed, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (__hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+// Persistent batched CG: one cooperative launch of as many blocks as can be
+// resident runs `count` iterations over the slot tables; in each, the
+// blocks stride over the apply slots, meet at a grid barrier, stride over
+// the update slots and meet again.  The per-slot work is that of
+// k_batch_apply / k_batch_update, so results equal theirs bit for bit.
+template <int C, class R, bool PER>
+__global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_persistent(const BatchMeshT<R> *__restrict__ meshes,
+                                                          const int2 *__restrict__ aslots, int na,
+                                                          const int2 *__restrict__ uslots, int nu, BatchCtl *ctl,
+                                                          int count, long long limit)
+{
+    extern __shared__ double smem_d[];
+    __shared__ double red[BLK / 64];
+    __shared__ int ok_lds;
+    R *smem = reinterpret_cast<R *>(smem_d);
+    // every block reads the first iteration before the first barrier; block
+    // 0 writes the next one after the last
+    const int k0 = ctl->k_apply;
+    bool ok = true;
+    for (int i = 0; i < count && ok; ++i) {
+        for (int j = blockIdx.x; j < na; j += gridDim.x) {
+            batch_apply_slot<C, R, PER>(meshes, aslots[j], k0 + i, smem, red);
+            __syncthreads();
+        }
+        ok = grid_barrier(ctl, gridDim.x, limit, &ok_lds);
+        if (!ok) break;
+        for (int j = blockIdx.x; j < nu; j += gridDim.x) {
+            batch_update_slot<R>(meshes, uslots[j], k0 + i, red);
+            __syncthreads();
+        }
+        ok = grid_barrier(ctl, gridDim.x, limit, &ok_lds);
+    }
+    if (ok && blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->k_update = k0 + count - 1;
+        ctl->k_apply = k0 + count;
+    }
 }
 
 __global__ void k_set_done(CGState *st)
@@ -2555,6 +2654,7 @@ const char *pressure_strerror(int status)
     case PM_ENOMEM: return "out of memory";
     case PM_EBREAKDOWN: return "CG breakdown (p.Ap <= 0 or not finite)";
     case PM_EHIP: return "HIP runtime error";
+    case PM_ETIMEOUT: return "a grid barrier of a persistent batched launch timed out";
     case PM_ETOOLARGE:
         return "larger than the static scratch of pressure_solve_noalloc (n_nodes > PM_NOALLOC_MAX_NODES or "
                "max_iter > PM_NOALLOC_MAX_ITER)";
@@ -3221,6 +3321,9 @@ struct pm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_iters = 16;
+    bool persistent = false;           // one cooperative launch per step (k_batch_persistent)
+    int coop_grid = 0;                 // resident blocks of the persistent kernel (0: not yet known)
+    long long bar_limit = 200000000;   // grid barrier time limit, 100 MHz ticks (2 s)
     int k_next = 1;          // launch index of the next batched iteration
     std::vector<double *> hist_seen;   // history pointers in the uploaded descriptors
 };
@@ -3300,6 +3403,55 @@ int launch_batch_iterations(pm_batch *b, int count, bool active, hipStream_t s)
 {
     return b->mixed ? launch_batch_iterations_t<float>(b, count, active, s)
                     : launch_batch_iterations_t<double>(b, count, active, s);
+}
+
+template <class R, bool PER>
+const void *batch_persistent_kernel(int c)
+{
+    switch (c) {
+    case 0: return (const void *)k_batch_persistent<0, R, PER>;
+    case 1: return (const void *)k_batch_persistent<1, R, PER>;
+    case 2: return (const void *)k_batch_persistent<2, R, PER>;
+    case 3: return (const void *)k_batch_persistent<3, R, PER>;
+    case 4: return (const void *)k_batch_persistent<4, R, PER>;
+    case 5: return (const void *)k_batch_persistent<5, R, PER>;
+    default: return nullptr;
+    }
+}
+
+// count iterations of the meshes in flight as one cooperative launch of
+// the persistent kernel, with as many blocks as can be resident (at most
+// one per slot).  The runtime rejects a cooperative grid that cannot be
+// resident at once.
+template <class R>
+int launch_batch_persistent_t(pm_batch *b, int count, hipStream_t s)
+{
+    const void *kern = b->periodic ? batch_persistent_kernel<R, true>(b->bclass)
+                                   : batch_persistent_kernel<R, false>(b->bclass);
+    if (!kern) return PM_EINVAL;
+    if (b->coop_grid <= 0) {
+        int per_cu = 0, cus = 0;
+        HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLK, b->lds));
+        HIPCK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+        if (per_cu < 1 || cus < 1) return PM_EHIP;
+        b->coop_grid = per_cu * cus;
+    }
+    const BatchMeshT<R> *meshes = (const BatchMeshT<R> *)b->d_meshes;
+    const int2 *as = b->d_aslots_act, *us = b->d_uslots_act;
+    int na = b->n_aslots_act, nu = b->n_uslots_act;
+    const int grid = std::min(b->coop_grid, std::max(na, nu));
+    if (grid < 1 || count < 1) return PM_OK;
+    BatchCtl *ctl = b->d_ctl;
+    long long limit = b->bar_limit;
+    void *args[] = {(void *)&meshes, (void *)&as, (void *)&na, (void *)&us, (void *)&nu, (void *)&ctl,
+                    (void *)&count, (void *)&limit};
+    HIPCK(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(BLK), args, (unsigned)b->lds, s));
+    return PM_OK;
+}
+
+int launch_batch_persistent(pm_batch *b, int count, hipStream_t s)
+{
+    return b->mixed ? launch_batch_persistent_t<float>(b, count, s) : launch_batch_persistent_t<double>(b, count, s);
 }
 
 // Upload the slot tables of the meshes in flight (in mesh order, each
@@ -3496,6 +3648,7 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     b->act_dirty = true;
     // solves of the handles that are in flight continue at launch index k_start
     b->k_next = k_start;
+    std::memset(b->h_ctl, 0, sizeof(BatchCtl));
     b->h_ctl->k_apply = k_start;
     b->h_ctl->k_update = k_start - 1;
     b->h_ctl->n_done = 0;
@@ -3693,7 +3846,12 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
     if (b->mixed) TRY(batch_corrections(b, s));
     TRY(refresh_active_slots(b, s));
     int its = 0;
-    if (b->graph_iters > 0 && b->n_aslots_act == b->n_aslots) {
+    if (b->persistent) {
+        // one cooperative launch over the slots of the meshes in flight
+        its = b->graph_iters > 0 ? b->graph_iters : 8;
+        if (b->n_aslots_act > 0) TRY(launch_batch_persistent(b, its, s));
+        else its = 0;
+    } else if (b->graph_iters > 0 && b->n_aslots_act == b->n_aslots) {
         // every mesh in flight: the captured graph over all slots (captured
         // on the batch's stream at the first such step)
         if (!b->gexec) TRY(batch_capture(b));
@@ -3715,6 +3873,15 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
     HIPCK(hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
     HIPCK(hipMemcpyAsync(b->h_states, b->d_states, sizeof(CGState) * n, hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
+    if (b->h_ctl->failed) {
+        // a grid barrier timed out: the solves in flight are lost; clear the
+        // barrier so the batch can be destroyed or its meshes begun again
+        b->h_ctl->failed = 0;
+        b->h_ctl->bar_count = 0;
+        HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s));
+        HIPCK(hipStreamSynchronize(s));
+        return PM_ETIMEOUT;
+    }
     return PM_OK;
 }
 
@@ -3808,6 +3975,13 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
+    return PM_OK;
+}
+
+int pressure_batch_set_persistent(pm_batch *b, int32_t persistent)
+{
+    if (!b || (persistent != 0 && persistent != 1)) return PM_EINVAL;
+    b->persistent = persistent != 0;
     return PM_OK;
 }
 

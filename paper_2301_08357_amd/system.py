@@ -334,6 +334,12 @@ class PressureBatch:
     def set_graph(self, iterations_per_replay):
         check(load().pressure_batch_set_graph(self._b, int(iterations_per_replay)), "pressure_batch_set_graph")
 
+    def set_persistent(self, persistent=True):
+        """Run each step as one cooperative launch of the persistent kernel
+        (grid barriers between the CG phases) instead of two launches per
+        iteration."""
+        check(load().pressure_batch_set_persistent(self._b, 1 if persistent else 0), "pressure_batch_set_persistent")
+
     def solve(self, rhs, x0=None, rtol=1e-10, max_iter=20000, out=None, stream=None):
         """rhs, x0, out: lists of float64 CUDA tensors (one per system).
         Returns (overall status, list of SolveResult)."""

@@ -207,3 +207,69 @@ def test_batch_real_mix_at_tuned_shape(mixed):
         assert single.iters == r.iters
         assert np.array_equal(_host(single.p).view(np.uint64), x.view(np.uint64))
         s.close()
+
+
+def test_persistent_batch_equals_two_launch_form():
+    """One cooperative launch per step (grid barriers between the CG phases)
+    gives the two-launch form's results bit for bit: whole batched solves
+    (FP64 and mixed, two chunk lengths), continuous batching with a late
+    join, and the real mix at its tuned shape."""
+    probs = _small_mix()
+    print("case persistent small mix", [(p.mesh.dim, p.mesh.n_nodes) for p in probs], flush=True)
+    As = [oracle.assemble_problem(p) for p in probs]
+    rhs = [_dev(_rhs(p, A)) for p, A in zip(probs, As)]
+    for mixed in (False, True):
+        flags = pm.PM_FP64 | (pm.PM_FP32_INNER if mixed else 0)
+        systems = [pm.PressureSystem.from_problem(p, flags=flags) for p in probs]
+        batch = pm.PressureBatch(systems, tiles_per_slot=2, nodes_per_lane=4, mixed=mixed, inner_rtol=1e-2)
+        code, res = batch.solve(rhs, rtol=1e-10)
+        assert code == 0
+        xb = [_host(r.p).copy() for r in res]
+        batch.set_persistent(True)
+        for g in (16, 6):
+            batch.set_graph(g)
+            print("case persistent mixed=%s chunk %d" % (mixed, g), flush=True)
+            code2, res2 = batch.solve(rhs, rtol=1e-10)
+            assert code2 == 0
+            for r, r2, x in zip(res, res2, xb):
+                assert r2.iters == r.iters
+                assert np.array_equal(_host(r2.p).view(np.uint64), x.view(np.uint64))
+        # continuous batching: mesh 3 joins two steps after mesh 0
+        print("case persistent continuous mixed=%s" % mixed, flush=True)
+        outs = {}
+        batch.begin(0, rhs[0], rtol=1e-10)
+        started, steps = {0}, 0
+        while len(outs) < 2:
+            done = batch.step()
+            steps += 1
+            for m in sorted(started):
+                if done[m] and m not in outs:
+                    outs[m] = batch.finish(m, rhs[m], rtol=1e-10)
+            if steps == 2:
+                batch.begin(3, rhs[3], rtol=1e-10)
+                started.add(3)
+            assert steps < 10000
+        for m in (0, 3):
+            assert outs[m].iters == res[m].iters
+            assert np.array_equal(_host(outs[m].p).view(np.uint64), xb[m].view(np.uint64))
+        batch.close()
+        for s in systems:
+            s.close()
+    # the real mix at the tuned shape (its 3D FP64 size class)
+    probs = _real_mix_sample()
+    print("case persistent real mix", [(p.mesh.dim, p.mesh.n_nodes) for p in probs], flush=True)
+    rhs = [_dev(fields.sine_product(p.mesh.coords)) for p in probs]
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    batch = pm.PressureBatch(systems, tiles_per_slot=8, nodes_per_lane=4)
+    code, res = batch.solve(rhs, rtol=1e-10)
+    assert code == 0
+    xb = [_host(r.p).copy() for r in res]
+    batch.set_persistent(True)
+    code2, res2 = batch.solve(rhs, rtol=1e-10)
+    assert code2 == 0
+    for r, r2, x in zip(res, res2, xb):
+        assert r2.iters == r.iters
+        assert np.array_equal(_host(r2.p).view(np.uint64), x.view(np.uint64))
+    batch.close()
+    for s in systems:
+        s.close()
