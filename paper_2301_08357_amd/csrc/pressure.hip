@@ -1714,8 +1714,23 @@ struct BatchCtl {
     int k_update;  // iteration the next update launch runs
     int n_done;
     int failed;    // persistent launches: a grid barrier timed out
-    unsigned bar_count, bar_gen;   // persistent launches: grid barrier
-    int pad[2];
+};
+
+// Grid barrier state of the persistent launches (zero at creation; every
+// launch leaves it as it found it but for the generations).
+// Each counter has a 128-byte line of its own, so that the blocks polling
+// one XCD's generation do not contend with the arrivals of another.
+constexpr int MAX_XCC = 16;
+struct alignas(128) BarWord {
+    unsigned v;
+    unsigned pad[31];
+};
+struct GridBar {
+    BarWord reg[MAX_XCC];   // blocks of the current launch per XCD (registration)
+    BarWord cnt[MAX_XCC];   // arrivals per XCD at the current barrier
+    BarWord gen[MAX_XCC];   // barrier generation per XCD
+    BarWord n_reg;          // blocks registered in the current launch
+    BarWord gcnt, ggen;     // XCD leaders' arrivals and generation
 };
 
 // The apply of iteration k (launch index) for one (mesh, tile slot) pair
@@ -1789,42 +1804,113 @@ __global__ void __launch_bounds__(BLK) k_batch_update(const BatchMeshT<R> *__res
 }
 
 // Grid barrier of a persistent launch (every block resident: cooperative
-// launch).  Thread 0 of each block releases the block's writes at agent
-// scope (on gfx950 a write-back of its XCD's L2) and arrives on the
-// counter; the last block to arrive resets the counter and advances the
-// generation, the others poll the generation with relaxed loads (an acquire
-// per poll would invalidate the L2 under the blocks still working) and
-// acquire once it has moved.  The wait is bounded by wall-clock time (the
-// 100 MHz constant clock, `limit` ticks): a block that waits longer marks
-// the launch failed and returns false, as does every block once the mark
-// is set, so a launch ends in bounded time whatever happens to its blocks.
-__device__ bool grid_barrier(BatchCtl *ctl, unsigned nblocks, long long limit, int *ok_lds)
+// launch), two-level so that each XCD's L2 is written back once per
+// barrier, not once per block.  Blocks on one XCD share its L2: a block
+// makes its stores reach that L2 (every wave waits for its stores), and
+// thread 0 arrives on the XCD's counter.  The last block of the XCD to
+// arrive is its leader: it releases at agent scope (writing back the L2,
+// which now holds every store of the XCD's blocks), arrives on the global
+// counter of leaders, waits for the leaders' generation to move, acquires
+// at agent scope and only then advances the XCD's generation; the other
+// blocks of the XCD wait for that and acquire at agent scope themselves (an
+// invalidate of the L1 alone was measured to leave stale lines visible).
+// Waits poll with relaxed loads and are bounded by
+// wall-clock time (the 100 MHz constant clock, `limit` ticks): a block that
+// waits longer marks the launch failed and returns false, as does every
+// block once the mark is set, so a launch ends in bounded time whatever
+// happens to its blocks.
+__device__ __forceinline__ unsigned xcc_id()
 {
-    __syncthreads();
+    unsigned x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & unsigned(MAX_XCC - 1);
+}
+
+// Wait (thread 0) until *w differs from v; false on time-out or failure mark.
+__device__ __forceinline__ bool bar_wait(const unsigned *w, unsigned v, BatchCtl *ctl, long long limit)
+{
+    const long long t0 = wall_clock64();
+    // the clock and the shared failure mark are looked at every 32nd poll
+    for (unsigned n = 1; __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == v; ++n) {
+        if ((n & 31u) == 0u && (wall_clock64() - t0 > limit ||
+                                __hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            __hip_atomic_store(&ctl->failed, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+struct BarLane {
+    unsigned xcc, n_xcc, n_groups;   // this block's XCD, blocks on it, XCDs with blocks
+};
+
+// Registration at the start of a launch: every block counts itself on its
+// XCD; once all have, each learns its XCD's block count and the number of
+// XCDs in use.  Thread 0's view is broadcast through ok_lds / bl_lds.
+__device__ bool bar_register(GridBar *gb, BatchCtl *ctl, long long limit, BarLane *bl_lds, int *ok_lds)
+{
     if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if (arrived == nblocks) {
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->bar_gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        const unsigned x = xcc_id();
+        __hip_atomic_fetch_add(&gb->reg[x].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned done = __hip_atomic_fetch_add(&gb->n_reg.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        bool ok = true;
+        if (done < gridDim.x) {
             const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (wall_clock64() - t0 > limit ||
-                    __hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    ok = 0;
+            for (unsigned n = 1; __hip_atomic_load(&gb->n_reg.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x;
+                 ++n) {
+                if ((n & 31u) == 0u &&
+                    (wall_clock64() - t0 > limit ||
+                     __hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
                     __hip_atomic_store(&ctl->failed, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
-        *ok_lds = ok;
+        unsigned groups = 0;
+        for (int k = 0; k < MAX_XCC; ++k)
+            groups += (__hip_atomic_load(&gb->reg[k].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ? 1u : 0u;
+        bl_lds->xcc = x;
+        bl_lds->n_xcc = __hip_atomic_load(&gb->reg[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bl_lds->n_groups = groups;
+        *ok_lds = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+__device__ bool grid_barrier(GridBar *gb, BatchCtl *ctl, const BarLane &bl, long long limit, int *ok_lds)
+{
+    // this wave's stores reach the L2 before thread 0 arrives
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        const unsigned x = bl.xcc;
+        const unsigned g = __hip_atomic_load(&gb->gen[x].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(&gb->cnt[x].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == bl.n_xcc) {
+            __hip_atomic_store(&gb->cnt[x].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned gg = __hip_atomic_load(&gb->ggen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned a2 = __hip_atomic_fetch_add(&gb->gcnt.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (a2 == bl.n_groups) {
+                __hip_atomic_store(&gb->gcnt.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&gb->ggen.v, gg + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = bar_wait(&gb->ggen.v, gg, ctl, limit);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(&gb->gen[x].v, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = bar_wait(&gb->gen[x].v, g, ctl, limit);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if (__hip_atomic_load(&ctl->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = false;
+        *ok_lds = ok ? 1 : 0;
     }
     __syncthreads();
     return *ok_lds != 0;
@@ -1839,30 +1925,36 @@ template <int C, class R, bool PER>
 __global__ void __launch_bounds__(BLK, (tile_waves<R, TILE_CLASSES[C].t, TILE_CLASSES[C].lm>())) k_batch_persistent(const BatchMeshT<R> *__restrict__ meshes,
                                                           const int2 *__restrict__ aslots, int na,
                                                           const int2 *__restrict__ uslots, int nu, BatchCtl *ctl,
-                                                          int count, long long limit)
+                                                          GridBar *gb, int count, long long limit)
 {
     extern __shared__ double smem_d[];
     __shared__ double red[BLK / 64];
     __shared__ int ok_lds;
+    __shared__ BarLane bl_lds;
     R *smem = reinterpret_cast<R *>(smem_d);
     // every block reads the first iteration before the first barrier; block
     // 0 writes the next one after the last
     const int k0 = ctl->k_apply;
-    bool ok = true;
+    bool ok = bar_register(gb, ctl, limit, &bl_lds, &ok_lds);
+    const BarLane bl = bl_lds;
     for (int i = 0; i < count && ok; ++i) {
         for (int j = blockIdx.x; j < na; j += gridDim.x) {
             batch_apply_slot<C, R, PER>(meshes, aslots[j], k0 + i, smem, red);
             __syncthreads();
         }
-        ok = grid_barrier(ctl, gridDim.x, limit, &ok_lds);
+        ok = grid_barrier(gb, ctl, bl, limit, &ok_lds);
         if (!ok) break;
         for (int j = blockIdx.x; j < nu; j += gridDim.x) {
             batch_update_slot<R>(meshes, uslots[j], k0 + i, red);
             __syncthreads();
         }
-        ok = grid_barrier(ctl, gridDim.x, limit, &ok_lds);
+        ok = grid_barrier(gb, ctl, bl, limit, &ok_lds);
     }
+    // after the last barrier every block has read its registration: block 0
+    // clears it for the next launch
     if (ok && blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < MAX_XCC; ++k) __hip_atomic_store(&gb->reg[k].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&gb->n_reg.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ctl->k_update = k0 + count - 1;
         ctl->k_apply = k0 + count;
     }
@@ -3313,6 +3405,7 @@ struct pm_batch {
     int n_aslots_act = 0, n_uslots_act = 0;
     bool act_dirty = true;
     BatchCtl *d_ctl = nullptr, *h_ctl = nullptr;
+    GridBar *d_bar = nullptr;          // persistent launches: grid barrier state (zeroed)
     CGState *d_states = nullptr, *h_states = nullptr;
     int bclass = -1;
     size_t lds = 0;
@@ -3442,9 +3535,10 @@ int launch_batch_persistent_t(pm_batch *b, int count, hipStream_t s)
     const int grid = std::min(b->coop_grid, std::max(na, nu));
     if (grid < 1 || count < 1) return PM_OK;
     BatchCtl *ctl = b->d_ctl;
+    GridBar *gb = b->d_bar;
     long long limit = b->bar_limit;
     void *args[] = {(void *)&meshes, (void *)&as, (void *)&na, (void *)&us, (void *)&nu, (void *)&ctl,
-                    (void *)&count, (void *)&limit};
+                    (void *)&gb, (void *)&count, (void *)&limit};
     HIPCK(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(BLK), args, (unsigned)b->lds, s));
     return PM_OK;
 }
@@ -3484,7 +3578,7 @@ void batch_free(pm_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (void *p : {(void *)b->d_meshes, (void *)b->d_aslots, (void *)b->d_uslots, (void *)b->d_ctl,
+    for (void *p : {(void *)b->d_meshes, (void *)b->d_aslots, (void *)b->d_uslots, (void *)b->d_ctl, (void *)b->d_bar,
                     (void *)b->d_states, (void *)b->d_aslots_act, (void *)b->d_uslots_act})
         if (p) (void)hipFree(p);
     if (b->h_slots_act) (void)hipHostFree(b->h_slots_act);
@@ -3626,6 +3720,8 @@ int batch_create_impl(pm_batch *b, pm_handle *const *handles, int32_t n, const i
     TRY(up(&b->d_uslots_act, uslots));
     HIPCK(hipHostMalloc((void **)&b->h_slots_act, sizeof(int2) * (b->n_aslots + b->n_uslots), hipHostMallocDefault));
     if (hipMalloc((void **)&b->d_ctl, sizeof(BatchCtl)) != hipSuccess) return PM_ENOMEM;
+    if (hipMalloc((void **)&b->d_bar, sizeof(GridBar)) != hipSuccess) return PM_ENOMEM;
+    HIPCK(hipMemset(b->d_bar, 0, sizeof(GridBar)));
     if (hipMalloc((void **)&b->d_states, sizeof(CGState) * n) != hipSuccess) return PM_ENOMEM;
     HIPCK(hipHostMalloc((void **)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault));
     HIPCK(hipHostMalloc((void **)&b->h_states, sizeof(CGState) * n, hipHostMallocDefault));
@@ -3838,6 +3934,12 @@ int batch_corrections(pm_batch *b, hipStream_t s)
     return PM_OK;
 }
 
+bool batch_mesh_done(const pm_batch *b, int m)
+{
+    if (b->mixed) return b->hs[m]->mx.phase == MX_IDLE || b->hs[m]->mx.phase == MX_FINISHED;
+    return b->h_states[m].done != 0;
+}
+
 // Advance every solve in flight by one chunk of iterations (mixed batches:
 // after the correction pass); copies the states to b->h_states.
 int batch_step_impl(pm_batch *b, hipStream_t s)
@@ -3877,19 +3979,21 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
         // a grid barrier timed out: the solves in flight are lost; clear the
         // barrier so the batch can be destroyed or its meshes begun again
         b->h_ctl->failed = 0;
-        b->h_ctl->bar_count = 0;
         HIPCK(hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s));
+        HIPCK(hipMemsetAsync(b->d_bar, 0, sizeof(GridBar), s));
         HIPCK(hipStreamSynchronize(s));
         return PM_ETIMEOUT;
     }
+    // solves that have stopped leave the active tables: later steps launch
+    // no blocks for them (pressure_batch_finish still takes them)
+    for (int m = 0; m < n; ++m)
+        if (b->in_flight[m] && batch_mesh_done(b, m)) {
+            b->in_flight[m] = 0;
+            b->act_dirty = true;
+        }
     return PM_OK;
 }
 
-bool batch_mesh_done(const pm_batch *b, int m)
-{
-    if (b->mixed) return b->hs[m]->mx.phase == MX_IDLE || b->hs[m]->mx.phase == MX_FINISHED;
-    return b->h_states[m].done != 0;
-}
 
 // True residual and output of a finished mesh; for FP64 solves, residual
 // replacement (as in pressure_solve) when the recursive residual met rtol
