@@ -349,9 +349,10 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
  * The batch runs on a stream of its own: _begin and _step start after the
  * work already queued on `stream`, _finish's output is ready in `stream`
  * order, and _step returns with the batch's work complete.  A step launches
- * blocks only for the meshes in flight (begun and not yet finished): with
- * every mesh in flight it replays the captured graph, otherwise it launches
- * the same iterations directly over the slots of those meshes. */
+ * blocks only for the meshes in flight (begun, and not yet stopped or
+ * finished): with every mesh in flight it replays the captured graph,
+ * otherwise it launches the same iterations directly over the slots of
+ * those meshes. */
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
                          int32_t max_iter, void *stream);
 int pressure_batch_step(pm_batch *b, int32_t *done, void *stream);
