@@ -1466,18 +1466,102 @@ __device__ __forceinline__ void lader_side(double r, const double u[3], const do
     }
 }
 
+// The diffusive terms of cell a's side on element T_k (first order in
+// time): the viscous stress from the Crouzeix-Raviart gradient of the face
+// velocities, and the heat flux from the cells' temperatures.  rs, us: the
+// states of T_k's d+1 faces; n, det: its adjugate normals and determinant;
+// pn, v: the vertex pressures.
+template <int DIM>
+__device__ __forceinline__ void visc_side(int a, const double rs[4], const double us[4][3], const double n[4][3],
+                                          double det, const double *__restrict__ pn, const int v[4],
+                                          const TransArgs &ta, double acc[5])
+{
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    constexpr double ceta = double(DIM) / (double(DIM + 1) * dfact);
+    // Crouzeix-Raviart gradient of the face velocities on T_k,
+    // grad u = -d sum_b u_b (x) grad phi_b, and the stress
+    // tau = mu (grad u + grad u^T - 2/3 div u I), constant on T_k
+    double vel[4][DIM], gu[DIM][DIM], tau[DIM][DIM], ir[4];
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+        ir[b] = 1.0 / rs[b];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) vel[b][c] = us[b][c] * ir[b];
+    }
+    const double gs = -double(DIM) / det;
+    double dv = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+            double t = 0.0;
+#pragma unroll
+            for (int b = 0; b <= DIM; ++b) t += vel[b][c] * n[b][e];
+            gu[c][e] = t * gs;
+            if (c == e) dv += gu[c][e];
+        }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int e = 0; e < DIM; ++e)
+            tau[c][e] = ta.mu * (gu[c][e] + gu[e][c] - ((c == e) ? (2.0 / 3.0) * dv : 0.0));
+    // momentum: minus the integral of tau eta over the cell's dual
+    // faces in T_k, which close on n_a / (d-1)!
+    constexpr double ffact = (DIM == 2) ? 1.0 : 2.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) t += tau[c][e] * n[a][e];
+        acc[1 + c] -= t / ffact;
+    }
+    // energy: minus (tau u) . eta on each dual face, u the mean
+    // velocity of the two cells
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+        if (b == a) continue;
+        double te = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) t += tau[c][e] * (ceta * (n[a][e] - n[b][e]));
+            te += t * (0.5 * (vel[a][c] + vel[b][c]));
+        }
+        acc[4] -= te;
+    }
+    // heat flux Q = -lambda grad Theta with Theta = P / (rho R) on
+    // each cell, P the mean of its face's vertex pressures, and
+    // the same Galerkin gradient; Q . eta over the cell's dual
+    // faces in T_k closes on Q . n_a / (d-1)!
+    double pv[4], ps = 0.0;
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+        pv[b] = pn[v[b]];
+        ps += pv[b];
+    }
+    double qn = 0.0;
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+        const double th = (ps - pv[b]) * (1.0 / double(DIM)) * ir[b];
+        double nn = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) nn += n[b][e] * n[a][e];
+        qn += th * nn;
+    }
+    acc[4] -= ta.lam_r * gs * qn / ffact;
+}
+
 // One pass per dual cell f, two lanes per cell (adjacent lanes 2f and
 // 2f+1 of a wave): lane `side` takes the cell's element in that slot, the
 // fluxes to the element's other d faces (ascending local index) and its
 // share |T|/(d+1) grad(P^n) of the pressure force; the even lane adds the
 // odd lane's sums to its own (side 0 + side 1) and writes the update with
 // the gravity sources.  VISC adds the diffusive terms: the viscous stress
-// and the heat flux.  LADER takes the convective fluxes at the evolved
-// states of the two sides of each dual face (lader_side, from the element
-// gradients of k_tr_grad) instead of the cell states.  Cells go to XCDs in
-// contiguous chunks (xcd_block): the element and neighbour data of nearby
-// cells then share one L2, which more than halves the kernel's HBM reads.
-template <int DIM, bool PER, bool VISC, bool LADER>
+// and the heat flux.  Cells go to XCDs in contiguous chunks (xcd_block):
+// the element and neighbour data of nearby cells then share one L2, which
+// more than halves the kernel's HBM reads.
+template <int DIM, bool PER, bool VISC>
 __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const double *__restrict__ pn, int F,
                                                  double *__restrict__ rho_out, double *__restrict__ wu_out,
                                                  double *__restrict__ we_out)
@@ -1507,60 +1591,6 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
             // viscous stress needs all of them at once
             double rs[4], us[4][3];
             const CellState s0 = cell_state(r0, u0);
-            if constexpr (LADER) {
-                // the element k of this side, the cell's other element (the
-                // upwind one of its ENO choices), grad P^n on k, and the
-                // positions of k's vertices and barycentre relative to vertex 0
-                constexpr int NG = DIM + DIM * DIM;
-                const int2 sl = ta.fsl[f];
-                const int k = (side ? sl.y : sl.x) >> 2;
-                const int so = side ? sl.x : sl.y;
-                const double *gk = ta.grad + int64_t(NG) * k;
-                const double *ga = (so < 0) ? gk : ta.grad + int64_t(NG) * (so >> 2);
-                double X[4][3], Bc[3], gp[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    X[0][c] = 0.0;
-                    double t = 0.0, sp = 0.0;
-#pragma unroll
-                    for (int b = 1; b <= DIM; ++b) {
-                        X[b][c] = ed[b - 1][c];
-                        t += X[b][c];
-                    }
-#pragma unroll
-                    for (int b = 0; b <= DIM; ++b) sp += pn[v[b]] * n[b][c];
-                    Bc[c] = t / double(DIM + 1);
-                    gp[c] = (c < DIM) ? sp / det : 0.0;
-                }
-                const double hdt = 0.5 * ta.dt;
-#pragma unroll
-                for (int b = 0; b <= DIM; ++b) {
-                    if (b == a) continue;
-                    const int fb = fe4[b];
-                    const double rB = ta.rho[fb];
-                    double ub[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) ub[c] = (c < DIM) ? ta.wu[DIM * fb + c] : 0.0;
-                    // the other element of face b (besides k): side b's upwind element
-                    const int2 sb = ta.fsl[fb];
-                    const int e0 = sb.x >> 2, e1 = (sb.y < 0) ? -1 : (sb.y >> 2);
-                    const int kb = (e0 == k) ? e1 : e0;
-                    const double *gb = (kb < 0) ? gk : ta.grad + int64_t(NG) * kb;
-                    // N_ab - N_a = (B - X_b) / d and N_ab - N_b = (B - X_a) / d
-                    double dla[3], dlb[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        dla[c] = (Bc[c] - X[b][c]) / double(DIM);
-                        dlb[c] = (Bc[c] - X[a][c]) / double(DIM);
-                    }
-                    double rEa, uEa[3], rEb, uEb[3], eta[3];
-                    lader_side<DIM>(r0, u0, gk, ga, dla, gp, ta.g, hdt, rEa, uEa);
-                    lader_side<DIM>(rB, ub, gk, gb, dlb, gp, ta.g, hdt, rEb, uEb);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) eta[c] = ceta * (n[a][c] - n[b][c]);
-                    rusanov_add(cell_state(rEa, uEa), uEa, cell_state(rEb, uEb), uEb, eta, ta.calpha, acc);
-                }
-            }
             if constexpr (VISC) {
 #pragma unroll
                 for (int b = 0; b <= DIM; ++b) {
@@ -1573,7 +1603,7 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
             }
 #pragma unroll
             for (int b = 0; b <= DIM; ++b) {
-                if (LADER || b == a) continue;
+                if (b == a) continue;
                 double eta[3], rb, ub[3];
                 if constexpr (VISC) {
                     rb = rs[b];
@@ -1596,80 +1626,7 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
                 for (int b = 0; b <= DIM; ++b) tp += pn[v[b]] * n[b][c];
                 acc[1 + c] += tp * share;
             }
-            if constexpr (VISC) {
-                // Crouzeix-Raviart gradient of the face velocities on T_k,
-                // grad u = -d sum_b u_b (x) grad phi_b, and the stress
-                // tau = mu (grad u + grad u^T - 2/3 div u I), constant on T_k
-                double vel[4][DIM], gu[DIM][DIM], tau[DIM][DIM], ir[4];
-#pragma unroll
-                for (int b = 0; b <= DIM; ++b) {
-                    ir[b] = 1.0 / rs[b];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) vel[b][c] = us[b][c] * ir[b];
-                }
-                const double gs = -double(DIM) / det;
-                double dv = 0.0;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                    for (int e = 0; e < DIM; ++e) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int b = 0; b <= DIM; ++b) t += vel[b][c] * n[b][e];
-                        gu[c][e] = t * gs;
-                        if (c == e) dv += gu[c][e];
-                    }
-#pragma unroll
-                for (int c = 0; c < DIM; ++c)
-#pragma unroll
-                    for (int e = 0; e < DIM; ++e)
-                        tau[c][e] = ta.mu * (gu[c][e] + gu[e][c] - ((c == e) ? (2.0 / 3.0) * dv : 0.0));
-                // momentum: minus the integral of tau eta over the cell's dual
-                // faces in T_k, which close on n_a / (d-1)!
-                constexpr double ffact = (DIM == 2) ? 1.0 : 2.0;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int e = 0; e < DIM; ++e) t += tau[c][e] * n[a][e];
-                    acc[1 + c] -= t / ffact;
-                }
-                // energy: minus (tau u) . eta on each dual face, u the mean
-                // velocity of the two cells
-#pragma unroll
-                for (int b = 0; b <= DIM; ++b) {
-                    if (b == a) continue;
-                    double te = 0.0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int e = 0; e < DIM; ++e) t += tau[c][e] * (ceta * (n[a][e] - n[b][e]));
-                        te += t * (0.5 * (vel[a][c] + vel[b][c]));
-                    }
-                    acc[4] -= te;
-                }
-                // heat flux Q = -lambda grad Theta with Theta = P / (rho R) on
-                // each cell, P the mean of its face's vertex pressures, and
-                // the same Galerkin gradient; Q . eta over the cell's dual
-                // faces in T_k closes on Q . n_a / (d-1)!
-                double pv[4], ps = 0.0;
-#pragma unroll
-                for (int b = 0; b <= DIM; ++b) {
-                    pv[b] = pn[v[b]];
-                    ps += pv[b];
-                }
-                double qn = 0.0;
-#pragma unroll
-                for (int b = 0; b <= DIM; ++b) {
-                    const double th = (ps - pv[b]) * (1.0 / double(DIM)) * ir[b];
-                    double nn = 0.0;
-#pragma unroll
-                    for (int e = 0; e < DIM; ++e) nn += n[b][e] * n[a][e];
-                    qn += th * nn;
-                }
-                acc[4] -= ta.lam_r * gs * qn / ffact;
-            }
+            if constexpr (VISC) visc_side<DIM>(a, rs, us, n, det, pn, v, ta, acc);
         }
     }
     // the pair's lanes are 2f and 2f+1 of the same wave (BLK is a multiple of 64)
@@ -1678,6 +1635,166 @@ __global__ void __launch_bounds__(BLK) k_tr_cell(Mesh g, TransArgs ta, const dou
     vol += __shfl_xor(vol, 1);
     if (!live || side) return;
     const double q = ta.dt / vol;   // dt / |C_f|
+    rho_out[f] = r0 - q * acc[0];
+    double gw = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        gw += ta.g[c] * u0[c];
+        wu_out[DIM * f + c] = u0[c] - q * acc[1 + c] + ta.dt * r0 * ta.g[c];
+    }
+    we_out[f] = ta.we[f] - q * acc[4] + ta.dt * gw;
+}
+
+// LADER (Sec. 3.2.1), the element pass: four adjacent lanes per element k
+// (lanes 4k' .. 4k'+3 of a wave; in 2D the fourth idles), lane a for the
+// side of k's face a, that is of the dual cell f_a.  Lane a forms, for each
+// other face b (ascending), the evolved state of its cell at the dual face
+// between f_a and f_b (lader_side with the centred gradient of k and the
+// upwind gradient of f_a's other element); the state of f_b's side at the
+// same dual face is lane b's, read from LDS.  So each side of
+// each dual face is evolved once, and the two lanes of a dual face see the
+// same two states and opposite fluxes.  The lane sums its Rusanov fluxes in
+// ascending b, adds its share of the pressure force (and with VISC the
+// diffusive terms) and writes them with the share |T|/(d+1) of the cell
+// volume as the slot record of (k, a): 6 doubles at 6 (4k + a).
+template <int DIM, bool PER, bool VISC>
+__global__ void __launch_bounds__(BLK) k_lader_elem(Mesh g, TransArgs ta, const int *__restrict__ efc,
+                                                    const double *__restrict__ pn, double *__restrict__ slots)
+{
+    constexpr int NG = DIM + DIM * DIM, NV = DIM + 1;
+    constexpr double dfact = (DIM == 2) ? 2.0 : 6.0;
+    constexpr double ceta = double(DIM) / (double(DIM + 1) * dfact);
+    constexpr double share = 1.0 / (dfact * double(DIM + 1));
+    const int t = xcd_block(int(blockIdx.x), int(gridDim.x)) * BLK + threadIdx.x;
+    const int k = t >> 2, a = t & 3;
+    const bool live = k < g.E && a < NV;
+    const int kk = (k < g.E) ? k : g.E - 1;   // lanes past the end mirror the last element
+    int v[4];
+    double ed[3][3], n[4][3];
+    elem_corners<DIM, PER>(g, kk, v, ed);
+    const double det = elem_normals<DIM>(ed, n);
+    // vertex positions relative to vertex 0, barycentre, grad P^n on k
+    double X[4][3], Bc[3], gp[3], tp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        X[0][c] = 0.0;
+        double s = 0.0, sp = 0.0;
+#pragma unroll
+        for (int b = 1; b <= DIM; ++b) {
+            X[b][c] = ed[b - 1][c];
+            s += X[b][c];
+        }
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b) sp += pn[v[b]] * n[b][c];
+        Bc[c] = s / double(DIM + 1);
+        gp[c] = (c < DIM) ? sp / det : 0.0;
+        tp[c] = sp;
+    }
+    // this lane's cell, its state and its upwind element (the other
+    // element of face a; k itself on the boundary)
+    const int al = (a < NV) ? a : 0;
+    const int fa = efc[4 * kk + al];
+    const double r0 = ta.rho[fa];
+    double u0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u0[c] = (c < DIM) ? ta.wu[DIM * fa + c] : 0.0;
+    const int2 sla = ta.fsl[fa];
+    const int so = (sla.x == 4 * kk + al) ? sla.y : sla.x;
+    const double *gk = ta.grad + int64_t(NG) * kk;
+    const double *ga = (so < 0) ? gk : ta.grad + int64_t(NG) * (so >> 2);
+    const double hdt = 0.5 * ta.dt;
+    // the lane's normal n_a, and per partner j (b = j or j + 1, ascending)
+    // the partner's normal and position, chosen without indexing local
+    // arrays by the lane number
+    double na[3], nb[3][3], Xb[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        na[c] = n[0][c];
+#pragma unroll
+        for (int q = 1; q <= DIM; ++q)
+            if (al == q) na[c] = n[q][c];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            const bool sh = j >= al;
+            nb[j][c] = sh ? n[j + 1][c] : n[j][c];
+            Xb[j][c] = sh ? X[j + 1][c] : X[j][c];
+        }
+    }
+    // evolved states of this side at its d dual faces (partner b ascending)
+    // go to LDS, (lane, j)-major, 4 doubles each: the lanes of a dual face
+    // read each other's there
+    __shared__ double sE[BLK * DIM * 4];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+        double dl[3], er, eu[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dl[c] = (Bc[c] - Xb[j][c]) / double(DIM);
+        lader_side<DIM>(r0, u0, gk, ga, dl, gp, ta.g, hdt, er, eu);
+        double *e = sE + 4 * (DIM * int(threadIdx.x) + j);
+        e[0] = er;
+        e[1] = eu[0];
+        e[2] = eu[1];
+        e[3] = eu[2];
+    }
+    __syncthreads();
+    if (!live) return;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+        const int b = j + ((j >= al) ? 1 : 0);
+        const int jb = al - ((al > b) ? 1 : 0);   // this lane's index among lane b's partners
+        const double *e = sE + 4 * (DIM * int(threadIdx.x) + j);
+        const double *fp = sE + 4 * (DIM * int((threadIdx.x & ~3u) + unsigned(b)) + jb);
+        const double eu[3] = {e[1], e[2], e[3]}, fu[3] = {fp[1], fp[2], fp[3]};
+        double eta[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) eta[c] = ceta * (na[c] - nb[j][c]);
+        rusanov_add(cell_state(e[0], eu), eu, cell_state(fp[0], fu), fu, eta, ta.calpha, acc);
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[1 + c] += tp[c] * share;
+    if constexpr (VISC) {
+        double rs[4], us[4][3];
+#pragma unroll
+        for (int b = 0; b <= DIM; ++b) {
+            const int fb = efc[4 * kk + b];
+            rs[b] = (b == al) ? r0 : ta.rho[fb];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) us[b][c] = (b == al) ? u0[c] : ((c < DIM) ? ta.wu[DIM * fb + c] : 0.0);
+        }
+        visc_side<DIM>(al, rs, us, n, det, pn, v, ta, acc);
+    }
+    double *out = slots + 6 * (int64_t(4) * k + a);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = acc[c];
+    out[5] = det * share;
+}
+
+// LADER, the cell pass: cell f adds the slot records of its two sides
+// (side 0 + side 1) and takes the update with the gravity sources, as the
+// first-order kernel does.
+template <int DIM>
+__global__ void __launch_bounds__(BLK) k_lader_cell(TransArgs ta, int F, const double *__restrict__ slots,
+                                                    double *__restrict__ rho_out, double *__restrict__ wu_out,
+                                                    double *__restrict__ we_out)
+{
+    const int f = xcd_block(int(blockIdx.x), int(gridDim.x)) * BLK + threadIdx.x;
+    if (f >= F) return;
+    const int2 sl = ta.fsl[f];
+    double acc[6];
+    const double *r0p = slots + 6 * int64_t(sl.x);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] = r0p[c];
+    if (sl.y >= 0) {
+        const double *r1p = slots + 6 * int64_t(sl.y);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += r1p[c];
+    }
+    const double r0 = ta.rho[f];
+    double u0[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) u0[c] = ta.wu[DIM * f + c];
+    const double q = ta.dt / acc[5];   // dt / |C_f|
     rho_out[f] = r0 - q * acc[0];
     double gw = 0.0;
 #pragma unroll
@@ -2133,6 +2250,7 @@ struct pm_handle {
         int2 *fsl = nullptr;        // per face: element slots 4k + a (-1)
         int4 *trec = nullptr;       // transport records, 2 per (face, side); built on the first transport
         double *grad = nullptr;     // LADER: element gradients of rho and W_u; allocated on the first LADER step
+        double *slots = nullptr;    // LADER: slot records (5 sums + volume share) per (element, face); idem
         double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
@@ -2811,7 +2929,8 @@ void pressure_destroy(pm_handle *h)
                     h->t_nflag, h->b, h->x, h->r, h->q, h->t, h->pbuf[0],
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
-                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.trec, h->pj.grad};
+                    h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.trec, h->pj.grad,
+                    h->pj.slots};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -4371,7 +4490,7 @@ int transport_impl(pm_handle *h, const double *rho_dev, const double *wu_dev, co
     TRY(ensure_faces(h));
     hipStream_t s = (hipStream_t)stream;
     const int N = int(h->N), F = int(h->pj.F.n_faces);
-    if (!h->pj.trec) {
+    if (!lader && !h->pj.trec) {
         TRY(dalloc(h, &h->pj.trec, size_t(4) * size_t(F)));
         hipLaunchKernelGGL(k_tr_records, dim3(grid_of(2 * int64_t(F))), dim3(BLK), 0, s, F, h->pj.fsl, h->conn,
                            h->pj.efc, h->pj.trec);
@@ -4379,6 +4498,7 @@ int transport_impl(pm_handle *h, const double *rho_dev, const double *wu_dev, co
     }
     const int NG = h->dim + h->dim * h->dim;
     if (lader && !h->pj.grad) TRY(dalloc(h, &h->pj.grad, size_t(NG) * size_t(h->E)));
+    if (lader && !h->pj.slots) TRY(dalloc(h, &h->pj.slots, size_t(24) * size_t(h->E)));
     TransArgs ta;
     ta.trec = h->pj.trec;
     ta.fsl = h->pj.fsl;
@@ -4401,18 +4521,21 @@ int transport_impl(pm_handle *h, const double *rho_dev, const double *wu_dev, co
         if (lader) {
             hipLaunchKernelGGL((k_tr_grad<DIM, PER>), dim3(grid_of(h->E)), dim3(BLK), 0, s, g, h->pj.efc, rho_dev,
                                wu_dev, h->pj.grad);
+            const dim3 eg(grid_of(4 * h->E));
             if (visc)
-                hipLaunchKernelGGL((k_tr_cell<DIM, PER, true, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F,
-                                   rho_out, wu_out, we_out);
+                hipLaunchKernelGGL((k_lader_elem<DIM, PER, true>), eg, dim3(BLK), 0, s, g, ta, h->pj.efc, h->pj.pn,
+                                   h->pj.slots);
             else
-                hipLaunchKernelGGL((k_tr_cell<DIM, PER, false, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F,
-                                   rho_out, wu_out, we_out);
+                hipLaunchKernelGGL((k_lader_elem<DIM, PER, false>), eg, dim3(BLK), 0, s, g, ta, h->pj.efc, h->pj.pn,
+                                   h->pj.slots);
+            hipLaunchKernelGGL((k_lader_cell<DIM>), dim3(grid_of(F)), dim3(BLK), 0, s, ta, F, h->pj.slots, rho_out,
+                               wu_out, we_out);
         } else if (visc) {
-            hipLaunchKernelGGL((k_tr_cell<DIM, PER, true, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
+            hipLaunchKernelGGL((k_tr_cell<DIM, PER, true>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
                                wu_out, we_out);
         } else {
-            hipLaunchKernelGGL((k_tr_cell<DIM, PER, false, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F,
-                               rho_out, wu_out, we_out);
+            hipLaunchKernelGGL((k_tr_cell<DIM, PER, false>), grid, dim3(BLK), 0, s, g, ta, h->pj.pn, F, rho_out,
+                               wu_out, we_out);
         }
     };
     if (h->dim == 2)
