@@ -584,10 +584,14 @@ int pressure_transport(pm_handle *h, const double *rho_dev, const double *wu_dev
  *  4. the Rusanov flux of eq. flux_lmnt_lader at the evolved states of the
  *     two sides (rho K from the evolved rho and W_u).
  * The pressure force, gravity sources and the viscous and heat-flux terms
- * are those of pressure_transport (first order in time).  The first call on a
- * handle also allocates (d + d^2) doubles per primal element for the
- * gradients, kept until pressure_destroy.  Synchronises the stream before
- * returning. */
+ * are those of pressure_transport (first order in time).  The step runs
+ * per primal element: each side of each dual face is evolved once, the two
+ * sides of a dual face see opposite fluxes (conservative), and a cell adds
+ * the sums of its two elements.  The first call on a handle also allocates
+ * (d + d^2) doubles per primal element for the gradients and 24 doubles
+ * per primal element for the per-side sums, kept until pressure_destroy;
+ * it does not allocate pressure_transport's element records.  Synchronises
+ * the stream before returning. */
 int pressure_transport_lader(pm_handle *h, const double *rho_dev, const double *wu_dev, const double *we_dev,
                              const double *p_dev, const double *gravity, double c_alpha, double mu, double lambda,
                              double r_gas, double dt, double *rho_out, double *wu_out, double *we_out, void *stream);
