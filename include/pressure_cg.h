@@ -74,6 +74,7 @@ extern "C" {
 /* Status codes. */
 #define PM_OK 0               /* success                                          */
 #define PM_NOT_CONVERGED 1    /* max_iter reached; the output holds the last iterate */
+#define PM_PENDING 2          /* pressure_batch_step_poll: the step is still running */
 #define PM_EINVAL (-1)        /* invalid argument (NULL, dim, index, rtol, c_e, NaN) */
 #define PM_EDEGENERATE (-2)   /* an element has zero volume                       */
 #define PM_ENOMEM (-3)        /* device or host allocation failed                 */
@@ -356,6 +357,20 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
                          int32_t max_iter, void *stream);
 int pressure_batch_step(pm_batch *b, int32_t *done, void *stream);
+
+/* pressure_batch_step in two halves, so that one host thread can keep the
+ * steps of several batches (each on its own stream) running on the device
+ * at once: _launch queues the step after the work already queued on
+ * `stream` and returns without waiting; _wait waits for it and writes
+ * done[] as pressure_batch_step does.  Between the two no other call may be
+ * made on the batch but _poll (PM_EINVAL: a second _launch, _begin, _finish,
+ * _step, _solve; _wait without a _launch).  Errors as pressure_batch_step. */
+int pressure_batch_step_launch(pm_batch *b, void *stream);
+int pressure_batch_step_wait(pm_batch *b, int32_t *done);
+
+/* _wait without blocking: PM_PENDING (nothing written) while the step
+ * queued by _launch still runs, else what _wait returns. */
+int pressure_batch_step_poll(pm_batch *b, int32_t *done);
 int pressure_batch_finish(pm_batch *b, int32_t m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
                           double *true_relres, void *stream);
 

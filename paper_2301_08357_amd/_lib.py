@@ -10,6 +10,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libpressure.so")
 
 PM_OK, PM_NOT_CONVERGED, PM_EINVAL, PM_EDEGENERATE, PM_ENOMEM, PM_EBREAKDOWN, PM_EHIP = 0, 1, -1, -2, -3, -4, -5
+PM_PENDING = 2
 PM_ETOOLARGE = -6
 PM_ETIMEOUT = -7
 PM_NOALLOC_MAX_NODES, PM_NOALLOC_MAX_ITER = 524288, 65535
@@ -56,6 +57,9 @@ SIGNATURES = {
     "pressure_batch_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, _P, _P, _P, _P]),
     "pressure_batch_set_graph": (ctypes.c_int, [_P, _i32]),
     "pressure_batch_set_persistent": (ctypes.c_int, [_P, _i32]),
+    "pressure_batch_step_launch": (ctypes.c_int, [_P, _P]),
+    "pressure_batch_step_wait": (ctypes.c_int, [_P, _P]),
+    "pressure_batch_step_poll": (ctypes.c_int, [_P, _P]),
     "pressure_batch_next_index": (ctypes.c_int, [_P, ctypes.POINTER(_i32)]),
     "pressure_batch_begin": (ctypes.c_int, [_P, _i32, _P, _P, _dbl, _i32, _P]),
     "pressure_batch_step": (ctypes.c_int, [_P, _P, _P]),

@@ -2865,6 +2865,7 @@ const char *pressure_strerror(int status)
     case PM_EBREAKDOWN: return "CG breakdown (p.Ap <= 0 or not finite)";
     case PM_EHIP: return "HIP runtime error";
     case PM_ETIMEOUT: return "a grid barrier of a persistent batched launch timed out";
+    case PM_PENDING: return "the batch step is still running";
     case PM_ETOOLARGE:
         return "larger than the static scratch of pressure_solve_noalloc (n_nodes > PM_NOALLOC_MAX_NODES or "
                "max_iter > PM_NOALLOC_MAX_ITER)";
@@ -3534,6 +3535,7 @@ struct pm_batch {
     hipGraphExec_t gexec = nullptr;
     int graph_iters = 16;
     bool persistent = false;           // one cooperative launch per step (k_batch_persistent)
+    bool step_pending = false;         // pressure_batch_step_launch without its _wait yet
     int coop_grid = 0;                 // resident blocks of the persistent kernel (0: not yet known)
     long long bar_limit = 200000000;   // grid barrier time limit, 100 MHz ticks (2 s)
     int k_next = 1;          // launch index of the next batched iteration
@@ -4061,7 +4063,7 @@ bool batch_mesh_done(const pm_batch *b, int m)
 
 // Advance every solve in flight by one chunk of iterations (mixed batches:
 // after the correction pass); copies the states to b->h_states.
-int batch_step_impl(pm_batch *b, hipStream_t s)
+int batch_step_launch(pm_batch *b, hipStream_t s)
 {
     const int n = int(b->hs.size());
     if (b->mixed) TRY(batch_corrections(b, s));
@@ -4093,6 +4095,14 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
     HIPCK(hipGetLastError());
     HIPCK(hipMemcpyAsync(b->h_ctl, b->d_ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
     HIPCK(hipMemcpyAsync(b->h_states, b->d_states, sizeof(CGState) * n, hipMemcpyDeviceToHost, s));
+    return PM_OK;
+}
+
+// The end of a step started by batch_step_launch: wait for it; the states
+// are then in b->h_states.
+int batch_step_wait(pm_batch *b, hipStream_t s)
+{
+    const int n = int(b->hs.size());
     HIPCK(hipStreamSynchronize(s));
     if (b->h_ctl->failed) {
         // a grid barrier timed out: the solves in flight are lost; clear the
@@ -4111,6 +4121,12 @@ int batch_step_impl(pm_batch *b, hipStream_t s)
             b->act_dirty = true;
         }
     return PM_OK;
+}
+
+int batch_step_impl(pm_batch *b, hipStream_t s)
+{
+    TRY(batch_step_launch(b, s));
+    return batch_step_wait(b, s);
 }
 
 
@@ -4211,7 +4227,7 @@ int pressure_batch_set_persistent(pm_batch *b, int32_t persistent)
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
                          int32_t max_iter, void *stream)
 {
-    if (!b || m < 0 || m >= int(b->hs.size()) || !rhs_dev || !(rtol > 0.0) || !std::isfinite(rtol) || max_iter < 0)
+    if (!b || b->step_pending || m < 0 || m >= int(b->hs.size()) || !rhs_dev || !(rtol > 0.0) || !std::isfinite(rtol) || max_iter < 0)
         return PM_EINVAL;
     hipStream_t us = (hipStream_t)stream, s = b->stream;
     HIPCK(hipEventRecord(b->ev, us));
@@ -4220,9 +4236,37 @@ int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const do
     return batch_refresh(b);
 }
 
+int pressure_batch_step_launch(pm_batch *b, void *stream)
+{
+    if (!b || b->step_pending) return PM_EINVAL;
+    HIPCK(hipEventRecord(b->ev, (hipStream_t)stream));
+    HIPCK(hipStreamWaitEvent(b->stream, b->ev, 0));
+    TRY(batch_step_launch(b, b->stream));
+    b->step_pending = true;
+    return PM_OK;
+}
+
+int pressure_batch_step_poll(pm_batch *b, int32_t *done)
+{
+    if (!b || !done || !b->step_pending) return PM_EINVAL;
+    const hipError_t q = hipStreamQuery(b->stream);
+    if (q == hipErrorNotReady) return PM_PENDING;
+    if (q != hipSuccess) return hip_failed(q, "hipStreamQuery(b->stream)", __LINE__);
+    return pressure_batch_step_wait(b, done);
+}
+
+int pressure_batch_step_wait(pm_batch *b, int32_t *done)
+{
+    if (!b || !done || !b->step_pending) return PM_EINVAL;
+    b->step_pending = false;
+    TRY(batch_step_wait(b, b->stream));
+    for (size_t m = 0; m < b->hs.size(); ++m) done[m] = batch_mesh_done(b, int(m)) ? 1 : 0;
+    return PM_OK;
+}
+
 int pressure_batch_step(pm_batch *b, int32_t *done, void *stream)
 {
-    if (!b || !done) return PM_EINVAL;
+    if (!b || !done || b->step_pending) return PM_EINVAL;
     // the batch runs on its own stream, after the caller's work so far
     HIPCK(hipEventRecord(b->ev, (hipStream_t)stream));
     HIPCK(hipStreamWaitEvent(b->stream, b->ev, 0));
@@ -4234,7 +4278,7 @@ int pressure_batch_step(pm_batch *b, int32_t *done, void *stream)
 int pressure_batch_finish(pm_batch *b, int32_t m, const double *rhs_dev, double rtol, double *p_dev, int32_t *iters,
                           double *true_relres, void *stream)
 {
-    if (!b || m < 0 || m >= int(b->hs.size()) || !rhs_dev || !p_dev || !iters || !true_relres) return PM_EINVAL;
+    if (!b || b->step_pending || m < 0 || m >= int(b->hs.size()) || !rhs_dev || !p_dev || !iters || !true_relres) return PM_EINVAL;
     hipStream_t us = (hipStream_t)stream, s = b->stream;
     const int code = batch_finish_impl(b, m, rhs_dev, rtol, p_dev, iters, true_relres, s);
     HIPCK(hipEventRecord(b->ev, s));
@@ -4246,8 +4290,8 @@ int pressure_batch_solve(pm_batch *b, const double *const *rhs_dev, const double
                          int32_t max_iter, double *const *p_dev, int32_t *iters, double *true_relres,
                          int32_t *status, void *stream)
 {
-    if (!b || !rhs_dev || !p_dev || !iters || !true_relres || !status || !(rtol > 0.0) || !std::isfinite(rtol) ||
-        max_iter < 0)
+    if (!b || b->step_pending || !rhs_dev || !p_dev || !iters || !true_relres || !status || !(rtol > 0.0) ||
+        !std::isfinite(rtol) || max_iter < 0)
         return PM_EINVAL;
     const int n = int(b->hs.size());
     for (int m = 0; m < n; ++m)

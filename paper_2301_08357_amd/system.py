@@ -381,6 +381,26 @@ class PressureBatch:
         check(load().pressure_batch_step(self._b, _ptr(done), _stream_handle(stream)), "pressure_batch_step")
         return done != 0
 
+    def step_launch(self, stream=None):
+        """Queue one step (as step) and return at once; step_wait() ends it."""
+        check(load().pressure_batch_step_launch(self._b, _stream_handle(stream)), "pressure_batch_step_launch")
+
+    def step_wait(self):
+        """Wait for the step queued by step_launch; returns the done flags."""
+        done = np.zeros(len(self.systems), dtype=np.int32)
+        check(load().pressure_batch_step_wait(self._b, _ptr(done)), "pressure_batch_step_wait")
+        return done != 0
+
+    def step_poll(self):
+        """The done flags if the step queued by step_launch has ended (as
+        step_wait), else None."""
+        done = np.zeros(len(self.systems), dtype=np.int32)
+        code = load().pressure_batch_step_poll(self._b, _ptr(done))
+        if code == _lib.PM_PENDING:
+            return None
+        check(code, "pressure_batch_step_poll")
+        return done != 0
+
     def finish(self, m, rhs, rtol=1e-10, out=None, stream=None):
         import torch
         s = self.systems[m]

@@ -92,6 +92,7 @@ def test_batch_edge_cases():
     zero = _dev(np.zeros(probs[1].mesh.n_nodes))
     code, res = batch.solve([b0, zero], rtol=1e-10)
     assert code == 0 and res[1].iters == 0 and np.all(_host(res[1].p) == 0)
+    iters_ref, p_ref = res[0].iters, _host(res[0].p).copy()
     code, res = batch.solve([b0, _dev(_rhs(probs[1], As[1]))], rtol=1e-12, max_iter=3)
     assert code == pm.PM_NOT_CONVERGED
     assert all(r.status == pm.PM_NOT_CONVERGED and r.iters == 3 for r in res)
@@ -101,6 +102,30 @@ def test_batch_edge_cases():
     assert code == 0 and res2[0].iters == 0
     with pytest.raises(pm.PressureError):
         batch.set_graph(3)
+    # a step split in two: nothing else may run on the batch in between
+    batch.begin(0, b0, rtol=1e-10)
+    batch.step_launch()
+    with pytest.raises(pm.PressureError):
+        batch.begin(1, zero, rtol=1e-10)
+    with pytest.raises(pm.PressureError):
+        batch.step_launch()
+    done = batch.step_wait()
+    with pytest.raises(pm.PressureError):
+        batch.step_wait()
+    for _ in range(1000):
+        if done[0]:
+            break
+        batch.step_launch()
+        # the non-blocking form ends the step as step_wait does
+        done = None
+        for _ in range(10 ** 6):
+            done = batch.step_poll()
+            if done is not None:
+                break
+        assert done is not None
+    res3 = batch.finish(0, b0, rtol=1e-10)
+    assert res3.status == 0 and res3.iters == iters_ref
+    assert np.array_equal(_host(res3.p).view(np.uint64), p_ref.view(np.uint64))
     batch.close()
     for s in systems:
         s.close()
