@@ -322,6 +322,8 @@ def bench_cube160(args):
         out["tgv2d_32"] = extra_tgv2d32(args)
     if main_line and not args.no_cpu:
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline_cube160(prob, s, args)
+        if not args.no_extras:
+            out["cpu_baseline"]["other_configs"] = oracle_other_configs(args)
     print(json.dumps(out), flush=True)
     s.close()
 
@@ -400,6 +402,88 @@ def extra_tgv2d32(args, solves=300):
             "solves_per_s": round(solves / el, 1), "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
             "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4), "iterations": its[0],
             "GDOF_iter_per_s": round(nfree * sum(its) / el / 1e9, 4)}
+
+
+def oracle_other_configs(args, single_seconds=6.0):
+    """The CPU oracle on the other fixed configurations, beside the GPU:
+    tgv2d_32 (to rtol 1e-12), cube64 (the three w, to rtol 1e-10) and 16
+    meshes of the batched mix (to rtol 1e-10; the GPU solves them as one
+    batch at the tuned shape).  Assembly is not timed; each oracle solve runs
+    on all host cores and on one thread (the batch subset on one thread over
+    its first meshes, about single_seconds)."""
+    import torch
+    import oracle
+    import paper_2301_08357_amd as pm
+    from synth import fields, workloads
+    cores = len(os.sched_getaffinity(0))
+
+    def solve_all(cases, rtol, threads, budget=None):
+        oracle.set_threads(threads)
+        t_sum, dofit, iters = 0.0, 0.0, []
+        for A, b, nfree, dirichlet in cases:
+            ta = time.perf_counter()
+            _, st, it, _, _ = oracle.cg(A, b, rtol=rtol, max_iter=20000, dirichlet=dirichlet)
+            t_sum += time.perf_counter() - ta
+            dofit += nfree * it
+            iters.append(it)
+            if budget is not None and t_sum > budget:
+                break
+        oracle.set_threads(1)
+        return {"value": round(dofit / t_sum / 1e9, 5), "seconds": round(t_sum, 3), "iterations": iters}
+
+    out = {"cores": cores}
+    # config 1: b = A p* (the oracle's operator), repeated to about 0.2 s
+    prob = workloads.tgv2d(32)
+    A = oracle.assemble_problem(prob)
+    b = A.matvec(fields.sine_product(prob.mesh.coords))
+    nf = int((prob.mesh.dirichlet == 0).sum())
+    reps = 40
+    one = [(A, b, nf, prob.mesh.dirichlet)] * reps
+    out["tgv2d_32"] = {"all_cores": solve_all(one, 1e-12, cores), "single_thread": solve_all(one, 1e-12, 1),
+                       "solves": reps}
+    for k in ("all_cores", "single_thread"):
+        rec = out["tgv2d_32"][k]
+        rec["latency_ms"] = round(rec["seconds"] / reps * 1e3, 4)
+        rec["iterations"] = rec["iterations"][0]
+    # config 2: the three w
+    cases = []
+    for w in workloads.CUBE64_W:
+        prob = workloads.cube64(w)
+        A = oracle.assemble_problem(prob)
+        cases.append((A, A.matvec(prob.extra["xstar"]), int((prob.mesh.dirichlet == 0).sum()), prob.mesh.dirichlet))
+    out["cube64"] = {"all_cores": solve_all(cases, args.rtol, cores), "single_thread": solve_all(cases, args.rtol, 1)}
+    # 16 meshes of the batched mix, and the GPU's batched solve of the same systems
+    params = workloads.batch_params()
+    probs = [workloads.batch_problem(i, params) for i in workloads.batch_sample(16, params)]
+    cases = []
+    for prob in probs:
+        A = oracle.assemble_problem(prob)
+        cases.append((A, A.matvec(prob.extra["xstar"]), int((prob.mesh.dirichlet == 0).sum()), prob.mesh.dirichlet))
+    out["batch16"] = {"all_cores": solve_all(cases, args.rtol, cores),
+                      "single_thread": solve_all(cases, args.rtol, 1, budget=single_seconds)}
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    rhs = [torch.tensor(c[1], device="cuda") for c in cases]
+    batch = pm.PressureBatch(systems, tiles_per_slot=8, nodes_per_lane=4)
+    batch.solve(rhs, rtol=args.rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_rep, dofit = 3, 0.0
+    for _ in range(n_rep):
+        code, res = batch.solve(rhs, rtol=args.rtol)
+        if code != 0:
+            raise RuntimeError("batch16 status %d" % code)
+        dofit += sum(c[2] * r.iters for c, r in zip(cases, res))
+    el = time.perf_counter() - t0
+    out["batch16"]["gpu"] = {"value": round(dofit / el / 1e9, 4), "solves_per_s": round(16 * n_rep / el, 1),
+                             "ms_per_batched_solve": round(el / n_rep * 1e3, 3),
+                             "iterations": [r.iters for r in res]}
+    batch.close()
+    for q in systems:
+        q.close()
+    out["unit"] = "GDOF*iter/s"
+    out["note"] = ("oracle: assembled CSR + textbook CG (OpenMP SpMV rows, fixed-order dots on all cores); "
+                   "GPU figures for tgv2d_32 and cube64 are the line's tgv2d_32 and cube64 entries")
+    return out
 
 
 def cpu_baseline_cube160(prob, s, args):

@@ -89,6 +89,26 @@ def batch_params(n_meshes=256, seed=MASTER_SEED):
     return out
 
 
+def batch_sample(k=16, params=None):
+    """Indices of k meshes of the batched mix: its largest 2D and 3D meshes,
+    its smallest one and its extreme mass weights, the rest spread evenly
+    over the list (the same meshes every run)."""
+    params = batch_params() if params is None else params
+    size = [(n + 1) ** d for d, n, w in params]
+    idx = set()
+    for d in (2, 3):
+        same = [i for i in range(len(params)) if params[i][0] == d]
+        idx.add(max(same, key=lambda i: size[i]))
+    idx.add(min(range(len(params)), key=lambda i: size[i]))
+    idx.add(min(range(len(params)), key=lambda i: params[i][2]))
+    idx.add(max(range(len(params)), key=lambda i: params[i][2]))
+    for i in np.linspace(0, len(params) - 1, 2 * k).astype(int):
+        if len(idx) >= k:
+            break
+        idx.add(int(i))
+    return sorted(idx)
+
+
 def batch_problem(mi, params, seed=MASTER_SEED):
     dim, n, w = params[mi]
     s = seed + 1 + mi

@@ -180,23 +180,11 @@ def test_mixed_batch_matches_single_mixed():
 
 
 def _real_mix_sample(k=16):
-    """k meshes of the 256-mesh batched workload itself: its largest 2D and
-    3D meshes, its smallest one and its extreme mass weights, the rest
-    spread evenly over the list (seeded, same meshes every run)."""
+    """k meshes of the 256-mesh batched workload itself (its largest 2D and
+    3D meshes, its smallest one, its extreme mass weights, the rest spread
+    over the list)."""
     params = workloads.batch_params()
-    size = [(n + 1) ** d for d, n, w in params]
-    idx = set()
-    for d in (2, 3):
-        same = [i for i in range(len(params)) if params[i][0] == d]
-        idx.add(max(same, key=lambda i: size[i]))
-    idx.add(min(range(len(params)), key=lambda i: size[i]))
-    idx.add(min(range(len(params)), key=lambda i: params[i][2]))
-    idx.add(max(range(len(params)), key=lambda i: params[i][2]))
-    for i in np.linspace(0, len(params) - 1, 2 * k).astype(int):
-        if len(idx) >= k:
-            break
-        idx.add(int(i))
-    return [workloads.batch_problem(i, params) for i in sorted(idx)]
+    return [workloads.batch_problem(i, params) for i in workloads.batch_sample(k, params)]
 
 
 @pytest.mark.parametrize("mixed", [False, True])
