@@ -1304,6 +1304,7 @@ struct TransArgs {
     const double *rho, *wu, *we;  // per face; wu: dim per face
     const int2 *fsl;              // per face: element slots 4k + a of its two sides (-1: none)
     const double *grad;           // LADER: Galerkin gradients of rho and W_u per element (DIM + DIM^2 each)
+    const int *oslot;             // LADER: per element slot 4k + a, the other slot of face a's cell (-1: none)
     double calpha;                // artificial viscosity coefficient c_alpha
     double mu;                    // dynamic viscosity (0: inviscid)
     double lam_r;                 // thermal conductivity over the gas constant, lambda / R
@@ -1371,6 +1372,23 @@ __global__ void __launch_bounds__(BLK) k_tr_records(int F, const int2 *__restric
     }
     trec[2 * t] = va;
     trec[2 * t + 1] = fa;
+}
+
+// Per element slot s = 4k + a (a <= d): the other slot of the cell of k's
+// face a, whose element is that cell's upwind element for this side (-1 on
+// the boundary).  Built once, so that the LADER element pass reaches the
+// upwind gradient without looking up the face first.
+__global__ void __launch_bounds__(BLK) k_tr_oslot(int n_slots, int nv, const int *__restrict__ efc,
+                                                  const int2 *__restrict__ fsl, int *__restrict__ oslot)
+{
+    const int s = blockIdx.x * BLK + threadIdx.x;
+    if (s >= n_slots) return;
+    int o = -1;
+    if ((s & 3) < nv) {
+        const int2 sl = fsl[efc[s]];
+        o = (sl.x == s) ? sl.y : sl.x;
+    }
+    oslot[s] = o;
 }
 
 // LADER (Sec. 3.2.1), the gradients: on every primal element the Galerkin
@@ -1674,7 +1692,9 @@ __global__ void __launch_bounds__(BLK) k_lader_elem(Mesh g, TransArgs ta, const 
     elem_corners<DIM, PER>(g, kk, v, ed);
     const double det = elem_normals<DIM>(ed, n);
     // vertex positions relative to vertex 0, barycentre, grad P^n on k
+    // (divisions by d + 1, d and det as products with reciprocals)
     double X[4][3], Bc[3], gp[3], tp[3];
+    const double idet = 1.0 / det;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         X[0][c] = 0.0;
@@ -1686,8 +1706,8 @@ __global__ void __launch_bounds__(BLK) k_lader_elem(Mesh g, TransArgs ta, const 
         }
 #pragma unroll
         for (int b = 0; b <= DIM; ++b) sp += pn[v[b]] * n[b][c];
-        Bc[c] = s / double(DIM + 1);
-        gp[c] = (c < DIM) ? sp / det : 0.0;
+        Bc[c] = s * (1.0 / double(DIM + 1));
+        gp[c] = (c < DIM) ? sp * idet : 0.0;
         tp[c] = sp;
     }
     // this lane's cell, its state and its upwind element (the other
@@ -1698,8 +1718,7 @@ __global__ void __launch_bounds__(BLK) k_lader_elem(Mesh g, TransArgs ta, const 
     double u0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) u0[c] = (c < DIM) ? ta.wu[DIM * fa + c] : 0.0;
-    const int2 sla = ta.fsl[fa];
-    const int so = (sla.x == 4 * kk + al) ? sla.y : sla.x;
+    const int so = ta.oslot[4 * kk + al];
     const double *gk = ta.grad + int64_t(NG) * kk;
     const double *ga = (so < 0) ? gk : ta.grad + int64_t(NG) * (so >> 2);
     const double hdt = 0.5 * ta.dt;
@@ -1728,7 +1747,7 @@ __global__ void __launch_bounds__(BLK) k_lader_elem(Mesh g, TransArgs ta, const 
     for (int j = 0; j < DIM; ++j) {
         double dl[3], er, eu[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dl[c] = (Bc[c] - Xb[j][c]) / double(DIM);
+        for (int c = 0; c < 3; ++c) dl[c] = (Bc[c] - Xb[j][c]) * (1.0 / double(DIM));
         lader_side<DIM>(r0, u0, gk, ga, dl, gp, ta.g, hdt, er, eu);
         double *e = sE + 4 * (DIM * int(threadIdx.x) + j);
         e[0] = er;
@@ -2251,6 +2270,7 @@ struct pm_handle {
         int4 *trec = nullptr;       // transport records, 2 per (face, side); built on the first transport
         double *grad = nullptr;     // LADER: element gradients of rho and W_u; allocated on the first LADER step
         double *slots = nullptr;    // LADER: slot records (5 sums + volume share) per (element, face); idem
+        int *oslot = nullptr;       // LADER: the other slot of each element slot's cell; idem
         double *contrib = nullptr;  // 4 per element: right-hand-side contributions
         double *e = nullptr;        // erho | ewe | erk | evol | ewu (x3) | egrad (x3), per element
         double *pn = nullptr, *gd = nullptr, *b = nullptr, *dp = nullptr, *dpi = nullptr;
@@ -2931,7 +2951,7 @@ void pressure_destroy(pm_handle *h)
                     h->pbuf[1], h->part, h->st, h->hist, h->coords32, h->w32, h->t_inst_w32, h->r32, h->q32,
                     h->d32, h->p32[0], h->p32[1], h->st_in, h->mw, h->pj.efc, h->pj.fel, h->pj.enew2old,
                     h->pj.e, h->pj.pn, h->pj.gd, h->pj.b, h->pj.dp, h->pj.dpi, h->pj.ebnd, h->pj.contrib, h->pj.fsl, h->pj.trec, h->pj.grad,
-                    h->pj.slots};
+                    h->pj.slots, h->pj.oslot};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
@@ -4543,10 +4563,17 @@ int transport_impl(pm_handle *h, const double *rho_dev, const double *wu_dev, co
     const int NG = h->dim + h->dim * h->dim;
     if (lader && !h->pj.grad) TRY(dalloc(h, &h->pj.grad, size_t(NG) * size_t(h->E)));
     if (lader && !h->pj.slots) TRY(dalloc(h, &h->pj.slots, size_t(24) * size_t(h->E)));
+    if (lader && !h->pj.oslot) {
+        TRY(dalloc(h, &h->pj.oslot, size_t(4) * size_t(h->E)));
+        hipLaunchKernelGGL(k_tr_oslot, dim3(grid_of(4 * h->E)), dim3(BLK), 0, s, int(4 * h->E), h->dim + 1, h->pj.efc,
+                           h->pj.fsl, h->pj.oslot);
+        HIPCK(hipGetLastError());
+    }
     TransArgs ta;
     ta.trec = h->pj.trec;
     ta.fsl = h->pj.fsl;
     ta.grad = h->pj.grad;
+    ta.oslot = h->pj.oslot;
     ta.rho = rho_dev;
     ta.wu = wu_dev;
     ta.we = we_dev;
