@@ -460,9 +460,10 @@ constexpr size_t tile_lds_bytes(int dim, int lm, int max_deg)
 //     (writes for halo vertices go to a sink);
 //  3. each own node sums S[0..deg-1][i] in row order (ascending element id).
 // Every element is computed once per tile that contains one of its vertices.
-// The loads of tile k+1 (instances, node data) are issued as soon as tile
-// k's elements are done, and its halo ids and offsets one step earlier, so
-// their latency overlaps the row sums of tile k and the other blocks of the
+// The loads of tile k+1 are issued while tile k is processed: its offsets
+// one tile earlier, its halo ids at tile k's staging, its node data as tile
+// k's element phase starts and its instances slot by slot during it, so
+// their latency overlaps tile k's work and that of the other blocks of the
 // CU.  IPT instances per lane and LM node-table entries cover the largest
 // tile (checked at setup).  Own node l of the tile is staged by lane
 // l mod BLK in slot l / BLK, which is also the lane that sums its row, so the
@@ -592,9 +593,18 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
         if (tn >= 0) load_ids(sn, cnn, h0n, nhn, gidn);
         __syncthreads();
         // 2. element contributions into the sums table.  The next tile's
-        // loads go into the registers as this tile frees them: its instances
-        // slot by slot, its node data once its halo ids have arrived.
-        constexpr int NODES_AT = (IPT > 2) ? 2 : IPT - 1;
+        // loads go into the registers as this tile frees them: its node
+        // data at once (the staging above freed those registers), its
+        // instances slot by slot.  The waves run this phase at raised
+        // priority, so that the issue slots of a SIMD go to the element
+        // work of whichever block is in it, while the other phases mostly
+        // wait on LDS and memory.
+        if (tn >= 0) {
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) gidx[q] = gidn[q];
+            load_nodes(gidx);
+        }
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
             const int j = threadIdx.x + k * NTH;
@@ -617,15 +627,9 @@ __device__ __forceinline__ void apply_tiled_body(const MeshT<R> &g, const TileAr
                 for (int a = 0; a <= DIM; ++a)
                     sS[int(u[a] >> G::LVB) * RS + int(u[a] & unsigned(T - 1))] = o[a];
             }
-            if (tn >= 0) {
-                load_inst(k, i0n, nin);
-                if (k == NODES_AT) {
-#pragma unroll
-                    for (int q = 0; q < SPT; ++q) gidx[q] = gidn[q];
-                    load_nodes(gidx);
-                }
-            }
+            if (tn >= 0) load_inst(k, i0n, nin);
         }
+        __builtin_amdgcn_s_setprio(0);
         const int tn2 = (tn >= 0) ? tile_at(vb, kt + 2, nvb, ta.n_tiles) : -1;
         vo = load_offsets(tn2);
         __syncthreads();
