@@ -432,7 +432,7 @@ def oracle_other_configs(args, single_seconds=6.0):
         return {"value": round(dofit / t_sum / 1e9, 5), "seconds": round(t_sum, 3), "iterations": iters}
 
     out = {"cores": cores}
-    # config 1: b = A p* (the oracle's operator), repeated to about 0.2 s
+    # tgv2d_32: b = A p* (the oracle's operator), repeated to about 0.2 s
     prob = workloads.tgv2d(32)
     A = oracle.assemble_problem(prob)
     b = A.matvec(fields.sine_product(prob.mesh.coords))
@@ -445,7 +445,7 @@ def oracle_other_configs(args, single_seconds=6.0):
         rec = out["tgv2d_32"][k]
         rec["latency_ms"] = round(rec["seconds"] / reps * 1e3, 4)
         rec["iterations"] = rec["iterations"][0]
-    # config 2: the three w
+    # cube64: the three w
     cases = []
     for w in workloads.CUBE64_W:
         prob = workloads.cube64(w)
