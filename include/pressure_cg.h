@@ -394,6 +394,11 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay);
  * (begin them again).  Errors: PM_EINVAL. */
 int pressure_batch_set_persistent(pm_batch *b, int32_t persistent);
 
+/* Time limit of each grid-barrier wait of the persistent form, in
+ * microseconds (0: the default, 2 s; at most 600 s).  A wait that exceeds
+ * it ends the step with PM_ETIMEOUT.  Errors: PM_EINVAL. */
+int pressure_batch_set_barrier_limit(pm_batch *b, int64_t microseconds);
+
 /* Release the batch (not its handles).  NULL is ignored. */
 void pressure_batch_destroy(pm_batch *b);
 

@@ -57,6 +57,7 @@ SIGNATURES = {
     "pressure_batch_solve": (ctypes.c_int, [_P, _P, _P, _dbl, _i32, _P, _P, _P, _P, _P]),
     "pressure_batch_set_graph": (ctypes.c_int, [_P, _i32]),
     "pressure_batch_set_persistent": (ctypes.c_int, [_P, _i32]),
+    "pressure_batch_set_barrier_limit": (ctypes.c_int, [_P, ctypes.c_int64]),
     "pressure_batch_step_launch": (ctypes.c_int, [_P, _P]),
     "pressure_batch_step_wait": (ctypes.c_int, [_P, _P]),
     "pressure_batch_step_poll": (ctypes.c_int, [_P, _P]),

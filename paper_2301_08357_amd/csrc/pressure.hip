@@ -4248,6 +4248,13 @@ int pressure_batch_set_persistent(pm_batch *b, int32_t persistent)
     return PM_OK;
 }
 
+int pressure_batch_set_barrier_limit(pm_batch *b, int64_t microseconds)
+{
+    if (!b || microseconds < 0 || microseconds > int64_t(600) * 1000000) return PM_EINVAL;
+    b->bar_limit = (microseconds == 0) ? 200000000LL : 100LL * microseconds;   // 100 MHz ticks
+    return PM_OK;
+}
+
 int pressure_batch_begin(pm_batch *b, int32_t m, const double *rhs_dev, const double *x0_dev, double rtol,
                          int32_t max_iter, void *stream)
 {

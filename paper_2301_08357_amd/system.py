@@ -340,6 +340,10 @@ class PressureBatch:
         iteration."""
         check(load().pressure_batch_set_persistent(self._b, 1 if persistent else 0), "pressure_batch_set_persistent")
 
+    def set_barrier_limit(self, microseconds):
+        """Time limit of each grid-barrier wait of the persistent form (0: 2 s)."""
+        check(load().pressure_batch_set_barrier_limit(self._b, int(microseconds)), "pressure_batch_set_barrier_limit")
+
     def solve(self, rhs, x0=None, rtol=1e-10, max_iter=20000, out=None, stream=None):
         """rhs, x0, out: lists of float64 CUDA tensors (one per system).
         Returns (overall status, list of SolveResult)."""

@@ -286,3 +286,42 @@ def test_persistent_batch_equals_two_launch_form():
     batch.close()
     for s in systems:
         s.close()
+
+
+def test_persistent_barrier_time_out_is_reported():
+    """A grid-barrier wait bound far below what the launch needs (1 us) ends
+    the step with PM_ETIMEOUT instead of waiting: every wait of the kernel
+    is bounded, so the launch ends on its own.  The batch then clears its
+    barrier; destroyed, it leaves handles that solve correctly again.  (If
+    every barrier happened to complete within the bound, the results must
+    be the two-launch form's.)"""
+    probs = _small_mix()[:4]
+    print("case persistent barrier limit", [(p.mesh.dim, p.mesh.n_nodes) for p in probs], flush=True)
+    As = [oracle.assemble_problem(p) for p in probs]
+    rhs = [_dev(_rhs(p, A)) for p, A in zip(probs, As)]
+    systems = [pm.PressureSystem.from_problem(p) for p in probs]
+    batch = pm.PressureBatch(systems, tiles_per_slot=2, nodes_per_lane=4)
+    code, ref = batch.solve(rhs, rtol=1e-10)
+    assert code == 0
+    xr = [_host(r.p).copy() for r in ref]
+    batch.set_persistent(True)
+    with pytest.raises(pm.PressureError):
+        batch.set_barrier_limit(-1)
+    batch.set_barrier_limit(1)
+    try:
+        code2, res2 = batch.solve(rhs, rtol=1e-10)
+        timed_out = False
+    except pm.PressureError as e:
+        assert e.status == pm.PM_ETIMEOUT, e
+        timed_out = True
+    print("timed out:", timed_out, flush=True)
+    if not timed_out:
+        for r, x in zip(res2, xr):
+            assert np.array_equal(_host(r.p).view(np.uint64), x.view(np.uint64))
+    batch.close()
+    # the handles are usable again: single solves give the batched results
+    for s, b, r, x in zip(systems, rhs, ref, xr):
+        single = s.solve(b, rtol=1e-10)
+        assert single.iters == r.iters
+        assert np.array_equal(_host(single.p).view(np.uint64), x.view(np.uint64))
+        s.close()
