@@ -388,7 +388,9 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay);
  * step's iterations (pressure_batch_set_graph's count, 8 if 0) over the
  * slots of the meshes in flight; inside it the phases (apply of every
  * slot, update of every slot) are separated by grid barriers instead of
- * kernel boundaries.  The arithmetic is the same, so results equal the
+ * kernel boundaries.  With every mesh in flight the launch is replayed from
+ * a HIP graph captured at the first such step (launched directly if the
+ * runtime does not capture it).  The arithmetic is the same, so results equal the
  * two-launch form bit for bit.  Each barrier wait is bounded (2 s); if one
  * times out the step returns PM_ETIMEOUT and the solves in flight are lost
  * (begin them again).  Errors: PM_EINVAL. */

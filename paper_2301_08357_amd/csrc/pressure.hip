@@ -3557,6 +3557,9 @@ struct pm_batch {
     hipEvent_t ev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t pgraph = nullptr;       // persistent form: its launch over every slot, captured
+    hipGraphExec_t pgexec = nullptr;
+    bool pgraph_failed = false;        // the runtime would not capture it: launch directly
     int graph_iters = 16;
     bool persistent = false;           // one cooperative launch per step (k_batch_persistent)
     bool step_pending = false;         // pressure_batch_step_launch without its _wait yet
@@ -3662,7 +3665,7 @@ const void *batch_persistent_kernel(int c)
 // one per slot).  The runtime rejects a cooperative grid that cannot be
 // resident at once.
 template <class R>
-int launch_batch_persistent_t(pm_batch *b, int count, hipStream_t s)
+int launch_batch_persistent_t(pm_batch *b, int count, bool active, hipStream_t s)
 {
     const void *kern = b->periodic ? batch_persistent_kernel<R, true>(b->bclass)
                                    : batch_persistent_kernel<R, false>(b->bclass);
@@ -3675,8 +3678,8 @@ int launch_batch_persistent_t(pm_batch *b, int count, hipStream_t s)
         b->coop_grid = per_cu * cus;
     }
     const BatchMeshT<R> *meshes = (const BatchMeshT<R> *)b->d_meshes;
-    const int2 *as = b->d_aslots_act, *us = b->d_uslots_act;
-    int na = b->n_aslots_act, nu = b->n_uslots_act;
+    const int2 *as = active ? b->d_aslots_act : b->d_aslots, *us = active ? b->d_uslots_act : b->d_uslots;
+    int na = active ? b->n_aslots_act : b->n_aslots, nu = active ? b->n_uslots_act : b->n_uslots;
     const int grid = std::min(b->coop_grid, std::max(na, nu));
     if (grid < 1 || count < 1) return PM_OK;
     BatchCtl *ctl = b->d_ctl;
@@ -3688,9 +3691,49 @@ int launch_batch_persistent_t(pm_batch *b, int count, hipStream_t s)
     return PM_OK;
 }
 
-int launch_batch_persistent(pm_batch *b, int count, hipStream_t s)
+int launch_batch_persistent(pm_batch *b, int count, bool active, hipStream_t s)
 {
-    return b->mixed ? launch_batch_persistent_t<float>(b, count, s) : launch_batch_persistent_t<double>(b, count, s);
+    return b->mixed ? launch_batch_persistent_t<float>(b, count, active, s)
+                    : launch_batch_persistent_t<double>(b, count, active, s);
+}
+
+void drop_graph(hipGraph_t *g, hipGraphExec_t *e)
+{
+    if (*e) (void)hipGraphExecDestroy(*e);
+    if (*g) (void)hipGraphDestroy(*g);
+    *e = nullptr;
+    *g = nullptr;
+}
+
+// The persistent form's step over every slot, captured once in a HIP graph
+// (a cooperative kernel node).  If the runtime will not capture the
+// cooperative launch, the step launches it directly from then on.
+int batch_capture_persistent(pm_batch *b)
+{
+    drop_graph(&b->pgraph, &b->pgexec);
+    // the resident-block count is queried before the capture (no launch: count 0)
+    TRY(launch_batch_persistent(b, 0, false, b->stream));
+    HIPCK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const int st = launch_batch_persistent(b, b->graph_iters, false, b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    (void)hipGetLastError();
+    if (st != PM_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        b->pgraph_failed = true;
+        if (std::getenv("PM_DEBUG"))
+            std::fprintf(stderr, "libpressure: persistent batch launch not captured (%s); launching directly\n",
+                         hipGetErrorString(e));
+        return PM_OK;
+    }
+    if (std::getenv("PM_DEBUG")) std::fprintf(stderr, "libpressure: persistent batch launch captured in a graph\n");
+    b->pgraph = g;
+    if (hipGraphInstantiate(&b->pgexec, b->pgraph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        drop_graph(&b->pgraph, &b->pgexec);
+        b->pgraph_failed = true;
+    }
+    return PM_OK;
 }
 
 // Upload the slot tables of the meshes in flight (in mesh order, each
@@ -3723,6 +3766,7 @@ void batch_free(pm_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    drop_graph(&b->pgraph, &b->pgexec);
     for (void *p : {(void *)b->d_meshes, (void *)b->d_aslots, (void *)b->d_uslots, (void *)b->d_ctl, (void *)b->d_bar,
                     (void *)b->d_states, (void *)b->d_aslots_act, (void *)b->d_uslots_act})
         if (p) (void)hipFree(p);
@@ -4094,10 +4138,18 @@ int batch_step_launch(pm_batch *b, hipStream_t s)
     TRY(refresh_active_slots(b, s));
     int its = 0;
     if (b->persistent) {
-        // one cooperative launch over the slots of the meshes in flight
+        // one cooperative launch over the slots of the meshes in flight;
+        // with every mesh in flight, replayed from its captured graph
         its = b->graph_iters > 0 ? b->graph_iters : 8;
-        if (b->n_aslots_act > 0) TRY(launch_batch_persistent(b, its, s));
-        else its = 0;
+        if (b->graph_iters > 0 && b->n_aslots_act == b->n_aslots && !b->pgraph_failed) {
+            if (!b->pgexec) TRY(batch_capture_persistent(b));
+        }
+        if (b->graph_iters > 0 && b->n_aslots_act == b->n_aslots && b->pgexec)
+            HIPCK(hipGraphLaunch(b->pgexec, s));
+        else if (b->n_aslots_act > 0)
+            TRY(launch_batch_persistent(b, its, true, s));
+        else
+            its = 0;
     } else if (b->graph_iters > 0 && b->n_aslots_act == b->n_aslots) {
         // every mesh in flight: the captured graph over all slots (captured
         // on the batch's stream at the first such step)
@@ -4229,6 +4281,7 @@ int pressure_batch_set_graph(pm_batch *b, int32_t iterations_per_replay)
     if (!b || iterations_per_replay < 0 || iterations_per_replay > 256 || (iterations_per_replay % 2) != 0)
         return PM_EINVAL;
     b->graph_iters = iterations_per_replay;
+    drop_graph(&b->pgraph, &b->pgexec);
     // the graph of the new length is captured at the next step that replays it
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
@@ -4245,6 +4298,7 @@ int pressure_batch_set_persistent(pm_batch *b, int32_t persistent)
 {
     if (!b || (persistent != 0 && persistent != 1)) return PM_EINVAL;
     b->persistent = persistent != 0;
+    drop_graph(&b->pgraph, &b->pgexec);
     return PM_OK;
 }
 
@@ -4252,6 +4306,7 @@ int pressure_batch_set_barrier_limit(pm_batch *b, int64_t microseconds)
 {
     if (!b || microseconds < 0 || microseconds > int64_t(600) * 1000000) return PM_EINVAL;
     b->bar_limit = (microseconds == 0) ? 200000000LL : 100LL * microseconds;   // 100 MHz ticks
+    drop_graph(&b->pgraph, &b->pgexec);   // the captured launch holds the old limit
     return PM_OK;
 }
 
