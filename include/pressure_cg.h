@@ -186,7 +186,16 @@ int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *strea
  *   true_relres host out or NULL: ||rhs - A_D p|| / ||rhs|| at exit
  * Returns PM_OK, PM_NOT_CONVERGED, PM_EBREAKDOWN, PM_EINVAL or PM_EHIP.
  * rhs = 0 gives p = 0 after 0 iterations.  Synchronises the stream before
- * returning (the host outputs are final). */
+ * returning (the host outputs are final).
+ * Each CG iteration is two launches (the operator apply fused with the
+ * direction update, then the vector update), run in chunks between reads
+ * of the solver state.  A mesh whose coordinates, vectors and element
+ * contributions fit one workgroup's LDS (in FP64 (dim + 6) * n_nodes +
+ * 4 * n_elems doubles, a few more per tile; pressure_info entry 8 says
+ * whether a handle qualifies) instead runs all its iterations in a single
+ * launch of one workgroup, with the same arithmetic and the same reduction
+ * order, so p, iters and res_hist are bit for bit those of the two-launch
+ * form.  Timing (pressure_timing_enable) keeps the two-launch form. */
 int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                    int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
                    double *true_relres, void *stream);
@@ -281,7 +290,10 @@ int pressure_timing_read(pm_handle *h, int64_t *launches, double *total_ms);
  *   [4] algorithmic bytes of one FP64 apply (x read, y written, coordinates,
  *       connectivity, element coefficient: each once),
  *   [5] device bytes held by the handle, [6] number of tiles, [7] element
- *       instances over all tiles. */
+ *       instances over all tiles, [8] 1 if pressure_solve runs its CG
+ *       iterations in one launch (a mesh small enough for one workgroup's
+ *       LDS, on the tiled kernel with timing off; see pressure_solve), else 0.
+ * Entries past n_info are not written. */
 int pressure_info(pm_handle *h, int64_t *info, int32_t n_info);
 
 /* ------------------------------------------------------------------------

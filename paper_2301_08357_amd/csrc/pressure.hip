@@ -73,10 +73,59 @@ struct CGState {
 
 // ------------------------------------------------------------------ reductions
 
+// Lane moves for the wave sum, on the two 32-bit halves of a double.
+// lanes_down32: lane l < 32 receives lane l + 32 (v_permlane32_swap);
+// lanes_down16: lane l of rows 0 and 2 receives lane l + 16
+// (v_permlane16_swap); row_down<N>: lane l receives lane l + N of its row
+// of 16 (DPP row_shl, N < 16).  Other lanes receive values the sum does
+// not use.
+__device__ __forceinline__ double lanes_down32(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane32_swap(unsigned(b), unsigned(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(unsigned(b >> 32), unsigned(b >> 32), false, false);
+    return __longlong_as_double((long long)((unsigned long long)hi[1] << 32 | lo[1]));
+}
+
+__device__ __forceinline__ double lanes_down16(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap(unsigned(b), unsigned(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(unsigned(b >> 32), unsigned(b >> 32), false, false);
+    return __longlong_as_double((long long)((unsigned long long)hi[1] << 32 | lo[1]));
+}
+
+template <int N>
+__device__ __forceinline__ double row_down(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), 0x100 + N, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), 0x100 + N, 0xf, 0xf, true);
+    return __longlong_as_double((long long)((unsigned long long)unsigned(hi) << 32 | unsigned(lo)));
+}
+
+// Sum over the 64 lanes of a wave as a fixed tree: lane l adds lane l + 32,
+// then l + 16, 8, 4, 2 and 1 (each step only needs the lanes below the
+// stride).  The sum is in lane 0 only; the other lanes hold partial or
+// meaningless values.  The lane moves are VALU operations, not LDS
+// permutes, so the six steps cost a few dozen cycles.
 __device__ inline double wave_sum(double v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    v += lanes_down32(v);
+    v += lanes_down16(v);
+    v += row_down<8>(v);
+    v += row_down<4>(v);
+    v += row_down<2>(v);
+    v += row_down<1>(v);
     return v;
+}
+
+// Lane 0's value of v in every lane (two scalar reads).
+__device__ __forceinline__ double from_lane0(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane(unsigned(b), 0), hi = __builtin_amdgcn_readlane(unsigned(b >> 32), 0);
+    return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
 }
 
 // Block sum in a fixed order; the result is valid in every thread.  NTH is
@@ -690,6 +739,292 @@ __global__ void __launch_bounds__(NTH, (tile_waves<R, T, LM>())) k_apply_tiled(M
 }
 
 // ------------------------------------------------------------- CG vectors
+
+// ------------------------------------------- one-launch solve of a small mesh
+
+constexpr int SMALL_NTH = 1024;   // one workgroup
+// elements per lane: E <= 4096 triangles or 3072 tetrahedra
+constexpr int small_ept(int dim) { return dim == 2 ? 4 : 3; }
+constexpr int SMALL_MPT = 4;      // nodes per lane of the update (N <= 4 * 256 * n_vblocks)
+
+// Bytes of dynamic LDS the one-launch solve needs (see k_solve_small).
+inline size_t small_lds_bytes(int dim, int64_t N, int64_t E, int n_ablocks, int n_tiles)
+{
+    const size_t dbl = size_t(dim + 4) * size_t(N) + size_t(dim + 1) * size_t(E) + size_t(n_ablocks) + 16;
+    return 8 * dbl + 4 * (size_t(N) + 1 + size_t(n_tiles) + 1) + size_t(N);
+}
+
+// Sum over one wave as a 256-lane block_sum_all forms it when the other
+// three waves hold zeros: this wave's sum, then three zero wave sums.  The
+// result (formed in lane 0, where wave_sum is exact) goes to every lane.
+__device__ __forceinline__ double wave_as_block(double v)
+{
+    double s = wave_sum(v);
+    s += 0.0;
+    s += 0.0;
+    s += 0.0;
+    return from_lane0(s);
+}
+
+// A whole CG solve of a small mesh in one launch of one 1024-lane workgroup,
+// from iteration k0 (a start or a restart: beta = 0) until it stops.  The
+// coordinates, the node values and the element contributions live in LDS;
+// each lane keeps its elements (vertex ids, contribution slots, factor) and
+// the residual at its update nodes in registers for the whole solve, and an
+// iteration is four phases between block barriers: the direction update,
+// the element contributions, the node sums with the p.q partials, and the
+// vector update with the r.r partials.
+// The arithmetic is that of the two-kernel loop, operation for operation
+// and in the same order, reductions included, so x, r, the iteration count,
+// the history and the state equal the two-kernel loop's bit for bit:
+//  - a node sums its element contributions in ascending element order
+//    (its slots in the contribution table are its node-to-element list);
+//  - the p.q partial of apply block vb is formed as that block forms it,
+//    one tile per block, own node l of the tile in lane l of a 256-lane
+//    block (waves 2 and 3 of it hold zeros): here one wave does a tile;
+//  - the update lane tid takes nodes tid + m * 256 * n_vblocks, as lane
+//    tid mod 256 of update block tid / 256 does, and the four wave sums
+//    of an update block are added in order;
+//  - the sums of partials are those of sum_partials in a 256-lane block,
+//    which every wave forms for itself (in its lane 0, then broadcast).
+// Requires one tile per apply block (at most 256 tiles of at most 128
+// nodes), at most 4 update blocks, N <= SMALL_MPT * 256 * n_vblocks and
+// E <= small_ept(DIM) * 1024; the host checks all of it.
+template <int DIM, bool PER>
+__global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__restrict__ n2e_off,
+                                                         const int *__restrict__ n2e_ent,
+                                                         const int *__restrict__ node_off, int n_tiles, int n_ablocks,
+                                                         int n_vblocks, double *__restrict__ x,
+                                                         double *__restrict__ r, CGState *st,
+                                                         double *__restrict__ hist,
+                                                         const double *__restrict__ rr_part0, int k0)
+{
+    extern __shared__ double sm[];
+    const int N = g.N, E = g.E, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NV = DIM + 1;
+    // node table: per node X, Y, (Z,) and p with Dirichlet entries 0, so
+    // one address per vertex reaches all of them
+    double *const sN = sm;
+    double *const sp = sN + size_t(NV) * N, *const sq = sp + N, *const sx = sq + N;
+    double *const sC = sx + N;                                        // NV * E contributions, by slot
+    double *const spart = sC + size_t(NV) * E, *const sred = spart + n_ablocks;
+    int *const sOff = reinterpret_cast<int *>(sred + 16);            // N + 1 slot offsets
+    int *const sTo = sOff + N + 1;                                    // n_tiles + 1 tile offsets
+    uint8_t *const sDir = reinterpret_cast<uint8_t *>(sTo + n_tiles + 1);
+    int *const sInv = reinterpret_cast<int *>(sC);                    // setup only: slot of 4e + a
+
+    __shared__ int done0;
+    if (tid == 0) done0 = st->done;
+    for (int i = tid; i < N; i += SMALL_NTH) {
+        sN[NV * i] = g.X[i];
+        sN[NV * i + 1] = g.Y[i];
+        if (DIM == 3) sN[NV * i + 2] = g.Z[i];
+        sDir[i] = g.dir[i];
+        const int j0 = n2e_off[i], j1 = n2e_off[i + 1];
+        sOff[i] = j0;
+        for (int j = j0; j < j1; ++j) sInv[n2e_ent[j]] = j;
+    }
+    if (tid == 0) sOff[N] = n2e_off[N];
+    for (int t = tid; t <= n_tiles; t += SMALL_NTH) sTo[t] = node_off[t];
+    // the update nodes of this lane
+    const int ustride = n_vblocks * BLK;
+    double ur[SMALL_MPT];
+    unsigned udir = 0;
+#pragma unroll
+    for (int m = 0; m < SMALL_MPT; ++m) {
+        const int i = tid + m * ustride;
+        ur[m] = 0.0;
+        if (tid < ustride && i < N) {
+            sx[i] = x[i];
+            ur[m] = r[i];
+            if (g.dir[i]) udir |= 1u << m;
+        }
+    }
+    __syncthreads();
+    // this lane's elements: vertex id (low 16 bits) and contribution slot
+    // (high 16 bits) per vertex, and the element factor
+    constexpr int EPT = small_ept(DIM);
+    unsigned ev[EPT][NV];
+    double ew[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = tid + k * SMALL_NTH;
+        ew[k] = 0.0;
+#pragma unroll
+        for (int a = 0; a < NV; ++a) ev[k][a] = 0;
+        if (e < E) {
+            const int4 c = g.conn[e];
+            const int cv[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int a = 0; a < NV; ++a) ev[k][a] = unsigned(cv[a] & 0x7fffffff) | (unsigned(sInv[4 * e + a]) << 16);
+            ew[k] = g.w[e];
+        }
+    }
+    __syncthreads();   // sInv is read; sC takes contributions from here on
+    if (done0) return;
+    const double tol = st->tol, bnorm = st->bnorm;
+    const int max_iter = st->max_iter;
+    double rr, rr_prev = 0.0;
+    {
+        double v = 0.0;
+        if (lane < n_vblocks) v += rr_part0[lane];
+        rr = wave_as_block(v);
+    }
+    bool first = true;
+    for (int k = k0;; ++k) {
+        // the decision of the apply of iteration k (iter_decide)
+        const double nr = sqrt(rr);
+        const bool bad = !isfinite(rr);
+        const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
+        if (tid == 0) {
+            if (!(first && k > 1)) hist[k - 1] = nr / bnorm;
+            st->iter = k - 1;
+            st->rr = rr;
+            if (bad) st->status = PM_EBREAKDOWN;
+            if (stop) st->done = 1;
+        }
+        if (stop) break;
+        const double beta = first ? 0.0 : rr / rr_prev;
+        // 1. p_k = r + beta p_{k-1}
+#pragma unroll
+        for (int m = 0; m < SMALL_MPT; ++m) {
+            const int i = tid + m * ustride;
+            if (tid < ustride && i < N) {
+                double v = ur[m];
+                if (!first) v = v + beta * sp[i];
+                sp[i] = v;
+                sN[NV * i + DIM] = (udir >> m) & 1u ? 0.0 : v;
+            }
+        }
+        __syncthreads();
+        // 2. element contributions, each into its slot
+#pragma unroll
+        for (int kk = 0; kk < EPT; ++kk) {
+            if (tid + kk * SMALL_NTH < E) {
+                double X[4], Y[4], Z[4], xv[4], o[4];
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    const int v = int(ev[kk][a] & 0xffffu);
+                    const double *nv = sN + NV * v;
+                    X[a] = nv[0];
+                    Y[a] = nv[1];
+                    Z[a] = (DIM == 3) ? nv[2] : 0.0;
+                    xv[a] = nv[DIM];
+                }
+                if (DIM == 2) xv[3] = 0.0;
+                double ed[3][3];
+                elem_edges<DIM, PER>(X, Y, Z, g, ed);
+                elem_contrib<DIM, double>(ed, xv, ew[kk], g.mdiag, g.mfull, o);
+#pragma unroll
+                for (int a = 0; a < NV; ++a) sC[ev[kk][a] >> 16] = o[a];
+            }
+        }
+        __syncthreads();
+        // 3. q = A p by node sums in slot order (ascending element id);
+        // Dirichlet rows copy p; the p.q partial of each apply block
+        for (int vb = wv; vb < n_ablocks; vb += SMALL_NTH / 64) {
+            const int t = tile_at(vb, 0, n_ablocks, n_tiles);
+            const int s0 = (t >= 0) ? sTo[t] : 0, nt = (t >= 0) ? sTo[t + 1] - s0 : 0;
+            double ws[2] = {0.0, 0.0};   // the sum of a wave of zeros is +0
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (64 * h >= nt) break;
+                double part = 0.0;
+                const int l = lane + 64 * h;
+                if (l < nt) {
+                    const int i = s0 + l;
+                    const double pi = sp[i];
+                    double yi = 0.0;
+                    if (sDir[i]) {
+                        yi = pi;
+                    } else {
+                        // slots in chunks of 8: the reads of a chunk are issued together
+                        const int j0 = sOff[i], d = sOff[i + 1] - j0;
+                        for (int c = 0; c < d; c += 8) {
+                            double cv[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                if (c + u < d) cv[u] = sC[j0 + c + u];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                if (c + u < d) yi += cv[u];
+                        }
+                    }
+                    sq[i] = yi;
+                    part += pi * yi;
+                }
+                ws[h] = wave_sum(part);
+            }
+            double s = ws[0];
+            s += ws[1];
+            s += 0.0;
+            s += 0.0;
+            if (lane == 0) spart[vb] = s;
+        }
+        __syncthreads();
+        // 4. the update: alpha = rr / p.q, x += alpha p, r -= alpha q
+        double pq;
+        {
+            double w4[4] = {0.0, 0.0, 0.0, 0.0};   // waves past the partials sum zeros
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (u * 64 >= n_ablocks) break;
+                double v = 0.0;
+                if (u * 64 + lane < n_ablocks) v += spart[u * 64 + lane];
+                w4[u] = wave_sum(v);
+            }
+            pq = w4[0];
+            pq += w4[1];
+            pq += w4[2];
+            pq += w4[3];
+            pq = from_lane0(pq);   // lane 0 holds the wave sums
+        }
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            if (tid == 0) {
+                st->status = PM_EBREAKDOWN;
+                st->done = 1;
+            }
+            break;
+        }
+        const double alpha = rr / pq;
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < SMALL_MPT; ++m) {
+            const int i = tid + m * ustride;
+            if (tid < ustride && i < N) {
+                sx[i] = sx[i] + alpha * sp[i];
+                const double ri = ur[m] - alpha * sq[i];
+                ur[m] = ri;
+                v += ri * ri;
+            }
+        }
+        v = wave_sum(v);
+        if (lane == 0) sred[wv] = v;
+        __syncthreads();
+        rr_prev = rr;
+        {
+            double u = 0.0;
+            if (lane < n_vblocks) {
+                double b4 = sred[4 * lane];
+                b4 += sred[4 * lane + 1];
+                b4 += sred[4 * lane + 2];
+                b4 += sred[4 * lane + 3];
+                u += b4;
+            }
+            rr = wave_as_block(u);
+        }
+        first = false;
+    }
+#pragma unroll
+    for (int m = 0; m < SMALL_MPT; ++m) {
+        const int i = tid + m * ustride;
+        if (tid < ustride && i < N) {
+            x[i] = sx[i];
+            r[i] = ur[m];
+        }
+    }
+}
+
 
 // update(k): alpha = rr_{k-1} / p_k.q; x += alpha p_k; r -= alpha q;
 // partials of r_k.r_k.  Runs as virtual block vb of nvb.
@@ -3245,6 +3580,34 @@ static int read_state(pm_handle *h, hipStream_t s)
     return PM_OK;
 }
 
+// The one-launch solve takes meshes whose data fit one block's LDS, on
+// the tiled kernel's grids with one tile per apply block; sampled kernel
+// timing needs the per-iteration launches.
+static bool small_ok(const pm_handle *h)
+{
+    if (h->variant != PM_VARIANT_TILED || h->timing || h->tile_nodes != 128) return false;
+    if (h->n_ablocks != h->n_tiles || h->n_tiles > 256 || h->n_vblocks > 4) return false;
+    if (h->N > int64_t(SMALL_MPT) * BLK * h->n_vblocks || h->E > int64_t(small_ept(h->dim)) * SMALL_NTH) return false;
+    return small_lds_bytes(h->dim, h->N, h->E, h->n_ablocks, h->n_tiles) <= size_t(h->lds_limit);
+}
+
+static int launch_small(pm_handle *h, int k0, hipStream_t s)
+{
+    const size_t lds = small_lds_bytes(h->dim, h->N, h->E, h->n_ablocks, h->n_tiles);
+    Mesh g = make_mesh<double>(h);
+    auto go = [&]<int DIM, bool PER>() -> int {
+        const void *kern = (const void *)k_solve_small<DIM, PER>;
+        if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+        hipLaunchKernelGGL((k_solve_small<DIM, PER>), dim3(1), dim3(SMALL_NTH), lds, s, g, h->n2e_off, h->n2e_ent,
+                           h->t_node_off, h->n_tiles, h->n_ablocks, h->n_vblocks, h->x, h->r, h->st, h->hist,
+                           h->part_rr((k0 - 1) & 1), k0);
+        HIPCK(hipGetLastError());
+        return PM_OK;
+    };
+    if (h->dim == 2) return h->periodic ? go.template operator()<2, true>() : go.template operator()<2, false>();
+    return h->periodic ? go.template operator()<3, true>() : go.template operator()<3, false>();
+}
+
 int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                    int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
                    double *true_relres, void *stream)
@@ -3269,11 +3632,17 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
     int k = 1;            // next iteration to launch
     bool first = true;    // k is the first iteration after a (re)start
     size_t timed = 0;
+    const bool small = small_ok(h);
     for (;;) {
         int chunk = 4;
         double rr_seen = -1.0;
         int it_seen = 0;
-        for (;;) {
+        if (small) {
+            // the iterations up to the stop in one launch
+            TRY(launch_small(h, k, s));
+            TRY(read_state(h, s));
+        }
+        for (; !small;) {
             const size_t t0 = timed;
             TRY(launch_iterations(h, k, chunk, first, &timed, s));
             const int kfirst = k;
@@ -3518,10 +3887,10 @@ int pressure_info(pm_handle *h, int64_t *info, int32_t n_info)
 {
     if (!h || !info || n_info < 0) return PM_EINVAL;
     const int64_t d = h->dim;
-    int64_t v[8] = {h->N, h->E, h->n_free, d,
+    int64_t v[9] = {h->N, h->E, h->n_free, d,
                     16 * h->N + 8 * d * h->N + 4 * (d + 1) * h->E + 8 * h->E,
-                    int64_t(h->dev_bytes), h->n_tiles, h->n_inst};
-    for (int k = 0; k < n_info && k < 8; ++k) info[k] = v[k];
+                    int64_t(h->dev_bytes), h->n_tiles, h->n_inst, small_ok(h) ? 1 : 0};
+    for (int k = 0; k < n_info && k < 9; ++k) info[k] = v[k];
     return PM_OK;
 }
 

@@ -294,9 +294,10 @@ class PressureSystem:
         return rho_out, wu_out, we_out
 
     def info(self):
-        v = (ctypes.c_int64 * 8)()
-        check(load().pressure_info(self._h, v, 8), "pressure_info")
-        keys = ("n_nodes", "n_elems", "n_free", "dim", "apply_bytes", "device_bytes", "n_tiles", "n_instances")
+        v = (ctypes.c_int64 * 9)()
+        check(load().pressure_info(self._h, v, 9), "pressure_info")
+        keys = ("n_nodes", "n_elems", "n_free", "dim", "apply_bytes", "device_bytes", "n_tiles", "n_instances",
+                "one_launch_solve")
         return dict(zip(keys, list(v)))
 
 

@@ -303,6 +303,61 @@ def test_tiled_and_node_kernels_agree_bitwise(tile):
         s.close()
 
 
+# ------------------------------------------------------ one-launch small-mesh solve
+ONE_LAUNCH = [
+    ("tgv2d_32", lambda: workloads.tgv2d(32)),
+    ("cube7_lognormal_jit", lambda: workloads.cube(7, w=1e-4, jitter=0.2, rho="lognormal")),
+    ("periodic_square_24", lambda: workloads.periodic_square(24)),
+    ("periodic_cube6_alpha0", lambda: workloads.periodic_cube(6, w=0.0)),
+]
+
+
+@pytest.mark.parametrize("name,make", ONE_LAUNCH)
+def test_one_launch_solve_equals_two_launch_loop(name, make):
+    """A mesh that fits one workgroup's LDS runs all its CG iterations in one
+    launch; kernel timing keeps the two-launch loop.  The two give the same
+    bits (solution, status, iteration count, residual history, true
+    residual) on a cold start, a warm start, an iteration cap, an rtol
+    below what FP64 reaches (residual replacement and its restart) and a
+    zero right-hand side."""
+    prob = make()
+    m = prob.mesh
+    print("case", name, m.n_nodes, m.n_elems, flush=True)
+    A = oracle.assemble_problem(prob)
+    b = _dev(_rhs_for(prob, A))
+    s = pm.PressureSystem.from_problem(prob)
+    assert s.info()["one_launch_solve"] == 1
+    x0 = _dev(np.random.default_rng(3).normal(size=m.n_nodes))
+    cases = [("cold", b, dict(rtol=1e-10)), ("warm", b, dict(x0=x0, rtol=1e-10)),
+             ("cap7", b, dict(rtol=1e-10, max_iter=7)), ("tight", b, dict(rtol=1e-17, max_iter=3000)),
+             ("zero", torch.zeros_like(b), dict(rtol=1e-10))]
+    for label, rhs, kw in cases:
+        print("  ", label, flush=True)
+        out = []
+        for timing in (False, True):
+            s.timing_enable(timing)
+            assert s.info()["one_launch_solve"] == (0 if timing else 1)
+            r = s.solve(rhs, **kw)
+            out.append((_host(r.p).copy(), r.status, r.iters, r.hist, r.true_relres))
+        (p1, st1, it1, h1, t1), (p2, st2, it2, h2, t2) = out
+        assert (st1, it1) == (st2, it2), (label, st1, it1, st2, it2)
+        assert np.array_equal(p1.view(np.uint64), p2.view(np.uint64)), label
+        assert np.array_equal(h1.view(np.uint64), h2.view(np.uint64)), label
+        assert t1 == t2 or (np.isnan(t1) and np.isnan(t2)), label
+        if label == "cold":
+            assert st1 == 0 and t1 <= 1e-10
+        if label == "cap7":
+            assert st1 == pm.PM_NOT_CONVERGED and it1 == 7
+        if label == "zero":
+            assert it1 == 0 and not np.any(p1)
+    s.timing_enable(False)
+    s.close()
+    # a mesh too large for one workgroup's LDS keeps the two-launch form
+    big = pm.PressureSystem.from_problem(workloads.tgv2d(45))
+    assert big.info()["one_launch_solve"] == 0
+    big.close()
+
+
 # ------------------------------------------------------ mixed precision
 @pytest.mark.parametrize("mode", [pm.PM_MIXED_KEEP_DIRECTION, pm.PM_MIXED_RESTART])
 @pytest.mark.parametrize("name,make", [PROBLEMS[0], PROBLEMS[1], PROBLEMS[3]])
