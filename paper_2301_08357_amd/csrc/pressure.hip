@@ -750,7 +750,7 @@ constexpr int SMALL_MPT = 4;      // nodes per lane of the update (N <= 4 * 256 
 // Bytes of dynamic LDS the one-launch solve needs (see k_solve_small).
 inline size_t small_lds_bytes(int dim, int64_t N, int64_t E, int n_ablocks, int n_tiles)
 {
-    const size_t dbl = size_t(dim + 4) * size_t(N) + size_t(dim + 1) * size_t(E) + size_t(n_ablocks) + 16;
+    const size_t dbl = size_t(dim + 4) * size_t(N) + size_t(dim + 1) * size_t(E) + 2 * size_t(n_ablocks) + 16;
     return 8 * dbl + 4 * (size_t(N) + 1 + size_t(n_tiles) + 1) + size_t(N);
 }
 
@@ -781,7 +781,8 @@ __device__ __forceinline__ double wave_as_block(double v)
 //    (its slots in the contribution table are its node-to-element list);
 //  - the p.q partial of apply block vb is formed as that block forms it,
 //    one tile per block, own node l of the tile in lane l of a 256-lane
-//    block (waves 2 and 3 of it hold zeros): here one wave does a tile;
+//    block (waves 2 and 3 of it hold zeros): here one wave sums each half
+//    of a tile, and the halves and zeros are added in the block's order;
 //  - the update lane tid takes nodes tid + m * 256 * n_vblocks, as lane
 //    tid mod 256 of update block tid / 256 does, and the four wave sums
 //    of an update block are added in order;
@@ -807,7 +808,7 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
     double *const sN = sm;
     double *const sp = sN + size_t(NV) * N, *const sq = sp + N, *const sx = sq + N;
     double *const sC = sx + N;                                        // NV * E contributions, by slot
-    double *const spart = sC + size_t(NV) * E, *const sred = spart + n_ablocks;
+    double *const sph = sC + size_t(NV) * E, *const sred = sph + 2 * n_ablocks;   // half-tile sums
     int *const sOff = reinterpret_cast<int *>(sred + 16);            // N + 1 slot offsets
     int *const sTo = sOff + N + 1;                                    // n_tiles + 1 tile offsets
     uint8_t *const sDir = reinterpret_cast<uint8_t *>(sTo + n_tiles + 1);
@@ -885,15 +886,26 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
         }
         if (stop) break;
         const double beta = first ? 0.0 : rr / rr_prev;
-        // 1. p_k = r + beta p_{k-1}
+        // 1. p_k = r + beta p_{k-1}.  Every phase reads all it needs
+        // before it writes, so the reads of its items are issued together
+        // (the LDS arrays share one base, and the compiler would otherwise
+        // order each read after the previous item's writes).
+        {
+            double pv[SMALL_MPT];
 #pragma unroll
-        for (int m = 0; m < SMALL_MPT; ++m) {
-            const int i = tid + m * ustride;
-            if (tid < ustride && i < N) {
-                double v = ur[m];
-                if (!first) v = v + beta * sp[i];
-                sp[i] = v;
-                sN[NV * i + DIM] = (udir >> m) & 1u ? 0.0 : v;
+            for (int m = 0; m < SMALL_MPT; ++m) {
+                const int i = tid + m * ustride;
+                pv[m] = (!first && tid < ustride && i < N) ? sp[i] : 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < SMALL_MPT; ++m) {
+                const int i = tid + m * ustride;
+                if (tid < ustride && i < N) {
+                    double v = ur[m];
+                    if (!first) v = v + beta * pv[m];
+                    sp[i] = v;
+                    sN[NV * i + DIM] = (udir >> m) & 1u ? 0.0 : v;
+                }
             }
         }
         __syncthreads();
@@ -921,45 +933,40 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
         }
         __syncthreads();
         // 3. q = A p by node sums in slot order (ascending element id);
-        // Dirichlet rows copy p; the p.q partial of each apply block
-        for (int vb = wv; vb < n_ablocks; vb += SMALL_NTH / 64) {
-            const int t = tile_at(vb, 0, n_ablocks, n_tiles);
+        // Dirichlet rows copy p.  A wave takes one half (64 nodes) of a
+        // tile and stores the wave sum of its p.q terms, which phase 4
+        // adds up as the apply block does: the two halves, then the two
+        // zero waves.
+        for (int hv = wv; hv < 2 * n_ablocks; hv += SMALL_NTH / 64) {
+            const int t = tile_at(hv >> 1, 0, n_ablocks, n_tiles);
             const int s0 = (t >= 0) ? sTo[t] : 0, nt = (t >= 0) ? sTo[t + 1] - s0 : 0;
-            double ws[2] = {0.0, 0.0};   // the sum of a wave of zeros is +0
+            const int l = lane + 64 * (hv & 1);
+            double part = 0.0;
+            if (l < nt) {
+                const int i = s0 + l;
+                const double pi = sp[i];
+                double yi = 0.0;
+                if (sDir[i]) {
+                    yi = pi;
+                } else {
+                    // slots in chunks of 8: the reads of a chunk are issued together
+                    const int j0 = sOff[i], d = sOff[i + 1] - j0;
+                    for (int c = 0; c < d; c += 8) {
+                        double cv[8];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (64 * h >= nt) break;
-                double part = 0.0;
-                const int l = lane + 64 * h;
-                if (l < nt) {
-                    const int i = s0 + l;
-                    const double pi = sp[i];
-                    double yi = 0.0;
-                    if (sDir[i]) {
-                        yi = pi;
-                    } else {
-                        // slots in chunks of 8: the reads of a chunk are issued together
-                        const int j0 = sOff[i], d = sOff[i + 1] - j0;
-                        for (int c = 0; c < d; c += 8) {
-                            double cv[8];
+                        for (int u = 0; u < 8; ++u)
+                            if (c + u < d) cv[u] = sC[j0 + c + u];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u)
-                                if (c + u < d) cv[u] = sC[j0 + c + u];
-#pragma unroll
-                            for (int u = 0; u < 8; ++u)
-                                if (c + u < d) yi += cv[u];
-                        }
+                        for (int u = 0; u < 8; ++u)
+                            if (c + u < d) yi += cv[u];
                     }
-                    sq[i] = yi;
-                    part += pi * yi;
                 }
-                ws[h] = wave_sum(part);
+                sq[i] = yi;
+                part += pi * yi;
             }
-            double s = ws[0];
-            s += ws[1];
-            s += 0.0;
-            s += 0.0;
-            if (lane == 0) spart[vb] = s;
+            // a half with no nodes sums to +0, as the wave sum of zeros does
+            const double ws = wave_sum(part);
+            if (lane == 0) sph[hv] = ws;
         }
         __syncthreads();
         // 4. the update: alpha = rr / p.q, x += alpha p, r -= alpha q
@@ -970,7 +977,15 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
             for (int u = 0; u < 4; ++u) {
                 if (u * 64 >= n_ablocks) break;
                 double v = 0.0;
-                if (u * 64 + lane < n_ablocks) v += spart[u * 64 + lane];
+                const int vb = u * 64 + lane;
+                if (vb < n_ablocks) {
+                    // the partial of apply block vb
+                    double bs = sph[2 * vb];
+                    bs += sph[2 * vb + 1];
+                    bs += 0.0;
+                    bs += 0.0;
+                    v += bs;
+                }
                 w4[u] = wave_sum(v);
             }
             pq = w4[0];
@@ -988,14 +1003,27 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
         }
         const double alpha = rr / pq;
         double v = 0.0;
+        {
+            double xv[SMALL_MPT], pv[SMALL_MPT], qv[SMALL_MPT];
 #pragma unroll
-        for (int m = 0; m < SMALL_MPT; ++m) {
-            const int i = tid + m * ustride;
-            if (tid < ustride && i < N) {
-                sx[i] = sx[i] + alpha * sp[i];
-                const double ri = ur[m] - alpha * sq[i];
-                ur[m] = ri;
-                v += ri * ri;
+            for (int m = 0; m < SMALL_MPT; ++m) {
+                const int i = tid + m * ustride;
+                xv[m] = pv[m] = qv[m] = 0.0;
+                if (tid < ustride && i < N) {
+                    xv[m] = sx[i];
+                    pv[m] = sp[i];
+                    qv[m] = sq[i];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < SMALL_MPT; ++m) {
+                const int i = tid + m * ustride;
+                if (tid < ustride && i < N) {
+                    sx[i] = xv[m] + alpha * pv[m];
+                    const double ri = ur[m] - alpha * qv[m];
+                    ur[m] = ri;
+                    v += ri * ri;
+                }
             }
         }
         v = wave_sum(v);
