@@ -190,12 +190,13 @@ int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *strea
  * Each CG iteration is two launches (the operator apply fused with the
  * direction update, then the vector update), run in chunks between reads
  * of the solver state.  A mesh whose coordinates, vectors and element
- * contributions fit one workgroup's LDS (in FP64 (dim + 6) * n_nodes +
- * 4 * n_elems doubles, a few more per tile; pressure_info entry 8 says
- * whether a handle qualifies) instead runs all its iterations in a single
- * launch of one workgroup, with the same arithmetic and the same reduction
- * order, so p, iters and res_hist are bit for bit those of the two-launch
- * form.  Timing (pressure_timing_enable) keeps the two-launch form. */
+ * contributions fit one workgroup's LDS (about (dim + 4) * n_nodes +
+ * (dim + 1) * n_elems doubles; pressure_info entry 8 says whether a handle
+ * qualifies) instead runs the whole solve (the start, every iteration and
+ * the true residual) in a single launch of one workgroup, with the same
+ * arithmetic and the same reduction order, so p, iters, res_hist and
+ * true_relres are bit for bit those of the multi-launch form.  Timing
+ * (pressure_timing_enable) keeps the multi-launch form. */
 int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                    int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
                    double *true_relres, void *stream);

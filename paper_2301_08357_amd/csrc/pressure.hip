@@ -766,45 +766,63 @@ __device__ __forceinline__ double wave_as_block(double v)
     return from_lane0(s);
 }
 
-// A whole CG solve of a small mesh in one launch of one 1024-lane workgroup,
-// from iteration k0 (a start or a restart: beta = 0) until it stops.  The
+// Arguments of the one-launch solve (vectors in internal node order).
+struct SmallArgs {
+    const int *n2e_off, *n2e_ent;   // node-to-element lists (entries 4e + a)
+    const int *node_off;            // tile t owns nodes [node_off[t], node_off[t+1])
+    const int *new2old;             // internal -> caller node order
+    int n_tiles, n_ablocks, n_vblocks;
+    double *x, *r, *b;
+    CGState *st;
+    double *hist;
+    double *rr_parts;               // r.r partials of parity 0; parity 1 at + VGRID_MAX
+    int k0;                         // first iteration of this launch
+    const double *rhs, *x0;         // with rhs set (k0 = 1): form b, x, r and the state first
+    double rtol;
+    int max_iter;
+};
+
+// A CG solve of a small mesh in one launch of one 1024-lane workgroup.
+// With a.rhs set it starts the solve (the gather of rhs and x0, ||rhs||
+// and the state, r = b - A x0); then it runs iterations from a.k0 (a start
+// or a restart: beta = 0) until the stop, and if the solve stopped
+// without a failure it forms the true residual b - A x of the final
+// iterate, its norm in st->tt and its partials for a restart.  The
 // coordinates, the node values and the element contributions live in LDS;
 // each lane keeps its elements (vertex ids, contribution slots, factor) and
 // the residual at its update nodes in registers for the whole solve, and an
 // iteration is four phases between block barriers: the direction update,
 // the element contributions, the node sums with the p.q partials, and the
 // vector update with the r.r partials.
-// The arithmetic is that of the two-kernel loop, operation for operation
-// and in the same order, reductions included, so x, r, the iteration count,
-// the history and the state equal the two-kernel loop's bit for bit:
+// The arithmetic is that of the multi-launch solve (k_prepare, k_begin,
+// the apply, k_start, the two-kernel iteration, k_true_residual and
+// k_finish_tt), operation for operation and in the same order, reductions
+// included, so x, r, b, the iteration count, the history and the state
+// equal the multi-launch solve's bit for bit:
 //  - a node sums its element contributions in ascending element order
 //    (its slots in the contribution table are its node-to-element list);
 //  - the p.q partial of apply block vb is formed as that block forms it,
 //    one tile per block, own node l of the tile in lane l of a 256-lane
 //    block (waves 2 and 3 of it hold zeros): here one wave sums each half
 //    of a tile, and the halves and zeros are added in the block's order;
-//  - the update lane tid takes nodes tid + m * 256 * n_vblocks, as lane
-//    tid mod 256 of update block tid / 256 does, and the four wave sums
-//    of an update block are added in order;
+//  - the vector lane tid takes nodes tid + m * 256 * n_vblocks, as lane
+//    tid mod 256 of vector block tid / 256 does, and the four wave sums
+//    of a vector block are added in order;
 //  - the sums of partials are those of sum_partials in a 256-lane block,
 //    which every wave forms for itself (in its lane 0, then broadcast).
 // Requires one tile per apply block (at most 256 tiles of at most 128
-// nodes), at most 4 update blocks, N <= SMALL_MPT * 256 * n_vblocks and
+// nodes), at most 4 vector blocks, N <= SMALL_MPT * 256 * n_vblocks and
 // E <= small_ept(DIM) * 1024; the host checks all of it.
 template <int DIM, bool PER>
-__global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__restrict__ n2e_off,
-                                                         const int *__restrict__ n2e_ent,
-                                                         const int *__restrict__ node_off, int n_tiles, int n_ablocks,
-                                                         int n_vblocks, double *__restrict__ x,
-                                                         double *__restrict__ r, CGState *st,
-                                                         double *__restrict__ hist,
-                                                         const double *__restrict__ rr_part0, int k0)
+__global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
 {
     extern __shared__ double sm[];
     const int N = g.N, E = g.E, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n_tiles = a.n_tiles, n_ablocks = a.n_ablocks, n_vblocks = a.n_vblocks;
+    const bool start = a.rhs != nullptr;
     constexpr int NV = DIM + 1;
-    // node table: per node X, Y, (Z,) and p with Dirichlet entries 0, so
-    // one address per vertex reaches all of them
+    // node table: per node X, Y, (Z,) and the operand with Dirichlet
+    // entries 0, so one address per vertex reaches all of them
     double *const sN = sm;
     double *const sp = sN + size_t(NV) * N, *const sq = sp + N, *const sx = sq + N;
     double *const sC = sx + N;                                        // NV * E contributions, by slot
@@ -815,31 +833,50 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
     int *const sInv = reinterpret_cast<int *>(sC);                    // setup only: slot of 4e + a
 
     __shared__ int done0;
-    if (tid == 0) done0 = st->done;
+    if (tid == 0) done0 = start ? 0 : a.st->done;
     for (int i = tid; i < N; i += SMALL_NTH) {
         sN[NV * i] = g.X[i];
         sN[NV * i + 1] = g.Y[i];
         if (DIM == 3) sN[NV * i + 2] = g.Z[i];
         sDir[i] = g.dir[i];
-        const int j0 = n2e_off[i], j1 = n2e_off[i + 1];
+        const int j0 = a.n2e_off[i], j1 = a.n2e_off[i + 1];
         sOff[i] = j0;
-        for (int j = j0; j < j1; ++j) sInv[n2e_ent[j]] = j;
+        for (int j = j0; j < j1; ++j) sInv[a.n2e_ent[j]] = j;
     }
-    if (tid == 0) sOff[N] = n2e_off[N];
-    for (int t = tid; t <= n_tiles; t += SMALL_NTH) sTo[t] = node_off[t];
-    // the update nodes of this lane
+    if (tid == 0) sOff[N] = a.n2e_off[N];
+    for (int t = tid; t <= n_tiles; t += SMALL_NTH) sTo[t] = a.node_off[t];
+    // the vector nodes of this lane
     const int ustride = n_vblocks * BLK;
+    auto unode = [&](int m) { return tid + m * ustride; };
+    auto uvalid = [&](int m) { return tid < ustride && unode(m) < N; };
     double ur[SMALL_MPT];
     unsigned udir = 0;
+    double v = 0.0;   // start: partial of rhs.rhs
 #pragma unroll
     for (int m = 0; m < SMALL_MPT; ++m) {
-        const int i = tid + m * ustride;
+        const int i = unode(m);
         ur[m] = 0.0;
-        if (tid < ustride && i < N) {
-            sx[i] = x[i];
-            ur[m] = r[i];
+        if (uvalid(m)) {
             if (g.dir[i]) udir |= 1u << m;
+            if (start) {
+                // k_prepare: gather rhs and x0; Dirichlet entries of x0 take rhs
+                const int o = a.new2old[i];
+                const double bi = a.rhs[o];
+                double xi = a.x0 ? a.x0[o] : 0.0;
+                if ((udir >> m) & 1u) xi = bi;
+                a.b[i] = bi;
+                sp[i] = bi;   // b until the first direction
+                sx[i] = xi;
+                v += bi * bi;
+            } else {
+                sx[i] = a.x[i];
+                ur[m] = a.r[i];
+            }
         }
+    }
+    if (start) {
+        v = wave_sum(v);
+        if (lane == 0) sred[wv] = v;
     }
     __syncthreads();
     // this lane's elements: vertex id (low 16 bits) and contribution slot
@@ -852,91 +889,93 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
         const int e = tid + k * SMALL_NTH;
         ew[k] = 0.0;
 #pragma unroll
-        for (int a = 0; a < NV; ++a) ev[k][a] = 0;
+        for (int c = 0; c < NV; ++c) ev[k][c] = 0;
         if (e < E) {
-            const int4 c = g.conn[e];
-            const int cv[4] = {c.x, c.y, c.z, c.w};
+            const int4 c4 = g.conn[e];
+            const int cv[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
-            for (int a = 0; a < NV; ++a) ev[k][a] = unsigned(cv[a] & 0x7fffffff) | (unsigned(sInv[4 * e + a]) << 16);
+            for (int c = 0; c < NV; ++c) ev[k][c] = unsigned(cv[c] & 0x7fffffff) | (unsigned(sInv[4 * e + c]) << 16);
             ew[k] = g.w[e];
         }
     }
-    __syncthreads();   // sInv is read; sC takes contributions from here on
-    if (done0) return;
-    const double tol = st->tol, bnorm = st->bnorm;
-    const int max_iter = st->max_iter;
-    double rr, rr_prev = 0.0;
-    {
-        double v = 0.0;
-        if (lane < n_vblocks) v += rr_part0[lane];
-        rr = wave_as_block(v);
-    }
-    bool first = true;
-    for (int k = k0;; ++k) {
-        // the decision of the apply of iteration k (iter_decide)
-        const double nr = sqrt(rr);
-        const bool bad = !isfinite(rr);
-        const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
+    // sum_partials of the 256-lane blocks' sums of sred (n_vblocks blocks of 4 waves), in every lane
+    auto vector_sum = [&]() {
+        double u = 0.0;
+        if (lane < n_vblocks) {
+            double b4 = sred[4 * lane];
+            b4 += sred[4 * lane + 1];
+            b4 += sred[4 * lane + 2];
+            b4 += sred[4 * lane + 3];
+            u += b4;
+        }
+        return wave_as_block(u);
+    };
+    double tol, bnorm;
+    int max_iter, status = 0;
+    if (start) {
+        // k_begin
+        const double bb = vector_sum();
+        bnorm = sqrt(bb);
+        tol = a.rtol * bnorm;
+        max_iter = a.max_iter;
+        const bool ok = isfinite(bnorm), stop0 = !ok || !(bnorm > 0.0);
+        status = ok ? 0 : PM_EINVAL;
         if (tid == 0) {
-            if (!(first && k > 1)) hist[k - 1] = nr / bnorm;
-            st->iter = k - 1;
-            st->rr = rr;
-            if (bad) st->status = PM_EBREAKDOWN;
-            if (stop) st->done = 1;
+            CGState *st = a.st;
+            st->bnorm = bnorm;
+            st->tol = tol;
+            st->rr = 0.0;
+            st->tt = 0.0;
+            st->iter = 0;
+            st->max_iter = max_iter;
+            st->status = ok ? 0 : PM_EINVAL;
+            st->done = stop0 ? 1 : 0;
+            st->k_first = 1;
+            if (!(bnorm > 0.0)) a.hist[0] = 0.0;
+            done0 = stop0 ? 1 : 0;
         }
-        if (stop) break;
-        const double beta = first ? 0.0 : rr / rr_prev;
-        // 1. p_k = r + beta p_{k-1}.  Every phase reads all it needs
-        // before it writes, so the reads of its items are issued together
-        // (the LDS arrays share one base, and the compiler would otherwise
-        // order each read after the previous item's writes).
-        {
-            double pv[SMALL_MPT];
+    } else {
+        tol = a.st->tol;
+        bnorm = a.st->bnorm;
+        max_iter = a.st->max_iter;
+    }
+    __syncthreads();   // sInv is read; sC takes contributions from here on
+
+    // The operator apply y = A v of the staged node values (Dirichlet
+    // entries 0 in the node table, Dirichlet rows y = v): the element
+    // contributions, then the node sums into sq.  With PART each half tile
+    // stores the wave sum of its v.y terms in sph.
+    auto apply = [&](const double *__restrict__ sv, bool part_on) {
+        // The element records pass through an empty asm statement, so the
+        // compiler forms their LDS addresses here instead of keeping one
+        // register per address for the whole solve.
 #pragma unroll
-            for (int m = 0; m < SMALL_MPT; ++m) {
-                const int i = tid + m * ustride;
-                pv[m] = (!first && tid < ustride && i < N) ? sp[i] : 0.0;
-            }
+        for (int kk = 0; kk < EPT; ++kk)
 #pragma unroll
-            for (int m = 0; m < SMALL_MPT; ++m) {
-                const int i = tid + m * ustride;
-                if (tid < ustride && i < N) {
-                    double v = ur[m];
-                    if (!first) v = v + beta * pv[m];
-                    sp[i] = v;
-                    sN[NV * i + DIM] = (udir >> m) & 1u ? 0.0 : v;
-                }
-            }
-        }
-        __syncthreads();
-        // 2. element contributions, each into its slot
+            for (int c = 0; c < NV; ++c) asm volatile("" : "+v"(ev[kk][c]));
 #pragma unroll
         for (int kk = 0; kk < EPT; ++kk) {
             if (tid + kk * SMALL_NTH < E) {
                 double X[4], Y[4], Z[4], xv[4], o[4];
 #pragma unroll
-                for (int a = 0; a < NV; ++a) {
-                    const int v = int(ev[kk][a] & 0xffffu);
-                    const double *nv = sN + NV * v;
-                    X[a] = nv[0];
-                    Y[a] = nv[1];
-                    Z[a] = (DIM == 3) ? nv[2] : 0.0;
-                    xv[a] = nv[DIM];
+                for (int c = 0; c < NV; ++c) {
+                    const double *nv = sN + NV * int(ev[kk][c] & 0xffffu);
+                    X[c] = nv[0];
+                    Y[c] = nv[1];
+                    Z[c] = (DIM == 3) ? nv[2] : 0.0;
+                    xv[c] = nv[DIM];
                 }
                 if (DIM == 2) xv[3] = 0.0;
                 double ed[3][3];
                 elem_edges<DIM, PER>(X, Y, Z, g, ed);
                 elem_contrib<DIM, double>(ed, xv, ew[kk], g.mdiag, g.mfull, o);
 #pragma unroll
-                for (int a = 0; a < NV; ++a) sC[ev[kk][a] >> 16] = o[a];
+                for (int c = 0; c < NV; ++c) sC[ev[kk][c] >> 16] = o[c];
             }
         }
         __syncthreads();
-        // 3. q = A p by node sums in slot order (ascending element id);
-        // Dirichlet rows copy p.  A wave takes one half (64 nodes) of a
-        // tile and stores the wave sum of its p.q terms, which phase 4
-        // adds up as the apply block does: the two halves, then the two
-        // zero waves.
+        // A wave takes one half (64 nodes) of a tile; a half with no nodes
+        // sums to +0, as the wave sum of zeros does.
         for (int hv = wv; hv < 2 * n_ablocks; hv += SMALL_NTH / 64) {
             const int t = tile_at(hv >> 1, 0, n_ablocks, n_tiles);
             const int s0 = (t >= 0) ? sTo[t] : 0, nt = (t >= 0) ? sTo[t + 1] - s0 : 0;
@@ -944,10 +983,10 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
             double part = 0.0;
             if (l < nt) {
                 const int i = s0 + l;
-                const double pi = sp[i];
+                const double vi = sv[i];
                 double yi = 0.0;
                 if (sDir[i]) {
-                    yi = pi;
+                    yi = vi;
                 } else {
                     // slots in chunks of 8: the reads of a chunk are issued together
                     const int j0 = sOff[i], d = sOff[i + 1] - j0;
@@ -962,95 +1001,194 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, const int *__
                     }
                 }
                 sq[i] = yi;
-                part += pi * yi;
+                part += vi * yi;
             }
-            // a half with no nodes sums to +0, as the wave sum of zeros does
-            const double ws = wave_sum(part);
-            if (lane == 0) sph[hv] = ws;
+            if (part_on) {
+                const double ws = wave_sum(part);
+                if (lane == 0) sph[hv] = ws;
+            }
         }
         __syncthreads();
-        // 4. the update: alpha = rr / p.q, x += alpha p, r -= alpha q
-        double pq;
-        {
-            double w4[4] = {0.0, 0.0, 0.0, 0.0};   // waves past the partials sum zeros
+    };
+    // the node table's operand entries from x
+    auto stage_x = [&]() {
+        double xv[SMALL_MPT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (u * 64 >= n_ablocks) break;
-                double v = 0.0;
-                const int vb = u * 64 + lane;
-                if (vb < n_ablocks) {
-                    // the partial of apply block vb
-                    double bs = sph[2 * vb];
-                    bs += sph[2 * vb + 1];
-                    bs += 0.0;
-                    bs += 0.0;
-                    v += bs;
+        for (int m = 0; m < SMALL_MPT; ++m) xv[m] = uvalid(m) ? sx[unode(m)] : 0.0;
+#pragma unroll
+        for (int m = 0; m < SMALL_MPT; ++m)
+            if (uvalid(m)) sN[NV * unode(m) + DIM] = (udir >> m) & 1u ? 0.0 : xv[m];
+        __syncthreads();
+    };
+
+    double rr = 0.0, rr_prev = 0.0;
+    if (start) {
+        // q = A x0; k_start: r = b - q (||rhs|| = 0 or not finite: x = 0,
+        // r = 0), partials of r.r
+        stage_x();
+        apply(sx, false);
+        const bool zero = !(bnorm > 0.0);
+        double u = 0.0;
+#pragma unroll
+        for (int m = 0; m < SMALL_MPT; ++m)
+            if (uvalid(m)) {
+                const int i = unode(m);
+                double ri = sp[i] - sq[i];
+                if (zero) {
+                    sx[i] = 0.0;
+                    ri = 0.0;
                 }
-                w4[u] = wave_sum(v);
+                ur[m] = ri;
+                u += ri * ri;
             }
-            pq = w4[0];
-            pq += w4[1];
-            pq += w4[2];
-            pq += w4[3];
-            pq = from_lane0(pq);   // lane 0 holds the wave sums
-        }
-        if (!(pq > 0.0) || !isfinite(pq)) {
+        u = wave_sum(u);
+        if (lane == 0) sred[wv] = u;
+        __syncthreads();
+        rr = vector_sum();
+    } else {
+        double u = 0.0;
+        if (lane < n_vblocks) u += a.rr_parts[((a.k0 - 1) & 1) * VGRID_MAX + lane];
+        rr = wave_as_block(u);
+    }
+    int k = a.k0;
+    bool first = true;
+    if (!done0) {
+        for (;; ++k) {
+            // the decision of the apply of iteration k (iter_decide)
+            const double nr = sqrt(rr);
+            const bool bad = !isfinite(rr);
+            const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
+            if (bad) status = PM_EBREAKDOWN;
             if (tid == 0) {
-                st->status = PM_EBREAKDOWN;
-                st->done = 1;
+                if (!(first && k > 1)) a.hist[k - 1] = nr / bnorm;
+                a.st->iter = k - 1;
+                a.st->rr = rr;
+                if (bad) a.st->status = PM_EBREAKDOWN;
+                if (stop) a.st->done = 1;
             }
-            break;
-        }
-        const double alpha = rr / pq;
-        double v = 0.0;
-        {
-            double xv[SMALL_MPT], pv[SMALL_MPT], qv[SMALL_MPT];
+            if (stop) break;
+            const double beta = first ? 0.0 : rr / rr_prev;
+            // 1. p_k = r + beta p_{k-1}.  Each phase reads all it needs
+            // before it writes, so the reads of its items are issued
+            // together (the LDS arrays share one base, and the compiler
+            // would otherwise order each read after the previous item's
+            // writes).
+            {
+                double pv[SMALL_MPT];
 #pragma unroll
-            for (int m = 0; m < SMALL_MPT; ++m) {
-                const int i = tid + m * ustride;
-                xv[m] = pv[m] = qv[m] = 0.0;
-                if (tid < ustride && i < N) {
-                    xv[m] = sx[i];
-                    pv[m] = sp[i];
-                    qv[m] = sq[i];
-                }
-            }
+                for (int m = 0; m < SMALL_MPT; ++m) pv[m] = (!first && uvalid(m)) ? sp[unode(m)] : 0.0;
 #pragma unroll
-            for (int m = 0; m < SMALL_MPT; ++m) {
-                const int i = tid + m * ustride;
-                if (tid < ustride && i < N) {
-                    sx[i] = xv[m] + alpha * pv[m];
-                    const double ri = ur[m] - alpha * qv[m];
-                    ur[m] = ri;
-                    v += ri * ri;
-                }
+                for (int m = 0; m < SMALL_MPT; ++m)
+                    if (uvalid(m)) {
+                        const int i = unode(m);
+                        double pk = ur[m];
+                        if (!first) pk = pk + beta * pv[m];
+                        sp[i] = pk;
+                        sN[NV * i + DIM] = (udir >> m) & 1u ? 0.0 : pk;
+                    }
             }
-        }
-        v = wave_sum(v);
-        if (lane == 0) sred[wv] = v;
-        __syncthreads();
-        rr_prev = rr;
-        {
+            __syncthreads();
+            // 2, 3. q = A p and the p.q partials of the apply blocks
+            apply(sp, true);
+            // 4. the update: alpha = rr / p.q, x += alpha p, r -= alpha q
+            double pq;
+            {
+                double w4[4] = {0.0, 0.0, 0.0, 0.0};   // waves past the partials sum zeros
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u * 64 >= n_ablocks) break;
+                    double pv = 0.0;
+                    const int vb = u * 64 + lane;
+                    if (vb < n_ablocks) {
+                        // the partial of apply block vb: its two halves, then two zero waves
+                        double bs = sph[2 * vb];
+                        bs += sph[2 * vb + 1];
+                        bs += 0.0;
+                        bs += 0.0;
+                        pv += bs;
+                    }
+                    w4[u] = wave_sum(pv);
+                }
+                pq = w4[0];
+                pq += w4[1];
+                pq += w4[2];
+                pq += w4[3];
+                pq = from_lane0(pq);   // lane 0 holds the wave sums
+            }
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                status = PM_EBREAKDOWN;
+                if (tid == 0) {
+                    a.st->status = PM_EBREAKDOWN;
+                    a.st->done = 1;
+                }
+                break;
+            }
+            const double alpha = rr / pq;
             double u = 0.0;
-            if (lane < n_vblocks) {
-                double b4 = sred[4 * lane];
-                b4 += sred[4 * lane + 1];
-                b4 += sred[4 * lane + 2];
-                b4 += sred[4 * lane + 3];
-                u += b4;
+            {
+                double xv[SMALL_MPT], pv[SMALL_MPT], qv[SMALL_MPT];
+#pragma unroll
+                for (int m = 0; m < SMALL_MPT; ++m) {
+                    xv[m] = pv[m] = qv[m] = 0.0;
+                    if (uvalid(m)) {
+                        const int i = unode(m);
+                        xv[m] = sx[i];
+                        pv[m] = sp[i];
+                        qv[m] = sq[i];
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < SMALL_MPT; ++m)
+                    if (uvalid(m)) {
+                        sx[unode(m)] = xv[m] + alpha * pv[m];
+                        const double ri = ur[m] - alpha * qv[m];
+                        ur[m] = ri;
+                        u += ri * ri;
+                    }
             }
-            rr = wave_as_block(u);
+            u = wave_sum(u);
+            if (lane == 0) sred[wv] = u;
+            __syncthreads();
+            rr_prev = rr;
+            rr = vector_sum();
+            first = false;
         }
-        first = false;
+    }
+    if (status == 0 && bnorm > 0.0) {
+        // the true residual of the final iterate (launch_apply of x,
+        // k_true_residual into the r.r partials of the final iteration's
+        // parity, k_finish_tt)
+        const int kdone = done0 ? a.st->iter : k - 1;
+        stage_x();
+        apply(sx, false);
+        double u = 0.0;
+#pragma unroll
+        for (int m = 0; m < SMALL_MPT; ++m)
+            if (uvalid(m)) {
+                const int i = unode(m);
+                const double ri = a.b[i] - sq[i];
+                ur[m] = ri;
+                u += ri * ri;
+            }
+        u = wave_sum(u);
+        if (lane == 0) sred[wv] = u;
+        __syncthreads();
+        if (wv < n_vblocks && lane == 0) {
+            double b4 = sred[4 * wv];
+            b4 += sred[4 * wv + 1];
+            b4 += sred[4 * wv + 2];
+            b4 += sred[4 * wv + 3];
+            a.rr_parts[(kdone & 1) * VGRID_MAX + wv] = b4;
+        }
+        const double tt = vector_sum();
+        if (tid == 0) a.st->tt = tt;
     }
 #pragma unroll
-    for (int m = 0; m < SMALL_MPT; ++m) {
-        const int i = tid + m * ustride;
-        if (tid < ustride && i < N) {
-            x[i] = sx[i];
-            r[i] = ur[m];
+    for (int m = 0; m < SMALL_MPT; ++m)
+        if (uvalid(m)) {
+            a.x[unode(m)] = sx[unode(m)];
+            a.r[unode(m)] = ur[m];
         }
-    }
 }
 
 
@@ -3619,16 +3757,36 @@ static bool small_ok(const pm_handle *h)
     return small_lds_bytes(h->dim, h->N, h->E, h->n_ablocks, h->n_tiles) <= size_t(h->lds_limit);
 }
 
-static int launch_small(pm_handle *h, int k0, hipStream_t s)
+// One launch of the one-workgroup solve from iteration k0; with rhs set
+// (k0 = 1) it also starts the solve from rhs and x0.
+static int launch_small(pm_handle *h, int k0, const double *rhs, const double *x0, double rtol, int max_iter,
+                        hipStream_t s)
 {
     const size_t lds = small_lds_bytes(h->dim, h->N, h->E, h->n_ablocks, h->n_tiles);
     Mesh g = make_mesh<double>(h);
+    SmallArgs a;
+    a.n2e_off = h->n2e_off;
+    a.n2e_ent = h->n2e_ent;
+    a.node_off = h->t_node_off;
+    a.new2old = h->new2old;
+    a.n_tiles = h->n_tiles;
+    a.n_ablocks = h->n_ablocks;
+    a.n_vblocks = h->n_vblocks;
+    a.x = h->x;
+    a.r = h->r;
+    a.b = h->b;
+    a.st = h->st;
+    a.hist = h->hist;
+    a.rr_parts = h->part_rr(0);
+    a.k0 = k0;
+    a.rhs = rhs;
+    a.x0 = x0;
+    a.rtol = rtol;
+    a.max_iter = max_iter;
     auto go = [&]<int DIM, bool PER>() -> int {
         const void *kern = (const void *)k_solve_small<DIM, PER>;
         if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-        hipLaunchKernelGGL((k_solve_small<DIM, PER>), dim3(1), dim3(SMALL_NTH), lds, s, g, h->n2e_off, h->n2e_ent,
-                           h->t_node_off, h->n_tiles, h->n_ablocks, h->n_vblocks, h->x, h->r, h->st, h->hist,
-                           h->part_rr((k0 - 1) & 1), k0);
+        hipLaunchKernelGGL((k_solve_small<DIM, PER>), dim3(1), dim3(SMALL_NTH), lds, s, g, a);
         HIPCK(hipGetLastError());
         return PM_OK;
     };
@@ -3647,27 +3805,34 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
     const int N = int(h->N);
     const unsigned vg = h->n_vblocks;
 
-    hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
-                       h->part_misc());
-    TRY(project_rhs(h, s));
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist, 1);
-    HIPCK(hipGetLastError());
-    TRY(launch_apply(h, h->x, h->q, nullptr, s));
-    hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
-    HIPCK(hipGetLastError());
+    // A small mesh runs each pass of the solve (the start, the iterations
+    // up to the stop, the true residual) in one launch; the first pass also
+    // starts the solve unless the rhs must first be projected onto V_0.
+    const bool small = small_ok(h);
+    const bool small_start = small && !h->singular;
+    if (!small_start) {
+        hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
+                           h->part_misc());
+        TRY(project_rhs(h, s));
+        hipLaunchKernelGGL(k_begin, dim3(1), dim3(BLK), 0, s, h->st, h->part_misc(), int(vg), rtol, max_iter, h->hist,
+                           1);
+        HIPCK(hipGetLastError());
+        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        hipLaunchKernelGGL(k_start, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->x, h->r, h->st, h->part_rr(0));
+        HIPCK(hipGetLastError());
+    }
 
     int replaced = 0;
     int k = 1;            // next iteration to launch
     bool first = true;    // k is the first iteration after a (re)start
     size_t timed = 0;
-    const bool small = small_ok(h);
     for (;;) {
         int chunk = 4;
         double rr_seen = -1.0;
         int it_seen = 0;
         if (small) {
-            // the iterations up to the stop in one launch
-            TRY(launch_small(h, k, s));
+            const bool with_start = small_start && k == 1 && replaced == 0;
+            TRY(launch_small(h, k, with_start ? rhs_dev : nullptr, x0_dev, rtol, max_iter, s));
             TRY(read_state(h, s));
         }
         for (; !small;) {
@@ -3699,13 +3864,16 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
         }
         if (h->hst->status != 0) break;
         if (!(h->hst->bnorm > 0.0)) break;
-        // true residual of the final iterate
-        TRY(launch_apply(h, h->x, h->q, nullptr, s));
+        // true residual of the final iterate (the one-launch pass formed it)
         const int kdone = h->hst->iter;
-        hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r, h->part_rr(kdone & 1));
-        hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_rr(kdone & 1), int(vg));
-        HIPCK(hipGetLastError());
-        TRY(read_state(h, s));
+        if (!small) {
+            TRY(launch_apply(h, h->x, h->q, nullptr, s));
+            hipLaunchKernelGGL(k_true_residual, dim3(vg), dim3(BLK), 0, s, N, h->b, h->q, h->r,
+                               h->part_rr(kdone & 1));
+            hipLaunchKernelGGL(k_finish_tt, dim3(1), dim3(BLK), 0, s, h->st, h->part_rr(kdone & 1), int(vg));
+            HIPCK(hipGetLastError());
+            TRY(read_state(h, s));
+        }
         const double rel = std::sqrt(h->hst->tt) / h->hst->bnorm;
         if (rel <= rtol || replaced >= 2 || kdone >= max_iter) break;
         // residual replacement: r is now the true residual; restart the directions
