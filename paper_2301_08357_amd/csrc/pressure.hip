@@ -745,6 +745,10 @@ __global__ void __launch_bounds__(NTH, (tile_waves<R, T, LM>())) k_apply_tiled(M
 constexpr int SMALL_NTH = 1024;   // one workgroup
 // elements per lane: E <= 4096 triangles or 3072 tetrahedra
 constexpr int small_ept(int dim) { return dim == 2 ? 4 : 3; }
+// With at most two triangles per lane (E <= 2048) the lanes also keep
+// their elements' edge vectors in registers, so the element phase reads
+// only the operand from LDS (tetrahedra would spill).
+constexpr int SMALL_GEO_EPT = 2;
 constexpr int SMALL_MPT = 4;      // nodes per lane of the update (N <= 4 * 256 * n_vblocks)
 
 // Bytes of dynamic LDS the one-launch solve needs (see k_solve_small).
@@ -812,8 +816,10 @@ struct SmallArgs {
 //    which every wave forms for itself (in its lane 0, then broadcast).
 // Requires one tile per apply block (at most 256 tiles of at most 128
 // nodes), at most 4 vector blocks, N <= SMALL_MPT * 256 * n_vblocks and
-// E <= small_ept(DIM) * 1024; the host checks all of it.
-template <int DIM, bool PER>
+// E <= EPT * 1024; the host checks all of it.  GEO: the edge vectors of
+// the lane's elements stay in registers (the same values elem_edges forms
+// from the node table in every apply otherwise).
+template <int DIM, bool PER, int EPT, bool GEO>
 __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
 {
     extern __shared__ double sm[];
@@ -881,7 +887,6 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
     __syncthreads();
     // this lane's elements: vertex id (low 16 bits) and contribution slot
     // (high 16 bits) per vertex, and the element factor
-    constexpr int EPT = small_ept(DIM);
     unsigned ev[EPT][NV];
     double ew[EPT];
 #pragma unroll
@@ -940,6 +945,23 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
         max_iter = a.st->max_iter;
     }
     __syncthreads();   // sInv is read; sC takes contributions from here on
+    double ged[GEO ? EPT : 1][3][3];
+    if constexpr (GEO) {
+#pragma unroll
+        for (int kk = 0; kk < EPT; ++kk) {
+            double X[4] = {0.0, 0.0, 0.0, 0.0}, Y[4] = {0.0, 0.0, 0.0, 0.0}, Z[4] = {0.0, 0.0, 0.0, 0.0};
+            if (tid + kk * SMALL_NTH < E) {
+#pragma unroll
+                for (int c = 0; c < NV; ++c) {
+                    const double *nv = sN + NV * int(ev[kk][c] & 0xffffu);
+                    X[c] = nv[0];
+                    Y[c] = nv[1];
+                    Z[c] = (DIM == 3) ? nv[2] : 0.0;
+                }
+            }
+            elem_edges<DIM, PER>(X, Y, Z, g, ged[kk]);
+        }
+    }
 
     // The operator apply y = A v of the staged node values (Dirichlet
     // entries 0 in the node table, Dirichlet rows y = v): the element
@@ -956,19 +978,27 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
 #pragma unroll
         for (int kk = 0; kk < EPT; ++kk) {
             if (tid + kk * SMALL_NTH < E) {
-                double X[4], Y[4], Z[4], xv[4], o[4];
+                double xv[4], o[4];
+                if constexpr (GEO) {
 #pragma unroll
-                for (int c = 0; c < NV; ++c) {
-                    const double *nv = sN + NV * int(ev[kk][c] & 0xffffu);
-                    X[c] = nv[0];
-                    Y[c] = nv[1];
-                    Z[c] = (DIM == 3) ? nv[2] : 0.0;
-                    xv[c] = nv[DIM];
+                    for (int c = 0; c < NV; ++c) xv[c] = sN[NV * int(ev[kk][c] & 0xffffu) + DIM];
+                    if (DIM == 2) xv[3] = 0.0;
+                    elem_contrib<DIM, double>(ged[kk], xv, ew[kk], g.mdiag, g.mfull, o);
+                } else {
+                    double X[4], Y[4], Z[4];
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) {
+                        const double *nv = sN + NV * int(ev[kk][c] & 0xffffu);
+                        X[c] = nv[0];
+                        Y[c] = nv[1];
+                        Z[c] = (DIM == 3) ? nv[2] : 0.0;
+                        xv[c] = nv[DIM];
+                    }
+                    if (DIM == 2) xv[3] = 0.0;
+                    double ed[3][3];
+                    elem_edges<DIM, PER>(X, Y, Z, g, ed);
+                    elem_contrib<DIM, double>(ed, xv, ew[kk], g.mdiag, g.mfull, o);
                 }
-                if (DIM == 2) xv[3] = 0.0;
-                double ed[3][3];
-                elem_edges<DIM, PER>(X, Y, Z, g, ed);
-                elem_contrib<DIM, double>(ed, xv, ew[kk], g.mdiag, g.mfull, o);
 #pragma unroll
                 for (int c = 0; c < NV; ++c) sC[ev[kk][c] >> 16] = o[c];
             }
@@ -3784,11 +3814,16 @@ static int launch_small(pm_handle *h, int k0, const double *rhs, const double *x
     a.rtol = rtol;
     a.max_iter = max_iter;
     auto go = [&]<int DIM, bool PER>() -> int {
-        const void *kern = (const void *)k_solve_small<DIM, PER>;
-        if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-        hipLaunchKernelGGL((k_solve_small<DIM, PER>), dim3(1), dim3(SMALL_NTH), lds, s, g, a);
-        HIPCK(hipGetLastError());
-        return PM_OK;
+        auto run = [&]<int EPT, bool GEO>() -> int {
+            const void *kern = (const void *)k_solve_small<DIM, PER, EPT, GEO>;
+            if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+            hipLaunchKernelGGL((k_solve_small<DIM, PER, EPT, GEO>), dim3(1), dim3(SMALL_NTH), lds, s, g, a);
+            HIPCK(hipGetLastError());
+            return PM_OK;
+        };
+        if constexpr (DIM == 2)
+            if (h->E <= int64_t(SMALL_GEO_EPT) * SMALL_NTH) return run.template operator()<SMALL_GEO_EPT, true>();
+        return run.template operator()<small_ept(DIM), false>();
     };
     if (h->dim == 2) return h->periodic ? go.template operator()<2, true>() : go.template operator()<2, false>();
     return h->periodic ? go.template operator()<3, true>() : go.template operator()<3, false>();
