@@ -1082,22 +1082,35 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
     }
     int k = a.k0;
     bool first = true;
+    // The scalar steps of an iteration (the stopping decision and beta,
+    // then p.q and alpha) run in wave 0 alone, which holds rr; lane 0
+    // passes the outcome to the other waves through LDS.  Every VALU
+    // instruction of a wave costs the SIMD four cycles, and one workgroup
+    // is all the work there is, so steps done once instead of in all 16
+    // waves shorten the iteration.
+    __shared__ double s_beta, s_alpha;
+    __shared__ int s_flag;   // 0: go on; 1: stop; 2: stop with a breakdown
     if (!done0) {
         for (;; ++k) {
-            // the decision of the apply of iteration k (iter_decide)
-            const double nr = sqrt(rr);
-            const bool bad = !isfinite(rr);
-            const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
-            if (bad) status = PM_EBREAKDOWN;
             if (tid == 0) {
+                // the decision of the apply of iteration k (iter_decide)
+                const double nr = sqrt(rr);
+                const bool bad = !isfinite(rr);
+                const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
                 if (!(first && k > 1)) a.hist[k - 1] = nr / bnorm;
                 a.st->iter = k - 1;
                 a.st->rr = rr;
                 if (bad) a.st->status = PM_EBREAKDOWN;
                 if (stop) a.st->done = 1;
+                s_beta = (first || stop) ? 0.0 : rr / rr_prev;
+                s_flag = stop ? (bad ? 2 : 1) : 0;
             }
-            if (stop) break;
-            const double beta = first ? 0.0 : rr / rr_prev;
+            __syncthreads();
+            if (s_flag) {
+                if (s_flag == 2) status = PM_EBREAKDOWN;
+                break;
+            }
+            const double beta = s_beta;
             // 1. p_k = r + beta p_{k-1}.  Each phase reads all it needs
             // before it writes, so the reads of its items are issued
             // together (the LDS arrays share one base, and the compiler
@@ -1121,8 +1134,7 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             // 2, 3. q = A p and the p.q partials of the apply blocks
             apply(sp, true);
             // 4. the update: alpha = rr / p.q, x += alpha p, r -= alpha q
-            double pq;
-            {
+            if (wv == 0) {
                 double w4[4] = {0.0, 0.0, 0.0, 0.0};   // waves past the partials sum zeros
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -1139,21 +1151,26 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
                     }
                     w4[u] = wave_sum(pv);
                 }
-                pq = w4[0];
-                pq += w4[1];
-                pq += w4[2];
-                pq += w4[3];
-                pq = from_lane0(pq);   // lane 0 holds the wave sums
-            }
-            if (!(pq > 0.0) || !isfinite(pq)) {
-                status = PM_EBREAKDOWN;
-                if (tid == 0) {
-                    a.st->status = PM_EBREAKDOWN;
-                    a.st->done = 1;
+                if (lane == 0) {
+                    double pq = w4[0];
+                    pq += w4[1];
+                    pq += w4[2];
+                    pq += w4[3];
+                    if (!(pq > 0.0) || !isfinite(pq)) {
+                        a.st->status = PM_EBREAKDOWN;
+                        a.st->done = 1;
+                        s_flag = 2;
+                    } else {
+                        s_alpha = rr / pq;
+                    }
                 }
+            }
+            __syncthreads();
+            if (s_flag) {
+                status = PM_EBREAKDOWN;
                 break;
             }
-            const double alpha = rr / pq;
+            const double alpha = s_alpha;
             double u = 0.0;
             {
                 double xv[SMALL_MPT], pv[SMALL_MPT], qv[SMALL_MPT];
@@ -1179,8 +1196,10 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             u = wave_sum(u);
             if (lane == 0) sred[wv] = u;
             __syncthreads();
-            rr_prev = rr;
-            rr = vector_sum();
+            if (wv == 0) {
+                rr_prev = rr;
+                rr = vector_sum();
+            }
             first = false;
         }
     }
@@ -1210,8 +1229,10 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             b4 += sred[4 * wv + 3];
             a.rr_parts[(kdone & 1) * VGRID_MAX + wv] = b4;
         }
-        const double tt = vector_sum();
-        if (tid == 0) a.st->tt = tt;
+        if (wv == 0) {
+            const double tt = vector_sum();
+            if (tid == 0) a.st->tt = tt;
+        }
     }
 #pragma unroll
     for (int m = 0; m < SMALL_MPT; ++m)
