@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--workload", default="cube160",
                     choices=["cube160", "cube64", "cube160p", "projection160", "transport160", "timestep160",
-                             "batch256", "serve", "copy"],
+                             "batch256", "serve", "copy", "tgv2d32"],
                     help="cube160 (default line) or one of the other synthetic workloads")
     ap.add_argument("--no-extras", action="store_true", help="cube160: skip the cube64 and tgv2d_32 legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -116,6 +116,19 @@ def main():
         return bench_serve(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "tgv2d32":
+        return bench_tgv2d32(args)
+
+
+def bench_tgv2d32(args):
+    """The small 2D case alone: --steps x 100 single solves of tgv2d_32 (each
+    one launch of the one-workgroup solver, a state read and the scatter);
+    the line's value is the p50 latency."""
+    rec = extra_tgv2d32(args, solves=100 * max(1, args.steps))
+    print(json.dumps({"metric": "tgv2d_32 single-solve latency (FP64 CG to rtol 1e-12)",
+                      "value": rec["latency_ms_p50"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": rec["workload"]}, **{k: v for k, v in rec.items() if k != "workload"}}))
 
 
 def bench_cube64(args):
@@ -395,13 +408,15 @@ def extra_tgv2d32(args, solves=300):
         lat.append(time.perf_counter() - ta)
         its.append(r.iters)
     el = time.perf_counter() - t0
-    nfree = q.info()["n_free"]
+    info = q.info()
+    nfree = info["n_free"]
     q.close()
     return {"workload": "tgv2d_32: unit square 32x32 x 2 tris (2048 tris, 1089 nodes), jitter 0.2h, c=1, w=1e-2, "
                         "FP64 CG to rtol 1e-12, b = A_D p*, %d single solves" % solves,
             "solves_per_s": round(solves / el, 1), "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
             "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4), "iterations": its[0],
-            "GDOF_iter_per_s": round(nfree * sum(its) / el / 1e9, 4)}
+            "GDOF_iter_per_s": round(nfree * sum(its) / el / 1e9, 4),
+            "one_launch_solve": bool(info["one_launch_solve"])}
 
 
 def oracle_other_configs(args, single_seconds=6.0):
