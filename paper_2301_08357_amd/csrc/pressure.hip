@@ -1082,41 +1082,40 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
     }
     int k = a.k0;
     bool first = true;
-    // The scalar steps of an iteration (the stopping decision and beta,
-    // then p.q and alpha) run in wave 0 alone, which holds rr; lane 0
-    // passes the outcome to the other waves through LDS.  Every VALU
-    // instruction of a wave costs the SIMD four cycles, and one workgroup
-    // is all the work there is, so steps done once instead of in all 16
-    // waves shorten the iteration.
-    __shared__ double s_beta, s_alpha;
-    __shared__ int s_flag;   // 0: go on; 1: stop; 2: stop with a breakdown
+    // Every VALU instruction of a wave costs its SIMD four cycles, and one
+    // workgroup is all the work there is, so work is kept off the waves
+    // that do not need it: p.q and alpha are formed in wave 0 alone, whose
+    // lane 0 passes them on through LDS, and the waves past the vector
+    // blocks skip the vector phases.  The stopping decision and beta, from
+    // rr, cost less in every wave than a barrier would.
+    __shared__ double s_alpha;
+    __shared__ int s_flag;   // set to 2 on a p.q breakdown
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
     if (!done0) {
         for (;; ++k) {
+            // the decision of the apply of iteration k (iter_decide), in every wave
+            const double nr = sqrt(rr);
+            const bool bad = !isfinite(rr);
+            const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
             if (tid == 0) {
-                // the decision of the apply of iteration k (iter_decide)
-                const double nr = sqrt(rr);
-                const bool bad = !isfinite(rr);
-                const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
                 if (!(first && k > 1)) a.hist[k - 1] = nr / bnorm;
                 a.st->iter = k - 1;
                 a.st->rr = rr;
                 if (bad) a.st->status = PM_EBREAKDOWN;
                 if (stop) a.st->done = 1;
-                s_beta = (first || stop) ? 0.0 : rr / rr_prev;
-                s_flag = stop ? (bad ? 2 : 1) : 0;
             }
-            __syncthreads();
-            if (s_flag) {
-                if (s_flag == 2) status = PM_EBREAKDOWN;
+            if (stop) {
+                if (bad) status = PM_EBREAKDOWN;
                 break;
             }
-            const double beta = s_beta;
+            const double beta = first ? 0.0 : rr / rr_prev;
             // 1. p_k = r + beta p_{k-1}.  Each phase reads all it needs
             // before it writes, so the reads of its items are issued
             // together (the LDS arrays share one base, and the compiler
             // would otherwise order each read after the previous item's
             // writes).
-            {
+            if (tid < ustride) {   // whole waves
                 double pv[SMALL_MPT];
 #pragma unroll
                 for (int m = 0; m < SMALL_MPT; ++m) pv[m] = (!first && uvalid(m)) ? sp[unode(m)] : 0.0;
@@ -1172,7 +1171,7 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             }
             const double alpha = s_alpha;
             double u = 0.0;
-            {
+            if (tid < ustride) {   // whole waves
                 double xv[SMALL_MPT], pv[SMALL_MPT], qv[SMALL_MPT];
 #pragma unroll
                 for (int m = 0; m < SMALL_MPT; ++m) {
@@ -1193,13 +1192,13 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
                         u += ri * ri;
                     }
             }
-            u = wave_sum(u);
-            if (lane == 0) sred[wv] = u;
-            __syncthreads();
-            if (wv == 0) {
-                rr_prev = rr;
-                rr = vector_sum();
+            if (tid < ustride) {
+                u = wave_sum(u);
+                if (lane == 0) sred[wv] = u;
             }
+            __syncthreads();
+            rr_prev = rr;
+            rr = vector_sum();
             first = false;
         }
     }
