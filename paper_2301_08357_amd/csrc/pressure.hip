@@ -784,6 +784,8 @@ struct SmallArgs {
     const double *rhs, *x0;         // with rhs set (k0 = 1): form b, x, r and the state first
     double rtol;
     int max_iter;
+    double *hist_host;              // pinned host memory or null: the history, also written here
+    CGState *st_host;               // pinned host memory or null: the final state, copied here
 };
 
 // A CG solve of a small mesh in one launch of one 1024-lane workgroup.
@@ -936,7 +938,10 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             st->status = ok ? 0 : PM_EINVAL;
             st->done = stop0 ? 1 : 0;
             st->k_first = 1;
-            if (!(bnorm > 0.0)) a.hist[0] = 0.0;
+            if (!(bnorm > 0.0)) {
+                a.hist[0] = 0.0;
+                if (a.hist_host) a.hist_host[0] = 0.0;
+            }
             done0 = stop0 ? 1 : 0;
         }
     } else {
@@ -1099,7 +1104,10 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             const bool bad = !isfinite(rr);
             const bool stop = bad || !(nr > tol) || (k - 1) >= max_iter;
             if (tid == 0) {
-                if (!(first && k > 1)) a.hist[k - 1] = nr / bnorm;
+                if (!(first && k > 1)) {
+                    a.hist[k - 1] = nr / bnorm;
+                    if (a.hist_host) a.hist_host[k - 1] = nr / bnorm;
+                }
                 a.st->iter = k - 1;
                 a.st->rr = rr;
                 if (bad) a.st->status = PM_EBREAKDOWN;
@@ -1239,6 +1247,8 @@ __global__ void __launch_bounds__(SMALL_NTH) k_solve_small(Mesh g, SmallArgs a)
             a.x[unode(m)] = sx[unode(m)];
             a.r[unode(m)] = ur[m];
         }
+    // every write to the state came from this lane, which reads them back
+    if (tid == 0 && a.st_host) *a.st_host = *a.st;
 }
 
 
@@ -2810,6 +2820,9 @@ struct pm_handle {
     double *hist = nullptr;
     int32_t hist_cap = 0;
     CGState *hst = nullptr;     // pinned host mirror
+    double *hist_host = nullptr;   // pinned host copy of the history (one-launch solves)
+    int32_t hist_host_cap = 0;
+    bool in_noalloc = false;       // inside pressure_solve_noalloc: allocate nothing
     size_t dev_bytes = 0;
     std::vector<int32_t> elem_new2old;   // host copy, for coefficient updates
     // projection stage: dual cells (built at the first use) and buffers
@@ -3244,6 +3257,24 @@ int ensure_hist(pm_handle *h, int32_t max_iter)
     return PM_OK;
 }
 
+// The pinned host history of the one-launch solve, or nullptr when the
+// call may not allocate and the buffer is too small.
+static int ensure_hist_host(pm_handle *h, int32_t max_iter, double **out)
+{
+    *out = nullptr;
+    if (max_iter + 1 > h->hist_host_cap) {
+        if (h->in_noalloc) return PM_OK;
+        if (h->hist_host) HIPCK(hipHostFree(h->hist_host));
+        h->hist_host = nullptr;
+        h->hist_host_cap = 0;
+        const int32_t cap = std::max<int32_t>(max_iter + 1, 1024);
+        HIPCK(hipHostMalloc((void **)&h->hist_host, sizeof(double) * size_t(cap), hipHostMallocDefault));
+        h->hist_host_cap = cap;
+    }
+    *out = h->hist_host;
+    return PM_OK;
+}
+
 int event_pair(pm_handle *h, size_t k, hipEvent_t *a, hipEvent_t *b)
 {
     while (h->ev.size() < 2 * (k + 1)) {
@@ -3415,11 +3446,13 @@ struct ScratchSwap {
         h->hist_cap = int32_t(NA_HIST);
         h->st = reinterpret_cast<CGState *>(h->hist + NA_HIST);
         h->timing = false;   // timing events would be created on demand
+        h->in_noalloc = true;
     }
     ~ScratchSwap()
     {
         h->b = b, h->x = x, h->r = r, h->q = q, h->pbuf[0] = p0, h->pbuf[1] = p1;
         h->part = part, h->hist = hist, h->st = st, h->hist_cap = hist_cap, h->timing = timing;
+        h->in_noalloc = false;
     }
 };
 }  // namespace
@@ -3510,6 +3543,7 @@ void pressure_destroy(pm_handle *h)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hst) (void)hipHostFree(h->hst);
+    if (h->hist_host) (void)hipHostFree(h->hist_host);
     if (h->hst_in) (void)hipHostFree(h->hst_in);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
@@ -3810,7 +3844,7 @@ static bool small_ok(const pm_handle *h)
 // One launch of the one-workgroup solve from iteration k0; with rhs set
 // (k0 = 1) it also starts the solve from rhs and x0.
 static int launch_small(pm_handle *h, int k0, const double *rhs, const double *x0, double rtol, int max_iter,
-                        hipStream_t s)
+                        double *hist_host, CGState *st_host, hipStream_t s)
 {
     const size_t lds = small_lds_bytes(h->dim, h->N, h->E, h->n_ablocks, h->n_tiles);
     Mesh g = make_mesh<double>(h);
@@ -3833,6 +3867,8 @@ static int launch_small(pm_handle *h, int k0, const double *rhs, const double *x
     a.x0 = x0;
     a.rtol = rtol;
     a.max_iter = max_iter;
+    a.hist_host = hist_host;
+    a.st_host = st_host;
     auto go = [&]<int DIM, bool PER>() -> int {
         auto run = [&]<int EPT, bool GEO>() -> int {
             const void *kern = (const void *)k_solve_small<DIM, PER, EPT, GEO>;
@@ -3865,6 +3901,8 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
     // starts the solve unless the rhs must first be projected onto V_0.
     const bool small = small_ok(h);
     const bool small_start = small && !h->singular;
+    double *hist_host = nullptr;   // set: the one-launch passes write the history and state to the host too
+    if (small_start) TRY(ensure_hist_host(h, max_iter, &hist_host));
     if (!small_start) {
         hipLaunchKernelGGL(k_prepare, dim3(vg), dim3(BLK), 0, s, N, h->new2old, h->dir, rhs_dev, x0_dev, h->b, h->x,
                            h->part_misc());
@@ -3887,8 +3925,20 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
         int it_seen = 0;
         if (small) {
             const bool with_start = small_start && k == 1 && replaced == 0;
-            TRY(launch_small(h, k, with_start ? rhs_dev : nullptr, x0_dev, rtol, max_iter, s));
-            TRY(read_state(h, s));
+            // the launch writes the history and the final state to pinned
+            // host memory as well, so one synchronisation ends the pass
+            TRY(launch_small(h, k, with_start ? rhs_dev : nullptr, x0_dev, rtol, max_iter, hist_host,
+                             hist_host ? h->hst : nullptr, s));
+            // The output goes out before the state is read: a solve that
+            // needs no restart (nearly all) is then complete at the read.  A
+            // restart pass scatters again.  (With the V_0 shift the output
+            // waits for the last pass: the shift changes x.)
+            if (!h->singular) {
+                hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
+                HIPCK(hipGetLastError());
+            }
+            if (hist_host) HIPCK(hipStreamSynchronize(s));
+            else TRY(read_state(h, s));
         }
         for (; !small;) {
             const size_t t0 = timed;
@@ -3939,10 +3989,14 @@ int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, do
         ++replaced;
     }
     TRY(shift_mean(h, s));
-    hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
-    HIPCK(hipGetLastError());
+    if (!(small && !h->singular)) {
+        hipLaunchKernelGGL(k_scatter, dim3(grid_of(N)), dim3(BLK), 0, s, N, h->new2old, h->x, p_dev);
+        HIPCK(hipGetLastError());
+    }
     const CGState fin = *h->hst;
-    if (res_hist) HIPCK(hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (fin.iter + 1), hipMemcpyDeviceToHost, s));
+    if (res_hist && hist_host) std::memcpy(res_hist, hist_host, sizeof(double) * size_t(fin.iter + 1));
+    else if (res_hist)
+        HIPCK(hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (fin.iter + 1), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     *iters = fin.iter;
     double rel = 0.0;
