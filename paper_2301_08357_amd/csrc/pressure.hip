@@ -43,6 +43,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -3872,7 +3873,13 @@ static int launch_small(pm_handle *h, int k0, const double *rhs, const double *x
     auto go = [&]<int DIM, bool PER>() -> int {
         auto run = [&]<int EPT, bool GEO>() -> int {
             const void *kern = (const void *)k_solve_small<DIM, PER, EPT, GEO>;
-            if (lds > 65536) HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+            // the LDS limit is raised to the device's once per kernel and device
+            static std::atomic<unsigned long long> raised{0};
+            const unsigned long long bit = 1ull << (h->device & 63);
+            if (lds > 65536 && !(raised.load() & bit)) {
+                HIPCK(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_limit)));
+                raised.fetch_or(bit);
+            }
             hipLaunchKernelGGL((k_solve_small<DIM, PER, EPT, GEO>), dim3(1), dim3(SMALL_NTH), lds, s, g, a);
             HIPCK(hipGetLastError());
             return PM_OK;

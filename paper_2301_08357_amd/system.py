@@ -160,7 +160,7 @@ class PressureSystem:
             out = torch.empty_like(rhs)
         it = ctypes.c_int32(0)
         tr = ctypes.c_double(0.0)
-        hist = np.zeros(max_iter + 1)
+        hist = np.empty(max_iter + 1)   # the library writes entries 0..iters
         st = load().pressure_solve(self._h, _dev_ptr(rhs, self.n_nodes, "rhs"),
                                    None if x0 is None else _dev_ptr(x0, self.n_nodes, "x0"),
                                    float(rtol), int(max_iter), _dev_ptr(out, self.n_nodes, "p"),
@@ -176,7 +176,7 @@ class PressureSystem:
         it = ctypes.c_int32(0)
         tr = ctypes.c_double(0.0)
         if hist is None:
-            hist = np.zeros(max_iter + 1)
+            hist = np.empty(max_iter + 1)   # the library writes entries 0..iters
         elif hist.dtype != np.float64 or not hist.flags.c_contiguous or hist.size < max_iter + 1:
             raise ValueError("hist must be a contiguous float64 array of at least max_iter + 1 entries")
         st = load().pressure_solve_noalloc(self._h, _dev_ptr(rhs, self.n_nodes, "rhs"),
@@ -193,7 +193,7 @@ class PressureSystem:
         it = ctypes.c_int32(0)
         outer = ctypes.c_int32(0)
         tr = ctypes.c_double(0.0)
-        hist = np.zeros(max_iter + 1)
+        hist = np.empty(max_iter + 1)   # the library writes entries 0..iters
         st = load().pressure_solve_mixed(self._h, _dev_ptr(rhs, self.n_nodes, "rhs"),
                                          None if x0 is None else _dev_ptr(x0, self.n_nodes, "x0"),
                                          float(rtol), float(inner_rtol), int(max_iter),
