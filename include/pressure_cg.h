@@ -196,7 +196,11 @@ int pressure_apply(pm_handle *h, const double *x_dev, double *y_dev, void *strea
  * the true residual) in a single launch of one workgroup, with the same
  * arithmetic and the same reduction order, so p, iters, res_hist and
  * true_relres are bit for bit those of the multi-launch form.  Timing
- * (pressure_timing_enable) keeps the multi-launch form. */
+ * (pressure_timing_enable) keeps the multi-launch form.  Such a launch also
+ * writes the history and the final state to pinned host memory held by the
+ * handle (max_iter + 1 doubles, grown on demand, freed by pressure_destroy;
+ * none is allocated inside pressure_solve_noalloc), so the call ends with one
+ * stream synchronisation. */
 int pressure_solve(pm_handle *h, const double *rhs_dev, const double *x0_dev, double rtol,
                    int32_t max_iter, double *p_dev, int32_t *iters, double *res_hist,
                    double *true_relres, void *stream);
