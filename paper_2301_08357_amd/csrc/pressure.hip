@@ -797,10 +797,12 @@ struct SmallArgs {
 // iterate, its norm in st->tt and its partials for a restart.  The
 // coordinates, the node values and the element contributions live in LDS;
 // each lane keeps its elements (vertex ids, contribution slots, factor) and
-// the residual at its update nodes in registers for the whole solve, and an
-// iteration is four phases between block barriers: the direction update,
-// the element contributions, the node sums with the p.q partials, and the
-// vector update with the r.r partials.
+// the residual at its vector nodes in registers for the whole solve.  An
+// iteration is five phases between block barriers: the direction update,
+// the element contributions, the node sums with the p.q partials, p.q and
+// alpha in wave 0, and the vector update with the r.r partials.  With
+// a.hist_host and a.st_host set the history and, at the end, the state are
+// written to those host buffers as well.
 // The arithmetic is that of the multi-launch solve (k_prepare, k_begin,
 // the apply, k_start, the two-kernel iteration, k_true_residual and
 // k_finish_tt), operation for operation and in the same order, reductions
