@@ -73,7 +73,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--tile", type=int, default=0, help="Morton tile nodes (128/256/512; 0 = library default)")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="Morton tile nodes (128/256/512; 0 = the library default, 128; -1 = the size the library's "
+                         "tile autotuner picks, on the cube160 line, else the default)")
     ap.add_argument("--inner-rtol", type=float, default=1e-2,
                     help="residual drop of the FP32 inner CG between FP64 corrections (mixed solve)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
@@ -131,6 +133,12 @@ def bench_tgv2d32(args):
                       "config": {"workload": rec["workload"]}, **{k: v for k, v in rec.items() if k != "workload"}}))
 
 
+def tile_flag_of(args):
+    """PM_TILE_* flag of --tile (-1, the autotuner, counts as the default here)."""
+    import paper_2301_08357_amd as pm
+    return {-1: 0, 0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
+
+
 def bench_cube64(args):
     """The 64^3 cube (1,572,864 tets, 274,625 nodes, no jitter), c = 1/rho
     with rho ~ U[0.5, 2] per element, one FP64 CG solve to rtol 1e-10 from
@@ -142,7 +150,7 @@ def bench_cube64(args):
     ws = workloads.CUBE64_W
     probs = [workloads.cube64(w) for w in ws]
     m = probs[0].mesh
-    tile_flag = {0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
+    tile_flag = tile_flag_of(args)
     flags = pm.PM_FP64 | pm.PM_FP32_INNER | tile_flag
     systems = [pm.PressureSystem.from_problem(p, flags=flags) for p in probs]
     for s in systems:
@@ -261,7 +269,9 @@ def bench_cube160(args):
     and FP32-inner defect correction, both to rtol 1e-10 (the default line,
     with the cube64 and tgv2d_32 legs and the CPU oracle).  cube160p: the
     same recipe on the fully periodic mesh with merged images; --lumped: the
-    lumped mass matrix (these two print the solve and roofline only)."""
+    lumped mass matrix (these two print the solve and roofline only).  The
+    default line takes the Morton tile size the library's autotuner picks for
+    the mesh (tuned before the timed region; --tile fixes it instead)."""
     import torch
     import paper_2301_08357_amd as pm
     from synth import workloads
@@ -270,7 +280,16 @@ def bench_cube160(args):
     if args.lumped:
         prob = workloads.lumped(prob)
     main_line = not periodic and not args.lumped
-    tile_flag = {0: 0, 128: pm.PM_TILE_128, 256: pm.PM_TILE_256, 512: pm.PM_TILE_512}[args.tile]
+    tile_flag = tile_flag_of(args)
+    tuning_s = None
+    if args.tile == -1 and main_line:
+        # the library's tile autotuner (pressure_tune_tile): CG iterations at
+        # each Morton tile size, the fastest kept (cached per device and build)
+        t_tune = time.perf_counter()
+        tuned, _ = pm.tune_tile(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER, iters=32)
+        tile_flag = tuned & 0xF0
+        tuning_s = round(time.perf_counter() - t_tune, 2)
+    tile_nodes = {0: 128, pm.PM_TILE_128: 128, pm.PM_TILE_256: 256, pm.PM_TILE_512: 512}[tile_flag]
     t_setup = time.perf_counter()
     s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER | tile_flag)
     t_setup = time.perf_counter() - t_setup
@@ -322,11 +341,13 @@ def bench_cube160(args):
                                          "to rtol %g from x0=0, b = A x* with x* = prod sin(pi x_i), Morton order; one "
                                          "step = one solve" % ("lumped" if args.lumped else "consistent", args.rtol),
                       "n_nodes": info["n_nodes"], "n_free": info["n_free"], "n_elems": info["n_elems"],
+                      "tile_nodes": tile_nodes, "n_tiles": info["n_tiles"],
+                      "tile_choice": "autotuner" if tuning_s is not None else "fixed",
                       "rtol": args.rtol, "iterations": its[0]},
            "solves_per_s": round(args.steps / el, 3),
            "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
-           "setup_s": round(t_setup, 2),
+           "setup_s": round(t_setup, 2), "tile_tuning_s": tuning_s,
            "rel_error_vs_manufactured": err, "roofline": roof}
     if not args.no_mixed:
         out["mixed"] = mixed_comparison([s], [b], xs, args, el / args.steps)

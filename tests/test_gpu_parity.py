@@ -229,21 +229,23 @@ def test_cube64_full_size_solve():
     s.close()
 
 
-def test_cube160_full_size_solves():
+@pytest.mark.parametrize("tile", [pm.PM_TILE_128, pm.PM_TILE_256])
+def test_cube160_full_size_solves(tile):
     """The 160^3 benchmark system (jittered, lognormal rho, w = 1e-4), in the
-    bench's launch configuration: the FP64 CG solve and the mixed solve
+    bench's launch configurations (the default 128-node tiles and the
+    256-node tiles the autotuner picks for it): the FP64 CG solve and the mixed solve
     (FP32 inner CG, FP64 corrections, inner residual drop 1e-2) of the
     oracle's right-hand side b = A x*, each accepted by one full residual of
     the oracle's element-by-element operator at 1.05 x rtol, and each within
     1e-10 relative of x*, the exact solution of that system."""
     prob = workloads.cube160()
     m = prob.mesh
-    print("case cube160 solves", flush=True)
+    print("case cube160 solves, tile flag", tile, flush=True)
     xs = prob.extra["xstar"]
     args = (3, m.coords, m.elems, prob.coef, prob.alpha, prob.beta, m.dirichlet)
     b = oracle.apply_elements(*args, xs)
     bn = np.linalg.norm(b)
-    s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER)
+    s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | pm.PM_FP32_INNER | tile)
     bd = _dev(b)
     r64 = s.solve(bd, rtol=1e-10)
     x64 = _host(r64.p).copy()
@@ -260,13 +262,14 @@ def test_cube160_full_size_solves():
         assert err <= 1e-10, (name, err)
 
 
-def test_cube160_sampled_rows():
+@pytest.mark.parametrize("tile", [pm.PM_TILE_128, pm.PM_TILE_256])
+def test_cube160_sampled_rows(tile):
     """The 160^3 mesh: sampled rows of y = A x against the oracle row by row."""
     prob = workloads.cube160()
     m = prob.mesh
-    print("case cube160", flush=True)
+    print("case cube160, tile flag", tile, flush=True)
     x = np.random.default_rng(11).normal(size=m.n_nodes)
-    s = pm.PressureSystem.from_problem(prob)
+    s = pm.PressureSystem.from_problem(prob, flags=pm.PM_FP64 | tile)
     y = _host(s.apply(_dev(x)))
     rows = np.random.default_rng(12).choice(m.n_nodes, 2000, replace=False)
     rows = np.concatenate([rows, [0, m.n_nodes - 1]])
